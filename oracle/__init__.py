@@ -1,0 +1,17 @@
+"""CPU oracle for the IP-GFCCSD linear-solve path (TEST INFRASTRUCTURE ONLY).
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
+``bench.py`` may import anything from this package.  The GPU library never
+calls it and shares no code with it; both sides only share the seeded input
+generator in ``synth``.
+
+* ``oracle.fockspace`` -- O1: a Fock-space brute force.  It needs no working
+  equations: it builds the second-quantised Hamiltonian, the cluster and
+  de-excitation operators as determinant matrices and forms the connected
+  similarity-transformed Hamiltonian, the ket ``abar_p|Phi>`` and the bra
+  ``<Phi|(1+Lambda) abar_q^dagger`` directly from their definitions (paper,
+  Sec. 2, eqs. for G_pq in the bi-orthogonal CC form and its compact form).
+* ``oracle.ipgfcc`` -- O2: a matrix-free spin-adapted closed-shell
+  implementation (intermediates, sigma product, diagonal, left vectors,
+  GMRES, Green's function), pinned against O1 and closed forms.
+"""

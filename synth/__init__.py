@@ -1,0 +1,161 @@
+"""Seeded synthetic closed-shell systems for the IP-GFCCSD linear-solve path.
+
+This module is the ONLY code shared by the CPU oracle (``oracle/``) and the
+GPU library's tests/benchmarks.  It draws random numbers and forms the MP2
+amplitudes that stand in for converged CCSD amplitudes; it contains none of
+the Green's-function arithmetic (no similarity-transformed Hamiltonian, no
+sigma product, no left vectors, no solver).
+
+Recipe (one ``numpy.random.Generator(PCG64(seed))`` stream, drawn in this
+order):
+
+1. ``eps_occ ~ U(-1.2, -0.3)`` (n_occ values), ``eps_vir ~ U(0.1, 2.0)``
+   (n_vir values), each block sorted ascending.
+2. Cholesky vectors ``L[Q, p, q]`` symmetric in (p, q): the upper triangle
+   including the diagonal is drawn i.i.d. ``N(0, sigma_L^2)`` and mirrored.
+3. ``T1[i, a] ~ N(0, sigma_T1^2)``.
+4. ``T2[i, j, a, b] = (ia|jb) / (e_i + e_j - e_a - e_b)`` with chemist
+   integrals ``(pq|rs) = sum_Q L[Q,p,q] L[Q,r,s]`` (MP2 amplitudes; pair
+   symmetric ``T2[i,j,a,b] = T2[j,i,b,a]``).
+5. ``Lambda = T^dagger``: ``l1 = T1``, ``l2 = T2`` (same index layout).
+6. Frequencies ``omega = linspace(w_min, w_max, n_omega)`` (both ends).
+
+Orbital energies are Hartree.  The Fock matrix of the reference is
+``diag(eps)``; occupied orbitals come first.
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+BASE_SEED = 2010_04768
+
+
+@dataclasses.dataclass
+class System:
+    """One synthetic closed-shell system (all arrays float64, C-contiguous)."""
+
+    n_occ: int
+    n_vir: int
+    n_chol: int
+    eps: np.ndarray  # [n_occ + n_vir]
+    L: np.ndarray  # [n_chol, n, n]
+    t1: np.ndarray  # [n_occ, n_vir]
+    t2: np.ndarray  # [n_occ, n_occ, n_vir, n_vir]
+    l1: np.ndarray  # [n_occ, n_vir]
+    l2: np.ndarray  # [n_occ, n_occ, n_vir, n_vir]
+    seed: int
+
+    @property
+    def n(self) -> int:
+        return self.n_occ + self.n_vir
+
+    @property
+    def dim(self) -> int:
+        """Dimension of the spin-adapted 1h + 2h1p space: o + o*o*v."""
+        return self.n_occ + self.n_occ * self.n_occ * self.n_vir
+
+
+def make_system(n_occ: int, n_vir: int, n_chol: int, seed: int, *,
+                sigma_L: float = 0.05, sigma_t1: float = 1e-3,
+                occ_range=(-1.2, -0.3), vir_range=(0.1, 2.0),
+                t1: bool = True, t2: bool = True, lam: bool = True,
+                L_zero: bool = False) -> System:
+    """Draw one system.  Switches zero whole amplitude classes (for pins)."""
+    o, v, Q = int(n_occ), int(n_vir), int(n_chol)
+    n = o + v
+    rng = np.random.Generator(np.random.PCG64(seed))
+    e_occ = np.sort(rng.uniform(occ_range[0], occ_range[1], size=o))
+    e_vir = np.sort(rng.uniform(vir_range[0], vir_range[1], size=v))
+    eps = np.concatenate([e_occ, e_vir])
+
+    iu, ju = np.triu_indices(n)
+    L = np.zeros((Q, n, n))
+    vals = rng.normal(0.0, sigma_L, size=(Q, iu.size))
+    L[:, iu, ju] = vals
+    L[:, ju, iu] = vals
+    del vals
+    if L_zero:
+        L[:] = 0.0
+
+    T1 = rng.normal(0.0, sigma_t1, size=(o, v))
+    if not t1:
+        T1[:] = 0.0
+
+    if t2:
+        Lov = np.ascontiguousarray(L[:, :o, o:]).reshape(Q, o * v)
+        iajb = (Lov.T @ Lov).reshape(o, v, o, v)
+        den = (e_occ[:, None, None, None] + e_occ[None, None, :, None]
+               - e_vir[None, :, None, None] - e_vir[None, None, None, :])
+        T2 = np.ascontiguousarray((iajb / den).transpose(0, 2, 1, 3))
+        del iajb, den
+    else:
+        T2 = np.zeros((o, o, v, v))
+
+    if lam:
+        l1 = T1.copy()
+        l2 = T2.copy()
+    else:
+        l1 = np.zeros_like(T1)
+        l2 = np.zeros_like(T2)
+    return System(o, v, Q, eps, L, T1, T2, l1, l2, seed)
+
+
+@dataclasses.dataclass
+class Workload:
+    """A named workload: one or more systems plus the (p, omega) grid."""
+
+    name: str
+    systems: List[System]
+    omegas: List[np.ndarray]
+    p_lists: List[np.ndarray]
+    eta: float
+    tol: float
+    restart: int
+
+    @property
+    def n_rhs(self) -> int:
+        return int(sum(len(w) * len(p) for w, p in zip(self.omegas, self.p_lists)))
+
+
+def _highest(n_occ: int, k: int) -> np.ndarray:
+    return np.arange(max(0, n_occ - k), n_occ, dtype=np.int64)
+
+
+# Workload shapes (o, v, Q, n_omega, omega range, eta, p selection, tol).
+WORKLOADS = {
+    "tiny-o4v16": dict(shapes=[(4, 16, 48)], n_omega=6, w=(-1.0, -0.2), eta=0.01,
+                       p="all", tol=1e-10, restart=30, seed_off=[1]),
+    "plain-o40v200": dict(shapes=[(40, 200, 800)], n_omega=64, w=(-1.2, -0.3), eta=0.01,
+                          p="all", tol=1e-8, restart=30, seed_off=[2]),
+    "mixed-3sys": dict(shapes=[(20, 100, 400), (40, 180, 720), (60, 300, 1200)], n_omega=128,
+                       w=(-1.2, -0.3), eta=0.01, p="all", tol=1e-8, restart=30,
+                       seed_off=[31, 32, 33]),
+    "learned-o90v420": dict(shapes=[(90, 420, 1800)], n_omega=256, w=(-1.2, -0.3), eta=0.005,
+                            p=30, tol=1e-8, restart=30, seed_off=[4]),
+    "c60-o120v600": dict(shapes=[(120, 600, 3000)], n_omega=400, w=(-1.2, -0.3), eta=0.005,
+                         p=30, tol=1e-8, restart=30, seed_off=[5]),
+}
+
+
+def make_workload(name: str, n_omega: Optional[int] = None,
+                  shapes: Optional[Sequence] = None) -> Workload:
+    """Build a named workload; ``n_omega``/``shapes`` override for reduced tests."""
+    spec = WORKLOADS[name]
+    shp = list(shapes) if shapes is not None else spec["shapes"]
+    nw = spec["n_omega"] if n_omega is None else int(n_omega)
+    systems, omegas, plists = [], [], []
+    for (o, v, Q), off in zip(shp, spec["seed_off"]):
+        systems.append(make_system(o, v, Q, BASE_SEED + off))
+        omegas.append(np.linspace(spec["w"][0], spec["w"][1], nw))
+        plists.append(np.arange(o, dtype=np.int64) if spec["p"] == "all"
+                      else _highest(o, spec["p"]))
+    return Workload(name, systems, omegas, plists, spec["eta"], spec["tol"], spec["restart"])
+
+
+def random_vectors(n_vec: int, dim: int, seed: int) -> np.ndarray:
+    """Complex128 test vectors [n_vec, dim] with N(0,1) real and imaginary parts."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return rng.normal(size=(n_vec, dim)) + 1j * rng.normal(size=(n_vec, dim))
