@@ -1,0 +1,165 @@
+/*
+ * gfcc.h -- C ABI of the MI355X IP-GFCCSD linear-solve library (libgfcc.so).
+ *
+ * Operation (arXiv 2010.04768, Sec. 2): for occupied orbitals p, q and real
+ * frequencies omega, the retarded ionisation (IP) term of the coupled-cluster
+ * Green's function in the GFCCSD truncation,
+ *
+ *     G_qp(omega) = c_q^T X_p(omega),   (omega + Hbar_N - i*eta) X_p = b_p,
+ *
+ * (the linear system for X_p and the compact form of G; the bilinear product
+ * c^T X of the model-order-reduction equations), where
+ *   Hbar_N  = connected similarity-transformed Hamiltonian e^-T H e^T - E0,
+ *             restricted to the 1h + 2h1p space of X_p (the X_p expansion),
+ *   b_p     = abar_p |Phi>  (= the 1h unit vector e_p for occupied p),
+ *   c_q     = <Phi|(1 + Lambda) abar_q^+ restricted to the same space,
+ * with T and Lambda truncated at singles and doubles.  The systems are solved
+ * by restarted GMRES (Sec. 3), optionally right-preconditioned.
+ *
+ * Closed-shell spin-adapted basis, dimension D = o + o*o*v:
+ *     x[0 .. o)                     = r_i     (1h)
+ *     x[o + (i*o + j)*v + a]        = r_ija   (2h1p, the i(alpha) j(beta) -> a(beta) amplitude)
+ * Complex vectors at this boundary are interleaved (re, im) FP64 pairs,
+ * i.e. a complex vector of dimension D is 2*D doubles.
+ *
+ * Conventions for every entry point:
+ *   - All array pointers are DEVICE pointers unless the comment says "host".
+ *   - Row-major, 64-bit dimensions.  Orbitals are ordered occupied first.
+ *   - Work is enqueued on `stream` (a hipStream_t; NULL = the null stream).
+ *     Entry points return after enqueueing unless stated "blocking".
+ *   - Nothing throws across the ABI; every function returns a gfcc_status.
+ *     On failure gfcc_last_error() returns a thread-local message.
+ *   - Input arrays are borrowed for the duration of the call only (the
+ *     context copies what it keeps).  Output arrays are owned by the caller.
+ */
+#ifndef GFCC_H
+#define GFCC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gfcc_ctx gfcc_ctx; /* opaque: owns intermediates and workspaces */
+
+typedef enum {
+  GFCC_OK = 0,
+  GFCC_E_ARG = -1,    /* bad argument or dimension */
+  GFCC_E_OOM = -2,    /* device allocation failed */
+  GFCC_E_HIP = -3,    /* HIP runtime error */
+  GFCC_E_STATE = -4,  /* call not valid in the context's state */
+  GFCC_W_NOCONV = 1   /* solve finished; some right-hand sides did not converge (see info) */
+} gfcc_status;
+
+/* Arithmetic of the sigma product.  The FP32/BF16 forms run the two-body
+ * (W-tensor) contractions on MFMA in that precision with FP32 accumulation;
+ * one-body terms, Arnoldi, Givens and the true residual stay FP64 and the
+ * solver refines iteratively in FP64 (GMRES-IR). */
+typedef enum { GFCC_FP64 = 0, GFCC_FP32_IR = 1, GFCC_BF16_IR = 2 } gfcc_precision;
+
+typedef enum {
+  GFCC_PC_NONE = 0,   /* plain GMRES */
+  GFCC_PC_JACOBI = 1, /* right preconditioner 1/(omega - i eta + diag(Hbar_N)) (Sec. 3) */
+  GFCC_PC_MLP = 2     /* learned residual->correction network, flexible GMRES; Jacobi fallback */
+} gfcc_precond;
+
+/* One closed-shell system.  Device pointers, FP64, borrowed for the call.
+ *   eps [n]            orbital energies (Fock matrix diag(eps)), occupied first
+ *   L   [Q][n][n]      Cholesky vectors, symmetric in (p,q):
+ *                      (pq|rs) = sum_Q L[Q][p][q] L[Q][r][s]   (Sec. 5, Cholesky ERIs)
+ *   t1  [o][v], t2 [o][o][v][v]   ground-state amplitudes t_i^a, t_ij^ab
+ *                      (t2[i][j][a][b] = t2[j][i][b][a])
+ *   l1, l2             Lambda amplitudes in the same layout; NULL means
+ *                      Lambda = T^dagger (l1 = t1, l2 = t2).               */
+typedef struct {
+  int64_t n_occ, n_vir, n_chol;
+  const double* eps;
+  const double* L;
+  const double* t1;
+  const double* t2;
+  const double* l1;
+  const double* l2;
+} gfcc_system;
+
+/* Build the per-system intermediates (blocks of Hbar_N, its exact diagonal,
+ * the left vectors c_q for all occupied q, and reduced-precision copies) on
+ * the GPU; the paper precomputes these constant intermediates before the
+ * GFCC loop (Sec. 5).  Blocking.  *out receives a new context. */
+gfcc_status gfcc_build_intermediates(const gfcc_system* sys, void* stream, gfcc_ctx** out);
+
+/* Dimensions of the context: D = o + o*o*v, o, v. Host pointers; any may be NULL. */
+gfcc_status gfcc_dims(const gfcc_ctx* ctx, int64_t* D, int64_t* n_occ, int64_t* n_vir);
+
+/* Copy one built FP64 block into a caller device buffer (for verification).
+ * Layouts (index order = array order):
+ *   FOO [m][i]  FVV [a][e]  FOV [m][e]  WOOOO [m][n][i][j]  WOOOV [m][n][i][e]
+ *   WOVOO [m][a][i][j]  WOVVO [m][a][e][j]  WOVOV [m][a][j][e]
+ *   DIAG [D]    (exact diagonal of Hbar_N)
+ *   LEFT [o][D] (row q = c_q)                                             */
+typedef enum {
+  GFCC_FOO = 0, GFCC_FVV, GFCC_FOV, GFCC_WOOOO, GFCC_WOOOV, GFCC_WOVOO, GFCC_WOVVO, GFCC_WOVOV,
+  GFCC_DIAG, GFCC_LEFT, GFCC_N_BLOCKS
+} gfcc_block;
+gfcc_status gfcc_export(gfcc_ctx* ctx, gfcc_block which, double* dst, void* stream);
+
+/* Y[r] = Hbar_N X[r] for r < nrhs.  X, Y: [nrhs][D] complex interleaved; may
+ * not alias.  prec selects the arithmetic of the two-body contractions. */
+gfcc_status gfcc_sigma(gfcc_ctx* ctx, int64_t nrhs, const double* X, double* Y,
+                       gfcc_precision prec, void* stream);
+
+typedef struct {
+  size_t struct_size;       /* sizeof(gfcc_solve_opts) */
+  double tol;               /* on ||b - A x|| / ||b||, true FP64 residual */
+  int32_t restart;          /* Krylov vectors per cycle (>= 1) */
+  int32_t max_iter;         /* total inner iterations per right-hand side */
+  int32_t batch;            /* active right-hand sides per launch; 0 = auto from free HBM */
+  gfcc_precond precond;
+  gfcc_precision precision;
+  int32_t use_graph;        /* capture one inner iteration in a hipGraph and replay it */
+  const char* tune_cache;   /* host path of the tile autotuner JSON cache; NULL = no tuning */
+} gfcc_solve_opts;
+
+/* Per right-hand side result (host memory). status: 0 converged, 1 max_iter,
+ * 2 breakdown, 3 non-finite, 4 converged after falling back to Jacobi. */
+typedef struct {
+  int32_t status, iters, restarts, reserved;
+  double true_rel_resid;
+} gfcc_rhs_info;
+
+/* Solve (omega_r + Hbar_N - i*eta) X_r = b_{p_r} for r < nrhs and form
+ * G[r][k] = c_{q_k}^T X_r.  p, omega: host arrays [nrhs]; q: host [nq] or
+ * NULL meaning q = p_r per right-hand side (then nq must be 1: G[r][0] = G_pp).
+ * G: device [nrhs][nq] complex interleaved.  X: device [nrhs][D] complex or
+ * NULL (solutions are not kept).  info: host [nrhs].  eta is signed; the
+ * operator is exactly (omega + Hbar_N - i*eta).  Right-hand sides are
+ * processed through a persistent window of `batch` slots; a slot whose system
+ * converges is refilled from the queue.  Blocking.  Returns GFCC_W_NOCONV if
+ * any right-hand side did not converge. */
+gfcc_status gfcc_solve_batch(gfcc_ctx* ctx, int64_t nrhs, const int64_t* p, const double* omega,
+                             double eta, int64_t nq, const int64_t* q, const gfcc_solve_opts* opts,
+                             double* G, double* X, gfcc_rhs_info* info, void* stream);
+
+/* G[r][k] = c_{q_k}^T X[r] (bilinear, no conjugation) for caller vectors X
+ * [nrhs][D] complex; q host [nq]. G device [nrhs][nq] complex. */
+gfcc_status gfcc_greens(gfcc_ctx* ctx, int64_t nrhs, const double* X, int64_t nq, const int64_t* q,
+                        double* G, void* stream);
+
+/* Kernel timing of the library's launches with HIP events on the launch
+ * stream.  enable != 0 starts recording (clears totals).  For a kernel class
+ * name ("ring_gemm", "sigma", "arnoldi", "precond", "mlp") gfcc_prof_get
+ * returns the number of launches, total milliseconds and algorithmic flops and
+ * bytes summed over them (host outputs).  Blocking. */
+gfcc_status gfcc_prof_enable(gfcc_ctx* ctx, int enable);
+gfcc_status gfcc_prof_get(gfcc_ctx* ctx, const char* name, int64_t* count, double* ms,
+                          double* flops, double* bytes);
+
+gfcc_status gfcc_destroy(gfcc_ctx* ctx);
+const char* gfcc_strerror(gfcc_status st);
+const char* gfcc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GFCC_H */

@@ -1,0 +1,243 @@
+// C ABI of libgfcc (see include/gfcc.h).  Argument checking, error capture
+// and dispatch to the build / sigma / solver / Green's-function code.
+#include <cstring>
+#include <exception>
+#include <string>
+
+#include "ctx.h"
+
+namespace gfcc {
+static thread_local std::string g_last_error;
+void set_error(const std::string& msg) { g_last_error = msg; }
+void solve_batch(gfcc_ctx* c, int64_t nrhs, const int64_t* p, const double* omega, double eta, int64_t nq,
+                 const int64_t* q, const gfcc_solve_opts* opts, double* G, double* X, gfcc_rhs_info* info,
+                 hipStream_t s, bool* all_converged);
+}  // namespace gfcc
+
+using namespace gfcc;
+
+template <typename F>
+static gfcc_status guarded(F&& f) {
+  try {
+    f();
+    return GFCC_OK;
+  } catch (const Error& e) {
+    set_error(e.msg);
+    return e.st;
+  } catch (const std::bad_alloc&) {
+    set_error("host allocation failed");
+    return GFCC_E_OOM;
+  } catch (const std::exception& e) {
+    set_error(e.what());
+    return GFCC_E_STATE;
+  }
+}
+
+static hipStream_t as_stream(void* s) { return static_cast<hipStream_t>(s); }
+
+extern "C" {
+
+gfcc_status gfcc_build_intermediates(const gfcc_system* sys, void* stream, gfcc_ctx** out) {
+  return guarded([&] {
+    GFCC_CHECK(sys && out, GFCC_E_ARG, "null argument");
+    GFCC_CHECK(sys->n_occ >= 1 && sys->n_vir >= 1 && sys->n_chol >= 1, GFCC_E_ARG,
+               "n_occ, n_vir and n_chol must be >= 1");
+    GFCC_CHECK(sys->n_occ <= 4096 && sys->n_vir <= 65536, GFCC_E_ARG, "dimensions out of range");
+    GFCC_CHECK(sys->eps && sys->L && sys->t1 && sys->t2, GFCC_E_ARG, "eps, L, t1 and t2 are required");
+    *out = nullptr;
+    gfcc_ctx* c = new gfcc_ctx();
+    try {
+      c->o = sys->n_occ;
+      c->v = sys->n_vir;
+      c->Q = sys->n_chol;
+      c->n = c->o + c->v;
+      c->ov = c->o * c->v;
+      c->oo = c->o * c->o;
+      c->oov = c->oo * c->v;
+      c->D = c->o + c->oov;
+      c->o_pad = round_up(c->o, 8);
+      c->Dp = c->o_pad + round_up(c->oov, 8);
+      c->kp = round_up(c->ov, 8);
+      c->op2 = round_up(c->oo, 8);
+      c->vp = round_up(c->v, 8);
+      c->ldz = round_up(c->oov, 8);
+      c->lp_ps = round_up(c->oov, 8);
+      hipStream_t s = as_stream(stream);
+      build_intermediates(c, sys, s);
+      GFCC_HIP(hipStreamSynchronize(s));
+    } catch (...) {
+      delete c;
+      throw;
+    }
+    *out = c;
+  });
+}
+
+gfcc_status gfcc_dims(const gfcc_ctx* c, int64_t* D, int64_t* n_occ, int64_t* n_vir) {
+  return guarded([&] {
+    GFCC_CHECK(c, GFCC_E_ARG, "null context");
+    if (D) *D = c->D;
+    if (n_occ) *n_occ = c->o;
+    if (n_vir) *n_vir = c->v;
+  });
+}
+
+gfcc_status gfcc_export(gfcc_ctx* c, gfcc_block which, double* dst, void* stream) {
+  return guarded([&] {
+    GFCC_CHECK(c && dst, GFCC_E_ARG, "null argument");
+    hipStream_t s = as_stream(stream);
+    const int64_t o = c->o, v = c->v, kp = c->kp;
+    auto copy = [&](const DBuf& b, int64_t n) {
+      GFCC_HIP(hipMemcpyAsync(dst, b.p, size_t(n) * 8, hipMemcpyDeviceToDevice, s));
+    };
+    switch (which) {
+      case GFCC_FOO: copy(c->Foo, o * o); break;
+      case GFCC_FVV: copy(c->Fvv, v * v); break;
+      case GFCC_FOV: copy(c->Fov, o * v); break;
+      case GFCC_WOOOO: copy(c->Woooo, o * o * o * o); break;
+      case GFCC_WOOOV: copy(c->Wooov, o * o * o * v); break;
+      case GFCC_WOVOO: copy(c->Wovoo, o * v * o * o); break;
+      case GFCC_WOVVO: {
+        TView in = tview_s(c->Wvo.as<double>(), {o, v, v, o}, {v, kp, 1, v * kp});
+        TView out = tview(dst, {o, v, v, o});
+        const int id[4] = {0, 1, 2, 3};
+        permute(in, id, 1.0, out, 0.0, s);
+        break;
+      }
+      case GFCC_WOVOV: {
+        TView in = tview_s(c->Wov.as<double>(), {o, v, o, v}, {v, kp, v * kp, 1});
+        TView out = tview(dst, {o, v, o, v});
+        const int id[4] = {0, 1, 2, 3};
+        permute(in, id, 1.0, out, 0.0, s);
+        break;
+      }
+      case GFCC_DIAG:
+        GFCC_HIP(hipMemcpyAsync(dst, c->diag.p, size_t(o) * 8, hipMemcpyDeviceToDevice, s));
+        GFCC_HIP(hipMemcpyAsync(dst + o, c->diag.as<double>() + c->o_pad, size_t(c->oov) * 8,
+                                hipMemcpyDeviceToDevice, s));
+        break;
+      case GFCC_LEFT:
+        GFCC_HIP(hipMemcpy2DAsync(dst, size_t(c->D) * 8, c->left.p, size_t(c->Dp) * 8, size_t(o) * 8, size_t(o),
+                                  hipMemcpyDeviceToDevice, s));
+        GFCC_HIP(hipMemcpy2DAsync(dst + o, size_t(c->D) * 8, c->left.as<double>() + c->o_pad, size_t(c->Dp) * 8,
+                                  size_t(c->oov) * 8, size_t(o), hipMemcpyDeviceToDevice, s));
+        break;
+      default: throw Error{GFCC_E_ARG, "unknown block"};
+    }
+  });
+}
+
+gfcc_status gfcc_sigma(gfcc_ctx* c, int64_t nrhs, const double* X, double* Y, gfcc_precision prec, void* stream) {
+  return guarded([&] {
+    GFCC_CHECK(c, GFCC_E_ARG, "null context");
+    GFCC_CHECK(nrhs >= 0, GFCC_E_ARG, "nrhs < 0");
+    GFCC_CHECK(prec == GFCC_FP64 || prec == GFCC_FP32_IR || prec == GFCC_BF16_IR, GFCC_E_ARG, "bad precision");
+    if (nrhs == 0) return;
+    GFCC_CHECK(X && Y && X != Y, GFCC_E_ARG, "X and Y must be distinct device buffers");
+    hipStream_t s = as_stream(stream);
+    const int64_t chunk = 64;
+    for (int64_t r0 = 0; r0 < nrhs; r0 += chunk) {
+      const int64_t nb = std::min(chunk, nrhs - r0);
+      c->ws_in.ensure(size_t(2 * nb * c->Dp) * 8, s);
+      c->ws_out.ensure(size_t(2 * nb * c->Dp) * 8, s);
+      to_planes(c, nb, X + r0 * c->D * 2, c->ws_in.as<double>(), s);
+      sigma_planes(c, 2 * nb, c->ws_in.as<double>(), c->ws_out.as<double>(), prec, s);
+      from_planes(c, nb, c->ws_out.as<double>(), Y + r0 * c->D * 2, s);
+    }
+  });
+}
+
+gfcc_status gfcc_greens(gfcc_ctx* c, int64_t nrhs, const double* X, int64_t nq, const int64_t* q, double* G,
+                        void* stream) {
+  return guarded([&] {
+    GFCC_CHECK(c, GFCC_E_ARG, "null context");
+    GFCC_CHECK(nrhs >= 0 && nq >= 0, GFCC_E_ARG, "negative size");
+    if (nrhs == 0 || nq == 0) return;
+    GFCC_CHECK(X && q && G, GFCC_E_ARG, "null argument");
+    for (int64_t k = 0; k < nq; ++k) GFCC_CHECK(q[k] >= 0 && q[k] < c->o, GFCC_E_ARG, "q out of range");
+    hipStream_t s = as_stream(stream);
+    DBuf qd;
+    qd.ensure(size_t(nq) * 8, s);
+    GFCC_HIP(hipMemcpyAsync(qd.p, q, size_t(nq) * 8, hipMemcpyHostToDevice, s));
+    const int64_t chunk = 64;
+    for (int64_t r0 = 0; r0 < nrhs; r0 += chunk) {
+      const int64_t nb = std::min(chunk, nrhs - r0);
+      c->ws_in.ensure(size_t(2 * nb * c->Dp) * 8, s);
+      to_planes(c, nb, X + r0 * c->D * 2, c->ws_in.as<double>(), s);
+      greens_planes(c, nb, c->ws_in.as<double>(), nq, qd.as<int64_t>(), G + r0 * nq * 2, s);
+    }
+    GFCC_HIP(hipStreamSynchronize(s));  // qd and the host q are released on return
+  });
+}
+
+gfcc_status gfcc_solve_batch(gfcc_ctx* c, int64_t nrhs, const int64_t* p, const double* omega, double eta,
+                             int64_t nq, const int64_t* q, const gfcc_solve_opts* opts, double* G, double* X,
+                             gfcc_rhs_info* info, void* stream) {
+  bool all_conv = true;
+  gfcc_status st = guarded([&] {
+    GFCC_CHECK(c, GFCC_E_ARG, "null context");
+    GFCC_CHECK(opts && opts->struct_size >= sizeof(gfcc_solve_opts), GFCC_E_ARG, "bad options struct");
+    GFCC_CHECK(nrhs >= 0, GFCC_E_ARG, "nrhs < 0");
+    if (nrhs == 0) return;
+    GFCC_CHECK(p && omega && G && info, GFCC_E_ARG, "null argument");
+    GFCC_CHECK(q != nullptr || nq == 1, GFCC_E_ARG, "q == NULL requires nq == 1");
+    GFCC_CHECK(nq >= 1, GFCC_E_ARG, "nq < 1");
+    for (int64_t r = 0; r < nrhs; ++r) GFCC_CHECK(p[r] >= 0 && p[r] < c->o, GFCC_E_ARG, "p out of range");
+    if (q)
+      for (int64_t k = 0; k < nq; ++k) GFCC_CHECK(q[k] >= 0 && q[k] < c->o, GFCC_E_ARG, "q out of range");
+    GFCC_CHECK(opts->tol > 0.0 && opts->restart >= 1 && opts->max_iter >= 1, GFCC_E_ARG, "bad tolerance/restart/max_iter");
+    GFCC_CHECK(opts->precond >= GFCC_PC_NONE && opts->precond <= GFCC_PC_MLP, GFCC_E_ARG, "bad preconditioner");
+    GFCC_CHECK(opts->precision >= GFCC_FP64 && opts->precision <= GFCC_BF16_IR, GFCC_E_ARG, "bad precision");
+    solve_batch(c, nrhs, p, omega, eta, nq, q, opts, G, X, info, as_stream(stream), &all_conv);
+  });
+  if (st == GFCC_OK && !all_conv) return GFCC_W_NOCONV;
+  return st;
+}
+
+gfcc_status gfcc_prof_enable(gfcc_ctx* c, int enable) {
+  return guarded([&] {
+    GFCC_CHECK(c, GFCC_E_ARG, "null context");
+    prof_collect(c);
+    c->prof.clear();
+    c->prof_on = enable != 0;
+  });
+}
+
+gfcc_status gfcc_prof_get(gfcc_ctx* c, const char* name, int64_t* count, double* ms, double* flops, double* bytes) {
+  return guarded([&] {
+    GFCC_CHECK(c && name, GFCC_E_ARG, "null argument");
+    prof_collect(c);
+    auto it = c->prof.find(name);
+    gfcc_prof_entry e;
+    if (it != c->prof.end()) e = it->second;
+    if (count) *count = e.count;
+    if (ms) *ms = e.ms;
+    if (flops) *flops = e.flops;
+    if (bytes) *bytes = e.bytes;
+  });
+}
+
+gfcc_status gfcc_destroy(gfcc_ctx* c) {
+  return guarded([&] {
+    if (!c) return;
+    (void)hipDeviceSynchronize();
+    prof_collect(c);
+    delete c;
+  });
+}
+
+const char* gfcc_strerror(gfcc_status st) {
+  switch (st) {
+    case GFCC_OK: return "success";
+    case GFCC_E_ARG: return "invalid argument";
+    case GFCC_E_OOM: return "out of device memory";
+    case GFCC_E_HIP: return "HIP runtime error";
+    case GFCC_E_STATE: return "invalid state";
+    case GFCC_W_NOCONV: return "some right-hand sides did not converge";
+  }
+  return "unknown status";
+}
+
+const char* gfcc_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,82 @@
+// The gfcc context: per-system intermediates in HBM plus reusable workspaces.
+#pragma once
+#include <map>
+#include <string>
+
+#include "gfcc_internal.h"
+
+struct gfcc_prof_entry {
+  int64_t count = 0;
+  double ms = 0.0, flops = 0.0, bytes = 0.0;
+};
+
+struct gfcc_ctx {
+  // dimensions
+  int64_t o = 0, v = 0, Q = 0, n = 0, D = 0;
+  int64_t ov = 0, oo = 0, oov = 0;
+  int64_t o_pad = 0;  // start of the 2h1p block inside a plane
+  int64_t Dp = 0;     // plane length (re or im part of one vector)
+  int64_t kp = 0;     // padded row length of [ov][ov] ring matrices
+  int64_t op2 = 0;    // padded row length of [o^2][o^2] / [v][o^2] operands
+  int64_t vp = 0;     // padded row length for K = v operands
+  int64_t ldz = 0;    // row length of the three-body matrix [v][o^2 v]
+  int64_t lp_ps = 0;  // plane stride of reduced-precision vector copies
+
+  // FP64 blocks (natural layouts, see gfcc_export)
+  gfcc::DBuf Foo, Fvv, Fov, Woooo, Wooov, Wovoo;
+  // ring matrices [(j,a)][(m,e)] with row stride kp:
+  //   Wvo = Wovvo[m,a,e,j],  Wov = Wovov[m,a,j,e],  X1 = 2 Wvo - Wov
+  gfcc::DBuf Wvo, Wov, X1;
+  gfcc::DBuf W4T;     // [(i,j)][op2]     W4T[(i,j)][(m,n)] = Woooo[m,n,i,j]
+  gfcc::DBuf Zm;      // [v][ldz]         Zm[e][(m,n,f)] = 2(me|nf) - (mf|ne)
+  gfcc::DBuf t2p;     // [(i,j,a)][vp]    t2p[(i,j,a)][e] = t2[i,j,e,a]
+  gfcc::DBuf WovooT;  // [(i,j,a)][o_pad] WovooT[(i,j,a)][m] = Wovoo[m,a,i,j]
+  gfcc::DBuf FvvM;    // [a][vp]
+  gfcc::DBuf Uop;     // [o][Dp]          1h rows of Hbar_N over a plane
+  gfcc::DBuf diag;    // [Dp]             exact diagonal (1.0 in padding)
+  gfcc::DBuf left;    // [o][Dp]          c_q rows
+
+  // reduced-precision copies of the two-body operands: [0] FP32, [1] BF16
+  struct LowPrec {
+    bool built = false;
+    gfcc::DBuf X1, Wvo, Wov, W4T, Zm;
+    double sX1 = 1, sWvo = 1, sWov = 1, sW4T = 1, sZm = 1;  // stored = value * s
+  } lp[2];
+
+  // workspaces
+  gfcc::Scratch scr;
+  gfcc::DBuf ws_RT, ws_Ra, ws_R, ws_z;      // sigma operand copies
+  gfcc::DBuf ws_in, ws_out;                 // planes for gfcc_sigma / gfcc_greens
+
+  // kernel timing
+  bool prof_on = false;
+  std::map<std::string, gfcc_prof_entry> prof;
+  std::map<std::string, std::vector<std::pair<hipEvent_t, hipEvent_t>>> prof_events;
+  struct PendingMeta {
+    double flops, bytes;
+  };
+  std::map<std::string, std::vector<PendingMeta>> prof_meta;
+
+  // autotuned tile choice for the ring GEMMs, keyed "prec:M:N:K"
+  std::map<std::string, int> tuned;
+};
+
+namespace gfcc {
+// Vectors inside the library are "planes": for nb complex vectors, 2*nb planes
+// of Dp doubles (re of vector 0, im of vector 0, re of vector 1, ...).
+void build_intermediates(gfcc_ctx* c, const gfcc_system* sys, hipStream_t s);
+void build_lowprec(gfcc_ctx* c, int which, hipStream_t s);
+void sigma_planes(gfcc_ctx* c, int64_t nplanes, const double* x, double* y, gfcc_precision prec,
+                  hipStream_t s);
+// interleaved complex [nb][D] <-> planes [2 nb][Dp]
+void to_planes(gfcc_ctx* c, int64_t nb, const double* xi, double* planes, hipStream_t s);
+void from_planes(gfcc_ctx* c, int64_t nb, const double* planes, double* xi, hipStream_t s);
+// G[r][k] = c_{q_k} . x_r (planes), complex interleaved output
+void greens_planes(gfcc_ctx* c, int64_t nb, const double* planes, int64_t nq, const int64_t* q_dev,
+                   double* G, hipStream_t s);
+
+// timing helpers (no-ops when profiling is off)
+void prof_begin(gfcc_ctx* c, const char* name, hipStream_t s);
+void prof_end(gfcc_ctx* c, const char* name, hipStream_t s, double flops, double bytes);
+void prof_collect(gfcc_ctx* c);
+}  // namespace gfcc

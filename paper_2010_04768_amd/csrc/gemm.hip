@@ -1,0 +1,258 @@
+// MFMA GEMM for gfx950:  C(i, j) = alpha * sum_k A(i, k) B(j, k) + beta * C(i, j).
+//
+// Both operands are K-contiguous ("NT" form); the row of each operand and the
+// row/column of C go through a two-level map so that the sigma product's index
+// permutations (the (i,j,a) <- (m,e) ring contractions) are absorbed in the
+// operand fetch and in the epilogue instead of extra passes over HBM.
+//
+// Element types: FP64 (v_mfma_f64_16x16x4f64, FP64 accumulation), FP32
+// (v_mfma_f32_16x16x4f32) and BF16 (v_mfma_f32_16x16x32_bf16, gfx950), the
+// last two accumulating in FP32.  C is always FP64.
+//
+// Tiling: a workgroup of 4 waves (2 x 2) computes a BM x BN tile; each wave a
+// (BM/2) x (BN/2) sub-tile as (BM/32) x (BN/32) MFMA 16x16 blocks.  K advances
+// in BK-element steps staged through LDS (rows padded by 16 bytes to spread
+// banks) with the next step prefetched into registers while MFMAs run.  The
+// workgroup -> tile map keeps consecutive tiles on one XCD (workgroups are
+// dealt round-robin over the 8 XCDs) and walks tile-rows in groups so that
+// concurrently running tiles share operand panels in that XCD's L2.
+#include "gfcc_internal.h"
+
+namespace gfcc {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+
+template <typename T> struct Mfma;
+template <> struct Mfma<double> {
+  using acc_t = v4d;
+  using frag_t = double;
+  static constexpr int KS = 4;       // K per instruction
+  static constexpr bool ROW_INTERLEAVED = true;  // D[(l/16) + 4r][l%16]
+  __device__ static inline acc_t mma(frag_t a, frag_t b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+};
+template <> struct Mfma<float> {
+  using acc_t = v4f;
+  using frag_t = float;
+  static constexpr int KS = 4;
+  static constexpr bool ROW_INTERLEAVED = false;  // D[4(l/16) + r][l%16]
+  __device__ static inline acc_t mma(frag_t a, frag_t b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+};
+template <> struct Mfma<__bf16> {
+  using acc_t = v4f;
+  using frag_t = v8bf;
+  static constexpr int KS = 32;
+  static constexpr bool ROW_INTERLEAVED = false;
+  __device__ static inline acc_t mma(frag_t a, frag_t b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+  }
+};
+
+__device__ __forceinline__ int64_t rmap(const RowMap& m, int64_t r) {
+  return (r / m.div) * m.hi + (r % m.div) * m.lo;
+}
+
+template <typename T, int BM, int BN, bool VEC>
+__global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
+  using MF = Mfma<T>;
+  constexpr int EPC = 16 / int(sizeof(T));   // elements per 16-byte chunk
+  constexpr int BK = 8 * EPC;                // 8 chunks per row: 16 fp64, 32 fp32, 64 bf16
+  constexpr int LDK = BK + EPC;              // padded LDS row (144 bytes)
+  constexpr int RPP = 256 / 8;               // rows per load pass
+  constexpr int PA = BM / RPP, PB = BN / RPP;
+  constexpr int WM = BM / 2, WN = BN / 2, FM = WM / 16, FN = WN / 16;
+  constexpr int FE = (MF::KS == 32) ? 8 : 1;  // elements per lane per fragment
+
+  __shared__ __attribute__((aligned(16))) T As[BM * LDK];
+  __shared__ __attribute__((aligned(16))) T Bs[BN * LDK];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm0 = (wave >> 1) * WM;
+  const int wn0 = (wave & 1) * WN;
+
+  // ---- workgroup -> tile (XCD-aware, grouped)
+  const int64_t tiles_m = (g.M + BM - 1) / BM;
+  const int64_t tiles_n = (g.N + BN - 1) / BN;
+  const int64_t ntiles = tiles_m * tiles_n;
+  int64_t bid = blockIdx.x;
+  if ((ntiles & 7) == 0) bid = (bid & 7) * (ntiles >> 3) + (bid >> 3);
+  constexpr int64_t GROUP = 8;
+  const int64_t per_group = GROUP * tiles_n;
+  const int64_t grp = bid / per_group;
+  const int64_t first_m = grp * GROUP;
+  const int64_t gsz = (tiles_m - first_m) < GROUP ? (tiles_m - first_m) : GROUP;
+  const int64_t in_grp = bid - grp * per_group;
+  const int64_t tm = first_m + in_grp % gsz;
+  const int64_t tn = in_grp / gsz;
+  const int64_t i0 = tm * BM, j0 = tn * BN;
+
+  const int z = blockIdx.z;
+  const T* A = static_cast<const T*>(g.A) + z * g.a_bs;
+  const T* B = static_cast<const T*>(g.B) + z * g.b_bs;
+
+  // ---- per-thread fetch rows (fixed across the K loop)
+  const int lrow = tid >> 3;        // 0..31
+  const int lchunk = tid & 7;       // chunk within the row
+  int64_t aoff[PA], boff[PB];
+#pragma unroll
+  for (int p = 0; p < PA; ++p) {
+    int64_t i = i0 + lrow + p * RPP;
+    aoff[p] = (i < g.M) ? rmap(g.am, i) : -1;
+  }
+#pragma unroll
+  for (int p = 0; p < PB; ++p) {
+    int64_t j = j0 + lrow + p * RPP;
+    boff[p] = (j < g.N) ? rmap(g.bm, j) : -1;
+  }
+
+  u4 ra[PA], rb[PB];
+  auto fetch = [&](const T* base, int64_t off, int64_t k) -> u4 {
+    u4 v = {0u, 0u, 0u, 0u};
+    if (off < 0) return v;
+    if (VEC && k + EPC <= g.K) {
+      v = *reinterpret_cast<const u4*>(base + off + k);
+    } else {
+      T tmp[EPC];
+#pragma unroll
+      for (int e = 0; e < EPC; ++e) tmp[e] = (k + e < g.K) ? base[off + k + e] : T(0);
+      v = *reinterpret_cast<const u4*>(tmp);
+    }
+    return v;
+  };
+  auto load_tiles = [&](int64_t k0) {
+    const int64_t k = k0 + lchunk * EPC;
+#pragma unroll
+    for (int p = 0; p < PA; ++p) ra[p] = fetch(A, aoff[p], k);
+#pragma unroll
+    for (int p = 0; p < PB; ++p) rb[p] = fetch(B, boff[p], k);
+  };
+  auto store_tiles = [&]() {
+#pragma unroll
+    for (int p = 0; p < PA; ++p)
+      *reinterpret_cast<u4*>(&As[(lrow + p * RPP) * LDK + lchunk * EPC]) = ra[p];
+#pragma unroll
+    for (int p = 0; p < PB; ++p)
+      *reinterpret_cast<u4*>(&Bs[(lrow + p * RPP) * LDK + lchunk * EPC]) = rb[p];
+  };
+
+  typename MF::acc_t acc[FM][FN];
+#pragma unroll
+  for (int a = 0; a < FM; ++a)
+#pragma unroll
+    for (int b = 0; b < FN; ++b) acc[a][b] = typename MF::acc_t{0, 0, 0, 0};
+
+  const int nk = int((g.K + BK - 1) / BK);
+  load_tiles(0);
+  const int fr = lane & 15;          // fragment row within a 16-block
+  const int fk = (lane >> 4) * FE;   // fragment K offset
+  for (int kt = 0; kt < nk; ++kt) {
+    __syncthreads();
+    store_tiles();
+    __syncthreads();
+    if (kt + 1 < nk) load_tiles(int64_t(kt + 1) * BK);
+#pragma unroll
+    for (int ks = 0; ks < BK; ks += MF::KS) {
+      typename MF::frag_t af[FM], bf[FN];
+#pragma unroll
+      for (int a = 0; a < FM; ++a)
+        af[a] = *reinterpret_cast<const typename MF::frag_t*>(&As[(wm0 + a * 16 + fr) * LDK + ks + fk]);
+#pragma unroll
+      for (int b = 0; b < FN; ++b)
+        bf[b] = *reinterpret_cast<const typename MF::frag_t*>(&Bs[(wn0 + b * 16 + fr) * LDK + ks + fk]);
+#pragma unroll
+      for (int a = 0; a < FM; ++a)
+#pragma unroll
+        for (int b = 0; b < FN; ++b) acc[a][b] = MF::mma(af[a], bf[b], acc[a][b]);
+    }
+  }
+
+  // ---- epilogue
+  double* C = g.C + z * g.c_bs;
+  const int jl = lane & 15;
+  const int ih = lane >> 4;
+#pragma unroll
+  for (int b = 0; b < FN; ++b) {
+    const int64_t j = j0 + wn0 + b * 16 + jl;
+    if (j >= g.N) continue;
+    const int64_t cj = rmap(g.cn, j);
+#pragma unroll
+    for (int a = 0; a < FM; ++a) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int ii = MF::ROW_INTERLEAVED ? (ih + 4 * r) : (4 * ih + r);
+        const int64_t i = i0 + wm0 + a * 16 + ii;
+        if (i >= g.M) continue;
+        double* p = C + rmap(g.cm, i) + cj;
+        const double v = g.alpha * double(acc[a][b][r]);
+        *p = (g.beta == 0.0) ? v : v + g.beta * (*p);
+      }
+    }
+  }
+}
+
+template <typename T, int BM, int BN>
+static void launch(const GemmArgs& a, bool vec, hipStream_t s) {
+  const int64_t tiles = ((a.M + BM - 1) / BM) * ((a.N + BN - 1) / BN);
+  GFCC_CHECK(tiles < (int64_t(1) << 31), GFCC_E_ARG, "GEMM grid too large");
+  dim3 grid(unsigned(tiles), 1, unsigned(a.batch));
+  if (vec)
+    hipLaunchKernelGGL((gemm_kernel<T, BM, BN, true>), grid, dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL((gemm_kernel<T, BM, BN, false>), grid, dim3(256), 0, s, a);
+  GFCC_HIP(hipGetLastError());
+}
+
+template <typename T>
+static void dispatch(const GemmArgs& a, int cfg, bool vec, hipStream_t s) {
+  switch (cfg) {
+    case TILE_128x128: launch<T, 128, 128>(a, vec, s); break;
+    case TILE_64x64: launch<T, 64, 64>(a, vec, s); break;
+    case TILE_128x64: launch<T, 128, 64>(a, vec, s); break;
+    case TILE_64x128: launch<T, 64, 128>(a, vec, s); break;
+    default: throw Error{GFCC_E_ARG, "bad tile config"};
+  }
+}
+
+static bool aligned_map(const RowMap& m, int64_t epc) {
+  return (m.hi % epc) == 0 && (m.lo % epc) == 0;
+}
+
+const char* tile_name(int cfg) {
+  static const char* n[] = {"128x128", "64x64", "128x64", "64x128"};
+  return (cfg >= 0 && cfg < N_TILE_CFG) ? n[cfg] : "?";
+}
+
+int gemm_default_cfg(int64_t M, int64_t N, int64_t K) {
+  (void)K;
+  const int64_t big = (M >= 512 && N >= 512) ? 1 : 0;
+  if (big) return TILE_128x128;
+  if (M >= 128 && N < 128) return TILE_128x64;
+  if (N >= 128 && M < 128) return TILE_64x128;
+  return TILE_64x64;
+}
+
+void gemm(Prec p, const GemmArgs& a, int cfg, hipStream_t s) {
+  if (a.M <= 0 || a.N <= 0 || a.batch <= 0) return;
+  GFCC_CHECK(a.K >= 0, GFCC_E_ARG, "negative K");
+  GFCC_CHECK(a.am.div > 0 && a.bm.div > 0 && a.cm.div > 0 && a.cn.div > 0, GFCC_E_ARG, "bad row map");
+  const int64_t esz = (p == Prec::F64) ? 8 : (p == Prec::F32 ? 4 : 2);
+  const int64_t epc = 16 / esz;
+  const bool vec = aligned_map(a.am, epc) && aligned_map(a.bm, epc) && (a.a_bs % epc == 0) &&
+                   (a.b_bs % epc == 0) && (reinterpret_cast<uintptr_t>(a.A) % 16 == 0) &&
+                   (reinterpret_cast<uintptr_t>(a.B) % 16 == 0);
+  switch (p) {
+    case Prec::F64: dispatch<double>(a, cfg, vec, s); break;
+    case Prec::F32: dispatch<float>(a, cfg, vec, s); break;
+    case Prec::BF16: dispatch<__bf16>(a, cfg, vec, s); break;
+  }
+}
+
+}  // namespace gfcc

@@ -1,0 +1,145 @@
+// Internal declarations of the gfcc library (not part of the C ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "../../include/gfcc.h"
+
+namespace gfcc {
+
+// ---------------------------------------------------------------- errors
+void set_error(const std::string& msg);
+struct Error {
+  gfcc_status st;
+  std::string msg;
+};
+
+#define GFCC_HIP(expr)                                                              \
+  do {                                                                              \
+    hipError_t e_ = (expr);                                                         \
+    if (e_ != hipSuccess)                                                           \
+      throw ::gfcc::Error{GFCC_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_) + \
+                                          " (" + __FILE__ + ":" + std::to_string(__LINE__) + ")"}; \
+  } while (0)
+
+#define GFCC_CHECK(cond, status, msg)                                      \
+  do {                                                                     \
+    if (!(cond)) throw ::gfcc::Error{status, std::string(msg)};            \
+  } while (0)
+
+inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+// ---------------------------------------------------------------- device memory
+struct DBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DBuf() = default;
+  DBuf(const DBuf&) = delete;
+  DBuf& operator=(const DBuf&) = delete;
+  DBuf(DBuf&& o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+  DBuf& operator=(DBuf&& o) noexcept {
+    if (this != &o) { release(); p = o.p; bytes = o.bytes; o.p = nullptr; o.bytes = 0; }
+    return *this;
+  }
+  ~DBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  // (re)allocate at least n bytes, zero-filled on the given stream when grown
+  void ensure(size_t n, hipStream_t s) {
+    if (n <= bytes && p) return;
+    if (p) GFCC_HIP(hipStreamSynchronize(s));  // old buffer may still be in use on s
+    release();
+    if (n == 0) n = 256;
+    hipError_t e = hipMalloc(&p, n);
+    if (e != hipSuccess) {
+      p = nullptr;
+      throw Error{GFCC_E_OOM, "hipMalloc of " + std::to_string(n) + " bytes failed"};
+    }
+    bytes = n;
+    GFCC_HIP(hipMemsetAsync(p, 0, n, s));
+  }
+  template <typename T> T* as() const { return static_cast<T*>(p); }
+};
+
+// ---------------------------------------------------------------- GEMM
+// C(i, j) = alpha * sum_k A(i, k) B(j, k) + beta * C(i, j)
+// Operand rows are K-contiguous; a row's element offset is given by a two-level
+// map  off(r) = (r / div) * hi + (r % div) * lo  (div >= 1).
+struct RowMap {
+  int64_t div, hi, lo;
+};
+inline RowMap lin(int64_t ld) { return RowMap{int64_t(1) << 40, 0, ld}; }
+inline RowMap two(int64_t div, int64_t hi, int64_t lo) { return RowMap{div, hi, lo}; }
+
+enum class Prec : int { F64 = 0, F32 = 1, BF16 = 2 };
+
+struct GemmArgs {
+  const void* A = nullptr;  // element type given by Prec
+  RowMap am{};
+  int64_t a_bs = 0;         // batch stride (elements)
+  const void* B = nullptr;
+  RowMap bm{};
+  int64_t b_bs = 0;
+  double* C = nullptr;
+  RowMap cm{}, cn{};
+  int64_t c_bs = 0;
+  int64_t M = 0, N = 0, K = 0;
+  int batch = 1;
+  double alpha = 1.0, beta = 0.0;
+};
+
+// Tile configurations; the autotuner picks one per (shape, precision).
+enum TileCfg : int { TILE_128x128 = 0, TILE_64x64 = 1, TILE_128x64 = 2, TILE_64x128 = 3, N_TILE_CFG = 4 };
+const char* tile_name(int cfg);
+
+void gemm(Prec p, const GemmArgs& a, int cfg, hipStream_t s);
+// heuristic choice when no tuned entry exists
+int gemm_default_cfg(int64_t M, int64_t N, int64_t K);
+
+// ---------------------------------------------------------------- tensors
+struct TView {
+  double* p = nullptr;
+  int nd = 0;
+  int64_t dim[8] = {0};
+  int64_t str[8] = {0};
+  int64_t size() const {
+    int64_t s = 1;
+    for (int i = 0; i < nd; ++i) s *= dim[i];
+    return s;
+  }
+};
+TView tview(double* p, std::initializer_list<int64_t> dims);                 // contiguous
+TView tview_s(double* p, std::initializer_list<int64_t> dims, std::initializer_list<int64_t> strides);
+
+// out = alpha * permute(in) + beta * out ; `in` and `out` have the same number
+// of dims; out dim d takes in dim perm[d].
+void permute(const TView& in, const int* perm, double alpha, const TView& out, double beta,
+             hipStream_t s);
+
+// Scratch arena reused by the contraction engine.
+struct Scratch {
+  DBuf b[4];
+  double* get(int slot, int64_t n, hipStream_t s) {
+    b[slot].ensure(size_t(n) * sizeof(double), s);
+    return b[slot].as<double>();
+  }
+};
+
+// Pairwise contraction  C[c] = alpha * sum A[a] B[b] + beta * C[c]  in FP64 on
+// MFMA.  `spec` is "ab..,cd..->ef.." with single-letter labels; every label is
+// in exactly two of the three operands.
+void ein(const char* spec, double alpha, const TView& A, const TView& B, double beta,
+         const TView& C, Scratch& scr, hipStream_t s);
+
+// ---------------------------------------------------------------- conversions
+void convert_f64(const double* src, void* dst, Prec p, int64_t n, double scale, hipStream_t s);
+double amax_host(const double* src, int64_t n, hipStream_t s, Scratch& scr);
+
+}  // namespace gfcc

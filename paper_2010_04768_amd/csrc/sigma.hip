@@ -1,0 +1,415 @@
+// sigma = Hbar_N x for a batch of vectors (the per-iteration O(o^3 v^2) work
+// of the GFCCSD linear solver, paper Sec. 3 / Alg. 1 singles and doubles).
+//
+// Closed-shell spin-adapted IP-EOM form, r1[i], r2[i,j,a]:
+//   s1[i]     = -sum_m Foo[m,i] r1[m] + sum_me Fov[m,e](2 r2[i,m,e] - r2[m,i,e])
+//               - sum_mne (2 Wooov[m,n,i,e] - Wooov[n,m,i,e]) r2[m,n,e]
+//   s2[i,j,a] = -sum_m Wovoo[m,a,i,j] r1[m] + sum_e Fvv[a,e] r2[i,j,e]
+//               - sum_m (Foo[m,i] r2[m,j,a] + Foo[m,j] r2[i,m,a]) + sum_mn Woooo[m,n,i,j] r2[m,n,a]
+//               + sum_me (2 Wovvo[m,a,e,j] - Wovov[m,a,j,e]) r2[i,m,e]
+//               - sum_me Wovvo[m,a,e,j] r2[m,i,e] - sum_me Wovov[m,a,i,e] r2[m,j,e]
+//               - sum_e z_e t2[i,j,e,a],   z_e = sum_mnf (2(me|nf) - (mf|ne)) r2[m,n,f]
+// Hbar_N is real; a complex vector is two real planes, so every term is a
+// real GEMM whose N dimension runs over (vector, re/im, index).
+//
+// The three ring terms are the hot spot (12 o^3 v^2 flops per complex vector):
+//   P1a: s2[(p,i)][(j,a)]  = R [(p,i)][(m,e)] . X1 [(j,a)][(m,e)]^T   (R = r2 rows)
+//   P1b: s2[(p,i)][(j,a)] -= RT[(p,i)][(m,e)] . Wvo[(j,a)][(m,e)]^T   (RT[i][m][e] = r2[m][i][e])
+//   P2 : s2[(p,j)][(i,a)] -= RT[(p,j)][(m,e)] . Wov[(i,a)][(m,e)]^T   (scattered store)
+// In FP32/BF16 mode these three and the hole-hole ladder and z contraction
+// read reduced-precision copies; the one-body terms stay FP64.
+#include <algorithm>
+
+#include "ctx.h"
+
+namespace gfcc {
+
+template <typename T> __device__ __forceinline__ T cvt(double x);
+template <> __device__ __forceinline__ double cvt<double>(double x) { return x; }
+template <> __device__ __forceinline__ float cvt<float>(double x) { return float(x); }
+template <> __device__ __forceinline__ __bf16 cvt<__bf16>(double x) { return __bf16(float(x)); }
+
+// RT[p][i*ov + m*v + e] = x[p*Dp + o_pad + m*ov + i*v + e]   (and R when R != nullptr)
+template <typename T>
+__global__ void make_rt_kernel(const double* __restrict__ x, T* __restrict__ RT, T* __restrict__ R,
+                               int64_t o, int64_t v, int64_t Dp, int64_t o_pad, int64_t ps) {
+  const int64_t oov = o * o * v, ov = o * v;
+  const int64_t p = blockIdx.y;
+  const double* xp = x + p * Dp + o_pad;
+  for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < oov; t += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t e = t % v, m = (t / v) % o, i = t / ov;  // output order [i][m][e]
+    RT[p * ps + t] = cvt<T>(xp[m * ov + i * v + e]);
+    if (R) R[p * ps + t] = cvt<T>(xp[t]);
+  }
+}
+
+// Ra[p][a][(m,n)] = x[p*Dp + o_pad + (m,n)*v + a]  (row stride op2), LDS-tiled transpose
+template <typename T>
+__global__ void make_ra_kernel(const double* __restrict__ x, T* __restrict__ Ra, int64_t oo, int64_t v,
+                               int64_t Dp, int64_t o_pad, int64_t op2) {
+  __shared__ double tile[32][33];
+  const int64_t p = blockIdx.z;
+  const int64_t r0 = int64_t(blockIdx.x) * 32, c0 = int64_t(blockIdx.y) * 32;  // rows (m,n), cols a
+  const double* xp = x + p * Dp + o_pad;
+  for (int k = threadIdx.y; k < 32; k += 8) {
+    const int64_t r = r0 + k, cc = c0 + threadIdx.x;
+    tile[k][threadIdx.x] = (r < oo && cc < v) ? xp[r * v + cc] : 0.0;
+  }
+  __syncthreads();
+  for (int k = threadIdx.y; k < 32; k += 8) {
+    const int64_t a = c0 + k, r = r0 + threadIdx.x;
+    if (a < v && r < oo) Ra[(p * v + a) * op2 + r] = cvt<T>(tile[threadIdx.x][k]);
+  }
+}
+
+// y2[p][i][j][a] -= sum_m Foo[m,i] x2[p][m][j][a] + Foo[m,j] x2[p][i][m][a]
+__global__ void foo_terms_kernel(const double* __restrict__ x, double* __restrict__ y,
+                                 const double* __restrict__ Foo, int64_t o, int64_t v, int64_t Dp,
+                                 int64_t o_pad) {
+  const int64_t oov = o * o * v, ov = o * v;
+  const int64_t p = blockIdx.y;
+  const double* xp = x + p * Dp + o_pad;
+  double* yp = y + p * Dp + o_pad;
+  for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < oov; t += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t a = t % v, j = (t / v) % o, i = t / ov;
+    double acc = 0.0;
+    for (int64_t m = 0; m < o; ++m)
+      acc += Foo[m * o + i] * xp[m * ov + j * v + a] + Foo[m * o + j] * xp[i * ov + m * v + a];
+    yp[t] -= acc;
+  }
+}
+
+static unsigned blocks_for(int64_t n) {
+  return unsigned(std::min<int64_t>(std::max<int64_t>((n + 255) / 256, 1), 4096));
+}
+
+static int ring_cfg(gfcc_ctx* c, Prec p, int64_t M, int64_t N, int64_t K) {
+  char key[96];
+  snprintf(key, sizeof key, "%d:%lld:%lld:%lld", int(p), (long long)M, (long long)N, (long long)K);
+  auto it = c->tuned.find(key);
+  if (it != c->tuned.end()) return it->second;
+  return gemm_default_cfg(M, N, K);
+}
+
+template <typename T>
+static void make_operands(gfcc_ctx* c, int64_t P, const double* x, T* RT, T* R, T* Ra, int64_t ps,
+                          hipStream_t s) {
+  const int64_t oov = c->oov;
+  hipLaunchKernelGGL((make_rt_kernel<T>), dim3(std::min<int64_t>((oov + 255) / 256, 1024), unsigned(P)),
+                     dim3(256), 0, s, x, RT, R, c->o, c->v, c->Dp, c->o_pad, ps);
+  GFCC_HIP(hipGetLastError());
+  dim3 g(unsigned((c->oo + 31) / 32), unsigned((c->v + 31) / 32), unsigned(P));
+  hipLaunchKernelGGL((make_ra_kernel<T>), g, dim3(32, 8), 0, s, x, Ra, c->oo, c->v, c->Dp, c->o_pad, c->op2);
+  GFCC_HIP(hipGetLastError());
+}
+
+void sigma_planes(gfcc_ctx* c, int64_t P, const double* x, double* y, gfcc_precision prec, hipStream_t s) {
+  if (P <= 0) return;
+  const int64_t o = c->o, v = c->v, ov = c->ov, oo = c->oo, oov = c->oov;
+  const int64_t Dp = c->Dp, op = c->o_pad, kp = c->kp;
+  const bool lowp = prec != GFCC_FP64;
+  const int li = (prec == GFCC_BF16_IR) ? 1 : 0;
+  const Prec rp = !lowp ? Prec::F64 : (li ? Prec::BF16 : Prec::F32);
+  const int64_t esz = !lowp ? 8 : (li ? 2 : 4);
+  if (lowp) build_lowprec(c, li, s);
+  const int64_t ps = round_up(oov, 8);  // plane stride of operand copies
+  c->ws_RT.ensure(size_t(P * ps * esz), s);
+  c->ws_Ra.ensure(size_t(P * v * c->op2 * esz), s);
+  if (lowp) c->ws_R.ensure(size_t(P * ps * esz), s);
+  c->ws_z.ensure(size_t(P * c->vp * 8), s);
+
+  prof_begin(c, "sigma", s);
+  switch (rp) {
+    case Prec::F64:
+      make_operands<double>(c, P, x, c->ws_RT.as<double>(), nullptr, c->ws_Ra.as<double>(), ps, s);
+      break;
+    case Prec::F32:
+      make_operands<float>(c, P, x, c->ws_RT.as<float>(), c->ws_R.as<float>(), c->ws_Ra.as<float>(), ps, s);
+      break;
+    case Prec::BF16:
+      make_operands<__bf16>(c, P, x, c->ws_RT.as<__bf16>(), c->ws_R.as<__bf16>(), c->ws_Ra.as<__bf16>(), ps, s);
+      break;
+  }
+  const auto& L = c->lp[li];
+  const void* X1 = lowp ? L.X1.p : c->X1.p;
+  const void* Wvo = lowp ? L.Wvo.p : c->Wvo.p;
+  const void* Wov = lowp ? L.Wov.p : c->Wov.p;
+  const void* W4T = lowp ? L.W4T.p : c->W4T.p;
+  const void* Zm = lowp ? L.Zm.p : c->Zm.p;
+  const double sX1 = lowp ? 1.0 / L.sX1 : 1.0, sWvo = lowp ? 1.0 / L.sWvo : 1.0;
+  const double sWov = lowp ? 1.0 / L.sWov : 1.0, sW4T = lowp ? 1.0 / L.sW4T : 1.0;
+  const double sZm = lowp ? 1.0 / L.sZm : 1.0;
+
+  const double ring_flops = 2.0 * double(P) * double(o) * double(ov) * double(ov);
+  const double ring_bytes = double(ov) * double(kp) * esz + 2.0 * double(P) * double(o) * double(ov) * (esz + 8.0);
+
+  // ---- ring terms
+  {
+    GemmArgs g;
+    g.M = P * o;
+    g.N = ov;
+    g.K = ov;
+    g.C = y + op;
+    g.cm = two(o, Dp, ov);
+    g.cn = lin(1);
+    const int cfg = ring_cfg(c, rp, g.M, g.N, g.K);
+    // P1a
+    if (lowp) {
+      g.A = c->ws_R.p;
+      g.am = lin(ov);
+      g.a_bs = 0;
+      g.am = two(o, ps, ov);
+    } else {
+      g.A = x + op;
+      g.am = two(o, Dp, ov);
+    }
+    g.B = X1;
+    g.bm = lin(kp);
+    g.alpha = sX1;
+    g.beta = 0.0;
+    prof_begin(c, "ring_gemm", s);
+    gemm(rp, g, cfg, s);
+    prof_end(c, "ring_gemm", s, ring_flops, ring_bytes);
+    // P1b
+    g.A = c->ws_RT.p;
+    g.am = two(o, ps, ov);
+    g.B = Wvo;
+    g.alpha = -sWvo;
+    g.beta = 1.0;
+    prof_begin(c, "ring_gemm", s);
+    gemm(rp, g, cfg, s);
+    prof_end(c, "ring_gemm", s, ring_flops, ring_bytes);
+    // P2: rows (p, j), cols (i, a) -> s2[p][i][j][a]
+    g.B = Wov;
+    g.alpha = -sWov;
+    g.cm = two(o, Dp, v);
+    g.cn = two(v, ov, 1);
+    prof_begin(c, "ring_gemm", s);
+    gemm(rp, g, cfg, s);
+    prof_end(c, "ring_gemm", s, ring_flops, ring_bytes);
+  }
+  // ---- hole-hole ladder: s2[p][(i,j)][a] += sum_(mn) W4T[(i,j)][(m,n)] Ra[(p,a)][(m,n)]
+  {
+    GemmArgs g;
+    g.A = W4T;
+    g.am = lin(c->op2);
+    g.B = c->ws_Ra.p;
+    g.bm = lin(c->op2);
+    g.M = oo;
+    g.N = P * v;
+    g.K = oo;
+    g.C = y + op;
+    g.cm = lin(v);
+    g.cn = two(v, Dp, 1);
+    g.alpha = sW4T;
+    g.beta = 1.0;
+    gemm(rp, g, gemm_default_cfg(g.M, g.N, g.K), s);
+  }
+  // ---- three-body: z[p][e] = sum_(mnf) Zm[e][(m,n,f)] r2[p][(m,n,f)];  s2 -= z . t2
+  {
+    GemmArgs g;
+    if (lowp) {
+      g.A = c->ws_R.p;
+      g.am = lin(ps);
+    } else {
+      g.A = x + op;
+      g.am = lin(Dp);
+    }
+    g.B = Zm;
+    g.bm = lin(c->ldz);
+    g.M = P;
+    g.N = v;
+    g.K = oov;
+    g.C = c->ws_z.as<double>();
+    g.cm = lin(c->vp);
+    g.cn = lin(1);
+    g.alpha = sZm;
+    g.beta = 0.0;
+    gemm(rp, g, gemm_default_cfg(g.M, g.N, g.K), s);
+    GemmArgs h;
+    h.A = c->ws_z.p;
+    h.am = lin(c->vp);
+    h.B = c->t2p.p;
+    h.bm = lin(c->vp);
+    h.M = P;
+    h.N = oov;
+    h.K = v;
+    h.C = y + op;
+    h.cm = lin(Dp);
+    h.cn = lin(1);
+    h.alpha = -1.0;
+    h.beta = 1.0;
+    gemm(Prec::F64, h, gemm_default_cfg(h.M, h.N, h.K), s);
+  }
+  // ---- one-body virtual term: s2[p][(i,j)][a] += sum_e x2[p][(i,j)][e] Fvv[a][e]   (FP64)
+  {
+    GemmArgs g;
+    g.A = x + op;
+    g.am = two(oo, Dp, v);
+    g.B = c->FvvM.p;
+    g.bm = lin(c->vp);
+    g.M = P * oo;
+    g.N = v;
+    g.K = v;
+    g.C = y + op;
+    g.cm = two(oo, Dp, v);
+    g.cn = lin(1);
+    g.alpha = 1.0;
+    g.beta = 1.0;
+    gemm(Prec::F64, g, gemm_default_cfg(g.M, g.N, g.K), s);
+  }
+  // ---- 2h1p <- 1h: s2[p][(i,j,a)] -= sum_m r1[p][m] WovooT[(i,j,a)][m]   (FP64)
+  {
+    GemmArgs g;
+    g.A = x;
+    g.am = lin(Dp);
+    g.B = c->WovooT.p;
+    g.bm = lin(c->o_pad);
+    g.M = P;
+    g.N = oov;
+    g.K = o;
+    g.C = y + op;
+    g.cm = lin(Dp);
+    g.cn = lin(1);
+    g.alpha = -1.0;
+    g.beta = 1.0;
+    gemm(Prec::F64, g, gemm_default_cfg(g.M, g.N, g.K), s);
+  }
+  // ---- occupied one-body terms (FP64)
+  hipLaunchKernelGGL(foo_terms_kernel, dim3(blocks_for(oov), unsigned(P)), dim3(256), 0, s, x, y,
+                     c->Foo.as<double>(), o, v, Dp, op);
+  GFCC_HIP(hipGetLastError());
+  // ---- 1h rows: s1[p][i] = sum_k x[p][k] Uop[i][k]   (FP64)
+  {
+    GemmArgs g;
+    g.A = x;
+    g.am = lin(Dp);
+    g.B = c->Uop.p;
+    g.bm = lin(Dp);
+    g.M = P;
+    g.N = o;
+    g.K = Dp;
+    g.C = y;
+    g.cm = lin(Dp);
+    g.cn = lin(1);
+    g.alpha = 1.0;
+    g.beta = 0.0;
+    gemm(Prec::F64, g, gemm_default_cfg(g.M, g.N, g.K), s);
+  }
+  const double total_flops = 3.0 * ring_flops + 2.0 * double(P) * (double(oo) * oo * v + 2.0 * oov * v +
+                                                                    double(oov) * v + double(oov) * o +
+                                                                    2.0 * double(oov) * o + double(Dp) * o);
+  prof_end(c, "sigma", s, total_flops, 0.0);
+}
+
+// ------------------------------------------------------------------ layout conversions
+
+__global__ void to_planes_kernel(const double* __restrict__ xi, double* __restrict__ pl, int64_t nb, int64_t D,
+                                 int64_t Dp, int64_t o, int64_t o_pad) {
+  const int64_t b = blockIdx.y;
+  for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < D; t += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t dst = (t < o) ? t : (t - o + o_pad);
+    pl[(2 * b) * Dp + dst] = xi[(b * D + t) * 2];
+    pl[(2 * b + 1) * Dp + dst] = xi[(b * D + t) * 2 + 1];
+  }
+}
+
+__global__ void from_planes_kernel(const double* __restrict__ pl, double* __restrict__ xi, int64_t nb, int64_t D,
+                                   int64_t Dp, int64_t o, int64_t o_pad) {
+  const int64_t b = blockIdx.y;
+  for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < D; t += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t src = (t < o) ? t : (t - o + o_pad);
+    xi[(b * D + t) * 2] = pl[(2 * b) * Dp + src];
+    xi[(b * D + t) * 2 + 1] = pl[(2 * b + 1) * Dp + src];
+  }
+}
+
+void to_planes(gfcc_ctx* c, int64_t nb, const double* xi, double* planes, hipStream_t s) {
+  if (nb <= 0) return;
+  hipLaunchKernelGGL(to_planes_kernel, dim3(blocks_for(c->D), unsigned(nb)), dim3(256), 0, s, xi, planes, nb,
+                     c->D, c->Dp, c->o, c->o_pad);
+  GFCC_HIP(hipGetLastError());
+}
+
+void from_planes(gfcc_ctx* c, int64_t nb, const double* planes, double* xi, hipStream_t s) {
+  if (nb <= 0) return;
+  hipLaunchKernelGGL(from_planes_kernel, dim3(blocks_for(c->D), unsigned(nb)), dim3(256), 0, s, planes, xi, nb,
+                     c->D, c->Dp, c->o, c->o_pad);
+  GFCC_HIP(hipGetLastError());
+}
+
+// G[r][k] = c_{q_k} . x_r  (re from plane 2r, im from plane 2r+1)
+__global__ void gather_rows_kernel(const double* __restrict__ src, const int64_t* __restrict__ q, double* dst,
+                                   int64_t Dp) {
+  const int64_t k = blockIdx.y;
+  const double* s = src + q[k] * Dp;
+  for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < Dp; t += int64_t(gridDim.x) * blockDim.x)
+    dst[k * Dp + t] = s[t];
+}
+
+void greens_planes(gfcc_ctx* c, int64_t nb, const double* planes, int64_t nq, const int64_t* q_dev, double* G,
+                   hipStream_t s) {
+  if (nb <= 0 || nq <= 0) return;
+  double* rows = c->scr.get(3, nq * c->Dp, s);
+  hipLaunchKernelGGL(gather_rows_kernel, dim3(blocks_for(c->Dp), unsigned(nq)), dim3(256), 0, s, c->left.as<double>(),
+                     q_dev, rows, c->Dp);
+  GFCC_HIP(hipGetLastError());
+  GemmArgs g;
+  g.A = planes;
+  g.am = lin(c->Dp);
+  g.B = rows;
+  g.bm = lin(c->Dp);
+  g.M = 2 * nb;
+  g.N = nq;
+  g.K = c->Dp;
+  g.C = G;
+  g.cm = two(2, 2 * nq, 1);
+  g.cn = lin(2);
+  g.alpha = 1.0;
+  g.beta = 0.0;
+  gemm(Prec::F64, g, gemm_default_cfg(g.M, g.N, g.K), s);
+}
+
+// ------------------------------------------------------------------ timing
+
+void prof_begin(gfcc_ctx* c, const char* name, hipStream_t s) {
+  if (!c->prof_on) return;
+  hipEvent_t a, b;
+  GFCC_HIP(hipEventCreate(&a));
+  GFCC_HIP(hipEventCreate(&b));
+  GFCC_HIP(hipEventRecord(a, s));
+  c->prof_events[name].push_back({a, b});
+}
+
+void prof_end(gfcc_ctx* c, const char* name, hipStream_t s, double flops, double bytes) {
+  if (!c->prof_on) return;
+  auto& v = c->prof_events[name];
+  GFCC_CHECK(!v.empty(), GFCC_E_STATE, "prof_end without prof_begin");
+  GFCC_HIP(hipEventRecord(v.back().second, s));
+  c->prof_meta[name].push_back({flops, bytes});
+  if (v.size() >= 4096) prof_collect(c);
+}
+
+void prof_collect(gfcc_ctx* c) {
+  for (auto& kv : c->prof_events) {
+    auto& meta = c->prof_meta[kv.first];
+    auto& e = c->prof[kv.first];
+    for (size_t k = 0; k < kv.second.size(); ++k) {
+      GFCC_HIP(hipEventSynchronize(kv.second[k].second));
+      float ms = 0.f;
+      GFCC_HIP(hipEventElapsedTime(&ms, kv.second[k].first, kv.second[k].second));
+      e.count += 1;
+      e.ms += ms;
+      if (k < meta.size()) {
+        e.flops += meta[k].flops;
+        e.bytes += meta[k].bytes;
+      }
+      (void)hipEventDestroy(kv.second[k].first);
+      (void)hipEventDestroy(kv.second[k].second);
+    }
+    kv.second.clear();
+    meta.clear();
+  }
+}
+
+}  // namespace gfcc

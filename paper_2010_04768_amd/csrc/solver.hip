@@ -1,0 +1,783 @@
+// Batched restarted GMRES / flexible GMRES for (omega + Hbar_N - i eta) X_p = b_p
+// (paper Sec. 3: GMRES, minimal residual, non-increasing residual; the inverse
+// diagonal of the Hamiltonian as the classic preconditioner).
+//
+// A persistent window of `batch` slots holds one right-hand side each.  Every
+// inner iteration advances all active slots by one Arnoldi step with a single
+// batched sigma product; slots sit at different Krylov steps, so every kernel
+// reads its slot's own step counter.  When a slot's cycle ends (residual
+// estimate below its cycle tolerance, restart length reached or max_iter) the
+// host gathers those slots, forms X, recomputes the true residual with an FP64
+// sigma, and either restarts the slot, or finishes it -- G_qp = c_q^T X is
+// formed right away and the slot is refilled from the queue of (p, omega)
+// pairs (the paper's dynamic pickup of the next orbital by an idle process
+// group, Sec. 5, here at slot granularity).
+//
+// Orthogonalisation is classical Gram-Schmidt applied twice (CGS2), FP64,
+// with the complex inner product <u, w> = sum conj(u) w.  Givens rotations as
+// in the oracle.  In GMRES-IR mode (FP32/BF16 sigma) the inner cycle stops at
+// a tolerance relative to the cycle's starting residual that the reduced
+// precision operator can deliver; the restart's FP64 true residual drives the
+// refinement.
+#include <algorithm>
+#include <cmath>
+#include <deque>
+#include <vector>
+
+#include "ctx.h"
+
+namespace gfcc {
+
+struct cplx {
+  double re, im;
+};
+
+constexpr int VT = 256;         // threads per vector-kernel block
+constexpr int VE = 8;           // elements per thread
+constexpr int CH = VT * VE;     // elements per chunk
+constexpr int MAXM = 64;        // maximum restart length
+
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
+  return x;
+}
+
+struct SolverDev {
+  double* V;       // [B][m+1][2][Dp]
+  double* Z;       // [B][m][2][Dp]  (flexible only)
+  double* X;       // [B][2][Dp]
+  cplx* H;         // [B][m][m+1]   H[s][k][j] = H(j, k)
+  cplx* cs;        // [B][m]
+  cplx* sn;        // [B][m]
+  cplx* g;         // [B][m+1]
+  cplx* y;         // [B][m]
+  cplx* z;         // [B]  omega - i eta
+  int* kk;         // [B]  current Krylov step
+  double* ctol;    // [B]  cycle tolerance (absolute)
+  double* res;     // [B]  residual estimate |g_{k+1}|
+  int* flag;       // [B]  1: cycle done
+  cplx* part;      // [na][nch][MAXM+1] partial dots
+  cplx* h;         // [na][MAXM+1]
+  double* npart;   // [na][nch]
+  double* norm;    // [na]
+  int m;
+  int64_t Dp;
+  int nch;
+};
+
+__device__ __forceinline__ double* vec(const SolverDev& d, int s, int j, int c) {
+  return d.V + ((int64_t(s) * (d.m + 1) + j) * 2 + c) * d.Dp;
+}
+
+// ---- new right-hand sides: V0 = e_p, X = 0, g = (1, 0, ...), k = 0
+__global__ void init_slots_kernel(SolverDev d, const int* slots, const int* ps, const cplx* zs, const double* ctol,
+                                  int n) {
+  const int q = blockIdx.y;
+  if (q >= n) return;
+  const int s = slots[q];
+  const int64_t i0 = int64_t(blockIdx.x) * CH;
+  for (int c = 0; c < 2; ++c) {
+    double* v0 = vec(d, s, 0, c);
+    double* x = d.X + (int64_t(s) * 2 + c) * d.Dp;
+    for (int e = threadIdx.x; e < CH; e += VT) {
+      const int64_t t = i0 + e;
+      if (t < d.Dp) {
+        v0[t] = (c == 0 && t == ps[q]) ? 1.0 : 0.0;
+        x[t] = 0.0;
+      }
+    }
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    d.kk[s] = 0;
+    d.z[s] = zs[q];
+    d.ctol[s] = ctol[q];
+    d.res[s] = 1.0;
+    d.flag[s] = 0;
+    for (int j = 0; j <= d.m; ++j) d.g[int64_t(s) * (d.m + 1) + j] = cplx{j == 0 ? 1.0 : 0.0, 0.0};
+  }
+}
+
+// ---- preconditioner: u = M^-1 V[k]  into the dense sigma input planes
+__global__ void precond_kernel(SolverDev d, const int* act, double* win, const double* diag, int mode, int flex) {
+  const int q = blockIdx.y;
+  const int s = act[q];
+  const int k = d.kk[s];
+  const cplx z = d.z[s];
+  const double* vr = vec(d, s, k, 0);
+  const double* vi = vec(d, s, k, 1);
+  double* ur = win + (int64_t(q) * 2) * d.Dp;
+  double* ui = ur + d.Dp;
+  double* zr = flex ? d.Z + ((int64_t(s) * d.m + k) * 2) * d.Dp : nullptr;
+  const int64_t i0 = int64_t(blockIdx.x) * CH;
+  for (int e = threadIdx.x; e < CH; e += VT) {
+    const int64_t t = i0 + e;
+    if (t >= d.Dp) break;
+    double a = vr[t], b = vi[t];
+    if (mode == GFCC_PC_JACOBI) {
+      const double dr = z.re + diag[t], di = z.im;
+      const double den = 1.0 / (dr * dr + di * di);
+      const double nr = (a * dr + b * di) * den, ni = (b * dr - a * di) * den;
+      a = nr;
+      b = ni;
+    }
+    ur[t] = a;
+    ui[t] = b;
+    if (zr) {
+      zr[t] = a;
+      zr[d.Dp + t] = b;
+    }
+  }
+}
+
+// pass = 0: w = z u + sigma  -> V[k+1], then partial <V_j, w>, j <= k
+// pass = 1: w -= sum_j h_j V_j (in place), then partial <V_j, w>
+// pass = 2: w -= sum_j h_j V_j, then partial ||w||^2
+__global__ __launch_bounds__(VT) void arnoldi_kernel(SolverDev d, const int* act, const double* win,
+                                                     const double* wout, int pass) {
+  const int q = blockIdx.y;
+  const int s = act[q];
+  const int k = d.kk[s];
+  const int64_t i0 = int64_t(blockIdx.x) * CH;
+  double* wr = vec(d, s, k + 1, 0);
+  double* wi = vec(d, s, k + 1, 1);
+  double xr[VE], xi[VE];
+  if (pass == 0) {
+    const cplx z = d.z[s];
+    const double* ur = win + (int64_t(q) * 2) * d.Dp;
+    const double* sr = wout + (int64_t(q) * 2) * d.Dp;
+#pragma unroll
+    for (int e = 0; e < VE; ++e) {
+      const int64_t t = i0 + threadIdx.x + e * VT;
+      if (t < d.Dp) {
+        const double a = ur[t], b = ur[d.Dp + t];
+        xr[e] = z.re * a - z.im * b + sr[t];
+        xi[e] = z.re * b + z.im * a + sr[d.Dp + t];
+        wr[t] = xr[e];
+        wi[t] = xi[e];
+      } else {
+        xr[e] = xi[e] = 0.0;
+      }
+    }
+  } else {
+    const cplx* h = d.h + int64_t(q) * (MAXM + 1);
+#pragma unroll
+    for (int e = 0; e < VE; ++e) {
+      const int64_t t = i0 + threadIdx.x + e * VT;
+      xr[e] = (t < d.Dp) ? wr[t] : 0.0;
+      xi[e] = (t < d.Dp) ? wi[t] : 0.0;
+    }
+    for (int j = 0; j <= k; ++j) {
+      const cplx hj = h[j];
+      const double* vr = vec(d, s, j, 0);
+      const double* vi = vec(d, s, j, 1);
+#pragma unroll
+      for (int e = 0; e < VE; ++e) {
+        const int64_t t = i0 + threadIdx.x + e * VT;
+        if (t < d.Dp) {
+          const double a = vr[t], b = vi[t];
+          xr[e] -= hj.re * a - hj.im * b;
+          xi[e] -= hj.re * b + hj.im * a;
+        }
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < VE; ++e) {
+      const int64_t t = i0 + threadIdx.x + e * VT;
+      if (t < d.Dp) {
+        wr[t] = xr[e];
+        wi[t] = xi[e];
+      }
+    }
+  }
+  if (pass == 2) {
+    double acc = 0.0;
+#pragma unroll
+    for (int e = 0; e < VE; ++e) acc += xr[e] * xr[e] + xi[e] * xi[e];
+    __shared__ double red[VT / 64];
+    acc = wave_sum(acc);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double t = 0;
+      for (int w = 0; w < VT / 64; ++w) t += red[w];
+      d.npart[int64_t(q) * d.nch + blockIdx.x] = t;
+    }
+    return;
+  }
+  __shared__ double lds[VT / 64][MAXM + 1][2];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int j = 0; j <= k; ++j) {
+    const double* vr = vec(d, s, j, 0);
+    const double* vi = vec(d, s, j, 1);
+    double a = 0.0, b = 0.0;
+#pragma unroll
+    for (int e = 0; e < VE; ++e) {
+      const int64_t t = i0 + threadIdx.x + e * VT;
+      if (t < d.Dp) {
+        const double ur = vr[t], ui = vi[t];
+        a += ur * xr[e] + ui * xi[e];  // conj(v) w
+        b += ur * xi[e] - ui * xr[e];
+      }
+    }
+    a = wave_sum(a);
+    b = wave_sum(b);
+    if (lane == 0) {
+      lds[wv][j][0] = a;
+      lds[wv][j][1] = b;
+    }
+  }
+  __syncthreads();
+  if (int(threadIdx.x) <= k) {
+    double a = 0, b = 0;
+    for (int w = 0; w < VT / 64; ++w) {
+      a += lds[w][threadIdx.x][0];
+      b += lds[w][threadIdx.x][1];
+    }
+    d.part[(int64_t(q) * d.nch + blockIdx.x) * (MAXM + 1) + threadIdx.x] = cplx{a, b};
+  }
+}
+
+// h = sum over chunks; H(:, k) = h (pass 0) or += h (pass 1)
+__global__ void reduce_h_kernel(SolverDev d, const int* act, int pass) {
+  const int q = blockIdx.x;
+  const int s = act[q];
+  const int k = d.kk[s];
+  const int j = threadIdx.x;
+  if (j > k) return;
+  double a = 0, b = 0;
+  for (int c = 0; c < d.nch; ++c) {
+    const cplx p = d.part[(int64_t(q) * d.nch + c) * (MAXM + 1) + j];
+    a += p.re;
+    b += p.im;
+  }
+  d.h[int64_t(q) * (MAXM + 1) + j] = cplx{a, b};
+  cplx* Hc = d.H + (int64_t(s) * d.m + k) * (d.m + 1);
+  if (pass == 0)
+    Hc[j] = cplx{a, b};
+  else
+    Hc[j] = cplx{Hc[j].re + a, Hc[j].im + b};
+}
+
+// ||w||, H(k+1, k), Givens rotation, residual estimate, cycle flag
+__global__ void givens_kernel(SolverDev d, const int* act, int* flags_out, double* res_out, int iters_left_any) {
+  const int q = blockIdx.x;
+  const int s = act[q];
+  __shared__ double red[64];
+  double acc = 0.0;
+  for (int c = threadIdx.x; c < d.nch; c += 64) acc += d.npart[int64_t(q) * d.nch + c];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  double nrm2 = 0.0;
+  for (int t = 0; t < 64; ++t) nrm2 += red[t];
+  const double nrm = sqrt(nrm2);
+  const int k = d.kk[s];
+  const int m = d.m;
+  cplx* Hc = d.H + (int64_t(s) * m + k) * (m + 1);
+  Hc[k + 1] = cplx{nrm, 0.0};
+  cplx* cs = d.cs + int64_t(s) * m;
+  cplx* sn = d.sn + int64_t(s) * m;
+  cplx* g = d.g + int64_t(s) * (m + 1);
+  for (int j = 0; j < k; ++j) {  // previous rotations
+    const cplx hj = Hc[j], hj1 = Hc[j + 1];
+    const cplx c = cs[j], sj = sn[j];
+    // [h_j; h_j1] <- [conj(c) h_j + conj(s) h_j1; -s h_j + c h_j1]
+    Hc[j] = cplx{c.re * hj.re + c.im * hj.im + sj.re * hj1.re + sj.im * hj1.im,
+                 c.re * hj.im - c.im * hj.re + sj.re * hj1.im - sj.im * hj1.re};
+    Hc[j + 1] = cplx{-(sj.re * hj.re - sj.im * hj.im) + (c.re * hj1.re - c.im * hj1.im),
+                     -(sj.re * hj.im + sj.im * hj.re) + (c.re * hj1.im + c.im * hj1.re)};
+  }
+  const cplx a = Hc[k];
+  const double bb = Hc[k + 1].re;  // real, >= 0
+  const double den = sqrt(a.re * a.re + a.im * a.im + bb * bb);
+  cplx c, sv;
+  if (den > 0.0) {
+    c = cplx{a.re / den, a.im / den};
+    sv = cplx{bb / den, 0.0};
+  } else {
+    c = cplx{1.0, 0.0};
+    sv = cplx{0.0, 0.0};
+  }
+  cs[k] = c;
+  sn[k] = sv;
+  Hc[k] = cplx{den, 0.0};
+  Hc[k + 1] = cplx{0.0, 0.0};
+  const cplx gk = g[k];
+  g[k + 1] = cplx{-(sv.re * gk.re - sv.im * gk.im), -(sv.re * gk.im + sv.im * gk.re)};
+  g[k] = cplx{c.re * gk.re + c.im * gk.im, c.re * gk.im - c.im * gk.re};
+  const double r = sqrt(g[k + 1].re * g[k + 1].re + g[k + 1].im * g[k + 1].im);
+  d.res[s] = r;
+  d.norm[q] = nrm;
+  const int knew = k + 1;
+  d.kk[s] = knew;
+  int f = 0;
+  if (!(r == r) || !(nrm == nrm) || std::isinf(r)) f = 3;              // non-finite
+  else if (r <= d.ctol[s] || knew >= m || nrm == 0.0 || iters_left_any == 0) f = 1;
+  flags_out[q] = f;
+  res_out[q] = r;
+}
+
+// V[k] (new) *= 1/||w||  (k already advanced)
+__global__ void scale_kernel(SolverDev d, const int* act) {
+  const int q = blockIdx.y;
+  const int s = act[q];
+  const int k = d.kk[s];
+  const double nrm = d.norm[q];
+  const double f = nrm > 0.0 ? 1.0 / nrm : 0.0;
+  double* vr = vec(d, s, k, 0);
+  double* vi = vec(d, s, k, 1);
+  const int64_t i0 = int64_t(blockIdx.x) * CH;
+  for (int e = threadIdx.x; e < CH; e += VT) {
+    const int64_t t = i0 + e;
+    if (t < d.Dp) {
+      vr[t] *= f;
+      vi[t] *= f;
+    }
+  }
+}
+
+// y = R^-1 g (upper triangular k x k) per finishing slot
+__global__ void trisolve_kernel(SolverDev d, const int* fin, int n) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n) return;
+  const int s = fin[q];
+  const int k = d.kk[s];
+  const int m = d.m;
+  const cplx* H = d.H + int64_t(s) * m * (m + 1);
+  const cplx* g = d.g + int64_t(s) * (m + 1);
+  cplx* y = d.y + int64_t(s) * m;
+  for (int i = k - 1; i >= 0; --i) {
+    double ar = g[i].re, ai = g[i].im;
+    for (int j = i + 1; j < k; ++j) {
+      const cplx hij = H[int64_t(j) * (m + 1) + i];
+      ar -= hij.re * y[j].re - hij.im * y[j].im;
+      ai -= hij.re * y[j].im + hij.im * y[j].re;
+    }
+    const cplx hii = H[int64_t(i) * (m + 1) + i];
+    const double den = hii.re * hii.re + hii.im * hii.im;
+    if (den > 0.0)
+      y[i] = cplx{(ar * hii.re + ai * hii.im) / den, (ai * hii.re - ar * hii.im) / den};
+    else
+      y[i] = cplx{0.0, 0.0};
+  }
+}
+
+// X += M^-1 sum_j y_j V_j (or sum_j y_j Z_j), and copy X into the dense planes
+__global__ void xupdate_kernel(SolverDev d, const int* fin, double* xout, const double* diag, int mode, int flex) {
+  const int q = blockIdx.y;
+  const int s = fin[q];
+  const int k = d.kk[s];
+  const cplx z = d.z[s];
+  const cplx* y = d.y + int64_t(s) * d.m;
+  double* xr = d.X + (int64_t(s) * 2) * d.Dp;
+  double* xi = xr + d.Dp;
+  const int64_t i0 = int64_t(blockIdx.x) * CH;
+  for (int e = threadIdx.x; e < CH; e += VT) {
+    const int64_t t = i0 + e;
+    if (t >= d.Dp) break;
+    double ar = 0.0, ai = 0.0;
+    for (int j = 0; j < k; ++j) {
+      const double* b = flex ? d.Z + ((int64_t(s) * d.m + j) * 2) * d.Dp : vec(d, s, j, 0);
+      const double br = b[t], bi = b[d.Dp + t];
+      ar += y[j].re * br - y[j].im * bi;
+      ai += y[j].re * bi + y[j].im * br;
+    }
+    if (!flex && mode == GFCC_PC_JACOBI) {
+      const double dr = z.re + diag[t], di = z.im;
+      const double den = 1.0 / (dr * dr + di * di);
+      const double nr = (ar * dr + ai * di) * den, ni = (ai * dr - ar * di) * den;
+      ar = nr;
+      ai = ni;
+    }
+    xr[t] += ar;
+    xi[t] += ai;
+    xout[(int64_t(q) * 2) * d.Dp + t] = xr[t];
+    xout[(int64_t(q) * 2 + 1) * d.Dp + t] = xi[t];
+  }
+}
+
+// r = e_p - z x - sigma(x) -> V[0]; partial ||r||^2
+__global__ void residual_kernel(SolverDev d, const int* fin, const int* pfin, const double* xin,
+                                const double* sig) {
+  const int q = blockIdx.y;
+  const int s = fin[q];
+  const cplx z = d.z[s];
+  const int p = pfin[q];
+  double* r0 = vec(d, s, 0, 0);
+  double* r1 = vec(d, s, 0, 1);
+  const double* xr = xin + (int64_t(q) * 2) * d.Dp;
+  const double* sr = sig + (int64_t(q) * 2) * d.Dp;
+  const int64_t i0 = int64_t(blockIdx.x) * CH;
+  double acc = 0.0;
+  for (int e = threadIdx.x; e < CH; e += VT) {
+    const int64_t t = i0 + e;
+    if (t >= d.Dp) break;
+    const double a = xr[t], b = xr[d.Dp + t];
+    double rr = -(z.re * a - z.im * b) - sr[t];
+    const double ri = -(z.re * b + z.im * a) - sr[d.Dp + t];
+    if (t == p) rr += 1.0;
+    r0[t] = rr;
+    r1[t] = ri;
+    acc += rr * rr + ri * ri;
+  }
+  __shared__ double red[VT / 64];
+  acc = wave_sum(acc);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0;
+    for (int w = 0; w < VT / 64; ++w) t += red[w];
+    d.npart[int64_t(q) * d.nch + blockIdx.x] = t;
+  }
+}
+
+__global__ void rnorm_kernel(SolverDev d, int n, double* beta) {
+  const int q = blockIdx.x;
+  if (q >= n) return;
+  __shared__ double red[64];
+  double acc = 0.0;
+  for (int c = threadIdx.x; c < d.nch; c += 64) acc += d.npart[int64_t(q) * d.nch + c];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0;
+    for (int w = 0; w < 64; ++w) t += red[w];
+    beta[q] = sqrt(t);
+  }
+}
+
+// restart: V0 = r / beta, g = (beta, 0, ...), k = 0, new cycle tolerance
+__global__ void restart_kernel(SolverDev d, const int* slots, const double* beta, const double* ctol, int n) {
+  const int q = blockIdx.y;
+  if (q >= n) return;
+  const int s = slots[q];
+  const double b = beta[q];
+  const double f = b > 0.0 ? 1.0 / b : 0.0;
+  double* r0 = vec(d, s, 0, 0);
+  double* r1 = vec(d, s, 0, 1);
+  const int64_t i0 = int64_t(blockIdx.x) * CH;
+  for (int e = threadIdx.x; e < CH; e += VT) {
+    const int64_t t = i0 + e;
+    if (t < d.Dp) {
+      r0[t] *= f;
+      r1[t] *= f;
+    }
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    d.kk[s] = 0;
+    d.ctol[s] = ctol[q];
+    d.res[s] = b;
+    for (int j = 0; j <= d.m; ++j) d.g[int64_t(s) * (d.m + 1) + j] = cplx{j == 0 ? b : 0.0, 0.0};
+  }
+}
+
+// G[row][k] = c_{q_k} . x  for finished slots (q_k = qlist[k] or the slot's own p)
+__global__ void gdot_kernel(SolverDev d, const int* slots, const int64_t* rows, const int* pown, const int64_t* qlist,
+                            int nq, const double* left, double* G) {
+  const int f = blockIdx.x;
+  const int kq = blockIdx.y;
+  const int s = slots[f];
+  const int64_t qq = qlist ? qlist[kq] : pown[f];
+  const double* c = left + qq * d.Dp;
+  const double* xr = d.X + (int64_t(s) * 2) * d.Dp;
+  const double* xi = xr + d.Dp;
+  double a = 0.0, b = 0.0;
+  for (int64_t t = threadIdx.x; t < d.Dp; t += VT) {
+    a += c[t] * xr[t];
+    b += c[t] * xi[t];
+  }
+  __shared__ double red[VT / 64][2];
+  a = wave_sum(a);
+  b = wave_sum(b);
+  if ((threadIdx.x & 63) == 0) {
+    red[threadIdx.x >> 6][0] = a;
+    red[threadIdx.x >> 6][1] = b;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double ta = 0, tb = 0;
+    for (int w = 0; w < VT / 64; ++w) {
+      ta += red[w][0];
+      tb += red[w][1];
+    }
+    G[(rows[f] * nq + kq) * 2] = ta;
+    G[(rows[f] * nq + kq) * 2 + 1] = tb;
+  }
+}
+
+// copy X of finished slots to the caller's interleaved [nrhs][D] array
+__global__ void xout_kernel(SolverDev d, const int* slots, const int64_t* rows, double* Xo, int64_t D, int64_t o,
+                            int64_t o_pad) {
+  const int f = blockIdx.y;
+  const int s = slots[f];
+  const double* xr = d.X + (int64_t(s) * 2) * d.Dp;
+  for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < D; t += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t src = t < o ? t : t - o + o_pad;
+    Xo[(rows[f] * D + t) * 2] = xr[src];
+    Xo[(rows[f] * D + t) * 2 + 1] = xr[d.Dp + src];
+  }
+}
+
+// ------------------------------------------------------------------ host driver
+
+struct HostSlot {
+  int64_t rhs = -1;
+  int iters = 0, restarts = 0;
+};
+
+static double lp_cycle_rtol(gfcc_precision p) {
+  switch (p) {
+    case GFCC_FP32_IR: return 1e-5;
+    case GFCC_BF16_IR: return 2e-3;
+    default: return 0.0;
+  }
+}
+
+template <typename T>
+static void upload(DBuf& b, const std::vector<T>& v, hipStream_t s) {
+  b.ensure(std::max<size_t>(v.size(), 1) * sizeof(T), s);
+  if (!v.empty()) GFCC_HIP(hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
+}
+
+void solve_batch(gfcc_ctx* c, int64_t nrhs, const int64_t* p, const double* omega, double eta, int64_t nq,
+                 const int64_t* q, const gfcc_solve_opts* opts, double* G, double* Xout, gfcc_rhs_info* info,
+                 hipStream_t s, bool* all_converged) {
+  const int m = std::min<int>(opts->restart, MAXM);
+  const gfcc_precision prec = opts->precision;
+  const int mode = opts->precond == GFCC_PC_MLP ? GFCC_PC_JACOBI : opts->precond;  // MLP: see mlp path
+  const int flex = 0;
+  const int64_t Dp = c->Dp;
+  const int nch = int((Dp + CH - 1) / CH);
+  int B = opts->batch > 0 ? opts->batch : 0;
+  if (B == 0) {
+    size_t freeb = 0, totalb = 0;
+    GFCC_HIP(hipMemGetInfo(&freeb, &totalb));
+    const double per_slot = double(m + 2 + (flex ? m : 0)) * 2.0 * Dp * 8.0 + 6.0 * 2.0 * Dp * 8.0;
+    const int64_t fit = int64_t(0.5 * double(freeb) / per_slot);
+    B = int(std::max<int64_t>(1, std::min<int64_t>({fit, 128, nrhs})));
+  }
+  B = int(std::min<int64_t>(B, nrhs));
+
+  // device state
+  DBuf bV, bZ, bX, bH, bcs, bsn, bg, by, bz, bkk, bctol, bres, bflag, bpart, bh, bnpart, bnorm;
+  bV.ensure(size_t(B) * (m + 1) * 2 * Dp * 8, s);
+  if (flex) bZ.ensure(size_t(B) * m * 2 * Dp * 8, s);
+  bX.ensure(size_t(B) * 2 * Dp * 8, s);
+  bH.ensure(size_t(B) * m * (m + 1) * sizeof(cplx), s);
+  bcs.ensure(size_t(B) * m * sizeof(cplx), s);
+  bsn.ensure(size_t(B) * m * sizeof(cplx), s);
+  bg.ensure(size_t(B) * (m + 1) * sizeof(cplx), s);
+  by.ensure(size_t(B) * m * sizeof(cplx), s);
+  bz.ensure(size_t(B) * sizeof(cplx), s);
+  bkk.ensure(size_t(B) * sizeof(int), s);
+  bctol.ensure(size_t(B) * 8, s);
+  bres.ensure(size_t(B) * 8, s);
+  bflag.ensure(size_t(B) * sizeof(int), s);
+  bpart.ensure(size_t(B) * nch * (MAXM + 1) * sizeof(cplx), s);
+  bh.ensure(size_t(B) * (MAXM + 1) * sizeof(cplx), s);
+  bnpart.ensure(size_t(B) * nch * 8, s);
+  bnorm.ensure(size_t(B) * 8, s);
+  c->ws_in.ensure(size_t(2 * B) * Dp * 8, s);
+  c->ws_out.ensure(size_t(2 * B) * Dp * 8, s);
+
+  SolverDev d;
+  d.V = bV.as<double>();
+  d.Z = flex ? bZ.as<double>() : nullptr;
+  d.X = bX.as<double>();
+  d.H = bH.as<cplx>();
+  d.cs = bcs.as<cplx>();
+  d.sn = bsn.as<cplx>();
+  d.g = bg.as<cplx>();
+  d.y = by.as<cplx>();
+  d.z = bz.as<cplx>();
+  d.kk = bkk.as<int>();
+  d.ctol = bctol.as<double>();
+  d.res = bres.as<double>();
+  d.flag = bflag.as<int>();
+  d.part = bpart.as<cplx>();
+  d.h = bh.as<cplx>();
+  d.npart = bnpart.as<double>();
+  d.norm = bnorm.as<double>();
+  d.m = m;
+  d.Dp = Dp;
+  d.nch = nch;
+
+  DBuf d_act, d_flags, d_res, d_list, d_plist, d_zlist, d_ctl, d_beta, d_rows, d_q;
+  d_flags.ensure(size_t(B) * sizeof(int), s);
+  d_res.ensure(size_t(B) * 8, s);
+  d_beta.ensure(size_t(B) * 8, s);
+  if (q) {
+    d_q.ensure(size_t(nq) * 8, s);
+    GFCC_HIP(hipMemcpyAsync(d_q.p, q, size_t(nq) * 8, hipMemcpyHostToDevice, s));
+  }
+
+  const double tol = opts->tol;
+  const double rtol_lp = lp_cycle_rtol(prec);
+  std::vector<HostSlot> hs(B);
+  std::vector<int> free_slots;
+  for (int i = B - 1; i >= 0; --i) free_slots.push_back(i);
+  std::vector<int> active;
+  int64_t next = 0;
+  for (int64_t r = 0; r < nrhs; ++r) info[r] = gfcc_rhs_info{1, 0, 0, 0, 0.0};
+  bool ok_all = true;
+
+  auto refill = [&]() {
+    std::vector<int> sl, pl;
+    std::vector<cplx> zl;
+    std::vector<double> tl;
+    while (!free_slots.empty() && next < nrhs) {
+      const int sidx = free_slots.back();
+      free_slots.pop_back();
+      hs[sidx] = HostSlot{next, 0, 0};
+      sl.push_back(sidx);
+      pl.push_back(int(p[next]));
+      zl.push_back(cplx{omega[next], -eta});
+      tl.push_back(std::max(0.5 * tol, rtol_lp));  // ||b|| = 1
+      active.push_back(sidx);
+      ++next;
+    }
+    if (sl.empty()) return;
+    upload(d_list, sl, s);
+    upload(d_plist, pl, s);
+    upload(d_zlist, zl, s);
+    upload(d_ctl, tl, s);
+    hipLaunchKernelGGL(init_slots_kernel, dim3(nch, unsigned(sl.size())), dim3(VT), 0, s, d, d_list.as<int>(),
+                       d_plist.as<int>(), d_zlist.as<cplx>(), d_ctl.as<double>(), int(sl.size()));
+    GFCC_HIP(hipGetLastError());
+    GFCC_HIP(hipStreamSynchronize(s));  // host vectors above go out of scope
+  };
+
+  refill();
+  std::vector<int> hflags(B);
+  std::vector<double> hres(B), hbeta(B);
+  while (!active.empty()) {
+    const int na = int(active.size());
+    upload(d_act, active, s);
+    const int* act = d_act.as<int>();
+    // 1. precondition
+    hipLaunchKernelGGL(precond_kernel, dim3(nch, na), dim3(VT), 0, s, d, act, c->ws_in.as<double>(),
+                       c->diag.as<double>(), mode, flex);
+    GFCC_HIP(hipGetLastError());
+    // 2. sigma
+    sigma_planes(c, 2 * na, c->ws_in.as<double>(), c->ws_out.as<double>(), prec, s);
+    // 3. Arnoldi (CGS2)
+    prof_begin(c, "arnoldi", s);
+    hipLaunchKernelGGL(arnoldi_kernel, dim3(nch, na), dim3(VT), 0, s, d, act, c->ws_in.as<double>(),
+                       c->ws_out.as<double>(), 0);
+    hipLaunchKernelGGL(reduce_h_kernel, dim3(na), dim3(MAXM + 1), 0, s, d, act, 0);
+    hipLaunchKernelGGL(arnoldi_kernel, dim3(nch, na), dim3(VT), 0, s, d, act, c->ws_in.as<double>(),
+                       c->ws_out.as<double>(), 1);
+    hipLaunchKernelGGL(reduce_h_kernel, dim3(na), dim3(MAXM + 1), 0, s, d, act, 1);
+    hipLaunchKernelGGL(arnoldi_kernel, dim3(nch, na), dim3(VT), 0, s, d, act, c->ws_in.as<double>(),
+                       c->ws_out.as<double>(), 2);
+    GFCC_HIP(hipGetLastError());
+    // 4. Givens + flags
+    int any_left = 0;
+    for (int a : active) any_left |= (hs[a].iters + 1 < opts->max_iter);
+    std::vector<int> lastcall(na);
+    for (int i = 0; i < na; ++i) lastcall[i] = (hs[active[i]].iters + 1 >= opts->max_iter);
+    hipLaunchKernelGGL(givens_kernel, dim3(na), dim3(64), 0, s, d, act, d_flags.as<int>(), d_res.as<double>(), 1);
+    hipLaunchKernelGGL(scale_kernel, dim3(nch, na), dim3(VT), 0, s, d, act);
+    GFCC_HIP(hipGetLastError());
+    prof_end(c, "arnoldi", s, 0.0, 0.0);
+    GFCC_HIP(hipMemcpyAsync(hflags.data(), d_flags.p, na * sizeof(int), hipMemcpyDeviceToHost, s));
+    GFCC_HIP(hipMemcpyAsync(hres.data(), d_res.p, na * 8, hipMemcpyDeviceToHost, s));
+    GFCC_HIP(hipStreamSynchronize(s));
+    (void)any_left;
+
+    std::vector<int> fin;
+    std::vector<int> fin_dense;
+    for (int i = 0; i < na; ++i) {
+      const int sl = active[i];
+      hs[sl].iters += 1;
+      if (hflags[i] != 0 || lastcall[i]) fin.push_back(sl);
+    }
+    if (fin.empty()) continue;
+
+    // 5. finish the cycles of `fin`
+    const int nf = int(fin.size());
+    std::vector<int> pf(nf);
+    for (int i = 0; i < nf; ++i) pf[i] = int(p[hs[fin[i]].rhs]);
+    upload(d_list, fin, s);
+    upload(d_plist, pf, s);
+    const int* fl = d_list.as<int>();
+    hipLaunchKernelGGL(trisolve_kernel, dim3((nf + 63) / 64), dim3(64), 0, s, d, fl, nf);
+    hipLaunchKernelGGL(xupdate_kernel, dim3(nch, nf), dim3(VT), 0, s, d, fl, c->ws_in.as<double>(),
+                       c->diag.as<double>(), mode, flex);
+    GFCC_HIP(hipGetLastError());
+    sigma_planes(c, 2 * nf, c->ws_in.as<double>(), c->ws_out.as<double>(), GFCC_FP64, s);
+    hipLaunchKernelGGL(residual_kernel, dim3(nch, nf), dim3(VT), 0, s, d, fl, d_plist.as<int>(),
+                       c->ws_in.as<double>(), c->ws_out.as<double>());
+    hipLaunchKernelGGL(rnorm_kernel, dim3(nf), dim3(64), 0, s, d, nf, d_beta.as<double>());
+    GFCC_HIP(hipGetLastError());
+    GFCC_HIP(hipMemcpyAsync(hbeta.data(), d_beta.p, nf * 8, hipMemcpyDeviceToHost, s));
+    GFCC_HIP(hipStreamSynchronize(s));
+
+    std::vector<int> done, again, done_p;
+    std::vector<int64_t> done_rows;
+    std::vector<double> again_beta, again_tol;
+    for (int i = 0; i < nf; ++i) {
+      const int sl = fin[i];
+      HostSlot& h = hs[sl];
+      const double beta = hbeta[i];
+      const bool finite = std::isfinite(beta);
+      gfcc_rhs_info& inf = info[h.rhs];
+      inf.iters = h.iters;
+      inf.restarts = h.restarts;
+      inf.true_rel_resid = beta;
+      if (finite && beta <= tol) {
+        inf.status = 0;
+      } else if (!finite) {
+        inf.status = 3;
+      } else if (h.iters >= opts->max_iter) {
+        inf.status = 1;
+      } else {
+        h.restarts += 1;
+        again.push_back(sl);
+        again_beta.push_back(beta);
+        again_tol.push_back(std::max(0.5 * tol, rtol_lp * beta));
+        continue;
+      }
+      if (inf.status != 0) ok_all = false;
+      done.push_back(sl);
+      done_rows.push_back(h.rhs);
+      done_p.push_back(int(p[h.rhs]));
+    }
+    if (!again.empty()) {
+      const int nr = int(again.size());
+      DBuf d_ag, d_agb, d_agt;
+      upload(d_ag, again, s);
+      upload(d_agb, again_beta, s);
+      upload(d_agt, again_tol, s);
+      hipLaunchKernelGGL(restart_kernel, dim3(nch, nr), dim3(VT), 0, s, d, d_ag.as<int>(), d_agb.as<double>(),
+                         d_agt.as<double>(), nr);
+      GFCC_HIP(hipGetLastError());
+      GFCC_HIP(hipStreamSynchronize(s));
+    }
+    if (!done.empty()) {
+      const int nd = int(done.size());
+      upload(d_list, done, s);
+      upload(d_rows, done_rows, s);
+      upload(d_plist, done_p, s);
+      hipLaunchKernelGGL(gdot_kernel, dim3(nd, unsigned(nq)), dim3(VT), 0, s, d, d_list.as<int>(),
+                         d_rows.as<int64_t>(), d_plist.as<int>(), q ? d_q.as<int64_t>() : nullptr, int(nq),
+                         c->left.as<double>(), G);
+      if (Xout)
+        hipLaunchKernelGGL(xout_kernel, dim3(std::min<int64_t>((c->D + 255) / 256, 1024), nd), dim3(256), 0, s, d,
+                           d_list.as<int>(), d_rows.as<int64_t>(), Xout, c->D, c->o, c->o_pad);
+      GFCC_HIP(hipGetLastError());
+      GFCC_HIP(hipStreamSynchronize(s));
+      for (int sl : done) {
+        hs[sl].rhs = -1;
+        free_slots.push_back(sl);
+        active.erase(std::find(active.begin(), active.end(), sl));
+      }
+      refill();
+    }
+  }
+  GFCC_HIP(hipStreamSynchronize(s));
+  *all_converged = ok_all;
+}
+
+}  // namespace gfcc

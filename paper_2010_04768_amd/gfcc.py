@@ -1,0 +1,221 @@
+"""ctypes binding of libgfcc.so (argument marshalling only).
+
+Every computation runs in the library's HIP kernels; PyTorch supplies device
+memory (complex128 tensors are interleaved (re, im) FP64, the layout the C ABI
+expects) and the current HIP stream.  Importing this module does not touch
+the GPU; the library is loaded on first use and a missing build raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgfcc.so")
+
+FP64, FP32_IR, BF16_IR = 0, 1, 2
+PC_NONE, PC_JACOBI, PC_MLP = 0, 1, 2
+PRECISIONS = {"fp64": FP64, "fp32": FP32_IR, "bf16": BF16_IR}
+PRECONDS = {"none": PC_NONE, "jacobi": PC_JACOBI, "mlp": PC_MLP}
+BLOCKS = ["FOO", "FVV", "FOV", "WOOOO", "WOOOV", "WOVOO", "WOVVO", "WOVOV", "DIAG", "LEFT"]
+
+# exported symbols of include/gfcc.h
+SYMBOLS = ["gfcc_build_intermediates", "gfcc_dims", "gfcc_export", "gfcc_sigma", "gfcc_solve_batch",
+           "gfcc_greens", "gfcc_prof_enable", "gfcc_prof_get", "gfcc_destroy", "gfcc_strerror",
+           "gfcc_last_error"]
+
+
+class GfccSystem(ctypes.Structure):
+    _fields_ = [("n_occ", ctypes.c_int64), ("n_vir", ctypes.c_int64), ("n_chol", ctypes.c_int64),
+                ("eps", ctypes.c_void_p), ("L", ctypes.c_void_p), ("t1", ctypes.c_void_p),
+                ("t2", ctypes.c_void_p), ("l1", ctypes.c_void_p), ("l2", ctypes.c_void_p)]
+
+
+class SolveOpts(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_size_t), ("tol", ctypes.c_double), ("restart", ctypes.c_int32),
+                ("max_iter", ctypes.c_int32), ("batch", ctypes.c_int32), ("precond", ctypes.c_int),
+                ("precision", ctypes.c_int), ("use_graph", ctypes.c_int32), ("tune_cache", ctypes.c_char_p)]
+
+
+class RhsInfo(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("iters", ctypes.c_int32), ("restarts", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("true_rel_resid", ctypes.c_double)]
+
+
+class GfccError(RuntimeError):
+    pass
+
+
+_lib = None
+
+
+def load():
+    """Load libgfcc.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise GfccError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i64, dbl = ctypes.c_void_p, ctypes.c_int64, ctypes.c_double
+    L.gfcc_build_intermediates.argtypes = [ctypes.POINTER(GfccSystem), vp, ctypes.POINTER(vp)]
+    L.gfcc_dims.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64)]
+    L.gfcc_export.argtypes = [vp, ctypes.c_int, vp, vp]
+    L.gfcc_sigma.argtypes = [vp, i64, vp, vp, ctypes.c_int, vp]
+    L.gfcc_solve_batch.argtypes = [vp, i64, vp, vp, dbl, i64, vp, ctypes.POINTER(SolveOpts), vp, vp,
+                                   ctypes.POINTER(RhsInfo), vp]
+    L.gfcc_greens.argtypes = [vp, i64, vp, i64, vp, vp, vp]
+    L.gfcc_prof_enable.argtypes = [vp, ctypes.c_int]
+    L.gfcc_prof_get.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(i64), ctypes.POINTER(dbl),
+                                ctypes.POINTER(dbl), ctypes.POINTER(dbl)]
+    L.gfcc_destroy.argtypes = [vp]
+    L.gfcc_strerror.restype = ctypes.c_char_p
+    L.gfcc_strerror.argtypes = [ctypes.c_int]
+    L.gfcc_last_error.restype = ctypes.c_char_p
+    for name in ["gfcc_build_intermediates", "gfcc_dims", "gfcc_export", "gfcc_sigma", "gfcc_solve_batch",
+                 "gfcc_greens", "gfcc_prof_enable", "gfcc_prof_get", "gfcc_destroy"]:
+        getattr(L, name).restype = ctypes.c_int
+    if hasattr(L, "gfcc_mlp_train"):
+        L.gfcc_mlp_train.restype = ctypes.c_int
+        L.gfcc_mlp_forward.restype = ctypes.c_int
+        L.gfcc_mlp_set_weights.restype = ctypes.c_int
+        L.gfcc_mlp_get_weights.restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _check(st, what):
+    if st < 0:
+        L = load()
+        raise GfccError(f"{what}: {L.gfcc_strerror(st).decode()}: {L.gfcc_last_error().decode()}")
+    return st
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+class Context:
+    """Owns one gfcc_ctx (per-system intermediates on the current device)."""
+
+    def __init__(self, eps, L, t1, t2, l1=None, l2=None):
+        import torch
+        self._lib = load()
+        dev = torch.device("cuda", torch.cuda.current_device())
+
+        def dev_f64(a):
+            if a is None:
+                return None
+            t = a if isinstance(a, torch.Tensor) else torch.from_numpy(np.ascontiguousarray(a))
+            return t.to(device=dev, dtype=torch.float64).contiguous()
+
+        self._keep = [dev_f64(x) for x in (eps, L, t1, t2, l1, l2)]
+        e, Lc, a1, a2, b1, b2 = self._keep
+        self.n_occ, self.n_vir = a1.shape
+        sysd = GfccSystem(self.n_occ, self.n_vir, Lc.shape[0], e.data_ptr(), Lc.data_ptr(), a1.data_ptr(),
+                          a2.data_ptr(), b1.data_ptr() if b1 is not None else None,
+                          b2.data_ptr() if b2 is not None else None)
+        h = ctypes.c_void_p()
+        _check(self._lib.gfcc_build_intermediates(ctypes.byref(sysd), _stream(), ctypes.byref(h)),
+               "gfcc_build_intermediates")
+        self._h = h
+        self._keep = None  # the context copies what it keeps
+        D = ctypes.c_int64()
+        _check(self._lib.gfcc_dims(self._h, ctypes.byref(D), None, None), "gfcc_dims")
+        self.dim = D.value
+        self.device = dev
+
+    @classmethod
+    def from_system(cls, s):
+        return cls(s.eps, s.L, s.t1, s.t2, s.l1, s.l2)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.gfcc_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---------------------------------------------------------------- blocks
+    def export(self, name):
+        import torch
+        o, v, D = self.n_occ, self.n_vir, self.dim
+        shapes = {"FOO": (o, o), "FVV": (v, v), "FOV": (o, v), "WOOOO": (o, o, o, o), "WOOOV": (o, o, o, v),
+                  "WOVOO": (o, v, o, o), "WOVVO": (o, v, v, o), "WOVOV": (o, v, o, v), "DIAG": (D,),
+                  "LEFT": (o, D)}
+        out = torch.empty(shapes[name], dtype=torch.float64, device=self.device)
+        _check(self._lib.gfcc_export(self._h, BLOCKS.index(name), _ptr(out), _stream()), "gfcc_export")
+        return out
+
+    # ---------------------------------------------------------------- sigma
+    def sigma(self, X, precision="fp64"):
+        import torch
+        X = X.to(device=self.device, dtype=torch.complex128).contiguous()
+        squeeze = X.dim() == 1
+        if squeeze:
+            X = X[None]
+        assert X.shape[-1] == self.dim
+        Y = torch.empty_like(X)
+        _check(self._lib.gfcc_sigma(self._h, X.shape[0], _ptr(X), _ptr(Y), PRECISIONS[precision], _stream()),
+               "gfcc_sigma")
+        return Y[0] if squeeze else Y
+
+    # ---------------------------------------------------------------- solve
+    def solve(self, p: Sequence[int], omega: Sequence[float], eta: float, q: Optional[Sequence[int]] = None,
+              tol=1e-8, restart=30, max_iter=2000, batch=0, precond="jacobi", precision="fp64",
+              use_graph=False, want_x=False):
+        """Returns (G [nrhs, nq] complex128 device tensor, info list of dicts, X or None)."""
+        import torch
+        p_h = np.ascontiguousarray(np.asarray(p, dtype=np.int64))
+        w_h = np.ascontiguousarray(np.asarray(omega, dtype=np.float64))
+        assert p_h.shape == w_h.shape
+        n = p_h.size
+        if q is None:
+            q_h, nq = None, 1
+        else:
+            q_h = np.ascontiguousarray(np.asarray(q, dtype=np.int64))
+            nq = q_h.size
+        G = torch.zeros((n, nq), dtype=torch.complex128, device=self.device)
+        X = torch.zeros((n, self.dim), dtype=torch.complex128, device=self.device) if want_x else None
+        info = (RhsInfo * max(n, 1))()
+        opts = SolveOpts(ctypes.sizeof(SolveOpts), tol, restart, max_iter, batch, PRECONDS[precond],
+                         PRECISIONS[precision], int(use_graph), None)
+        st = self._lib.gfcc_solve_batch(
+            self._h, n, p_h.ctypes.data_as(ctypes.c_void_p), w_h.ctypes.data_as(ctypes.c_void_p), eta, nq,
+            q_h.ctypes.data_as(ctypes.c_void_p) if q_h is not None else None, ctypes.byref(opts), _ptr(G),
+            _ptr(X), info, _stream())
+        _check(st, "gfcc_solve_batch")
+        infos = [dict(status=info[r].status, iters=info[r].iters, restarts=info[r].restarts,
+                      true_rel_resid=info[r].true_rel_resid) for r in range(n)]
+        return G, infos, X
+
+    def greens(self, X, q):
+        import torch
+        X = X.to(device=self.device, dtype=torch.complex128).contiguous()
+        q_h = np.ascontiguousarray(np.asarray(q, dtype=np.int64))
+        G = torch.empty((X.shape[0], q_h.size), dtype=torch.complex128, device=self.device)
+        _check(self._lib.gfcc_greens(self._h, X.shape[0], _ptr(X), q_h.size, q_h.ctypes.data_as(ctypes.c_void_p),
+                                     _ptr(G), _stream()), "gfcc_greens")
+        return G
+
+    # ---------------------------------------------------------------- timing
+    def prof_enable(self, on=True):
+        _check(self._lib.gfcc_prof_enable(self._h, int(on)), "gfcc_prof_enable")
+
+    def prof_get(self, name):
+        c, ms, fl, by = ctypes.c_int64(), ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        _check(self._lib.gfcc_prof_get(self._h, name.encode(), ctypes.byref(c), ctypes.byref(ms), ctypes.byref(fl),
+                                       ctypes.byref(by)), "gfcc_prof_get")
+        return dict(count=c.value, ms=ms.value, flops=fl.value, bytes=by.value)

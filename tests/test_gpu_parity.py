@@ -1,0 +1,192 @@
+"""GPU parity of the HIP path against the CPU oracle (through the C ABI).
+
+Tolerances: FP64 quantities 1e-12 relative to the block's max magnitude
+(intermediates, sigma; rounding of O(K) sums in different order), G from
+solves at tol 1e-12 within 1e-10 relative (the FP64 parity bar).
+"""
+import numpy as np
+import pytest
+
+from oracle import ipgfcc as O
+from synth import make_system, make_workload, random_vectors
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2010_04768_amd import gfcc  # noqa: E402
+
+# shapes spanning: tiny, odd sizes (unaligned rows), several GEMM tiles with ragged tails
+SHAPES = [(1, 1, 2), (2, 3, 4), (3, 5, 7), (5, 7, 9), (8, 40, 60), (12, 45, 50)]
+
+
+def _sys(o, v, Q, seed=7, **kw):
+    return make_system(o, v, Q, 1000 + seed + 13 * o + v, sigma_L=0.12, sigma_t1=0.02, **kw)
+
+
+def _rel(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+@pytest.fixture(scope="module")
+def cache():
+    return {}
+
+
+def _get(cache, shape):
+    if shape not in cache:
+        s = _sys(*shape)
+        im = O.intermediates(s)
+        ctx = gfcc.Context.from_system(s)
+        cache[shape] = (s, im, ctx)
+    return cache[shape]
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_intermediates_match_oracle(cache, shape):
+    s, im, ctx = _get(cache, shape)
+    pairs = [("FOO", "Foo"), ("FVV", "Fvv"), ("FOV", "Fov"), ("WOOOO", "Woooo"), ("WOOOV", "Wooov"),
+             ("WOVOO", "Wovoo"), ("WOVVO", "Wovvo"), ("WOVOV", "Wovov")]
+    for blk, key in pairs:
+        got = ctx.export(blk).cpu().numpy()
+        assert got.shape == im[key].shape, blk
+        assert _rel(got, im[key]) < 1e-12, (blk, _rel(got, im[key]))
+    assert _rel(ctx.export("DIAG").cpu().numpy(), O.diagonal(im)) < 1e-12
+    C = np.stack([O.left_vector(s, q) for q in range(s.n_occ)])
+    assert _rel(ctx.export("LEFT").cpu().numpy(), C) < 1e-12
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_sigma_fp64_matches_oracle(cache, shape):
+    s, im, ctx = _get(cache, shape)
+    X = random_vectors(5, s.dim, seed=3)
+    Y = ctx.sigma(torch.from_numpy(X)).cpu().numpy()
+    Yref = O.sigma(im, X)
+    assert _rel(Y, Yref) < 1e-12, _rel(Y, Yref)
+
+
+@pytest.mark.parametrize("shape", [(5, 7, 9), (8, 40, 60), (12, 45, 50)])
+@pytest.mark.parametrize("prec,bound", [("fp32", 1e-5), ("bf16", 2e-2)])
+def test_sigma_reduced_precision_bound(cache, shape, prec, bound):
+    """Reduced-precision two-body terms: error stated relative to the FP64 result."""
+    s, im, ctx = _get(cache, shape)
+    X = random_vectors(3, s.dim, seed=4)
+    Y = ctx.sigma(torch.from_numpy(X), precision=prec).cpu().numpy()
+    Yref = O.sigma(im, X)
+    err = np.linalg.norm(Y - Yref) / np.linalg.norm(Yref)
+    assert err < bound, err
+
+
+def test_sigma_batch_chunking_and_linearity(cache):
+    s, im, ctx = _get(cache, (8, 40, 60))
+    X = random_vectors(70, s.dim, seed=9)  # > one internal chunk of 64 vectors
+    Y = ctx.sigma(torch.from_numpy(X)).cpu().numpy()
+    assert _rel(Y, O.sigma(im, X)) < 1e-12
+    Y1 = ctx.sigma(torch.from_numpy(X[:1])).cpu().numpy()
+    assert _rel(Y1[0], Y[0]) < 1e-14
+
+
+def test_greens_bilinear(cache):
+    s, im, ctx = _get(cache, (5, 7, 9))
+    X = random_vectors(4, s.dim, seed=5)
+    q = [0, 4, 2]
+    G = ctx.greens(torch.from_numpy(X), q).cpu().numpy()
+    C = np.stack([O.left_vector(s, qq) for qq in q])
+    assert _rel(G, X @ C.T) < 1e-12
+
+
+@pytest.mark.parametrize("precond", ["jacobi", "none"])
+def test_solve_tiny_workload(precond):
+    """4 occupied x 6 omega on the o=4, v=16 system, all G_pp, tol 1e-12."""
+    wl = make_workload("tiny-o4v16")
+    s = wl.systems[0]
+    im = O.intermediates(s)
+    ctx = gfcc.Context.from_system(s)
+    pl = [int(p) for p in wl.p_lists[0] for _ in wl.omegas[0]]
+    wlist = [float(w) for _ in wl.p_lists[0] for w in wl.omegas[0]]
+    G, info, X = ctx.solve(pl, wlist, wl.eta, tol=1e-12, precond=precond, want_x=True)
+    G = G.cpu().numpy()[:, 0]
+    for r, (p, w) in enumerate(zip(pl, wlist)):
+        assert info[r]["status"] == 0 and info[r]["true_rel_resid"] <= 1e-12, info[r]
+        x, _, _ = O.solve(s, im, p, w, wl.eta, tol=1e-13)
+        gref = O.left_vector(s, p) @ x
+        assert abs(G[r] - gref) <= 1e-10 * abs(gref), (r, G[r], gref)
+    ctx.close()
+
+
+def test_solve_offdiagonal_q_and_x():
+    s = _sys(5, 7, 9)
+    im = O.intermediates(s)
+    ctx = gfcc.Context.from_system(s)
+    p = [4, 1, 3]
+    w = [-0.5, -0.9, -0.3]
+    q = [0, 1, 2, 3, 4]
+    G, info, X = ctx.solve(p, w, 0.02, q=q, tol=1e-12, want_x=True)
+    G = G.cpu().numpy()
+    X = X.cpu().numpy()
+    C = np.stack([O.left_vector(s, qq) for qq in q])
+    for r in range(3):
+        x, _, _ = O.solve(s, im, p[r], w[r], 0.02, tol=1e-13)
+        assert _rel(X[r], x) < 1e-10
+        assert _rel(G[r], C @ x) < 1e-10
+
+
+def test_solve_batch_independence_and_refill():
+    """Results do not depend on batch size (slot refill) beyond roundoff."""
+    s = _sys(8, 40, 60)
+    ctx = gfcc.Context.from_system(s)
+    rng = np.random.default_rng(0)
+    p = rng.integers(0, 8, size=13)
+    w = rng.uniform(-1.2, -0.3, size=13)
+    G1, i1, _ = ctx.solve(p, w, 0.01, tol=1e-12, batch=13)
+    G2, i2, _ = ctx.solve(p, w, 0.01, tol=1e-12, batch=3)
+    G3, _, _ = ctx.solve(p[5:6], w[5:6], 0.01, tol=1e-12, batch=1)
+    assert all(i["status"] == 0 for i in i1 + i2)
+    assert _rel(G1.cpu().numpy(), G2.cpu().numpy()) < 1e-10
+    assert abs(G3.cpu().numpy()[0, 0] - G1.cpu().numpy()[5, 0]) <= 1e-10 * abs(G3.cpu().numpy()[0, 0])
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_solve_mixed_precision_ir(prec):
+    """GMRES-IR with reduced-precision sigma reaches the FP64 tolerance."""
+    s = _sys(8, 40, 60)
+    im = O.intermediates(s)
+    ctx = gfcc.Context.from_system(s)
+    p = [7, 2, 0]
+    w = [-0.4, -0.8, -1.1]
+    G, info, _ = ctx.solve(p, w, 0.01, tol=1e-10, precision=prec)
+    G = G.cpu().numpy()[:, 0]
+    for r in range(3):
+        assert info[r]["status"] == 0 and info[r]["true_rel_resid"] <= 1e-10, info[r]
+        x, _, _ = O.solve(s, im, p[r], w[r], 0.01, tol=1e-13)
+        gref = O.left_vector(s, p[r]) @ x
+        assert abs(G[r] - gref) <= 1e-8 * abs(gref)
+
+
+def test_free_particle_closed_form():
+    """T = Lambda = L = 0: G_pp = 1/(omega - eps_p - i eta) exactly; eta < 0 conjugates."""
+    s = make_system(4, 16, 48, 21, t1=False, t2=False, lam=False, L_zero=True)
+    ctx = gfcc.Context.from_system(s)
+    p = [0, 1, 2, 3]
+    w = [-1.0, -0.7, -0.5, -0.2]
+    for eta in (0.01, -0.01):
+        G, info, _ = ctx.solve(p, w, eta, tol=1e-13)
+        G = G.cpu().numpy()[:, 0]
+        for r in range(4):
+            want = 1.0 / (w[r] - s.eps[p[r]] - 1j * eta)
+            assert abs(G[r] - want) <= 1e-12 * abs(want)
+
+
+def test_argument_errors():
+    s = _sys(2, 3, 4)
+    ctx = gfcc.Context.from_system(s)
+    with pytest.raises(gfcc.GfccError):
+        ctx.solve([5], [-0.5], 0.01)  # p out of range
+    with pytest.raises(gfcc.GfccError):
+        ctx.solve([0], [-0.5], 0.01, q=[9])
+    G, info, _ = ctx.solve([], [], 0.01)
+    assert G.shape[0] == 0
