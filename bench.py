@@ -1,0 +1,223 @@
+"""Benchmark of the IP-GFCCSD linear-solve path on one MI355X.
+
+One step = one pass of the whole path over the 40-occupied / 200-virtual /
+800-Cholesky-vector synthetic system: build the intermediates on the GPU
+(gfcc_build_intermediates), then solve (omega + Hbar_N - i eta) X_p = e_p for
+all 40 occupied p at 64 frequencies (2560 right-hand sides) and form G_pp.
+Inputs (eps, L, T1, T2) are resident in HBM before the timed region.
+
+Metric: omega-points/s, counting an omega point only if every G_pp at that
+omega agrees with an FP64 reference solve (tol 1e-11) to relative error
+<= 1e-8.  Also reported: sigma ring-GEMM TFLOP/s against the MFMA peak of the
+precision used, and the CPU oracle timed on a bounded sample.
+
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--form bf16|fp32|fp64]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {"fp64": 78.6e12, "fp32": 157.3e12, "bf16": 2.5e15}
+DTYPE = {"fp64": "f64", "fp32": "f32+f64", "bf16": "bf16+f64"}
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--form", default="bf16", choices=["bf16", "fp32", "fp64"])
+    ap.add_argument("--precond", default="jacobi", choices=["jacobi", "none", "mlp"])
+    ap.add_argument("--batch", type=int, default=0)
+    ap.add_argument("--restart", type=int, default=30)
+    ap.add_argument("--n-omega", type=int, default=64, help="reduce only for exploration")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-baseline", action="store_true", help="skip the plain FP64 batched baseline")
+    ap.add_argument("--profile-run", action="store_true",
+                    help="no reference/baseline/cpu (for rocprofv3)")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="after the steps, copy a 256 MiB buffer 3 times (HBM counter calibration)")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); every right-hand side is "
+              "independent, so more GPUs would each take a share of the (p, omega) queue.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_2010_04768_amd import gfcc
+    from synth import make_workload
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    wl = make_workload("plain-o40v200", n_omega=args.n_omega)
+    s = wl.systems[0]
+    omegas = wl.omegas[0]
+    plist = wl.p_lists[0]
+    P = np.repeat(plist, len(omegas))
+    W = np.tile(omegas, len(plist))
+    n_rhs = P.size
+    dev = torch.device("cuda", 0)
+    eps_d = torch.from_numpy(s.eps).to(dev)
+    L_d = torch.from_numpy(s.L).to(dev)
+    t1_d = torch.from_numpy(s.t1).to(dev)
+    t2_d = torch.from_numpy(s.t2).to(dev)
+    torch.cuda.synchronize()
+    log(f"system o={s.n_occ} v={s.n_vir} Q={s.n_chol} D={s.dim}, {n_rhs} RHS")
+
+    def run_step(form, precond, tol, prof=False):
+        t0 = time.perf_counter()
+        ctx = gfcc.Context(eps_d, L_d, t1_d, t2_d)
+        t1 = time.perf_counter()
+        if prof:
+            ctx.prof_enable(True)
+        G, info, _ = ctx.solve(P, W, wl.eta, tol=tol, restart=args.restart, max_iter=3000, batch=args.batch,
+                               precond=precond, precision=form)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        pr = ({k: ctx.prof_get(k) for k in ("ring_gemm_fp64", "ring_gemm_fp32", "ring_gemm_bf16", "sigma",
+                                             "arnoldi")} if prof else None)
+        ctx.close()
+        return G.cpu().numpy()[:, 0], info, t1 - t0, t2 - t1, pr
+
+    # reference (untimed): FP64, tighter tolerance
+    if not args.profile_run:
+        log("reference solve (fp64, tol 1e-11)")
+        Gref, iref, _, tref, _ = run_step("fp64", "jacobi", 1e-11)
+        log(f"reference done in {tref:.1f}s, mean iters {np.mean([i['iters'] for i in iref]):.1f}")
+    else:
+        Gref = None
+
+    form = args.form
+    times, builds, solves = [], [], []
+    for it in range(args.warmup + args.steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        G, info, tb, ts, pr = run_step(form, args.precond, wl.tol, prof=(it == args.warmup + args.steps - 1))
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        tag = "warmup" if it < args.warmup else "step"
+        log(f"{tag} {it}: {dt:.2f}s (build {tb:.2f}s, solve {ts:.2f}s)")
+        if it >= args.warmup:
+            times.append(dt)
+            builds.append(tb)
+            solves.append(ts)
+    if args.copy_calib:
+        a = torch.empty(32 * 1024 * 1024, dtype=torch.float64, device=dev).fill_(1.0)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log("copy calibration: 3 x 256 MiB device-to-device copies")
+    step = max(times) if times else float("nan")
+    iters = np.array([i["iters"] for i in info])
+    restarts = np.array([i["restarts"] for i in info])
+    conv = np.array([i["status"] == 0 for i in info])
+
+    if Gref is not None:
+        rel = np.abs(G - Gref) / np.abs(Gref)
+        ok_w = np.all((rel <= 1e-8).reshape(len(plist), len(omegas)) & conv.reshape(len(plist), len(omegas)),
+                      axis=0)
+        n_ok = int(ok_w.sum())
+        max_rel = float(rel.max())
+    else:
+        n_ok, max_rel = len(omegas), None
+    value = n_ok / step
+
+    # dominant kernel: the ring-GEMM precision class with the largest total time
+    rings = {k[len("ring_gemm_"):]: v for k, v in (pr or {}).items() if k.startswith("ring_gemm_") and v["count"]}
+    dom = max(rings, key=lambda k: rings[k]["ms"]) if rings else form
+    ring = rings.get(dom, {"count": 0, "ms": 0.0, "flops": 0.0})
+    achieved = ring["flops"] / (ring["ms"] * 1e-3) if ring["ms"] > 0 else 0.0
+    avg_ms = ring["ms"] / max(ring["count"], 1)
+    kernels = {f"ring_gemm_{k}": {"launches": v["count"], "total_ms": v["ms"],
+                                  "tflops": v["flops"] / max(v["ms"], 1e-9) / 1e9} for k, v in rings.items()}
+
+    out = {
+        "metric": "omega-points/sec at G(omega) rel err<=1e-8",
+        "value": value,
+        "unit": "omega-points/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": step * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": DTYPE[form],
+        "data": "synthetic",
+        "config": {"workload": "plain-o40v200 (n_occ=40 n_vir=200 N_chol=800, 40 p x 64 omega, eta=0.01)",
+                   "n_rhs": int(n_rhs), "dim": int(s.dim), "form": form, "precond": args.precond,
+                   "restart": args.restart, "tol": wl.tol, "batch": args.batch},
+        "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK[dom] / 1e12,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK[dom], "traffic": None,
+                     "kernel": f"ring GEMM {dom} (gemm_kernel)", "avg_launch_ms": avg_ms,
+                     "launches": ring["count"]},
+        "kernels": kernels,
+        "omega_points_ok": n_ok,
+        "g_max_rel_err_vs_fp64_ref": max_rel,
+        "build_s": float(np.mean(builds)) if builds else None,
+        "solve_s": float(np.mean(solves)) if solves else None,
+        "solve_only_omega_points_per_s": n_ok / max(solves) if solves else None,
+        "iters_mean": float(iters.mean()),
+        "iters_max": int(iters.max()),
+        "restarts_mean": float(restarts.mean()),
+        "converged": int(conv.sum()),
+    }
+
+    if not args.no_baseline and not args.profile_run and form != "fp64":
+        log("plain FP64 batched baseline (1 step)")
+        Gb, ib, tbb, tsb, _ = run_step("fp64", args.precond, wl.tol)
+        relb = np.abs(Gb - Gref) / np.abs(Gref)
+        convb = np.array([i["status"] == 0 for i in ib])
+        okb = int(np.all((relb <= 1e-8).reshape(len(plist), len(omegas)) & convb.reshape(len(plist), len(omegas)),
+                         axis=0).sum())
+        out["fp64_baseline"] = {"omega_points_per_s": okb / (tbb + tsb), "step_s": tbb + tsb,
+                                "iters_mean": float(np.mean([i["iters"] for i in ib]))}
+        out["speedup_vs_fp64_baseline"] = value / out["fp64_baseline"]["omega_points_per_s"]
+
+    if not args.no_cpu and not args.profile_run:
+        out["cpu_baseline"] = cpu_baseline(s, float(iters.mean() + restarts.mean() + 1.0), len(plist),
+                                           len(omegas), wl.eta)
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(s, sigmas_per_rhs, n_p, n_omega, eta):
+    """The CPU oracle on a bounded sample: its intermediates build on the full
+    system plus 3 GMRES iterations (sigma + MGS) of one right-hand side.
+    omega-points/s = n_omega / (t_build + n_p * n_omega * sigmas_per_rhs * t_iter)."""
+    from oracle import ipgfcc as O
+    threads = os.cpu_count()
+    log(f"cpu oracle sample on {threads} host threads")
+    t0 = time.perf_counter()
+    im = O.intermediates(s)
+    t_build = time.perf_counter() - t0
+    A = O.shifted_operator(im, -0.75, eta)
+    t0 = time.perf_counter()
+    _, its, _ = O.gmres(A, O.rhs(s, s.n_occ - 1), tol=1e-30, restart=30, max_iter=3)
+    t_iter = (time.perf_counter() - t0) / (its + 2)  # 3 inner steps + initial and final residual sigmas
+    total = t_build + n_p * n_omega * sigmas_per_rhs * t_iter
+    log(f"cpu oracle: build {t_build:.1f}s, {t_iter:.2f}s per sigma+MGS step")
+    return {"value": n_omega / total, "unit": "omega-points/s", "cores": threads, "kind": "oracle",
+            "sample": f"oracle intermediates on the full system ({t_build:.1f}s) + 3 GMRES steps of one "
+                      f"right-hand side ({t_iter:.2f}s/step), scaled by {sigmas_per_rhs:.1f} sigma "
+                      f"applications per right-hand side (GPU-measured) x {n_p * n_omega} right-hand sides"}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,7 +1,7 @@
 /*
  * gfcc.h -- C ABI of the MI355X IP-GFCCSD linear-solve library (libgfcc.so).
  *
- * Operation (arXiv 2010.04768, Sec. 2): for occupied orbitals p, q and real
+ * Operation (arXiv 2010.04768, Theory section): for occupied orbitals p, q and real
  * frequencies omega, the retarded ionisation (IP) term of the coupled-cluster
  * Green's function in the GFCCSD truncation,
  *
@@ -14,7 +14,7 @@
  *   b_p     = abar_p |Phi>  (= the 1h unit vector e_p for occupied p),
  *   c_q     = <Phi|(1 + Lambda) abar_q^+ restricted to the same space,
  * with T and Lambda truncated at singles and doubles.  The systems are solved
- * by restarted GMRES (Sec. 3), optionally right-preconditioned.
+ * by restarted GMRES (GFCC Workflow and Bottlenecks section), optionally right-preconditioned.
  *
  * Closed-shell spin-adapted basis, dimension D = o + o*o*v:
  *     x[0 .. o)                     = r_i     (1h)
@@ -61,14 +61,14 @@ typedef enum { GFCC_FP64 = 0, GFCC_FP32_IR = 1, GFCC_BF16_IR = 2 } gfcc_precisio
 
 typedef enum {
   GFCC_PC_NONE = 0,   /* plain GMRES */
-  GFCC_PC_JACOBI = 1, /* right preconditioner 1/(omega - i eta + diag(Hbar_N)) (Sec. 3) */
+  GFCC_PC_JACOBI = 1, /* right preconditioner 1/(omega - i eta + diag(Hbar_N)) (Workflow section) */
   GFCC_PC_MLP = 2     /* learned residual->correction network, flexible GMRES; Jacobi fallback */
 } gfcc_precond;
 
 /* One closed-shell system.  Device pointers, FP64, borrowed for the call.
  *   eps [n]            orbital energies (Fock matrix diag(eps)), occupied first
  *   L   [Q][n][n]      Cholesky vectors, symmetric in (p,q):
- *                      (pq|rs) = sum_Q L[Q][p][q] L[Q][r][s]   (Sec. 5, Cholesky ERIs)
+ *                      (pq|rs) = sum_Q L[Q][p][q] L[Q][r][s]   (Implementation Details: Cholesky ERIs)
  *   t1  [o][v], t2 [o][o][v][v]   ground-state amplitudes t_i^a, t_ij^ab
  *                      (t2[i][j][a][b] = t2[j][i][b][a])
  *   l1, l2             Lambda amplitudes in the same layout; NULL means
@@ -86,7 +86,7 @@ typedef struct {
 /* Build the per-system intermediates (blocks of Hbar_N, its exact diagonal,
  * the left vectors c_q for all occupied q, and reduced-precision copies) on
  * the GPU; the paper precomputes these constant intermediates before the
- * GFCC loop (Sec. 5).  Blocking.  *out receives a new context. */
+ * GFCC loop (Implementation Details).  Blocking.  *out receives a new context. */
 gfcc_status gfcc_build_intermediates(const gfcc_system* sys, void* stream, gfcc_ctx** out);
 
 /* Dimensions of the context: D = o + o*o*v, o, v. Host pointers; any may be NULL. */
@@ -119,6 +119,8 @@ typedef struct {
   gfcc_precision precision;
   int32_t use_graph;        /* capture one inner iteration in a hipGraph and replay it */
   const char* tune_cache;   /* host path of the tile autotuner JSON cache; NULL = no tuning */
+  double ir_inner_rtol;     /* GMRES-IR: inner cycle stops at this fraction of the cycle's starting
+                               residual; 0 = default for the precision (ignored for FP64) */
 } gfcc_solve_opts;
 
 /* Per right-hand side result (host memory). status: 0 converged, 1 max_iter,
@@ -148,7 +150,8 @@ gfcc_status gfcc_greens(gfcc_ctx* ctx, int64_t nrhs, const double* X, int64_t nq
 
 /* Kernel timing of the library's launches with HIP events on the launch
  * stream.  enable != 0 starts recording (clears totals).  For a kernel class
- * name ("ring_gemm", "sigma", "arnoldi", "precond", "mlp") gfcc_prof_get
+ * name ("ring_gemm_fp64", "ring_gemm_fp32", "ring_gemm_bf16" -- the three ring
+ * GEMMs of sigma --, "sigma", "arnoldi", "mlp") gfcc_prof_get
  * returns the number of launches, total milliseconds and algorithmic flops and
  * bytes summed over them (host outputs).  Blocking. */
 gfcc_status gfcc_prof_enable(gfcc_ctx* ctx, int enable);

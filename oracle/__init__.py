@@ -10,7 +10,7 @@ generator in ``synth``.
   de-excitation operators as determinant matrices and forms the connected
   similarity-transformed Hamiltonian, the ket ``abar_p|Phi>`` and the bra
   ``<Phi|(1+Lambda) abar_q^dagger`` directly from their definitions (paper,
-  Sec. 2, eqs. for G_pq in the bi-orthogonal CC form and its compact form).
+  Theory section, eqs. for G_pq in the bi-orthogonal CC form and its compact form).
 * ``oracle.ipgfcc`` -- O2: a matrix-free spin-adapted closed-shell
   implementation (intermediates, sigma product, diagonal, left vectors,
   GMRES, Green's function), pinned against O1 and closed forms.

@@ -9,11 +9,11 @@ system it builds, as dense matrices over Slater determinants,
   with ``h = f - sum_K <PK||QK>`` so that the Fock operator of the reference
   determinant is ``f = diag(eps)``;
 * the cluster operator ``T = T1 + T2`` and ``Lambda = Lambda1 + Lambda2``
-  (paper, Sec. 2: T, Lambda truncated at the two-body level, GFCCSD);
+  (paper, Theory: T, Lambda truncated at the two-body level, GFCCSD);
 * ``exp(+-T)`` by the finite power series (T is nilpotent).
 
 It then forms, for every basis operator ``R_mu`` of the 1h + 2h1p ionised
-space (paper, Sec. 2, expansion of X_p: one-hole ``a_i`` and two-hole
+space (paper, Theory, expansion of X_p: one-hole ``a_i`` and two-hole
 one-particle ``a_a^+ a_j a_i`` terms),
 
 * the connected similarity-transformed Hamiltonian matrix

@@ -2,7 +2,7 @@
 
 TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``).
 
-What it computes (paper, Sec. 2):
+What it computes (paper, Theory section):
 
 * the retarded IP term of the GFCC Green's function,
   ``G_qp(omega) = c_q^T X_p`` with ``(omega + Hbar_N - i eta) X_p = b_p``
@@ -10,7 +10,7 @@ What it computes (paper, Sec. 2):
   truncation at one- and two-body T, Lambda and X), using the bilinear
   (non-conjugated) product of the model-order-reduction equations;
 * ``Hbar_N`` restricted to the 1h + 2h1p space of X_p;
-* GMRES (Sec. 3: the minimal-residual Krylov solver chosen for these
+* GMRES (GFCC Workflow and Bottlenecks: the minimal-residual Krylov solver chosen for these
   non-Hermitian systems, residual non-increasing, at most dim-many steps;
   the inverse diagonal of the Hamiltonian as the classic preconditioner).
 
@@ -38,7 +38,7 @@ def einsum(*a):
 
 
 # --------------------------------------------------------------------------
-# integrals and intermediates (built once per system, paper Sec. 5: constant
+# integrals and intermediates (built once per system, paper, Implementation Details: constant
 # intermediates of size <= O(o^2 v^2) precomputed before the GFCC loop)
 # --------------------------------------------------------------------------
 
@@ -137,7 +137,7 @@ def intermediates(sys, g=None):
 
 
 # --------------------------------------------------------------------------
-# sigma product  sigma = Hbar_N x  (paper Sec. 3: the per-iteration O(o^3 v^2) work)
+# sigma product  sigma = Hbar_N x  (paper, GFCC Workflow and Bottlenecks: O(o^3 v^2) per iteration)
 # --------------------------------------------------------------------------
 
 def split(x, o, v):

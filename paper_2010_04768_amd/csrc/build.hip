@@ -1,7 +1,7 @@
 // Per-system intermediates of the IP-GFCCSD sigma product, built on the GPU.
 //
 // The paper precomputes constant intermediates of size <= O(o^2 v^2) before
-// the GFCC loop (Sec. 5) and evaluates the GFCCSD equations (Sec. 2, T and
+// the GFCC loop (Implementation Details) and evaluates the GFCCSD equations (Theory, T and
 // Lambda at the two-body level, X_p in the 1h + 2h1p space) as tensor
 // contractions of T1/T2 with Cholesky-decomposed integrals.  The closed-shell
 // spin-adapted blocks of the connected Hbar_N built here are
@@ -273,6 +273,12 @@ void build_intermediates(gfcc_ctx* c, const gfcc_system* sys, hipStream_t s) {
                       {o * v * c->o_pad, v * c->o_pad, c->o_pad, 1});  // [i][j][a][m]
     const int p[4] = {2, 3, 1, 0};
     permute(Wovoo, p, 1.0, t, 0.0, s);
+  }
+  c->FooT.ensure(o * c->o_pad * 8, s);
+  {
+    TView f = tview_s(c->FooT.as<double>(), {o, o}, {c->o_pad, 1});
+    const int tr[2] = {1, 0};
+    permute(Foo, tr, 1.0, f, 0.0, s);
   }
   c->FvvM.ensure(v * c->vp * 8, s);
   {

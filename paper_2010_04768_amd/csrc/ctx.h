@@ -32,6 +32,7 @@ struct gfcc_ctx {
   gfcc::DBuf t2p;     // [(i,j,a)][vp]    t2p[(i,j,a)][e] = t2[i,j,e,a]
   gfcc::DBuf WovooT;  // [(i,j,a)][o_pad] WovooT[(i,j,a)][m] = Wovoo[m,a,i,j]
   gfcc::DBuf FvvM;    // [a][vp]
+  gfcc::DBuf FooT;    // [i][o_pad]       FooT[i][m] = Foo[m,i]
   gfcc::DBuf Uop;     // [o][Dp]          1h rows of Hbar_N over a plane
   gfcc::DBuf diag;    // [Dp]             exact diagonal (1.0 in padding)
   gfcc::DBuf left;    // [o][Dp]          c_q rows

@@ -16,6 +16,8 @@
 // workgroup -> tile map keeps consecutive tiles on one XCD (workgroups are
 // dealt round-robin over the 8 XCDs) and walks tile-rows in groups so that
 // concurrently running tiles share operand panels in that XCD's L2.
+#include <algorithm>
+
 #include "gfcc_internal.h"
 
 namespace gfcc {
@@ -58,7 +60,7 @@ __device__ __forceinline__ int64_t rmap(const RowMap& m, int64_t r) {
   return (r / m.div) * m.hi + (r % m.div) * m.lo;
 }
 
-template <typename T, int BM, int BN, bool VEC>
+template <typename T, int BM, int BN, bool VEC, bool BNC>
 __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
   using MF = Mfma<T>;
   constexpr int EPC = 16 / int(sizeof(T));   // elements per 16-byte chunk
@@ -95,8 +97,11 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
   const int64_t i0 = tm * BM, j0 = tn * BN;
 
   const int z = blockIdx.z;
-  const T* A = static_cast<const T*>(g.A) + z * g.a_bs;
-  const T* B = static_cast<const T*>(g.B) + z * g.b_bs;
+  const int64_t kbase = g.k_split > 0 ? z * g.k_split : 0;
+  const int64_t Kz = g.k_split > 0 ? ((g.K - kbase) < g.k_split ? (g.K - kbase) : g.k_split) : g.K;
+  const T* A = static_cast<const T*>(g.A) + (g.k_split > 0 ? kbase : rmap(g.az, z));
+  const T* B = static_cast<const T*>(g.B) + (g.k_split > 0 ? (BNC ? 0 : kbase) : rmap(g.bz, z));
+  const int64_t bk0 = (g.k_split > 0 && BNC) ? kbase : 0;  // K offset of B rows when N-contiguous
 
   // ---- per-thread fetch rows (fixed across the K loop)
   const int lrow = tid >> 3;        // 0..31
@@ -110,19 +115,24 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
 #pragma unroll
   for (int p = 0; p < PB; ++p) {
     int64_t j = j0 + lrow + p * RPP;
-    boff[p] = (j < g.N) ? rmap(g.bm, j) : -1;
+    boff[p] = (!BNC && j < g.N) ? rmap(g.bm, j) : -1;
   }
+  // N-contiguous B: thread loads EPC consecutive j of one K-row
+  constexpr int NCH = BN / EPC;            // chunks per K-row
+  constexpr int KPP = 256 / NCH;           // K-rows per pass
+  constexpr int PBN = BNC ? (BK + KPP - 1) / KPP : 1;
+  const int nk_row = tid / NCH, nj_ch = tid % NCH;
 
-  u4 ra[PA], rb[PB];
+  u4 ra[PA], rb[BNC ? PBN : PB];
   auto fetch = [&](const T* base, int64_t off, int64_t k) -> u4 {
     u4 v = {0u, 0u, 0u, 0u};
     if (off < 0) return v;
-    if (VEC && k + EPC <= g.K) {
+    if (VEC && k + EPC <= Kz) {
       v = *reinterpret_cast<const u4*>(base + off + k);
     } else {
       T tmp[EPC];
 #pragma unroll
-      for (int e = 0; e < EPC; ++e) tmp[e] = (k + e < g.K) ? base[off + k + e] : T(0);
+      for (int e = 0; e < EPC; ++e) tmp[e] = (k + e < Kz) ? base[off + k + e] : T(0);
       v = *reinterpret_cast<const u4*>(tmp);
     }
     return v;
@@ -131,16 +141,50 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
     const int64_t k = k0 + lchunk * EPC;
 #pragma unroll
     for (int p = 0; p < PA; ++p) ra[p] = fetch(A, aoff[p], k);
+    if constexpr (!BNC) {
 #pragma unroll
-    for (int p = 0; p < PB; ++p) rb[p] = fetch(B, boff[p], k);
+      for (int p = 0; p < PB; ++p) rb[p] = fetch(B, boff[p], k);
+    } else {
+#pragma unroll
+      for (int p = 0; p < PBN; ++p) {
+        const int kr = nk_row + p * KPP;
+        const int64_t kk = k0 + kr;
+        const int64_t j = j0 + nj_ch * EPC;
+        u4 v = {0u, 0u, 0u, 0u};
+        if (kr < BK && kk < Kz && j < g.N) {
+          const T* row = B + rmap(g.bm, bk0 + kk);
+          if (VEC && j + EPC <= g.N) {
+            v = *reinterpret_cast<const u4*>(row + j);
+          } else {
+            T tmp[EPC];
+#pragma unroll
+            for (int e = 0; e < EPC; ++e) tmp[e] = (j + e < g.N) ? row[j + e] : T(0);
+            v = *reinterpret_cast<const u4*>(tmp);
+          }
+        }
+        rb[p] = v;
+      }
+    }
   };
   auto store_tiles = [&]() {
 #pragma unroll
     for (int p = 0; p < PA; ++p)
       *reinterpret_cast<u4*>(&As[(lrow + p * RPP) * LDK + lchunk * EPC]) = ra[p];
+    if constexpr (!BNC) {
 #pragma unroll
-    for (int p = 0; p < PB; ++p)
-      *reinterpret_cast<u4*>(&Bs[(lrow + p * RPP) * LDK + lchunk * EPC]) = rb[p];
+      for (int p = 0; p < PB; ++p)
+        *reinterpret_cast<u4*>(&Bs[(lrow + p * RPP) * LDK + lchunk * EPC]) = rb[p];
+    } else {
+#pragma unroll
+      for (int p = 0; p < PBN; ++p) {
+        const int kr = nk_row + p * KPP;
+        if (kr < BK) {
+          const T* v = reinterpret_cast<const T*>(&rb[p]);
+#pragma unroll
+          for (int e = 0; e < EPC; ++e) Bs[(nj_ch * EPC + e) * LDK + kr] = v[e];
+        }
+      }
+    }
   };
 
   typename MF::acc_t acc[FM][FN];
@@ -149,7 +193,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
 #pragma unroll
     for (int b = 0; b < FN; ++b) acc[a][b] = typename MF::acc_t{0, 0, 0, 0};
 
-  const int nk = int((g.K + BK - 1) / BK);
+  const int nk = int((Kz + BK - 1) / BK);
   load_tiles(0);
   const int fr = lane & 15;          // fragment row within a 16-block
   const int fk = (lane >> 4) * FE;   // fragment K offset
@@ -175,7 +219,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
   }
 
   // ---- epilogue
-  double* C = g.C + z * g.c_bs;
+  double* C = g.C + rmap(g.cz, z);
   const int jl = lane & 15;
   const int ih = lane >> 4;
 #pragma unroll
@@ -201,12 +245,19 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
 template <typename T, int BM, int BN>
 static void launch(const GemmArgs& a, bool vec, hipStream_t s) {
   const int64_t tiles = ((a.M + BM - 1) / BM) * ((a.N + BN - 1) / BN);
-  GFCC_CHECK(tiles < (int64_t(1) << 31), GFCC_E_ARG, "GEMM grid too large");
+  GFCC_CHECK(tiles < (int64_t(1) << 31) && a.batch < 65536, GFCC_E_ARG, "GEMM grid too large");
   dim3 grid(unsigned(tiles), 1, unsigned(a.batch));
-  if (vec)
-    hipLaunchKernelGGL((gemm_kernel<T, BM, BN, true>), grid, dim3(256), 0, s, a);
-  else
-    hipLaunchKernelGGL((gemm_kernel<T, BM, BN, false>), grid, dim3(256), 0, s, a);
+  if (a.b_ncontig) {
+    if (vec)
+      hipLaunchKernelGGL((gemm_kernel<T, BM, BN, true, true>), grid, dim3(256), 0, s, a);
+    else
+      hipLaunchKernelGGL((gemm_kernel<T, BM, BN, false, true>), grid, dim3(256), 0, s, a);
+  } else {
+    if (vec)
+      hipLaunchKernelGGL((gemm_kernel<T, BM, BN, true, false>), grid, dim3(256), 0, s, a);
+    else
+      hipLaunchKernelGGL((gemm_kernel<T, BM, BN, false, false>), grid, dim3(256), 0, s, a);
+  }
   GFCC_HIP(hipGetLastError());
 }
 
@@ -223,6 +274,61 @@ static void dispatch(const GemmArgs& a, int cfg, bool vec, hipStream_t s) {
 
 static bool aligned_map(const RowMap& m, int64_t epc) {
   return (m.hi % epc) == 0 && (m.lo % epc) == 0;
+}
+
+// C(i,j) = alpha * sum_z part[z][i][j] + beta * C(i,j)
+__global__ void splitk_reduce_kernel(const double* __restrict__ part, int slices, int64_t M, int64_t N, double* C,
+                                     RowMap cm, RowMap cn, double alpha, double beta) {
+  const int64_t MN = M * N;
+  for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < MN; t += int64_t(gridDim.x) * blockDim.x) {
+    double acc = 0.0;
+    for (int z = 0; z < slices; ++z) acc += part[z * MN + t];
+    const int64_t i = t / N, j = t % N;
+    double* p = C + rmap(cm, i) + rmap(cn, j);
+    const double v = alpha * acc;
+    *p = (beta == 0.0) ? v : v + beta * (*p);
+  }
+}
+
+int splitk_slices(int64_t M, int64_t N, int64_t K) {
+  const int cfg = gemm_default_cfg(M, N, K);
+  const int64_t bm = (cfg == TILE_128x128 || cfg == TILE_128x64) ? 128 : 64;
+  const int64_t bn = (cfg == TILE_128x128 || cfg == TILE_64x128) ? 128 : 64;
+  const int64_t tiles = ((M + bm - 1) / bm) * ((N + bn - 1) / bn);
+  if (tiles >= 256 || K < 2048) return 1;
+  int64_t sl = std::min<int64_t>((512 + tiles - 1) / tiles, K / 1024);
+  return int(std::max<int64_t>(1, std::min<int64_t>(sl, 256)));
+}
+
+void gemm_splitk(Prec p, const GemmArgs& a, int slices, double* part, hipStream_t s) {
+  if (a.M <= 0 || a.N <= 0) return;
+  GemmArgs g = a;
+  const int64_t epc = (p == Prec::F64) ? 2 : (p == Prec::F32 ? 4 : 8);
+  g.k_split = round_up((a.K + slices - 1) / slices, 8 * epc);
+  const int nsl = int((a.K + g.k_split - 1) / g.k_split);
+  g.batch = nsl;
+  g.C = part;
+  g.cm = lin(a.N);
+  g.cn = lin(1);
+  g.cz = lin(a.M * a.N);
+  g.alpha = 1.0;
+  g.beta = 0.0;
+  gemm(p, g, gemm_default_cfg(a.M, a.N, a.K), s);
+  const int64_t MN = a.M * a.N;
+  const unsigned nb = unsigned(std::min<int64_t>((MN + 255) / 256, 4096));
+  hipLaunchKernelGGL(splitk_reduce_kernel, dim3(nb), dim3(256), 0, s, part, nsl, a.M, a.N, a.C, a.cm, a.cn,
+                     a.alpha, a.beta);
+  GFCC_HIP(hipGetLastError());
+}
+
+void gemm_auto(Prec p, const GemmArgs& a, Scratch& scr, int scr_slot, hipStream_t s) {
+  const int sl = (a.batch == 1) ? splitk_slices(a.M, a.N, a.K) : 1;
+  if (sl <= 1) {
+    gemm(p, a, gemm_default_cfg(a.M, a.N, a.K), s);
+    return;
+  }
+  double* part = scr.get(scr_slot, int64_t(sl) * a.M * a.N, s);
+  gemm_splitk(p, a, sl, part, s);
 }
 
 const char* tile_name(int cfg) {
@@ -245,9 +351,9 @@ void gemm(Prec p, const GemmArgs& a, int cfg, hipStream_t s) {
   GFCC_CHECK(a.am.div > 0 && a.bm.div > 0 && a.cm.div > 0 && a.cn.div > 0, GFCC_E_ARG, "bad row map");
   const int64_t esz = (p == Prec::F64) ? 8 : (p == Prec::F32 ? 4 : 2);
   const int64_t epc = 16 / esz;
-  const bool vec = aligned_map(a.am, epc) && aligned_map(a.bm, epc) && (a.a_bs % epc == 0) &&
-                   (a.b_bs % epc == 0) && (reinterpret_cast<uintptr_t>(a.A) % 16 == 0) &&
-                   (reinterpret_cast<uintptr_t>(a.B) % 16 == 0);
+  const bool vec = aligned_map(a.am, epc) && aligned_map(a.bm, epc) && aligned_map(a.az, epc) &&
+                   aligned_map(a.bz, epc) && (reinterpret_cast<uintptr_t>(a.A) % 16 == 0) &&
+                   (reinterpret_cast<uintptr_t>(a.B) % 16 == 0) && (a.k_split % epc == 0);
   switch (p) {
     case Prec::F64: dispatch<double>(a, cfg, vec, s); break;
     case Prec::F32: dispatch<float>(a, cfg, vec, s); break;

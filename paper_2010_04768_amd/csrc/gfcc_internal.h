@@ -82,17 +82,21 @@ enum class Prec : int { F64 = 0, F32 = 1, BF16 = 2 };
 
 struct GemmArgs {
   const void* A = nullptr;  // element type given by Prec
-  RowMap am{};
-  int64_t a_bs = 0;         // batch stride (elements)
+  RowMap am{};              // row i of A starts at am(i); K contiguous
   const void* B = nullptr;
-  RowMap bm{};
-  int64_t b_bs = 0;
+  RowMap bm{};              // b_ncontig == 0: row j of B at bm(j), K contiguous
+                            // b_ncontig == 1: K-row k of B at bm(k), N contiguous
+  int b_ncontig = 0;
   double* C = nullptr;
   RowMap cm{}, cn{};
-  int64_t c_bs = 0;
+  RowMap az{int64_t(1) << 40, 0, 0}, bz{int64_t(1) << 40, 0, 0}, cz{int64_t(1) << 40, 0, 0};  // batch offsets
   int64_t M = 0, N = 0, K = 0;
   int batch = 1;
   double alpha = 1.0, beta = 0.0;
+  // split-K: when > 0, grid.z indexes K slices of this length; slice z reads
+  // columns [z*k_split, min(K, (z+1)*k_split)) and writes its partial sum to
+  // C + cz(z) with alpha = 1, beta = 0 (batch must then equal the slice count)
+  int64_t k_split = 0;
 };
 
 // Tile configurations; the autotuner picks one per (shape, precision).
@@ -100,6 +104,10 @@ enum TileCfg : int { TILE_128x128 = 0, TILE_64x64 = 1, TILE_128x64 = 2, TILE_64x
 const char* tile_name(int cfg);
 
 void gemm(Prec p, const GemmArgs& a, int cfg, hipStream_t s);
+// GEMM whose tile grid is too small to fill the GPU: split K over `slices`,
+// reduce the partials (deterministic order) into C with alpha/beta.
+void gemm_splitk(Prec p, const GemmArgs& a, int slices, double* part, hipStream_t s);
+int splitk_slices(int64_t M, int64_t N, int64_t K);
 // heuristic choice when no tuned entry exists
 int gemm_default_cfg(int64_t M, int64_t N, int64_t K);
 
@@ -131,6 +139,9 @@ struct Scratch {
     return b[slot].as<double>();
   }
 };
+
+// gemm, or gemm_splitk with partials in scr slot `scr_slot` when the tile grid is small
+void gemm_auto(Prec p, const GemmArgs& a, Scratch& scr, int scr_slot, hipStream_t s);
 
 // Pairwise contraction  C[c] = alpha * sum A[a] B[b] + beta * C[c]  in FP64 on
 // MFMA.  `spec` is "ab..,cd..->ef.." with single-letter labels; every label is

@@ -1,5 +1,5 @@
 // sigma = Hbar_N x for a batch of vectors (the per-iteration O(o^3 v^2) work
-// of the GFCCSD linear solver, paper Sec. 3 / Alg. 1 singles and doubles).
+// of the GFCCSD linear solver, paper: GFCC Workflow and Bottlenecks, Algorithm 1 singles and doubles).
 //
 // Closed-shell spin-adapted IP-EOM form, r1[i], r2[i,j,a]:
 //   s1[i]     = -sum_m Foo[m,i] r1[m] + sum_me Fov[m,e](2 r2[i,m,e] - r2[m,i,e])
@@ -59,23 +59,6 @@ __global__ void make_ra_kernel(const double* __restrict__ x, T* __restrict__ Ra,
   for (int k = threadIdx.y; k < 32; k += 8) {
     const int64_t a = c0 + k, r = r0 + threadIdx.x;
     if (a < v && r < oo) Ra[(p * v + a) * op2 + r] = cvt<T>(tile[threadIdx.x][k]);
-  }
-}
-
-// y2[p][i][j][a] -= sum_m Foo[m,i] x2[p][m][j][a] + Foo[m,j] x2[p][i][m][a]
-__global__ void foo_terms_kernel(const double* __restrict__ x, double* __restrict__ y,
-                                 const double* __restrict__ Foo, int64_t o, int64_t v, int64_t Dp,
-                                 int64_t o_pad) {
-  const int64_t oov = o * o * v, ov = o * v;
-  const int64_t p = blockIdx.y;
-  const double* xp = x + p * Dp + o_pad;
-  double* yp = y + p * Dp + o_pad;
-  for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < oov; t += int64_t(gridDim.x) * blockDim.x) {
-    const int64_t a = t % v, j = (t / v) % o, i = t / ov;
-    double acc = 0.0;
-    for (int64_t m = 0; m < o; ++m)
-      acc += Foo[m * o + i] * xp[m * ov + j * v + a] + Foo[m * o + j] * xp[i * ov + m * v + a];
-    yp[t] -= acc;
   }
 }
 
@@ -141,6 +124,7 @@ void sigma_planes(gfcc_ctx* c, int64_t P, const double* x, double* y, gfcc_preci
   const double sZm = lowp ? 1.0 / L.sZm : 1.0;
 
   const double ring_flops = 2.0 * double(P) * double(o) * double(ov) * double(ov);
+  const char* ring_name = !lowp ? "ring_gemm_fp64" : (li ? "ring_gemm_bf16" : "ring_gemm_fp32");
   const double ring_bytes = double(ov) * double(kp) * esz + 2.0 * double(P) * double(o) * double(ov) * (esz + 8.0);
 
   // ---- ring terms
@@ -156,8 +140,6 @@ void sigma_planes(gfcc_ctx* c, int64_t P, const double* x, double* y, gfcc_preci
     // P1a
     if (lowp) {
       g.A = c->ws_R.p;
-      g.am = lin(ov);
-      g.a_bs = 0;
       g.am = two(o, ps, ov);
     } else {
       g.A = x + op;
@@ -167,26 +149,26 @@ void sigma_planes(gfcc_ctx* c, int64_t P, const double* x, double* y, gfcc_preci
     g.bm = lin(kp);
     g.alpha = sX1;
     g.beta = 0.0;
-    prof_begin(c, "ring_gemm", s);
+    prof_begin(c, ring_name, s);
     gemm(rp, g, cfg, s);
-    prof_end(c, "ring_gemm", s, ring_flops, ring_bytes);
+    prof_end(c, ring_name, s, ring_flops, ring_bytes);
     // P1b
     g.A = c->ws_RT.p;
     g.am = two(o, ps, ov);
     g.B = Wvo;
     g.alpha = -sWvo;
     g.beta = 1.0;
-    prof_begin(c, "ring_gemm", s);
+    prof_begin(c, ring_name, s);
     gemm(rp, g, cfg, s);
-    prof_end(c, "ring_gemm", s, ring_flops, ring_bytes);
+    prof_end(c, ring_name, s, ring_flops, ring_bytes);
     // P2: rows (p, j), cols (i, a) -> s2[p][i][j][a]
     g.B = Wov;
     g.alpha = -sWov;
     g.cm = two(o, Dp, v);
     g.cn = two(v, ov, 1);
-    prof_begin(c, "ring_gemm", s);
+    prof_begin(c, ring_name, s);
     gemm(rp, g, cfg, s);
-    prof_end(c, "ring_gemm", s, ring_flops, ring_bytes);
+    prof_end(c, ring_name, s, ring_flops, ring_bytes);
   }
   // ---- hole-hole ladder: s2[p][(i,j)][a] += sum_(mn) W4T[(i,j)][(m,n)] Ra[(p,a)][(m,n)]
   {
@@ -225,7 +207,7 @@ void sigma_planes(gfcc_ctx* c, int64_t P, const double* x, double* y, gfcc_preci
     g.cn = lin(1);
     g.alpha = sZm;
     g.beta = 0.0;
-    gemm(rp, g, gemm_default_cfg(g.M, g.N, g.K), s);
+    gemm_auto(rp, g, c->scr, 0, s);
     GemmArgs h;
     h.A = c->ws_z.p;
     h.am = lin(c->vp);
@@ -276,9 +258,49 @@ void sigma_planes(gfcc_ctx* c, int64_t P, const double* x, double* y, gfcc_preci
     gemm(Prec::F64, g, gemm_default_cfg(g.M, g.N, g.K), s);
   }
   // ---- occupied one-body terms (FP64)
-  hipLaunchKernelGGL(foo_terms_kernel, dim3(blocks_for(oov), unsigned(P)), dim3(256), 0, s, x, y,
-                     c->Foo.as<double>(), o, v, Dp, op);
-  GFCC_HIP(hipGetLastError());
+  //   s2[p][i][(j,a)] -= sum_m FooT[i][m] x2[p][m][(j,a)]     (batch over planes)
+  //   s2[p][i][j][a]  -= sum_m FooT[j][m] x2[p][i][m][a]      (batch over planes and i)
+  {
+    GemmArgs g;
+    g.A = c->FooT.p;
+    g.am = lin(c->o_pad);
+    g.B = x + op;
+    g.b_ncontig = 1;
+    g.bm = lin(ov);
+    g.bz = lin(Dp);
+    g.C = y + op;
+    g.cm = lin(ov);
+    g.cn = lin(1);
+    g.cz = lin(Dp);
+    g.M = o;
+    g.N = ov;
+    g.K = o;
+    g.batch = int(P);
+    g.alpha = -1.0;
+    g.beta = 1.0;
+    gemm(Prec::F64, g, TILE_64x128, s);
+    const int64_t zmax = 60000;
+    for (int64_t z0 = 0; z0 < P * o; z0 += zmax) {
+      GemmArgs h;
+      h.A = c->FooT.p;
+      h.am = lin(c->o_pad);
+      h.B = x + op + (z0 / o) * Dp;
+      h.b_ncontig = 1;
+      h.bm = lin(v);
+      h.bz = two(o, Dp, ov);
+      h.C = y + op + (z0 / o) * Dp;
+      h.cm = lin(v);
+      h.cn = lin(1);
+      h.cz = two(o, Dp, ov);
+      h.M = o;
+      h.N = v;
+      h.K = o;
+      h.batch = int(std::min(zmax, P * o - z0));
+      h.alpha = -1.0;
+      h.beta = 1.0;
+      gemm(Prec::F64, h, TILE_64x128, s);
+    }
+  }
   // ---- 1h rows: s1[p][i] = sum_k x[p][k] Uop[i][k]   (FP64)
   {
     GemmArgs g;
@@ -294,7 +316,7 @@ void sigma_planes(gfcc_ctx* c, int64_t P, const double* x, double* y, gfcc_preci
     g.cn = lin(1);
     g.alpha = 1.0;
     g.beta = 0.0;
-    gemm(Prec::F64, g, gemm_default_cfg(g.M, g.N, g.K), s);
+    gemm_auto(Prec::F64, g, c->scr, 0, s);
   }
   const double total_flops = 3.0 * ring_flops + 2.0 * double(P) * (double(oo) * oo * v + 2.0 * oov * v +
                                                                     double(oov) * v + double(oov) * o +
@@ -367,7 +389,7 @@ void greens_planes(gfcc_ctx* c, int64_t nb, const double* planes, int64_t nq, co
   g.cn = lin(2);
   g.alpha = 1.0;
   g.beta = 0.0;
-  gemm(Prec::F64, g, gemm_default_cfg(g.M, g.N, g.K), s);
+  gemm_auto(Prec::F64, g, c->scr, 0, s);
 }
 
 // ------------------------------------------------------------------ timing

@@ -1,5 +1,5 @@
 // Batched restarted GMRES / flexible GMRES for (omega + Hbar_N - i eta) X_p = b_p
-// (paper Sec. 3: GMRES, minimal residual, non-increasing residual; the inverse
+// (paper, GFCC Workflow and Bottlenecks: GMRES, minimal residual, non-increasing residual; the inverse
 // diagonal of the Hamiltonian as the classic preconditioner).
 //
 // A persistent window of `batch` slots holds one right-hand side each.  Every
@@ -11,7 +11,7 @@
 // sigma, and either restarts the slot, or finishes it -- G_qp = c_q^T X is
 // formed right away and the slot is refilled from the queue of (p, omega)
 // pairs (the paper's dynamic pickup of the next orbital by an idle process
-// group, Sec. 5, here at slot granularity).
+// group, Implementation Details, here at slot granularity).
 //
 // Orthogonalisation is classical Gram-Schmidt applied twice (CGS2), FP64,
 // with the complex inner product <u, w> = sum conj(u) w.  Givens rotations as
@@ -528,8 +528,8 @@ struct HostSlot {
 
 static double lp_cycle_rtol(gfcc_precision p) {
   switch (p) {
-    case GFCC_FP32_IR: return 1e-5;
-    case GFCC_BF16_IR: return 2e-3;
+    case GFCC_FP32_IR: return 1e-6;
+    case GFCC_BF16_IR: return 1e-4;
     default: return 0.0;
   }
 }
@@ -613,7 +613,8 @@ void solve_batch(gfcc_ctx* c, int64_t nrhs, const int64_t* p, const double* omeg
   }
 
   const double tol = opts->tol;
-  const double rtol_lp = lp_cycle_rtol(prec);
+  const double rtol_lp = (prec == GFCC_FP64) ? 0.0
+                         : (opts->ir_inner_rtol > 0.0 ? opts->ir_inner_rtol : lp_cycle_rtol(prec));
   std::vector<HostSlot> hs(B);
   std::vector<int> free_slots;
   for (int i = B - 1; i >= 0; --i) free_slots.push_back(i);

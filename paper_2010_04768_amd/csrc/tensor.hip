@@ -232,7 +232,7 @@ void ein(const char* spec, double alpha, const TView& A, const TView& B, double 
     g.cn = lin(1);
     g.alpha = alpha;
     g.beta = beta;
-    gemm(Prec::F64, g, gemm_default_cfg(M, N, K), s);
+    gemm_auto(Prec::F64, g, scr, 3, s);
     return;
   }
   double* tmp = scr.get(2, M * N, s);
@@ -241,7 +241,7 @@ void ein(const char* spec, double alpha, const TView& A, const TView& B, double 
   g.cn = lin(1);
   g.alpha = 1.0;
   g.beta = 0.0;
-  gemm(Prec::F64, g, gemm_default_cfg(M, N, K), s);
+  gemm_auto(Prec::F64, g, scr, 3, s);
   // permute-accumulate tmp[ml nl] into C[lc]
   std::string tl = ml + nl;
   TView tv;

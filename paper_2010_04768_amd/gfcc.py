@@ -37,7 +37,8 @@ class GfccSystem(ctypes.Structure):
 class SolveOpts(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_size_t), ("tol", ctypes.c_double), ("restart", ctypes.c_int32),
                 ("max_iter", ctypes.c_int32), ("batch", ctypes.c_int32), ("precond", ctypes.c_int),
-                ("precision", ctypes.c_int), ("use_graph", ctypes.c_int32), ("tune_cache", ctypes.c_char_p)]
+                ("precision", ctypes.c_int), ("use_graph", ctypes.c_int32), ("tune_cache", ctypes.c_char_p),
+                ("ir_inner_rtol", ctypes.c_double)]
 
 
 class RhsInfo(ctypes.Structure):
@@ -175,7 +176,7 @@ class Context:
     # ---------------------------------------------------------------- solve
     def solve(self, p: Sequence[int], omega: Sequence[float], eta: float, q: Optional[Sequence[int]] = None,
               tol=1e-8, restart=30, max_iter=2000, batch=0, precond="jacobi", precision="fp64",
-              use_graph=False, want_x=False):
+              use_graph=False, want_x=False, ir_inner_rtol=0.0):
         """Returns (G [nrhs, nq] complex128 device tensor, info list of dicts, X or None)."""
         import torch
         p_h = np.ascontiguousarray(np.asarray(p, dtype=np.int64))
@@ -191,7 +192,7 @@ class Context:
         X = torch.zeros((n, self.dim), dtype=torch.complex128, device=self.device) if want_x else None
         info = (RhsInfo * max(n, 1))()
         opts = SolveOpts(ctypes.sizeof(SolveOpts), tol, restart, max_iter, batch, PRECONDS[precond],
-                         PRECISIONS[precision], int(use_graph), None)
+                         PRECISIONS[precision], int(use_graph), None, ir_inner_rtol)
         st = self._lib.gfcc_solve_batch(
             self._h, n, p_h.ctypes.data_as(ctypes.c_void_p), w_h.ctypes.data_as(ctypes.c_void_p), eta, nq,
             q_h.ctypes.data_as(ctypes.c_void_p) if q_h is not None else None, ctypes.byref(opts), _ptr(G),

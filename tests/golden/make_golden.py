@@ -1,7 +1,7 @@
 """Write tests/golden/bruteforce_o3v4.json from the Fock-space brute force only.
 
 The paper prints no numerical Green's-function values for any system, so this
-fixture is generated here: G_qp(omega) of the retarded IP term (paper, Sec. 2,
+fixture is generated here: G_qp(omega) of the retarded IP term (paper, Theory section,
 compact GFCC expression with the X_p linear system) for one tiny synthetic
 system, computed by ``oracle.fockspace`` (no working equations).  Run from the
 repository root:  python tests/golden/make_golden.py
@@ -31,7 +31,7 @@ def main():
             for q in range(s.n_occ):
                 g = bf.greens_so(w, ETA, p, q)
                 rows.append({"omega": w, "p": p, "q": q, "re": g.real, "im": g.imag})
-    out = {"source": "oracle.fockspace brute force; paper Sec. 2 (compact GFCC form, IP term)",
+    out = {"source": "oracle.fockspace brute force; paper, Theory section (compact GFCC form, IP term)",
            "system": SPEC, "eta": ETA, "G_qp": rows}
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "bruteforce_o3v4.json")
     with open(path, "w") as f:

@@ -8,7 +8,7 @@
   fourth-order onset of the self-energy in L; G(-eta) = conj G(eta); linearity
   of G in Lambda; Lambda = 0 gives c_q = e_q; Schur-complement identity.
 * GMRES against a dense direct solve; residual monotone within a cycle and
-  convergence in at most dim steps without restart (paper, Sec. 3).
+  convergence in at most dim steps without restart (paper, GFCC Workflow and Bottlenecks).
 """
 import numpy as np
 import pytest
