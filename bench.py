@@ -25,6 +25,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK = {"fp64": 78.6e12, "fp32": 157.3e12, "bf16": 2.5e15}
+# HBM bytes per 128-slot ring-GEMM launch from rocprofv3 FETCH_SIZE / WRITE_SIZE passes
+# (profiles/ring_gemm_o40v200_bf16ir.md; copy-kernel scale 2.0 for FETCH_SIZE, 1.0 for
+# WRITE_SIZE).  Valid only for the GEMM source they were taken on.
+TRAFFIC = {"gemm_src_sha256_16": "0a178ee3242a1455",
+           "fp64": {"fetch_GB": 19.43, "write_GB": 0.71}, "bf16": {"fetch_GB": 5.19, "write_GB": 0.72}}
 DTYPE = {"fp64": "f64", "fp32": "f32+f64", "bf16": "bf16+f64"}
 
 
@@ -165,7 +170,7 @@ def main():
                    "n_rhs": int(n_rhs), "dim": int(s.dim), "form": form, "precond": args.precond,
                    "restart": args.restart, "tol": wl.tol, "batch": args.batch},
         "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK[dom] / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK[dom], "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK[dom], "traffic": traffic_for(dom),
                      "kernel": f"ring GEMM {dom} (gemm_kernel)", "avg_launch_ms": avg_ms,
                      "launches": ring["count"]},
         "kernels": kernels,
@@ -195,6 +200,18 @@ def main():
         out["cpu_baseline"] = cpu_baseline(s, float(iters.mean() + restarts.mean() + 1.0), len(plist),
                                            len(omegas), wl.eta)
     print(json.dumps(out), flush=True)
+
+
+def traffic_for(prec):
+    """Counter-measured bytes per 128-slot launch, or None if the GEMM kernel changed since."""
+    import hashlib
+    src = os.path.join(ROOT, "paper_2010_04768_amd", "csrc", "gemm.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    t = TRAFFIC.get(prec)
+    if sha != TRAFFIC["gemm_src_sha256_16"] or t is None:
+        return None
+    return {"fetch_bytes": t["fetch_GB"] * 1e9, "write_bytes": t["write_GB"] * 1e9,
+            "launch": "128 slots (M=10240, N=K=8000)"}
 
 
 def cpu_baseline(s, sigmas_per_rhs, n_p, n_omega, eta):
