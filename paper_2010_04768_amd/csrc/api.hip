@@ -109,6 +109,14 @@ gfcc_status gfcc_export(gfcc_ctx* c, gfcc_block which, double* dst, void* stream
         TView out = tview(dst, {o, v, o, v});
         const int id[4] = {0, 1, 2, 3};
         permute(in, id, 1.0, out, 0.0, s);
+        // remove the folded off-diagonal Foo term  d_ae Foo_off[m,j]
+        const int id3[3] = {0, 1, 2}, id2[2] = {0, 1};
+        TView foo_b = tview_s(c->Foo.as<double>(), {o, v, o}, {1, 0, o});
+        TView foo_d = tview_s(c->Foo.as<double>(), {o, v}, {o + 1, 0});
+        TView o_ae = tview_s(dst, {o, v, o}, {v, o * v + 1, v * o * v});  // [j][a][m] at [m][a][j][a]
+        TView o_d = tview_s(dst, {o, v}, {v * o * v + v, o * v + 1});      // m = j
+        permute(foo_b, id3, -1.0, o_ae, 1.0, s);
+        permute(foo_d, id2, 1.0, o_d, 1.0, s);
         break;
       }
       case GFCC_DIAG:

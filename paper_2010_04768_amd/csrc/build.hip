@@ -245,6 +245,41 @@ void build_intermediates(gfcc_ctx* c, const gfcc_system* sys, hipStream_t s) {
     permute(a, id, 2.0, x, 0.0, s);
     permute(b, id, -1.0, x, 1.0, s);
   }
+  // Fold the off-diagonal one-body terms into the ring operands (exact):
+  //   sum_e Fvv_off[a,e] r[i][j][e]   = sum_(m,e) d_jm Fvv_off[a,e] r[i][m][e]   -> X1 (P1a)
+  //  -sum_m Foo_off[m,j] r[i][m][a]   = sum_(m,e) -d_ae Foo_off[m,j] r[i][m][e]  -> X1 (P1a)
+  //  -sum_m Foo_off[m,i] r[m][j][a]   = -sum_(m,e) d_ae Foo_off[m,i] RT[j][m][e] -> Wov (P2, alpha -1)
+  // The diagonal one-body part (Fvv[a,a] - Foo[i,i] - Foo[j,j]) r[i][j][a] is applied
+  // elementwise in FP64 by the sigma operand kernel.
+  {
+    double* X1p = c->X1.as<double>();
+    double* Wovp = c->Wov.as<double>();
+    const int id3[3] = {0, 1, 2}, id2[2] = {0, 1};
+    TView fvv_b = tview_s(c->Fvv.as<double>(), {o, v, v}, {0, v, 1});
+    TView fvv_d = tview_s(c->Fvv.as<double>(), {o, v}, {0, v + 1});
+    TView x_jm = tview_s(X1p, {o, v, v}, {v * kp + v, kp, 1});  // [j][a][e], m = j
+    TView x_jd = tview_s(X1p, {o, v}, {v * kp + v, kp + 1});    // [j][a],    m = j, e = a
+    permute(fvv_b, id3, 1.0, x_jm, 1.0, s);
+    permute(fvv_d, id2, -1.0, x_jd, 1.0, s);
+    TView foo_b = tview_s(c->Foo.as<double>(), {o, v, o}, {1, 0, o});  // [j][a][m] -> Foo[m][j]
+    TView foo_d = tview_s(c->Foo.as<double>(), {o, v}, {o + 1, 0});    // [j][a]    -> Foo[j][j]
+    TView x_ae = tview_s(X1p, {o, v, o}, {v * kp, kp + 1, v});        // [j][a][m], e = a
+    permute(foo_b, id3, -1.0, x_ae, 1.0, s);
+    permute(foo_d, id2, 1.0, x_jd, 1.0, s);
+    TView w_ae = tview_s(Wovp, {o, v, o}, {v * kp, kp + 1, v});       // [i][a][m], e = a
+    TView w_id = tview_s(Wovp, {o, v}, {v * kp + v, kp + 1});          // [i][a],    m = i, e = a
+    permute(foo_b, id3, 1.0, w_ae, 1.0, s);
+    permute(foo_d, id2, -1.0, w_id, 1.0, s);
+  }
+  // diagonal one-body part over the 2h1p block: d1b[(i,j,a)] = Fvv[a,a] - Foo[i,i] - Foo[j,j]
+  c->d1b.ensure(oov * 8, s);
+  {
+    TView out = tview(c->d1b.as<double>(), {o, o, v});
+    const int id3[3] = {0, 1, 2};
+    permute(tview_s(c->Fvv.as<double>(), {o, o, v}, {0, 0, v + 1}), id3, 1.0, out, 0.0, s);
+    permute(tview_s(c->Foo.as<double>(), {o, o, v}, {o + 1, 0, 0}), id3, -1.0, out, 1.0, s);
+    permute(tview_s(c->Foo.as<double>(), {o, o, v}, {0, o + 1, 0}), id3, -1.0, out, 1.0, s);
+  }
 
   // ---- sigma operands
   c->W4T.ensure(oo * c->op2 * 8, s);

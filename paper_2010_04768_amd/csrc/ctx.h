@@ -33,6 +33,8 @@ struct gfcc_ctx {
   gfcc::DBuf WovooT;  // [(i,j,a)][o_pad] WovooT[(i,j,a)][m] = Wovoo[m,a,i,j]
   gfcc::DBuf FvvM;    // [a][vp]
   gfcc::DBuf FooT;    // [i][o_pad]       FooT[i][m] = Foo[m,i]
+  gfcc::DBuf d1b;     // [(i,j,a)]        Fvv[a,a] - Foo[i,i] - Foo[j,j]
+  // note: X1 and Wov also carry the off-diagonal one-body terms (see build.hip)
   gfcc::DBuf Uop;     // [o][Dp]          1h rows of Hbar_N over a plane
   gfcc::DBuf diag;    // [Dp]             exact diagonal (1.0 in padding)
   gfcc::DBuf left;    // [o][Dp]          c_q rows

@@ -30,16 +30,21 @@ template <> __device__ __forceinline__ float cvt<float>(double x) { return float
 template <> __device__ __forceinline__ __bf16 cvt<__bf16>(double x) { return __bf16(float(x)); }
 
 // RT[p][i*ov + m*v + e] = x[p*Dp + o_pad + m*ov + i*v + e]   (and R when R != nullptr)
+// and the FP64 diagonal one-body part  y2[p][t] = d1b[t] x2[p][t]  (initialises y2)
 template <typename T>
 __global__ void make_rt_kernel(const double* __restrict__ x, T* __restrict__ RT, T* __restrict__ R,
-                               int64_t o, int64_t v, int64_t Dp, int64_t o_pad, int64_t ps) {
+                               double* __restrict__ y, const double* __restrict__ d1b, int64_t o, int64_t v,
+                               int64_t Dp, int64_t o_pad, int64_t ps) {
   const int64_t oov = o * o * v, ov = o * v;
   const int64_t p = blockIdx.y;
   const double* xp = x + p * Dp + o_pad;
+  double* yp = y + p * Dp + o_pad;
   for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < oov; t += int64_t(gridDim.x) * blockDim.x) {
     const int64_t e = t % v, m = (t / v) % o, i = t / ov;  // output order [i][m][e]
     RT[p * ps + t] = cvt<T>(xp[m * ov + i * v + e]);
-    if (R) R[p * ps + t] = cvt<T>(xp[t]);
+    const double xt = xp[t];
+    if (R) R[p * ps + t] = cvt<T>(xt);
+    yp[t] = d1b[t] * xt;
   }
 }
 
@@ -75,11 +80,11 @@ static int ring_cfg(gfcc_ctx* c, Prec p, int64_t M, int64_t N, int64_t K) {
 }
 
 template <typename T>
-static void make_operands(gfcc_ctx* c, int64_t P, const double* x, T* RT, T* R, T* Ra, int64_t ps,
+static void make_operands(gfcc_ctx* c, int64_t P, const double* x, T* RT, T* R, T* Ra, int64_t ps, double* y,
                           hipStream_t s) {
   const int64_t oov = c->oov;
   hipLaunchKernelGGL((make_rt_kernel<T>), dim3(std::min<int64_t>((oov + 255) / 256, 1024), unsigned(P)),
-                     dim3(256), 0, s, x, RT, R, c->o, c->v, c->Dp, c->o_pad, ps);
+                     dim3(256), 0, s, x, RT, R, y, c->d1b.as<double>(), c->o, c->v, c->Dp, c->o_pad, ps);
   GFCC_HIP(hipGetLastError());
   dim3 g(unsigned((c->oo + 31) / 32), unsigned((c->v + 31) / 32), unsigned(P));
   hipLaunchKernelGGL((make_ra_kernel<T>), g, dim3(32, 8), 0, s, x, Ra, c->oo, c->v, c->Dp, c->o_pad, c->op2);
@@ -104,13 +109,14 @@ void sigma_planes(gfcc_ctx* c, int64_t P, const double* x, double* y, gfcc_preci
   prof_begin(c, "sigma", s);
   switch (rp) {
     case Prec::F64:
-      make_operands<double>(c, P, x, c->ws_RT.as<double>(), nullptr, c->ws_Ra.as<double>(), ps, s);
+      make_operands<double>(c, P, x, c->ws_RT.as<double>(), nullptr, c->ws_Ra.as<double>(), ps, y, s);
       break;
     case Prec::F32:
-      make_operands<float>(c, P, x, c->ws_RT.as<float>(), c->ws_R.as<float>(), c->ws_Ra.as<float>(), ps, s);
+      make_operands<float>(c, P, x, c->ws_RT.as<float>(), c->ws_R.as<float>(), c->ws_Ra.as<float>(), ps, y, s);
       break;
     case Prec::BF16:
-      make_operands<__bf16>(c, P, x, c->ws_RT.as<__bf16>(), c->ws_R.as<__bf16>(), c->ws_Ra.as<__bf16>(), ps, s);
+      make_operands<__bf16>(c, P, x, c->ws_RT.as<__bf16>(), c->ws_R.as<__bf16>(), c->ws_Ra.as<__bf16>(), ps, y,
+                             s);
       break;
   }
   const auto& L = c->lp[li];
@@ -148,7 +154,7 @@ void sigma_planes(gfcc_ctx* c, int64_t P, const double* x, double* y, gfcc_preci
     g.B = X1;
     g.bm = lin(kp);
     g.alpha = sX1;
-    g.beta = 0.0;
+    g.beta = 1.0;  // y2 holds the diagonal one-body part
     prof_begin(c, ring_name, s);
     gemm(rp, g, cfg, s);
     prof_end(c, ring_name, s, ring_flops, ring_bytes);
@@ -223,23 +229,6 @@ void sigma_planes(gfcc_ctx* c, int64_t P, const double* x, double* y, gfcc_preci
     h.beta = 1.0;
     gemm(Prec::F64, h, gemm_default_cfg(h.M, h.N, h.K), s);
   }
-  // ---- one-body virtual term: s2[p][(i,j)][a] += sum_e x2[p][(i,j)][e] Fvv[a][e]   (FP64)
-  {
-    GemmArgs g;
-    g.A = x + op;
-    g.am = two(oo, Dp, v);
-    g.B = c->FvvM.p;
-    g.bm = lin(c->vp);
-    g.M = P * oo;
-    g.N = v;
-    g.K = v;
-    g.C = y + op;
-    g.cm = two(oo, Dp, v);
-    g.cn = lin(1);
-    g.alpha = 1.0;
-    g.beta = 1.0;
-    gemm(Prec::F64, g, gemm_default_cfg(g.M, g.N, g.K), s);
-  }
   // ---- 2h1p <- 1h: s2[p][(i,j,a)] -= sum_m r1[p][m] WovooT[(i,j,a)][m]   (FP64)
   {
     GemmArgs g;
@@ -256,50 +245,6 @@ void sigma_planes(gfcc_ctx* c, int64_t P, const double* x, double* y, gfcc_preci
     g.alpha = -1.0;
     g.beta = 1.0;
     gemm(Prec::F64, g, gemm_default_cfg(g.M, g.N, g.K), s);
-  }
-  // ---- occupied one-body terms (FP64)
-  //   s2[p][i][(j,a)] -= sum_m FooT[i][m] x2[p][m][(j,a)]     (batch over planes)
-  //   s2[p][i][j][a]  -= sum_m FooT[j][m] x2[p][i][m][a]      (batch over planes and i)
-  {
-    GemmArgs g;
-    g.A = c->FooT.p;
-    g.am = lin(c->o_pad);
-    g.B = x + op;
-    g.b_ncontig = 1;
-    g.bm = lin(ov);
-    g.bz = lin(Dp);
-    g.C = y + op;
-    g.cm = lin(ov);
-    g.cn = lin(1);
-    g.cz = lin(Dp);
-    g.M = o;
-    g.N = ov;
-    g.K = o;
-    g.batch = int(P);
-    g.alpha = -1.0;
-    g.beta = 1.0;
-    gemm(Prec::F64, g, TILE_64x128, s);
-    const int64_t zmax = 60000;
-    for (int64_t z0 = 0; z0 < P * o; z0 += zmax) {
-      GemmArgs h;
-      h.A = c->FooT.p;
-      h.am = lin(c->o_pad);
-      h.B = x + op + (z0 / o) * Dp;
-      h.b_ncontig = 1;
-      h.bm = lin(v);
-      h.bz = two(o, Dp, ov);
-      h.C = y + op + (z0 / o) * Dp;
-      h.cm = lin(v);
-      h.cn = lin(1);
-      h.cz = two(o, Dp, ov);
-      h.M = o;
-      h.N = v;
-      h.K = o;
-      h.batch = int(std::min(zmax, P * o - z0));
-      h.alpha = -1.0;
-      h.beta = 1.0;
-      gemm(Prec::F64, h, TILE_64x128, s);
-    }
   }
   // ---- 1h rows: s1[p][i] = sum_k x[p][k] Uop[i][k]   (FP64)
   {

@@ -652,49 +652,55 @@ void solve_batch(gfcc_ctx* c, int64_t nrhs, const int64_t* p, const double* omeg
   refill();
   std::vector<int> hflags(B);
   std::vector<double> hres(B), hbeta(B);
-  while (!active.empty()) {
+  std::vector<int> pending;  // slots whose cycle ended, waiting for a batched finish
+  while (!active.empty() || !pending.empty()) {
     const int na = int(active.size());
-    upload(d_act, active, s);
-    const int* act = d_act.as<int>();
-    // 1. precondition
-    hipLaunchKernelGGL(precond_kernel, dim3(nch, na), dim3(VT), 0, s, d, act, c->ws_in.as<double>(),
-                       c->diag.as<double>(), mode, flex);
-    GFCC_HIP(hipGetLastError());
-    // 2. sigma
-    sigma_planes(c, 2 * na, c->ws_in.as<double>(), c->ws_out.as<double>(), prec, s);
-    // 3. Arnoldi (CGS2)
-    prof_begin(c, "arnoldi", s);
-    hipLaunchKernelGGL(arnoldi_kernel, dim3(nch, na), dim3(VT), 0, s, d, act, c->ws_in.as<double>(),
-                       c->ws_out.as<double>(), 0);
-    hipLaunchKernelGGL(reduce_h_kernel, dim3(na), dim3(MAXM + 1), 0, s, d, act, 0);
-    hipLaunchKernelGGL(arnoldi_kernel, dim3(nch, na), dim3(VT), 0, s, d, act, c->ws_in.as<double>(),
-                       c->ws_out.as<double>(), 1);
-    hipLaunchKernelGGL(reduce_h_kernel, dim3(na), dim3(MAXM + 1), 0, s, d, act, 1);
-    hipLaunchKernelGGL(arnoldi_kernel, dim3(nch, na), dim3(VT), 0, s, d, act, c->ws_in.as<double>(),
-                       c->ws_out.as<double>(), 2);
-    GFCC_HIP(hipGetLastError());
-    // 4. Givens + flags
-    int any_left = 0;
-    for (int a : active) any_left |= (hs[a].iters + 1 < opts->max_iter);
-    std::vector<int> lastcall(na);
-    for (int i = 0; i < na; ++i) lastcall[i] = (hs[active[i]].iters + 1 >= opts->max_iter);
-    hipLaunchKernelGGL(givens_kernel, dim3(na), dim3(64), 0, s, d, act, d_flags.as<int>(), d_res.as<double>(), 1);
-    hipLaunchKernelGGL(scale_kernel, dim3(nch, na), dim3(VT), 0, s, d, act);
-    GFCC_HIP(hipGetLastError());
-    prof_end(c, "arnoldi", s, 0.0, 0.0);
-    GFCC_HIP(hipMemcpyAsync(hflags.data(), d_flags.p, na * sizeof(int), hipMemcpyDeviceToHost, s));
-    GFCC_HIP(hipMemcpyAsync(hres.data(), d_res.p, na * 8, hipMemcpyDeviceToHost, s));
-    GFCC_HIP(hipStreamSynchronize(s));
-    (void)any_left;
-
-    std::vector<int> fin;
-    std::vector<int> fin_dense;
-    for (int i = 0; i < na; ++i) {
-      const int sl = active[i];
-      hs[sl].iters += 1;
-      if (hflags[i] != 0 || lastcall[i]) fin.push_back(sl);
+    if (na > 0) {
+      upload(d_act, active, s);
+      const int* act = d_act.as<int>();
+      // 1. precondition
+      hipLaunchKernelGGL(precond_kernel, dim3(nch, na), dim3(VT), 0, s, d, act, c->ws_in.as<double>(),
+                         c->diag.as<double>(), mode, flex);
+      GFCC_HIP(hipGetLastError());
+      // 2. sigma
+      sigma_planes(c, 2 * na, c->ws_in.as<double>(), c->ws_out.as<double>(), prec, s);
+      // 3. Arnoldi (CGS2)
+      prof_begin(c, "arnoldi", s);
+      hipLaunchKernelGGL(arnoldi_kernel, dim3(nch, na), dim3(VT), 0, s, d, act, c->ws_in.as<double>(),
+                         c->ws_out.as<double>(), 0);
+      hipLaunchKernelGGL(reduce_h_kernel, dim3(na), dim3(MAXM + 1), 0, s, d, act, 0);
+      hipLaunchKernelGGL(arnoldi_kernel, dim3(nch, na), dim3(VT), 0, s, d, act, c->ws_in.as<double>(),
+                         c->ws_out.as<double>(), 1);
+      hipLaunchKernelGGL(reduce_h_kernel, dim3(na), dim3(MAXM + 1), 0, s, d, act, 1);
+      hipLaunchKernelGGL(arnoldi_kernel, dim3(nch, na), dim3(VT), 0, s, d, act, c->ws_in.as<double>(),
+                         c->ws_out.as<double>(), 2);
+      GFCC_HIP(hipGetLastError());
+      // 4. Givens + flags
+      hipLaunchKernelGGL(givens_kernel, dim3(na), dim3(64), 0, s, d, act, d_flags.as<int>(), d_res.as<double>(), 1);
+      hipLaunchKernelGGL(scale_kernel, dim3(nch, na), dim3(VT), 0, s, d, act);
+      GFCC_HIP(hipGetLastError());
+      prof_end(c, "arnoldi", s, 0.0, 0.0);
+      GFCC_HIP(hipMemcpyAsync(hflags.data(), d_flags.p, na * sizeof(int), hipMemcpyDeviceToHost, s));
+      GFCC_HIP(hipMemcpyAsync(hres.data(), d_res.p, na * 8, hipMemcpyDeviceToHost, s));
+      GFCC_HIP(hipStreamSynchronize(s));
+      std::vector<int> still;
+      for (int i = 0; i < na; ++i) {
+        const int sl = active[i];
+        hs[sl].iters += 1;
+        if (hflags[i] != 0 || hs[sl].iters >= opts->max_iter)
+          pending.push_back(sl);
+        else
+          still.push_back(sl);
+      }
+      active.swap(still);
     }
-    if (fin.empty()) continue;
+    // finish cycles in groups: wait until half of the live slots are pending
+    // (slots advance in near lock-step, so this costs little latency) so the
+    // FP64 true-residual sigma runs on a wide batch
+    if (pending.empty()) continue;
+    if (!active.empty() && pending.size() * 2 < active.size() + pending.size()) continue;
+    std::vector<int> fin;
+    fin.swap(pending);
 
     // 5. finish the cycles of `fin`
     const int nf = int(fin.size());
@@ -772,10 +778,10 @@ void solve_batch(gfcc_ctx* c, int64_t nrhs, const int64_t* p, const double* omeg
       for (int sl : done) {
         hs[sl].rhs = -1;
         free_slots.push_back(sl);
-        active.erase(std::find(active.begin(), active.end(), sl));
       }
-      refill();
     }
+    for (int sl : again) active.push_back(sl);
+    refill();
   }
   GFCC_HIP(hipStreamSynchronize(s));
   *all_converged = ok_all;
