@@ -148,6 +148,70 @@ gfcc_status gfcc_solve_batch(gfcc_ctx* ctx, int64_t nrhs, const int64_t* p, cons
 gfcc_status gfcc_greens(gfcc_ctx* ctx, int64_t nrhs, const double* X, int64_t nq, const int64_t* q,
                         double* G, void* stream);
 
+/* ---------------------------------------------------------------------------
+ * Learned preconditioner (GFCC_PC_MLP).  An elementwise network corrects the
+ * Jacobi step of the classic diagonal preconditioner (GFCC Workflow and
+ * Bottlenecks section): per element d of a complex vector r, with
+ * z = omega - i eta, exact diagonal D of Hbar_N, sD = mean |D| and
+ * n = ||r|| / sqrt(D_dim),
+ *   features x_d = [Re rh, Im rh, Re jh, Im jh, D_d/sD - 1, omega, [d < o], 100 eta],
+ *     rh = r/n, jh = rh sD/(z + D)
+ *   y_d = W3 tanh(W2 tanh(W1 x_d + b1) + b2) + b3        (8 -> W -> W -> 2)
+ *   M(r)_d = r_d/(z + D_d) + (y_d0 + i y_d1) n/sD
+ * Flat parameter layout (FP64): W1[W][8], b1[W], W2[W][W], b2[W], W3[2][W], b3[2].
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  size_t struct_size;   /* sizeof(gfcc_mlp_opts) */
+  int32_t width;        /* hidden width W: 64, 128 or 256 */
+  int32_t steps;        /* Adam steps */
+  int32_t batch;        /* sampled elements per minibatch */
+  int32_t pair_restart; /* restart length of the data-generating FP64 Jacobi solves */
+  double lr;            /* Adam learning rate */
+  uint64_t seed;        /* initialisation and sampling seed */
+  int32_t max_pairs;    /* cap on stored (residual, error) pairs */
+  int32_t reserved;
+} gfcc_mlp_opts;
+
+typedef struct {
+  int64_t n_pairs;      /* (residual, error) pairs collected */
+  int32_t steps, reserved;
+  double loss_first;    /* minibatch loss at step 0 (zero output layer: the plain Jacobi step) */
+  double loss_final;    /* mean minibatch loss over the last 5% of steps */
+  double data_seconds, train_seconds;
+} gfcc_mlp_report;
+
+/* Train the network on pairs the solver generates itself: FP64 Jacobi GMRES
+ * solves of the given (p, omega) right-hand sides with restart length
+ * opts->pair_restart record, at every restart, the true residual r_k and the
+ * iterate x_k; after convergence e_k = X* - x_k (so A e_k = r_k).  Minibatches
+ * of elements are sampled on the GPU; loss = mean |y - t|^2 with
+ * t = e sD/n - jh; Adam.  p, omega, report: host.  Blocking. */
+gfcc_status gfcc_mlp_train(gfcc_ctx* ctx, int64_t nrhs, const int64_t* p, const double* omega, double eta,
+                           const gfcc_mlp_opts* opts, gfcc_mlp_report* report, void* stream);
+
+/* Load / read the flat FP64 parameter vector (device).  get: *width is set;
+ * params may be NULL to query the width only. */
+gfcc_status gfcc_mlp_set_weights(gfcc_ctx* ctx, int32_t width, const double* params, void* stream);
+gfcc_status gfcc_mlp_get_weights(gfcc_ctx* ctx, int32_t* width, double* params, void* stream);
+
+/* FP64 network on caller features: Y[n][2] from X[n][8] (device). */
+gfcc_status gfcc_mlp_forward(gfcc_ctx* ctx, int64_t n, const double* X, double* Y, void* stream);
+
+/* Minibatch loss and flat gradient of the FP64 network: loss device [1],
+ * grad device [n_params]. */
+gfcc_status gfcc_mlp_loss_grad(gfcc_ctx* ctx, int64_t n, const double* X, const double* T, double* loss,
+                               double* grad, void* stream);
+
+/* Features of complex vectors R [nvec][D] (device, interleaved) at the
+ * per-vector frequencies omega (host [nvec]): X [nvec*D][8] (device). */
+gfcc_status gfcc_mlp_features(gfcc_ctx* ctx, int64_t nvec, const double* R, const double* omega, double eta,
+                              double* X, void* stream);
+
+/* The preconditioner itself (fused BF16-MFMA inference kernel):
+ * U[v] = M(R[v]) for complex vectors R, U [nvec][D] (device, interleaved). */
+gfcc_status gfcc_mlp_apply(gfcc_ctx* ctx, int64_t nvec, const double* R, const double* omega, double eta,
+                           double* U, void* stream);
+
 /* Kernel timing of the library's launches with HIP events on the launch
  * stream.  enable != 0 starts recording (clears totals).  For a kernel class
  * name ("ring_gemm_fp64", "ring_gemm_fp32", "ring_gemm_bf16" -- the three ring

@@ -1,5 +1,7 @@
 // C ABI of libgfcc (see include/gfcc.h).  Argument checking, error capture
 // and dispatch to the build / sigma / solver / Green's-function code.
+#include <chrono>
+#include <cmath>
 #include <cstring>
 #include <exception>
 #include <string>
@@ -9,9 +11,6 @@
 namespace gfcc {
 static thread_local std::string g_last_error;
 void set_error(const std::string& msg) { g_last_error = msg; }
-void solve_batch(gfcc_ctx* c, int64_t nrhs, const int64_t* p, const double* omega, double eta, int64_t nq,
-                 const int64_t* q, const gfcc_solve_opts* opts, double* G, double* X, gfcc_rhs_info* info,
-                 hipStream_t s, bool* all_converged);
 }  // namespace gfcc
 
 using namespace gfcc;
@@ -196,10 +195,214 @@ gfcc_status gfcc_solve_batch(gfcc_ctx* c, int64_t nrhs, const int64_t* p, const 
     GFCC_CHECK(opts->tol > 0.0 && opts->restart >= 1 && opts->max_iter >= 1, GFCC_E_ARG, "bad tolerance/restart/max_iter");
     GFCC_CHECK(opts->precond >= GFCC_PC_NONE && opts->precond <= GFCC_PC_MLP, GFCC_E_ARG, "bad preconditioner");
     GFCC_CHECK(opts->precision >= GFCC_FP64 && opts->precision <= GFCC_BF16_IR, GFCC_E_ARG, "bad precision");
-    solve_batch(c, nrhs, p, omega, eta, nq, q, opts, G, X, info, as_stream(stream), &all_conv);
+    solve_batch(c, nrhs, p, omega, eta, nq, q, opts, G, X, info, as_stream(stream), &all_conv, nullptr);
   });
   if (st == GFCC_OK && !all_conv) return GFCC_W_NOCONV;
   return st;
+}
+
+// ---------------------------------------------------------------- learned preconditioner
+
+static double diag_mean_abs(gfcc_ctx* c, hipStream_t s) {
+  std::vector<double> h(size_t(c->Dp));
+  GFCC_HIP(hipMemcpyAsync(h.data(), c->diag.p, size_t(c->Dp) * 8, hipMemcpyDeviceToHost, s));
+  GFCC_HIP(hipStreamSynchronize(s));
+  double acc = 0.0;
+  for (int64_t i = 0; i < c->o; ++i) acc += std::fabs(h[size_t(i)]);
+  for (int64_t i = 0; i < c->oov; ++i) acc += std::fabs(h[size_t(c->o_pad + i)]);
+  return acc / double(c->D);
+}
+
+__global__ void rms_kernel(const double* __restrict__ planes, int64_t Dp, int64_t D, double* out) {
+  __shared__ double red[256];
+  const double* x = planes + int64_t(blockIdx.x) * 2 * Dp;
+  double acc = 0.0;
+  for (int64_t t = threadIdx.x; t < 2 * Dp; t += 256) acc += x[t] * x[t];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (int(threadIdx.x) < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[blockIdx.x] = sqrt(red[0] / double(D));
+}
+
+gfcc_status gfcc_mlp_set_weights(gfcc_ctx* c, int32_t width, const double* params, void* stream) {
+  return guarded([&] {
+    GFCC_CHECK(c && params, GFCC_E_ARG, "null argument");
+    hipStream_t s = as_stream(stream);
+    mlp_init(c, width, 0, s);
+    c->mlp->sD = diag_mean_abs(c, s);
+    GFCC_HIP(hipMemcpyAsync(c->mlp->params.p, params, size_t(mlp_n_params(width)) * 8, hipMemcpyDeviceToDevice, s));
+    mlp_prepare_inference(c, s);
+    GFCC_HIP(hipStreamSynchronize(s));
+  });
+}
+
+gfcc_status gfcc_mlp_get_weights(gfcc_ctx* c, int32_t* width, double* params, void* stream) {
+  return guarded([&] {
+    GFCC_CHECK(c && width, GFCC_E_ARG, "null argument");
+    GFCC_CHECK(c->mlp != nullptr, GFCC_E_STATE, "no network in this context");
+    *width = c->mlp->width;
+    if (params)
+      GFCC_HIP(hipMemcpyAsync(params, c->mlp->params.p, size_t(mlp_n_params(c->mlp->width)) * 8,
+                              hipMemcpyDeviceToDevice, as_stream(stream)));
+  });
+}
+
+gfcc_status gfcc_mlp_forward(gfcc_ctx* c, int64_t n, const double* X, double* Y, void* stream) {
+  return guarded([&] {
+    GFCC_CHECK(c && X && Y && n >= 0, GFCC_E_ARG, "bad argument");
+    GFCC_CHECK(c->mlp != nullptr, GFCC_E_STATE, "no network in this context");
+    if (n == 0) return;
+    hipStream_t s = as_stream(stream);
+    const int W = c->mlp->width;
+    double* H1 = c->mlp->ws.get(6, n * W, s);
+    double* H2 = c->mlp->ws.get(7, n * W, s);
+    mlp_forward64(c, n, X, H1, H2, Y, s);
+    GFCC_HIP(hipStreamSynchronize(s));
+  });
+}
+
+gfcc_status gfcc_mlp_loss_grad(gfcc_ctx* c, int64_t n, const double* X, const double* T, double* loss, double* grad,
+                               void* stream) {
+  return guarded([&] {
+    GFCC_CHECK(c && X && T && loss && grad && n > 0, GFCC_E_ARG, "bad argument");
+    GFCC_CHECK(c->mlp != nullptr, GFCC_E_STATE, "no network in this context");
+    hipStream_t s = as_stream(stream);
+    mlp_loss_grad64(c, n, X, T, loss, grad, s);
+    GFCC_HIP(hipStreamSynchronize(s));
+  });
+}
+
+gfcc_status gfcc_mlp_features(gfcc_ctx* c, int64_t nvec, const double* R, const double* omega, double eta, double* X,
+                              void* stream) {
+  return guarded([&] {
+    GFCC_CHECK(c && R && omega && X && nvec >= 0, GFCC_E_ARG, "bad argument");
+    if (nvec == 0) return;
+    hipStream_t s = as_stream(stream);
+    if (!c->mlp) mlp_init(c, 64, 0, s);
+    c->mlp->sD = diag_mean_abs(c, s);
+    DBuf pl, om, nr;
+    pl.ensure(size_t(2 * nvec * c->Dp) * 8, s);
+    om.ensure(size_t(nvec) * 8, s);
+    nr.ensure(size_t(nvec) * 8, s);
+    GFCC_HIP(hipMemcpyAsync(om.p, omega, size_t(nvec) * 8, hipMemcpyHostToDevice, s));
+    to_planes(c, nvec, R, pl.as<double>(), s);
+    hipLaunchKernelGGL(rms_kernel, dim3(unsigned(nvec)), dim3(256), 0, s, pl.as<double>(), c->Dp, c->D, nr.as<double>());
+    mlp_features(c, nvec, pl.as<double>(), om.as<double>(), nr.as<double>(), eta, X, s);
+    GFCC_HIP(hipStreamSynchronize(s));
+  });
+}
+
+gfcc_status gfcc_mlp_apply(gfcc_ctx* c, int64_t nvec, const double* R, const double* omega, double eta, double* U,
+                           void* stream) {
+  return guarded([&] {
+    GFCC_CHECK(c && R && omega && U && nvec >= 0, GFCC_E_ARG, "bad argument");
+    GFCC_CHECK(c->mlp && c->mlp->trained, GFCC_E_STATE, "no trained network in this context");
+    if (nvec == 0) return;
+    hipStream_t s = as_stream(stream);
+    DBuf pl, out, om, nr;
+    pl.ensure(size_t(2 * nvec * c->Dp) * 8, s);
+    out.ensure(size_t(2 * nvec * c->Dp) * 8, s);
+    om.ensure(size_t(nvec) * 8, s);
+    nr.ensure(size_t(nvec) * 8, s);
+    GFCC_HIP(hipMemcpyAsync(om.p, omega, size_t(nvec) * 8, hipMemcpyHostToDevice, s));
+    to_planes(c, nvec, R, pl.as<double>(), s);
+    hipLaunchKernelGGL(rms_kernel, dim3(unsigned(nvec)), dim3(256), 0, s, pl.as<double>(), c->Dp, c->D, nr.as<double>());
+    MlpApplyArgs a;
+    a.src = pl.as<double>();
+    a.omega = om.as<double>();
+    a.nrm = nr.as<double>();
+    a.eta = eta;
+    a.dst = out.as<double>();
+    mlp_apply(c, a, nvec, s);
+    from_planes(c, nvec, out.as<double>(), U, s);
+    GFCC_HIP(hipStreamSynchronize(s));
+  });
+}
+
+gfcc_status gfcc_mlp_train(gfcc_ctx* c, int64_t nrhs, const int64_t* p, const double* omega, double eta,
+                           const gfcc_mlp_opts* mo, gfcc_mlp_report* rep, void* stream) {
+  return guarded([&] {
+    GFCC_CHECK(c && p && omega && mo && nrhs > 0, GFCC_E_ARG, "bad argument");
+    GFCC_CHECK(mo->struct_size >= sizeof(gfcc_mlp_opts), GFCC_E_ARG, "bad options struct");
+    GFCC_CHECK(mo->steps >= 0 && mo->batch >= 1 && mo->pair_restart >= 1 && mo->max_pairs >= 1 && mo->lr > 0.0,
+               GFCC_E_ARG, "bad training options");
+    for (int64_t r = 0; r < nrhs; ++r) GFCC_CHECK(p[r] >= 0 && p[r] < c->o, GFCC_E_ARG, "p out of range");
+    hipStream_t s = as_stream(stream);
+    const auto t0 = std::chrono::steady_clock::now();
+    mlp_init(c, mo->width, mo->seed, s);
+    c->mlp->sD = diag_mean_abs(c, s);
+    // 1. pairs from FP64 Jacobi solves
+    const int64_t Dp = c->Dp;
+    DBuf bR, bX, bXs, bE, bG;
+    bR.ensure(size_t(mo->max_pairs) * 2 * Dp * 8, s);
+    bX.ensure(size_t(mo->max_pairs) * 2 * Dp * 8, s);
+    bXs.ensure(size_t(nrhs) * 2 * Dp * 8, s);
+    bG.ensure(size_t(nrhs) * 16, s);
+    PairRec rec;
+    rec.R = bR.as<double>();
+    rec.X = bX.as<double>();
+    rec.xstar = bXs.as<double>();
+    rec.cap = mo->max_pairs;
+    gfcc_solve_opts so{};
+    so.struct_size = sizeof(so);
+    so.tol = 1e-11;
+    so.restart = mo->pair_restart;
+    so.max_iter = 4000;
+    so.precond = GFCC_PC_JACOBI;
+    so.precision = GFCC_FP64;
+    std::vector<gfcc_rhs_info> inf(static_cast<size_t>(nrhs));
+    bool conv = true;
+    solve_batch(c, nrhs, p, omega, eta, 1, nullptr, &so, bG.as<double>(), nullptr, inf.data(), s, &conv, &rec);
+    GFCC_CHECK(rec.n > 0, GFCC_E_STATE, "training solves produced no restart pairs (lower pair_restart)");
+    // drop pairs whose right-hand side did not converge (no X*)
+    std::vector<int> keep;
+    for (int64_t k = 0; k < rec.n; ++k)
+      if (inf[size_t(rec.rhs[size_t(k)])].status == 0) keep.push_back(int(k));
+    GFCC_CHECK(!keep.empty(), GFCC_E_STATE, "no converged training right-hand side");
+    const int64_t npairs = rec.n;
+    bE.ensure(size_t(npairs) * 2 * Dp * 8, s);
+    DBuf drhs, dom, dnr;
+    std::vector<int> rh(rec.rhs.begin(), rec.rhs.end());
+    drhs.ensure(rh.size() * sizeof(int), s);
+    GFCC_HIP(hipMemcpyAsync(drhs.p, rh.data(), rh.size() * sizeof(int), hipMemcpyHostToDevice, s));
+    mlp_pair_errors(bE.as<double>(), rec.X, rec.xstar, drhs.as<int>(), npairs, Dp, s);
+    // compact the kept pairs to the front (in place, order preserved)
+    std::vector<double> om, nr;
+    for (size_t i = 0; i < keep.size(); ++i) {
+      const int k = keep[i];
+      if (int64_t(i) != k) {
+        GFCC_HIP(hipMemcpyAsync(bR.as<double>() + i * 2 * Dp, bR.as<double>() + k * 2 * Dp, size_t(2 * Dp) * 8,
+                                hipMemcpyDeviceToDevice, s));
+        GFCC_HIP(hipMemcpyAsync(bE.as<double>() + i * 2 * Dp, bE.as<double>() + k * 2 * Dp, size_t(2 * Dp) * 8,
+                                hipMemcpyDeviceToDevice, s));
+      }
+      om.push_back(rec.omega[size_t(k)]);
+      nr.push_back(rec.nrm[size_t(k)]);
+    }
+    dom.ensure(om.size() * 8, s);
+    dnr.ensure(nr.size() * 8, s);
+    GFCC_HIP(hipMemcpyAsync(dom.p, om.data(), om.size() * 8, hipMemcpyHostToDevice, s));
+    GFCC_HIP(hipMemcpyAsync(dnr.p, nr.data(), nr.size() * 8, hipMemcpyHostToDevice, s));
+    GFCC_HIP(hipStreamSynchronize(s));
+    const auto t1 = std::chrono::steady_clock::now();
+    // 2. training
+    MlpPairs pr;
+    pr.R = bR.as<double>();
+    pr.E = bE.as<double>();
+    pr.omega = dom.as<double>();
+    pr.nrm = dnr.as<double>();
+    pr.n = int64_t(keep.size());
+    gfcc_mlp_report r{};
+    mlp_train(c, pr, mo->steps, mo->batch, mo->lr, mo->seed, eta, &r, s);
+    const auto t2 = std::chrono::steady_clock::now();
+    r.n_pairs = pr.n;
+    r.data_seconds = std::chrono::duration<double>(t1 - t0).count();
+    r.train_seconds = std::chrono::duration<double>(t2 - t1).count();
+    if (rep) *rep = r;
+  });
 }
 
 gfcc_status gfcc_prof_enable(gfcc_ctx* c, int enable) {

@@ -4,6 +4,7 @@
 #include <string>
 
 #include "gfcc_internal.h"
+#include "mlp.h"
 
 struct gfcc_prof_entry {
   int64_t count = 0;
@@ -62,9 +63,27 @@ struct gfcc_ctx {
 
   // autotuned tile choice for the ring GEMMs, keyed "prec:M:N:K"
   std::map<std::string, int> tuned;
+  std::map<std::string, float> tuned_ms;
+
+  // learned preconditioner (created by training or by setting weights)
+  std::unique_ptr<gfcc::Mlp> mlp;
 };
 
 namespace gfcc {
+// Training data recorded by a solve: at every restart the true residual r_k and
+// the iterate x_k of a right-hand side; X* when it converges.
+struct PairRec {
+  double* R = nullptr;      // [cap][2][Dp]
+  double* X = nullptr;      // [cap][2][Dp]
+  double* xstar = nullptr;  // [nrhs][2][Dp]
+  int64_t cap = 0, n = 0;
+  std::vector<int> rhs;
+  std::vector<double> omega, nrm;
+};
+void solve_batch(gfcc_ctx* c, int64_t nrhs, const int64_t* p, const double* omega, double eta, int64_t nq,
+                 const int64_t* q, const gfcc_solve_opts* opts, double* G, double* X, gfcc_rhs_info* info,
+                 hipStream_t s, bool* all_converged, PairRec* rec);
+
 // Vectors inside the library are "planes": for nb complex vectors, 2*nb planes
 // of Dp doubles (re of vector 0, im of vector 0, re of vector 1, ...).
 void build_intermediates(gfcc_ctx* c, const gfcc_system* sys, hipStream_t s);
@@ -77,6 +96,11 @@ void from_planes(gfcc_ctx* c, int64_t nb, const double* planes, double* xi, hipS
 // G[r][k] = c_{q_k} . x_r (planes), complex interleaved output
 void greens_planes(gfcc_ctx* c, int64_t nb, const double* planes, int64_t nq, const int64_t* q_dev,
                    double* G, hipStream_t s);
+
+// tile autotuner (tune.hip)
+void tune_load(gfcc_ctx* c, const char* path);
+void tune_save(gfcc_ctx* c, const char* path);
+void tune_ring(gfcc_ctx* c, Prec p, int64_t P, hipStream_t s);
 
 // timing helpers (no-ops when profiling is off)
 void prof_begin(gfcc_ctx* c, const char* name, hipStream_t s);

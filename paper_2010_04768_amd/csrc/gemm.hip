@@ -242,6 +242,165 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
   }
 }
 
+// Double-buffered variant for the large ring GEMMs (both operands K-contiguous):
+// NW = WGM x WGN waves, each computing a (BM/WGM) x (BN/WGN) sub-tile; two LDS
+// stages so that one barrier per K-step separates "store next" from "read
+// current"; global loads for step k+1 are issued before the MFMAs of step k.
+template <typename T, int BM, int BN, int WGM, int WGN, bool VEC>
+__global__ __launch_bounds__(64 * WGM * WGN) void gemm_db_kernel(GemmArgs g) {
+  using MF = Mfma<T>;
+  constexpr int NT = 64 * WGM * WGN;
+  constexpr int EPC = 16 / int(sizeof(T));
+  constexpr int BK = 8 * EPC;
+  constexpr int LDK = BK + EPC;
+  constexpr int RPP = NT / 8;
+  constexpr int PA = BM / RPP, PB = BN / RPP;
+  constexpr int WM = BM / WGM, WN = BN / WGN, FM = WM / 16, FN = WN / 16;
+  constexpr int FE = (MF::KS == 32) ? 8 : 1;
+  static_assert(PA >= 1 && PB >= 1 && BM % RPP == 0 && BN % RPP == 0, "tile/thread mismatch");
+
+  __shared__ __attribute__((aligned(16))) T As[2][BM * LDK];
+  __shared__ __attribute__((aligned(16))) T Bs[2][BN * LDK];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm0 = (wave / WGN) * WM;
+  const int wn0 = (wave % WGN) * WN;
+
+  const int64_t tiles_m = (g.M + BM - 1) / BM;
+  const int64_t tiles_n = (g.N + BN - 1) / BN;
+  const int64_t ntiles = tiles_m * tiles_n;
+  int64_t bid = blockIdx.x;
+  if ((ntiles & 7) == 0) bid = (bid & 7) * (ntiles >> 3) + (bid >> 3);
+  constexpr int64_t GROUP = 4;
+  const int64_t per_group = GROUP * tiles_n;
+  const int64_t grp = bid / per_group;
+  const int64_t first_m = grp * GROUP;
+  const int64_t gsz = (tiles_m - first_m) < GROUP ? (tiles_m - first_m) : GROUP;
+  const int64_t in_grp = bid - grp * per_group;
+  const int64_t tm = first_m + in_grp % gsz;
+  const int64_t tn = in_grp / gsz;
+  const int64_t i0 = tm * BM, j0 = tn * BN;
+
+  const int z = blockIdx.z;
+  const int64_t kbase = g.k_split > 0 ? z * g.k_split : 0;
+  const int64_t Kz = g.k_split > 0 ? ((g.K - kbase) < g.k_split ? (g.K - kbase) : g.k_split) : g.K;
+  const T* A = static_cast<const T*>(g.A) + (g.k_split > 0 ? kbase : rmap(g.az, z));
+  const T* B = static_cast<const T*>(g.B) + (g.k_split > 0 ? kbase : rmap(g.bz, z));
+
+  const int lrow = tid >> 3;
+  const int lchunk = tid & 7;
+  int64_t aoff[PA], boff[PB];
+#pragma unroll
+  for (int p = 0; p < PA; ++p) {
+    const int64_t i = i0 + lrow + p * RPP;
+    aoff[p] = (i < g.M) ? rmap(g.am, i) : -1;
+  }
+#pragma unroll
+  for (int p = 0; p < PB; ++p) {
+    const int64_t j = j0 + lrow + p * RPP;
+    boff[p] = (j < g.N) ? rmap(g.bm, j) : -1;
+  }
+  u4 ra[PA], rb[PB];
+  auto fetch = [&](const T* base, int64_t off, int64_t k) -> u4 {
+    u4 v = {0u, 0u, 0u, 0u};
+    if (off < 0) return v;
+    if (VEC && k + EPC <= Kz) {
+      v = *reinterpret_cast<const u4*>(base + off + k);
+    } else {
+      T tmp[EPC];
+#pragma unroll
+      for (int e = 0; e < EPC; ++e) tmp[e] = (k + e < Kz) ? base[off + k + e] : T(0);
+      v = *reinterpret_cast<const u4*>(tmp);
+    }
+    return v;
+  };
+  auto load_tiles = [&](int64_t k0) {
+    const int64_t k = k0 + lchunk * EPC;
+#pragma unroll
+    for (int p = 0; p < PA; ++p) ra[p] = fetch(A, aoff[p], k);
+#pragma unroll
+    for (int p = 0; p < PB; ++p) rb[p] = fetch(B, boff[p], k);
+  };
+  auto store_tiles = [&](int buf) {
+#pragma unroll
+    for (int p = 0; p < PA; ++p)
+      *reinterpret_cast<u4*>(&As[buf][(lrow + p * RPP) * LDK + lchunk * EPC]) = ra[p];
+#pragma unroll
+    for (int p = 0; p < PB; ++p)
+      *reinterpret_cast<u4*>(&Bs[buf][(lrow + p * RPP) * LDK + lchunk * EPC]) = rb[p];
+  };
+
+  typename MF::acc_t acc[FM][FN];
+#pragma unroll
+  for (int a = 0; a < FM; ++a)
+#pragma unroll
+    for (int b = 0; b < FN; ++b) acc[a][b] = typename MF::acc_t{0, 0, 0, 0};
+
+  const int nk = int((Kz + BK - 1) / BK);
+  const int fr = lane & 15;
+  const int fk = (lane >> 4) * FE;
+  load_tiles(0);
+  store_tiles(0);
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    const int cur = kt & 1;
+    if (kt + 1 < nk) load_tiles(int64_t(kt + 1) * BK);
+#pragma unroll
+    for (int ks = 0; ks < BK; ks += MF::KS) {
+      typename MF::frag_t af[FM], bf[FN];
+#pragma unroll
+      for (int a = 0; a < FM; ++a)
+        af[a] = *reinterpret_cast<const typename MF::frag_t*>(&As[cur][(wm0 + a * 16 + fr) * LDK + ks + fk]);
+#pragma unroll
+      for (int b = 0; b < FN; ++b)
+        bf[b] = *reinterpret_cast<const typename MF::frag_t*>(&Bs[cur][(wn0 + b * 16 + fr) * LDK + ks + fk]);
+#pragma unroll
+      for (int a = 0; a < FM; ++a)
+#pragma unroll
+        for (int b = 0; b < FN; ++b) acc[a][b] = MF::mma(af[a], bf[b], acc[a][b]);
+    }
+    if (kt + 1 < nk) store_tiles(cur ^ 1);
+    __syncthreads();
+  }
+
+  double* C = g.C + rmap(g.cz, z);
+  const int jl = lane & 15;
+  const int ih = lane >> 4;
+#pragma unroll
+  for (int b = 0; b < FN; ++b) {
+    const int64_t j = j0 + wn0 + b * 16 + jl;
+    if (j >= g.N) continue;
+    const int64_t cj = rmap(g.cn, j);
+#pragma unroll
+    for (int a = 0; a < FM; ++a) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int ii = MF::ROW_INTERLEAVED ? (ih + 4 * r) : (4 * ih + r);
+        const int64_t i = i0 + wm0 + a * 16 + ii;
+        if (i >= g.M) continue;
+        double* p = C + rmap(g.cm, i) + cj;
+        const double v = g.alpha * double(acc[a][b][r]);
+        *p = (g.beta == 0.0) ? v : v + g.beta * (*p);
+      }
+    }
+  }
+}
+
+template <typename T, int BM, int BN, int WGM, int WGN>
+static void launch_db(const GemmArgs& a, bool vec, hipStream_t s) {
+  const int64_t tiles = ((a.M + BM - 1) / BM) * ((a.N + BN - 1) / BN);
+  GFCC_CHECK(tiles < (int64_t(1) << 31) && a.batch < 65536, GFCC_E_ARG, "GEMM grid too large");
+  GFCC_CHECK(!a.b_ncontig, GFCC_E_ARG, "double-buffered tiles need a K-contiguous B");
+  dim3 grid(unsigned(tiles), 1, unsigned(a.batch));
+  if (vec)
+    hipLaunchKernelGGL((gemm_db_kernel<T, BM, BN, WGM, WGN, true>), grid, dim3(64 * WGM * WGN), 0, s, a);
+  else
+    hipLaunchKernelGGL((gemm_db_kernel<T, BM, BN, WGM, WGN, false>), grid, dim3(64 * WGM * WGN), 0, s, a);
+  GFCC_HIP(hipGetLastError());
+}
+
 template <typename T, int BM, int BN>
 static void launch(const GemmArgs& a, bool vec, hipStream_t s) {
   const int64_t tiles = ((a.M + BM - 1) / BM) * ((a.N + BN - 1) / BN);
@@ -268,6 +427,10 @@ static void dispatch(const GemmArgs& a, int cfg, bool vec, hipStream_t s) {
     case TILE_64x64: launch<T, 64, 64>(a, vec, s); break;
     case TILE_128x64: launch<T, 128, 64>(a, vec, s); break;
     case TILE_64x128: launch<T, 64, 128>(a, vec, s); break;
+    case TILE_DB_128x128: launch_db<T, 128, 128, 2, 2>(a, vec, s); break;
+    case TILE_DB_256x128: launch_db<T, 256, 128, 4, 2>(a, vec, s); break;
+    case TILE_DB_128x256: launch_db<T, 128, 256, 2, 4>(a, vec, s); break;
+    case TILE_DB_256x256: launch_db<T, 256, 256, 4, 2>(a, vec, s); break;
     default: throw Error{GFCC_E_ARG, "bad tile config"};
   }
 }
@@ -332,7 +495,8 @@ void gemm_auto(Prec p, const GemmArgs& a, Scratch& scr, int scr_slot, hipStream_
 }
 
 const char* tile_name(int cfg) {
-  static const char* n[] = {"128x128", "64x64", "128x64", "64x128"};
+  static const char* n[] = {"128x128", "64x64", "128x64", "64x128", "db128x128", "db256x128", "db128x256",
+                            "db256x256"};
   return (cfg >= 0 && cfg < N_TILE_CFG) ? n[cfg] : "?";
 }
 

@@ -34,6 +34,13 @@ struct Error {
 inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
 // ---------------------------------------------------------------- device memory
+// Incremented whenever a library buffer is (re)allocated; captured HIP graphs
+// hold raw addresses and are discarded when it changes.
+inline uint64_t& alloc_generation() {
+  static thread_local uint64_t g = 0;
+  return g;
+}
+
 struct DBuf {
   void* p = nullptr;
   size_t bytes = 0;
@@ -63,6 +70,7 @@ struct DBuf {
       throw Error{GFCC_E_OOM, "hipMalloc of " + std::to_string(n) + " bytes failed"};
     }
     bytes = n;
+    ++alloc_generation();
     GFCC_HIP(hipMemsetAsync(p, 0, n, s));
   }
   template <typename T> T* as() const { return static_cast<T*>(p); }
@@ -100,7 +108,12 @@ struct GemmArgs {
 };
 
 // Tile configurations; the autotuner picks one per (shape, precision).
-enum TileCfg : int { TILE_128x128 = 0, TILE_64x64 = 1, TILE_128x64 = 2, TILE_64x128 = 3, N_TILE_CFG = 4 };
+enum TileCfg : int {
+  TILE_128x128 = 0, TILE_64x64 = 1, TILE_128x64 = 2, TILE_64x128 = 3,
+  // double-buffered LDS, one barrier per K-step (K-contiguous B only)
+  TILE_DB_128x128 = 4, TILE_DB_256x128 = 5, TILE_DB_128x256 = 6, TILE_DB_256x256 = 7,
+  N_TILE_CFG = 8
+};
 const char* tile_name(int cfg);
 
 void gemm(Prec p, const GemmArgs& a, int cfg, hipStream_t s);
@@ -133,7 +146,7 @@ void permute(const TView& in, const int* perm, double alpha, const TView& out, d
 
 // Scratch arena reused by the contraction engine.
 struct Scratch {
-  DBuf b[4];
+  DBuf b[8];
   double* get(int slot, int64_t n, hipStream_t s) {
     b[slot].ensure(size_t(n) * sizeof(double), s);
     return b[slot].as<double>();

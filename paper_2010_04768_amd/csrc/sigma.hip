@@ -19,6 +19,8 @@
 // In FP32/BF16 mode these three and the hole-hole ladder and z contraction
 // read reduced-precision copies; the one-body terms stay FP64.
 #include <algorithm>
+#include <cstring>
+#include <string>
 
 #include "ctx.h"
 
@@ -76,6 +78,18 @@ static int ring_cfg(gfcc_ctx* c, Prec p, int64_t M, int64_t N, int64_t K) {
   snprintf(key, sizeof key, "%d:%lld:%lld:%lld", int(p), (long long)M, (long long)N, (long long)K);
   auto it = c->tuned.find(key);
   if (it != c->tuned.end()) return it->second;
+  // a tuned entry for the same precision and N, K with a large M serves any large M
+  if (M >= 1024) {
+    char pre[96];
+    snprintf(pre, sizeof pre, "%d:", int(p));
+    char suf[64];
+    snprintf(suf, sizeof suf, ":%lld:%lld", (long long)N, (long long)K);
+    for (const auto& kv : c->tuned) {
+      const std::string& k = kv.first;
+      if (k.rfind(pre, 0) == 0 && k.size() > strlen(suf) && k.compare(k.size() - strlen(suf), strlen(suf), suf) == 0)
+        return kv.second;
+    }
+  }
   return gemm_default_cfg(M, N, K);
 }
 

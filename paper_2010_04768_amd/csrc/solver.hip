@@ -22,6 +22,8 @@
 #include <algorithm>
 #include <cmath>
 #include <deque>
+#include <map>
+#include <set>
 #include <vector>
 
 #include "ctx.h"
@@ -524,6 +526,10 @@ __global__ void xout_kernel(SolverDev d, const int* slots, const int64_t* rows, 
 struct HostSlot {
   int64_t rhs = -1;
   int iters = 0, restarts = 0;
+  int k = 0;               // Krylov step (mirror of the device counter)
+  int mlp = 0;             // 1 while the learned preconditioner is in use
+  bool fell_back = false;  // switched to Jacobi after an MLP cycle stalled
+  double beta = 1.0;       // residual at the start of the current cycle
 };
 
 static double lp_cycle_rtol(gfcc_precision p) {
@@ -542,11 +548,14 @@ static void upload(DBuf& b, const std::vector<T>& v, hipStream_t s) {
 
 void solve_batch(gfcc_ctx* c, int64_t nrhs, const int64_t* p, const double* omega, double eta, int64_t nq,
                  const int64_t* q, const gfcc_solve_opts* opts, double* G, double* Xout, gfcc_rhs_info* info,
-                 hipStream_t s, bool* all_converged) {
+                 hipStream_t s, bool* all_converged, PairRec* rec) {
   const int m = std::min<int>(opts->restart, MAXM);
   const gfcc_precision prec = opts->precision;
-  const int mode = opts->precond == GFCC_PC_MLP ? GFCC_PC_JACOBI : opts->precond;  // MLP: see mlp path
-  const int flex = 0;
+  const bool use_mlp = opts->precond == GFCC_PC_MLP;
+  GFCC_CHECK(!use_mlp || (c->mlp && c->mlp->trained), GFCC_E_STATE,
+             "GFCC_PC_MLP needs trained or loaded network weights");
+  const int mode = use_mlp ? GFCC_PC_JACOBI : opts->precond;  // Jacobi is also the MLP fallback
+  const int flex = use_mlp ? 1 : 0;
   const int64_t Dp = c->Dp;
   const int nch = int((Dp + CH - 1) / CH);
   int B = opts->batch > 0 ? opts->batch : 0;
@@ -604,6 +613,7 @@ void solve_batch(gfcc_ctx* c, int64_t nrhs, const int64_t* p, const double* omeg
   d.nch = nch;
 
   DBuf d_act, d_flags, d_res, d_list, d_plist, d_zlist, d_ctl, d_beta, d_rows, d_q;
+  DBuf d_msrc, d_mzoff, d_mom, d_pmode;
   d_flags.ensure(size_t(B) * sizeof(int), s);
   d_res.ensure(size_t(B) * 8, s);
   d_beta.ensure(size_t(B) * 8, s);
@@ -630,7 +640,9 @@ void solve_batch(gfcc_ctx* c, int64_t nrhs, const int64_t* p, const double* omeg
     while (!free_slots.empty() && next < nrhs) {
       const int sidx = free_slots.back();
       free_slots.pop_back();
-      hs[sidx] = HostSlot{next, 0, 0};
+      hs[sidx] = HostSlot{};
+      hs[sidx].rhs = next;
+      hs[sidx].mlp = use_mlp ? 1 : 0;
       sl.push_back(sidx);
       pl.push_back(int(p[next]));
       zl.push_back(cplx{omega[next], -eta});
@@ -649,37 +661,121 @@ void solve_batch(gfcc_ctx* c, int64_t nrhs, const int64_t* p, const double* omeg
     GFCC_HIP(hipStreamSynchronize(s));  // host vectors above go out of scope
   };
 
+  if (opts->tune_cache) {  // pick ring-GEMM tiles for the full window (inner precision and FP64)
+    tune_load(c, opts->tune_cache);
+    const Prec ip = prec == GFCC_FP64 ? Prec::F64 : (prec == GFCC_FP32_IR ? Prec::F32 : Prec::BF16);
+    tune_ring(c, ip, 2 * int64_t(B), s);
+    if (ip != Prec::F64) tune_ring(c, Prec::F64, 2 * int64_t(B), s);
+    tune_save(c, opts->tune_cache);
+  }
   refill();
   std::vector<int> hflags(B);
   std::vector<double> hres(B), hbeta(B);
   std::vector<int> pending;  // slots whose cycle ended, waiting for a batched finish
+  std::map<std::pair<int, const void*>, hipGraphExec_t> graphs;
+  std::set<std::pair<int, const void*>> seen_sizes;
+  struct GraphGuard {
+    std::map<std::pair<int, const void*>, hipGraphExec_t>& g;
+    ~GraphGuard() {
+      for (auto& kv : g) (void)hipGraphExecDestroy(kv.second);
+    }
+  } graph_guard{graphs};
+  uint64_t graph_gen = alloc_generation();
   while (!active.empty() || !pending.empty()) {
     const int na = int(active.size());
     if (na > 0) {
       upload(d_act, active, s);
       const int* act = d_act.as<int>();
-      // 1. precondition
-      hipLaunchKernelGGL(precond_kernel, dim3(nch, na), dim3(VT), 0, s, d, act, c->ws_in.as<double>(),
-                         c->diag.as<double>(), mode, flex);
-      GFCC_HIP(hipGetLastError());
-      // 2. sigma
-      sigma_planes(c, 2 * na, c->ws_in.as<double>(), c->ws_out.as<double>(), prec, s);
-      // 3. Arnoldi (CGS2)
-      prof_begin(c, "arnoldi", s);
-      hipLaunchKernelGGL(arnoldi_kernel, dim3(nch, na), dim3(VT), 0, s, d, act, c->ws_in.as<double>(),
-                         c->ws_out.as<double>(), 0);
-      hipLaunchKernelGGL(reduce_h_kernel, dim3(na), dim3(MAXM + 1), 0, s, d, act, 0);
-      hipLaunchKernelGGL(arnoldi_kernel, dim3(nch, na), dim3(VT), 0, s, d, act, c->ws_in.as<double>(),
-                         c->ws_out.as<double>(), 1);
-      hipLaunchKernelGGL(reduce_h_kernel, dim3(na), dim3(MAXM + 1), 0, s, d, act, 1);
-      hipLaunchKernelGGL(arnoldi_kernel, dim3(nch, na), dim3(VT), 0, s, d, act, c->ws_in.as<double>(),
-                         c->ws_out.as<double>(), 2);
-      GFCC_HIP(hipGetLastError());
-      // 4. Givens + flags
-      hipLaunchKernelGGL(givens_kernel, dim3(na), dim3(64), 0, s, d, act, d_flags.as<int>(), d_res.as<double>(), 1);
-      hipLaunchKernelGGL(scale_kernel, dim3(nch, na), dim3(VT), 0, s, d, act);
-      GFCC_HIP(hipGetLastError());
-      prof_end(c, "arnoldi", s, 0.0, 0.0);
+      // One inner iteration: precondition, sigma, CGS2, Givens.  With use_graph
+      // (and a plain preconditioner) it is captured once per window size --
+      // when that size repeats, so every buffer is already sized and the
+      // capture holds kernels only -- and replayed afterwards.
+      auto iteration = [&]() {
+        if (!use_mlp) {
+          hipLaunchKernelGGL(precond_kernel, dim3(nch, na), dim3(VT), 0, s, d, act, c->ws_in.as<double>(),
+                             c->diag.as<double>(), mode, flex);
+          GFCC_HIP(hipGetLastError());
+        } else {
+          std::vector<int> sidx(na), pm(B);
+          std::vector<int64_t> zoff(na);
+          std::vector<double> om(na);
+          for (int i = 0; i < na; ++i) {
+            const int sl = active[i];
+            sidx[i] = sl * (m + 1) + hs[sl].k;
+            zoff[i] = ((int64_t(sl) * m + hs[sl].k) * 2) * Dp;
+            om[i] = omega[hs[sl].rhs];
+          }
+          for (int sl = 0; sl < B; ++sl) pm[sl] = hs[sl].mlp;
+          upload(d_msrc, sidx, s);
+          upload(d_mzoff, zoff, s);
+          upload(d_mom, om, s);
+          upload(d_pmode, pm, s);
+          MlpApplyArgs a;
+          a.src = d.V;
+          a.src_idx = d_msrc.as<int>();
+          a.slots = act;
+          a.mode = d_pmode.as<int>();
+          a.omega = d_mom.as<double>();
+          a.nrm = nullptr;
+          a.nrm_const = 1.0 / std::sqrt(double(c->D));  // Krylov vectors have unit norm
+          a.eta = eta;
+          a.dst = c->ws_in.as<double>();
+          a.zdst = d.Z;
+          a.zoff = d_mzoff.as<int64_t>();
+          prof_begin(c, "mlp", s);
+          mlp_apply(c, a, na, s);
+          prof_end(c, "mlp", s, 2.0 * double(na) * double(c->D) *
+                                    (double(MLP_F) * c->mlp->width + double(c->mlp->width) * c->mlp->width +
+                                     2.0 * c->mlp->width), 0.0);
+          GFCC_HIP(hipStreamSynchronize(s));  // host vectors above go out of scope
+        }
+        sigma_planes(c, 2 * na, c->ws_in.as<double>(), c->ws_out.as<double>(), prec, s);
+        prof_begin(c, "arnoldi", s);
+        hipLaunchKernelGGL(arnoldi_kernel, dim3(nch, na), dim3(VT), 0, s, d, act, c->ws_in.as<double>(),
+                           c->ws_out.as<double>(), 0);
+        hipLaunchKernelGGL(reduce_h_kernel, dim3(na), dim3(MAXM + 1), 0, s, d, act, 0);
+        hipLaunchKernelGGL(arnoldi_kernel, dim3(nch, na), dim3(VT), 0, s, d, act, c->ws_in.as<double>(),
+                           c->ws_out.as<double>(), 1);
+        hipLaunchKernelGGL(reduce_h_kernel, dim3(na), dim3(MAXM + 1), 0, s, d, act, 1);
+        hipLaunchKernelGGL(arnoldi_kernel, dim3(nch, na), dim3(VT), 0, s, d, act, c->ws_in.as<double>(),
+                           c->ws_out.as<double>(), 2);
+        GFCC_HIP(hipGetLastError());
+        hipLaunchKernelGGL(givens_kernel, dim3(na), dim3(64), 0, s, d, act, d_flags.as<int>(), d_res.as<double>(), 1);
+        hipLaunchKernelGGL(scale_kernel, dim3(nch, na), dim3(VT), 0, s, d, act);
+        GFCC_HIP(hipGetLastError());
+        prof_end(c, "arnoldi", s, 0.0, 0.0);
+      };
+      const bool graphable = opts->use_graph && !use_mlp && !c->prof_on;
+      if (graphable && graph_gen != alloc_generation()) {  // a buffer moved: drop stale graphs
+        for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
+        graphs.clear();
+        seen_sizes.clear();
+        graph_gen = alloc_generation();
+      }
+      if (!graphable) {
+        iteration();
+      } else {
+        const std::pair<int, const void*> gk{na, d_act.p};
+        auto it = graphs.find(gk);
+        if (it != graphs.end()) {
+          GFCC_HIP(hipGraphLaunch(it->second, s));
+        } else if (seen_sizes.count(gk)) {
+          hipGraph_t gr;
+          const uint64_t gen0 = alloc_generation();
+          GFCC_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+          iteration();
+          GFCC_HIP(hipStreamEndCapture(s, &gr));
+          GFCC_CHECK(alloc_generation() == gen0, GFCC_E_STATE, "allocation during graph capture");
+          hipGraphExec_t ex;
+          GFCC_HIP(hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0));
+          GFCC_HIP(hipGraphDestroy(gr));
+          graphs[gk] = ex;
+          GFCC_HIP(hipGraphLaunch(ex, s));
+        } else {
+          seen_sizes.insert(gk);
+          iteration();
+        }
+      }
       GFCC_HIP(hipMemcpyAsync(hflags.data(), d_flags.p, na * sizeof(int), hipMemcpyDeviceToHost, s));
       GFCC_HIP(hipMemcpyAsync(hres.data(), d_res.p, na * 8, hipMemcpyDeviceToHost, s));
       GFCC_HIP(hipStreamSynchronize(s));
@@ -687,6 +783,7 @@ void solve_batch(gfcc_ctx* c, int64_t nrhs, const int64_t* p, const double* omeg
       for (int i = 0; i < na; ++i) {
         const int sl = active[i];
         hs[sl].iters += 1;
+        hs[sl].k += 1;
         if (hflags[i] != 0 || hs[sl].iters >= opts->max_iter)
           pending.push_back(sl);
         else
@@ -734,19 +831,40 @@ void solve_batch(gfcc_ctx* c, int64_t nrhs, const int64_t* p, const double* omeg
       inf.restarts = h.restarts;
       inf.true_rel_resid = beta;
       if (finite && beta <= tol) {
-        inf.status = 0;
+        inf.status = h.fell_back ? 4 : 0;
+        if (rec) {  // keep X* of this right-hand side for the training pairs
+          GFCC_HIP(hipMemcpyAsync(rec->xstar + h.rhs * 2 * Dp, d.X + int64_t(sl) * 2 * Dp, size_t(2 * Dp) * 8,
+                                  hipMemcpyDeviceToDevice, s));
+        }
       } else if (!finite) {
         inf.status = 3;
       } else if (h.iters >= opts->max_iter) {
         inf.status = 1;
       } else {
+        if (rec && rec->n < rec->cap) {  // (r_k, x_k) pair: V[s][0] holds the unnormalised residual
+          GFCC_HIP(hipMemcpyAsync(rec->R + rec->n * 2 * Dp, d.V + int64_t(sl) * (m + 1) * 2 * Dp,
+                                  size_t(2 * Dp) * 8, hipMemcpyDeviceToDevice, s));
+          GFCC_HIP(hipMemcpyAsync(rec->X + rec->n * 2 * Dp, d.X + int64_t(sl) * 2 * Dp, size_t(2 * Dp) * 8,
+                                  hipMemcpyDeviceToDevice, s));
+          rec->rhs.push_back(int(h.rhs));
+          rec->omega.push_back(omega[h.rhs]);
+          rec->nrm.push_back(beta / std::sqrt(double(c->D)));
+          rec->n += 1;
+        }
+        // the learned preconditioner hands over to Jacobi when a cycle stalls
+        if (h.mlp && !(beta < 0.9 * h.beta)) {
+          h.mlp = 0;
+          h.fell_back = true;
+        }
+        h.beta = beta;
+        h.k = 0;
         h.restarts += 1;
         again.push_back(sl);
         again_beta.push_back(beta);
         again_tol.push_back(std::max(0.5 * tol, rtol_lp * beta));
         continue;
       }
-      if (inf.status != 0) ok_all = false;
+      if (inf.status != 0 && inf.status != 4) ok_all = false;
       done.push_back(sl);
       done_rows.push_back(h.rhs);
       done_p.push_back(int(p[h.rhs]));

@@ -25,7 +25,8 @@ BLOCKS = ["FOO", "FVV", "FOV", "WOOOO", "WOOOV", "WOVOO", "WOVVO", "WOVOV", "DIA
 # exported symbols of include/gfcc.h
 SYMBOLS = ["gfcc_build_intermediates", "gfcc_dims", "gfcc_export", "gfcc_sigma", "gfcc_solve_batch",
            "gfcc_greens", "gfcc_prof_enable", "gfcc_prof_get", "gfcc_destroy", "gfcc_strerror",
-           "gfcc_last_error"]
+           "gfcc_last_error", "gfcc_mlp_train", "gfcc_mlp_set_weights", "gfcc_mlp_get_weights",
+           "gfcc_mlp_forward", "gfcc_mlp_loss_grad", "gfcc_mlp_features", "gfcc_mlp_apply"]
 
 
 class GfccSystem(ctypes.Structure):
@@ -44,6 +45,18 @@ class SolveOpts(ctypes.Structure):
 class RhsInfo(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("iters", ctypes.c_int32), ("restarts", ctypes.c_int32),
                 ("reserved", ctypes.c_int32), ("true_rel_resid", ctypes.c_double)]
+
+
+class MlpOpts(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_size_t), ("width", ctypes.c_int32), ("steps", ctypes.c_int32),
+                ("batch", ctypes.c_int32), ("pair_restart", ctypes.c_int32), ("lr", ctypes.c_double),
+                ("seed", ctypes.c_uint64), ("max_pairs", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class MlpReport(ctypes.Structure):
+    _fields_ = [("n_pairs", ctypes.c_int64), ("steps", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("loss_first", ctypes.c_double), ("loss_final", ctypes.c_double),
+                ("data_seconds", ctypes.c_double), ("train_seconds", ctypes.c_double)]
 
 
 class GfccError(RuntimeError):
@@ -79,11 +92,16 @@ def load():
     for name in ["gfcc_build_intermediates", "gfcc_dims", "gfcc_export", "gfcc_sigma", "gfcc_solve_batch",
                  "gfcc_greens", "gfcc_prof_enable", "gfcc_prof_get", "gfcc_destroy"]:
         getattr(L, name).restype = ctypes.c_int
-    if hasattr(L, "gfcc_mlp_train"):
-        L.gfcc_mlp_train.restype = ctypes.c_int
-        L.gfcc_mlp_forward.restype = ctypes.c_int
-        L.gfcc_mlp_set_weights.restype = ctypes.c_int
-        L.gfcc_mlp_get_weights.restype = ctypes.c_int
+    L.gfcc_mlp_train.argtypes = [vp, i64, vp, vp, dbl, ctypes.POINTER(MlpOpts), ctypes.POINTER(MlpReport), vp]
+    L.gfcc_mlp_set_weights.argtypes = [vp, ctypes.c_int32, vp, vp]
+    L.gfcc_mlp_get_weights.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), vp, vp]
+    L.gfcc_mlp_forward.argtypes = [vp, i64, vp, vp, vp]
+    L.gfcc_mlp_loss_grad.argtypes = [vp, i64, vp, vp, vp, vp, vp]
+    L.gfcc_mlp_features.argtypes = [vp, i64, vp, vp, dbl, vp, vp]
+    L.gfcc_mlp_apply.argtypes = [vp, i64, vp, vp, dbl, vp, vp]
+    for name in ["gfcc_mlp_train", "gfcc_mlp_set_weights", "gfcc_mlp_get_weights", "gfcc_mlp_forward",
+                 "gfcc_mlp_loss_grad", "gfcc_mlp_features", "gfcc_mlp_apply"]:
+        getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
 
@@ -176,7 +194,7 @@ class Context:
     # ---------------------------------------------------------------- solve
     def solve(self, p: Sequence[int], omega: Sequence[float], eta: float, q: Optional[Sequence[int]] = None,
               tol=1e-8, restart=30, max_iter=2000, batch=0, precond="jacobi", precision="fp64",
-              use_graph=False, want_x=False, ir_inner_rtol=0.0):
+              use_graph=False, want_x=False, ir_inner_rtol=0.0, tune_cache=None):
         """Returns (G [nrhs, nq] complex128 device tensor, info list of dicts, X or None)."""
         import torch
         p_h = np.ascontiguousarray(np.asarray(p, dtype=np.int64))
@@ -192,7 +210,8 @@ class Context:
         X = torch.zeros((n, self.dim), dtype=torch.complex128, device=self.device) if want_x else None
         info = (RhsInfo * max(n, 1))()
         opts = SolveOpts(ctypes.sizeof(SolveOpts), tol, restart, max_iter, batch, PRECONDS[precond],
-                         PRECISIONS[precision], int(use_graph), None, ir_inner_rtol)
+                         PRECISIONS[precision], int(use_graph),
+                         tune_cache.encode() if tune_cache else None, ir_inner_rtol)
         st = self._lib.gfcc_solve_batch(
             self._h, n, p_h.ctypes.data_as(ctypes.c_void_p), w_h.ctypes.data_as(ctypes.c_void_p), eta, nq,
             q_h.ctypes.data_as(ctypes.c_void_p) if q_h is not None else None, ctypes.byref(opts), _ptr(G),
@@ -220,3 +239,68 @@ class Context:
         _check(self._lib.gfcc_prof_get(self._h, name.encode(), ctypes.byref(c), ctypes.byref(ms), ctypes.byref(fl),
                                        ctypes.byref(by)), "gfcc_prof_get")
         return dict(count=c.value, ms=ms.value, flops=fl.value, bytes=by.value)
+
+    # ---------------------------------------------------------------- learned preconditioner
+    def mlp_train(self, p, omega, eta, width=256, steps=1000, batch=8192, pair_restart=4, lr=1e-3, seed=0,
+                  max_pairs=512):
+        p_h = np.ascontiguousarray(np.asarray(p, dtype=np.int64))
+        w_h = np.ascontiguousarray(np.asarray(omega, dtype=np.float64))
+        o = MlpOpts(ctypes.sizeof(MlpOpts), width, steps, batch, pair_restart, lr, seed, max_pairs, 0)
+        rep = MlpReport()
+        _check(self._lib.gfcc_mlp_train(self._h, p_h.size, p_h.ctypes.data_as(ctypes.c_void_p),
+                                        w_h.ctypes.data_as(ctypes.c_void_p), eta, ctypes.byref(o),
+                                        ctypes.byref(rep), _stream()), "gfcc_mlp_train")
+        return dict(n_pairs=rep.n_pairs, steps=rep.steps, loss_first=rep.loss_first, loss_final=rep.loss_final,
+                    data_seconds=rep.data_seconds, train_seconds=rep.train_seconds)
+
+    def mlp_set_weights(self, width, params):
+        import torch
+        t = torch.as_tensor(np.asarray(params, dtype=np.float64)).to(self.device).contiguous()
+        _check(self._lib.gfcc_mlp_set_weights(self._h, width, _ptr(t), _stream()), "gfcc_mlp_set_weights")
+
+    def mlp_get_weights(self):
+        import torch
+        w = ctypes.c_int32()
+        _check(self._lib.gfcc_mlp_get_weights(self._h, ctypes.byref(w), None, _stream()), "gfcc_mlp_get_weights")
+        W = w.value
+        n = W * 8 + W + W * W + W + 2 * W + 2
+        out = torch.empty(n, dtype=torch.float64, device=self.device)
+        _check(self._lib.gfcc_mlp_get_weights(self._h, ctypes.byref(w), _ptr(out), _stream()), "gfcc_mlp_get_weights")
+        return W, out
+
+    def mlp_forward(self, X):
+        import torch
+        X = torch.as_tensor(X).to(self.device, torch.float64).contiguous()
+        Y = torch.empty((X.shape[0], 2), dtype=torch.float64, device=self.device)
+        _check(self._lib.gfcc_mlp_forward(self._h, X.shape[0], _ptr(X), _ptr(Y), _stream()), "gfcc_mlp_forward")
+        return Y
+
+    def mlp_loss_grad(self, X, T):
+        import torch
+        X = torch.as_tensor(X).to(self.device, torch.float64).contiguous()
+        T = torch.as_tensor(T).to(self.device, torch.float64).contiguous()
+        W, _ = self.mlp_get_weights()
+        n = W * 8 + W + W * W + W + 2 * W + 2
+        loss = torch.empty(1, dtype=torch.float64, device=self.device)
+        grad = torch.empty(n, dtype=torch.float64, device=self.device)
+        _check(self._lib.gfcc_mlp_loss_grad(self._h, X.shape[0], _ptr(X), _ptr(T), _ptr(loss), _ptr(grad),
+                                            _stream()), "gfcc_mlp_loss_grad")
+        return loss, grad
+
+    def mlp_features(self, R, omega, eta):
+        import torch
+        R = torch.as_tensor(R).to(self.device, torch.complex128).contiguous()
+        w_h = np.ascontiguousarray(np.asarray(omega, dtype=np.float64))
+        X = torch.empty((R.shape[0] * self.dim, 8), dtype=torch.float64, device=self.device)
+        _check(self._lib.gfcc_mlp_features(self._h, R.shape[0], _ptr(R), w_h.ctypes.data_as(ctypes.c_void_p), eta,
+                                           _ptr(X), _stream()), "gfcc_mlp_features")
+        return X
+
+    def mlp_apply(self, R, omega, eta):
+        import torch
+        R = torch.as_tensor(R).to(self.device, torch.complex128).contiguous()
+        w_h = np.ascontiguousarray(np.asarray(omega, dtype=np.float64))
+        U = torch.empty_like(R)
+        _check(self._lib.gfcc_mlp_apply(self._h, R.shape[0], _ptr(R), w_h.ctypes.data_as(ctypes.c_void_p), eta,
+                                        _ptr(U), _stream()), "gfcc_mlp_apply")
+        return U

@@ -1,0 +1,108 @@
+"""GPU parity of the learned preconditioner against its CPU oracle (oracle.mlp)."""
+import numpy as np
+import pytest
+
+from oracle import ipgfcc as O
+from oracle import mlp as M
+from synth import make_system, random_vectors
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2010_04768_amd import gfcc  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def sysctx():
+    s = make_system(6, 21, 30, 4242, sigma_L=0.12, sigma_t1=0.02)
+    im = O.intermediates(s)
+    ctx = gfcc.Context.from_system(s)
+    d = O.diagonal(im)
+    sD = float(np.mean(np.abs(d)))
+    yield s, im, ctx, d, sD
+    ctx.close()
+
+
+def _params(W, seed):
+    rng = np.random.default_rng(seed)
+    p = M.init_params(W, seed=seed)
+    p["W3"] = rng.normal(0, 0.05, p["W3"].shape)
+    p["b3"] = rng.normal(0, 0.01, 2)
+    p["b1"] = rng.normal(0, 0.1, W)
+    p["b2"] = rng.normal(0, 0.1, W)
+    return p
+
+
+def test_features_match_oracle(sysctx):
+    s, im, ctx, d, sD = sysctx
+    R = random_vectors(3, s.dim, seed=1)
+    om = [-0.9, -0.5, -0.3]
+    X = ctx.mlp_features(torch.from_numpy(R), om, 0.01).cpu().numpy()
+    for v in range(3):
+        Xo, _ = M.features(R[v], d, om[v], 0.01, s.n_occ, sD)
+        assert np.abs(X[v * s.dim:(v + 1) * s.dim] - Xo).max() < 1e-12 * max(1.0, np.abs(Xo).max())
+
+
+@pytest.mark.parametrize("W", [64, 128, 256])
+def test_forward_and_gradient_match_oracle(sysctx, W):
+    s, im, ctx, d, sD = sysctx
+    p = _params(W, W)
+    ctx.mlp_set_weights(W, M.flatten(p))
+    rng = np.random.default_rng(5)
+    X = rng.normal(size=(1000, M.N_FEAT))
+    T = rng.normal(size=(1000, 2))
+    Y = ctx.mlp_forward(torch.from_numpy(X)).cpu().numpy()
+    Yo, _ = M.forward(p, X)
+    assert np.abs(Y - Yo).max() < 1e-12 * max(1.0, np.abs(Yo).max())
+    loss, grad = ctx.mlp_loss_grad(torch.from_numpy(X), torch.from_numpy(T))
+    Lo, go = M.loss_and_grad(p, X, T)
+    assert abs(loss.item() - Lo) < 1e-12 * Lo
+    g = grad.cpu().numpy()
+    gflat = M.flatten(go)
+    assert np.abs(g - gflat).max() < 1e-11 * np.abs(gflat).max()
+
+
+@pytest.mark.parametrize("W", [64, 256])
+def test_fused_bf16_apply_matches_oracle(sysctx, W):
+    """The preconditioner's fused inference (BF16 layer 2) vs the FP64 oracle.
+
+    Bound: the network correction carries BF16 rounding (2^-8 relative per
+    product, accumulated in FP32 over W terms); stated as 3e-2 of the correction
+    magnitude, while the Jacobi part stays exact to 1e-12."""
+    s, im, ctx, d, sD = sysctx
+    p = _params(W, 7)
+    ctx.mlp_set_weights(W, M.flatten(p))
+    R = random_vectors(2, s.dim, seed=2)
+    om = [-0.8, -0.4]
+    U = ctx.mlp_apply(torch.from_numpy(R), om, 0.01).cpu().numpy()
+    for v in range(2):
+        uo = M.apply(p, R[v], d, om[v], 0.01, s.n_occ, sD)
+        jac = R[v] / (om[v] - 0.01j + d)
+        corr = uo - jac
+        assert np.abs(U[v] - uo).max() <= 3e-2 * np.abs(corr).max() + 1e-12 * np.abs(uo).max()
+
+
+def test_train_and_solve_with_learned_preconditioner(sysctx):
+    """Training lowers the loss below the plain-Jacobi value; FGMRES with the
+    network reaches the FP64 tolerance and the same G as the oracle."""
+    s, im, ctx, d, sD = sysctx
+    rng = np.random.default_rng(0)
+    pt = np.repeat(np.arange(s.n_occ), 4)
+    wt = np.tile(np.linspace(-1.15, -0.35, 4), s.n_occ)
+    rep = ctx.mlp_train(pt, wt, 0.01, width=64, steps=400, batch=4096, pair_restart=3, lr=2e-3, seed=1)
+    assert rep["n_pairs"] > 0
+    assert rep["loss_final"] < rep["loss_first"], rep
+    p = [5, 2, 0, 4]
+    w = [-0.45, -0.75, -1.05, -0.3]
+    G, info, _ = ctx.solve(p, w, 0.01, tol=1e-10, precond="mlp")
+    Gj, infoj, _ = ctx.solve(p, w, 0.01, tol=1e-10, precond="jacobi")
+    G = G.cpu().numpy()[:, 0]
+    for r in range(4):
+        assert info[r]["status"] in (0, 4) and info[r]["true_rel_resid"] <= 1e-10, info[r]
+        x, _, _ = O.solve(s, im, p[r], w[r], 0.01, tol=1e-13)
+        gref = O.left_vector(s, p[r]) @ x
+        assert abs(G[r] - gref) <= 1e-8 * abs(gref)
+    print("iterations mlp", [i["iters"] for i in info], "jacobi", [i["iters"] for i in infoj])
