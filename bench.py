@@ -14,6 +14,7 @@ precision used, and the CPU oracle timed on a bounded sample.
 python bench.py [--gpus 1] [--steps K] [--warmup W] [--form bf16|fp32|fp64]
 """
 import argparse
+import tempfile
 import json
 import os
 import sys
@@ -29,7 +30,8 @@ PEAK = {"fp64": 78.6e12, "fp32": 157.3e12, "bf16": 2.5e15}
 # (profiles/ring_gemm_o40v200_bf16ir.md; copy-kernel scale 2.0 for FETCH_SIZE, 1.0 for
 # WRITE_SIZE).  Valid only for the GEMM source they were taken on.
 TRAFFIC = {"gemm_src_sha256_16": "0a178ee3242a1455",
-           "fp64": {"fetch_GB": 19.43, "write_GB": 0.71}, "bf16": {"fetch_GB": 5.19, "write_GB": 0.72}}
+           "fp64": {"fetch_GB": 19.43, "write_GB": 0.71, "launch": "128 slots, M=10240 N=K=8000"},
+           "bf16": {"fetch_GB": 5.19, "write_GB": 0.72, "launch": "128 slots, M=10240 N=K=8000"}}
 DTYPE = {"fp64": "f64", "fp32": "f32+f64", "bf16": "bf16+f64"}
 
 
@@ -47,6 +49,9 @@ def parse():
     ap.add_argument("--batch", type=int, default=0)
     ap.add_argument("--restart", type=int, default=30)
     ap.add_argument("--n-omega", type=int, default=64, help="reduce only for exploration")
+    ap.add_argument("--tune-cache", default=os.path.join(tempfile.gettempdir(), "gfcc_tune_o40v200.json"),
+                    help="GEMM tile autotuner cache ('' disables tuning); the warmup step fills it")
+    ap.add_argument("--graph", type=int, default=1, help="1: replay the inner iteration as a hipGraph")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-baseline", action="store_true", help="skip the plain FP64 batched baseline")
     ap.add_argument("--profile-run", action="store_true",
@@ -91,7 +96,8 @@ def main():
         if prof:
             ctx.prof_enable(True)
         G, info, _ = ctx.solve(P, W, wl.eta, tol=tol, restart=args.restart, max_iter=3000, batch=args.batch,
-                               precond=precond, precision=form)
+                               precond=precond, precision=form, use_graph=bool(args.graph),
+                               tune_cache=args.tune_cache or None)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         pr = ({k: ctx.prof_get(k) for k in ("ring_gemm_fp64", "ring_gemm_fp32", "ring_gemm_bf16", "sigma",
@@ -150,6 +156,7 @@ def main():
     ring = rings.get(dom, {"count": 0, "ms": 0.0, "flops": 0.0})
     achieved = ring["flops"] / (ring["ms"] * 1e-3) if ring["ms"] > 0 else 0.0
     avg_ms = ring["ms"] / max(ring["count"], 1)
+    traffic, traffic_detail = traffic_for(dom)
     kernels = {f"ring_gemm_{k}": {"launches": v["count"], "total_ms": v["ms"],
                                   "tflops": v["flops"] / max(v["ms"], 1e-9) / 1e9} for k, v in rings.items()}
 
@@ -168,9 +175,11 @@ def main():
         "data": "synthetic",
         "config": {"workload": "plain-o40v200 (n_occ=40 n_vir=200 N_chol=800, 40 p x 64 omega, eta=0.01)",
                    "n_rhs": int(n_rhs), "dim": int(s.dim), "form": form, "precond": args.precond,
-                   "restart": args.restart, "tol": wl.tol, "batch": args.batch},
+                   "restart": args.restart, "tol": wl.tol, "batch": args.batch, "graph": bool(args.graph),
+                   "tuned": bool(args.tune_cache)},
         "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK[dom] / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK[dom], "traffic": traffic_for(dom),
+                     "unit": "TFLOP/s", "frac": achieved / PEAK[dom], "traffic": traffic,
+                     "traffic_detail": traffic_detail,
                      "kernel": f"ring GEMM {dom} (gemm_kernel)", "avg_launch_ms": avg_ms,
                      "launches": ring["count"]},
         "kernels": kernels,
@@ -203,15 +212,15 @@ def main():
 
 
 def traffic_for(prec):
-    """Counter-measured bytes per 128-slot launch, or None if the GEMM kernel changed since."""
+    """Counter-measured HBM bytes (fetch + write) per launch, or None if the GEMM kernel changed since."""
     import hashlib
     src = os.path.join(ROOT, "paper_2010_04768_amd", "csrc", "gemm.hip")
     sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
     t = TRAFFIC.get(prec)
     if sha != TRAFFIC["gemm_src_sha256_16"] or t is None:
-        return None
-    return {"fetch_bytes": t["fetch_GB"] * 1e9, "write_bytes": t["write_GB"] * 1e9,
-            "launch": "128 slots (M=10240, N=K=8000)"}
+        return None, None
+    return (t["fetch_GB"] + t["write_GB"]) * 1e9, {"fetch_bytes": t["fetch_GB"] * 1e9,
+                                                   "write_bytes": t["write_GB"] * 1e9, "launch": t["launch"]}
 
 
 def cpu_baseline(s, sigmas_per_rhs, n_p, n_omega, eta):
