@@ -212,6 +212,71 @@ gfcc_status gfcc_mlp_features(gfcc_ctx* ctx, int64_t nvec, const double* R, cons
 gfcc_status gfcc_mlp_apply(gfcc_ctx* ctx, int64_t nvec, const double* R, const double* omega, double eta,
                            double* U, void* stream);
 
+/* ---------------------------------------------------------------------------
+ * Model-order reduction over frequency levels (Theory section, eq. model;
+ * GFCC Workflow and Bottlenecks: the level loop of Algorithm 1, eq. Lmax).
+ * The context keeps an orthonormal REAL basis S (m columns): the real and
+ * imaginary parts of solved X_p(omega) are separate candidates, so the
+ * projected operator Hhat = S^T Hbar_N S is real.  The model system
+ * (omega - i eta + Hhat) Xhat = S^T b_p gives G_qp(omega) ~ (S^T c_q)^T Xhat.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  size_t struct_size;     /* sizeof(gfcc_mor_opts) */
+  double tol;             /* an interval is converged when the model built before its level predicts
+                             G_pp at its midpoint within tol (relative, every p) */
+  double drop_tol;        /* Gram-Schmidt drops a candidate whose norm falls below drop_tol times its
+                             norm before orthogonalisation */
+  int32_t max_levels;     /* 0: the bound floor(log2((omega_max - omega_min) / d_omega)) */
+  int32_t reserved;
+  gfcc_solve_opts solve;  /* options of the direct solves of each level */
+} gfcc_mor_opts;
+
+typedef struct {
+  int32_t levels;         /* levels run */
+  int32_t m;              /* final basis size */
+  int32_t n_solved;       /* grid frequencies solved directly */
+  int32_t converged;      /* 1: every interval closed before the level bound */
+  int32_t per_level[16];  /* frequencies solved at level 1, 2, ... */
+  double max_mid_err;     /* largest midpoint error of the last tested level */
+  double t_solve, t_basis, t_project, t_model;  /* seconds in each phase */
+} gfcc_mor_report;
+
+/* Forget the basis. */
+gfcc_status gfcc_mor_reset(gfcc_ctx* ctx);
+
+/* Gram-Schmidt the real and imaginary parts of n complex vectors X [n][D]
+ * (device, interleaved; not modified) into the basis (classical, one
+ * reorthogonalisation, dependent candidates dropped at drop_tol), apply the
+ * FP64 sigma to the new columns and extend Hhat.  *m_out (host, nullable):
+ * basis size afterwards.  Blocking. */
+gfcc_status gfcc_mor_extend(gfcc_ctx* ctx, int64_t n, const double* X, double drop_tol, int64_t* m_out,
+                            void* stream);
+
+/* Model Green's function at n_omega frequencies (host) for occupied p (host
+ * [np]) and q (host [nq]); q == NULL: the diagonal q = p, G [n_omega][np],
+ * else G [n_omega][np][nq]; complex interleaved, device.  E_STATE when the
+ * basis is empty or a model system is singular.  Blocking. */
+gfcc_status gfcc_mor_model(gfcc_ctx* ctx, int64_t np, const int64_t* p, int64_t nq, const int64_t* q,
+                           int64_t n_omega, const double* omega, double eta, double* G, void* stream);
+
+/* Copy the basis out: which = 0: Hhat [m][m] row-major, Hhat[i][j] = s_i . Hbar_N s_j;
+ * which = 1: S [m][D] (real vectors in the boundary layout).  dst: device,
+ * may be NULL to query *m_out (host). */
+gfcc_status gfcc_mor_export(gfcc_ctx* ctx, int32_t which, double* dst, int64_t* m_out, void* stream);
+
+/* The level loop on a uniform ascending grid omega[0:n_omega] (host): level 1
+ * solves both ends and the middle, level L > 1 solves the midpoints of the
+ * open intervals; an interval closes when its midpoint passes opts->tol and
+ * intervals without interior grid points close.  Each level's solutions
+ * extend the basis.  G [n_omega][np] (device, complex interleaved) is the
+ * final model G_pp on the whole grid; level_of (host [n_omega], nullable):
+ * the level at which a frequency was solved directly, 0 if never; report:
+ * host, nullable.  Returns GFCC_W_NOCONV when a direct solve did not converge.
+ * Blocking. */
+gfcc_status gfcc_mor_greens(gfcc_ctx* ctx, int64_t np, const int64_t* p, int64_t n_omega, const double* omega,
+                            double eta, const gfcc_mor_opts* opts, double* G, int32_t* level_of,
+                            gfcc_mor_report* report, void* stream);
+
 /* Kernel timing of the library's launches with HIP events on the launch
  * stream.  enable != 0 starts recording (clears totals).  For a kernel class
  * name ("ring_gemm_fp64", "ring_gemm_fp32", "ring_gemm_bf16" -- the three ring

@@ -405,6 +405,93 @@ gfcc_status gfcc_mlp_train(gfcc_ctx* c, int64_t nrhs, const int64_t* p, const do
   });
 }
 
+// ---------------------------------------------------------------- model-order reduction
+
+gfcc_status gfcc_mor_reset(gfcc_ctx* c) {
+  return guarded([&] {
+    GFCC_CHECK(c, GFCC_E_ARG, "null context");
+    mor_reset(c);
+  });
+}
+
+gfcc_status gfcc_mor_extend(gfcc_ctx* c, int64_t n, const double* X, double drop_tol, int64_t* m_out,
+                            void* stream) {
+  return guarded([&] {
+    GFCC_CHECK(c, GFCC_E_ARG, "null context");
+    GFCC_CHECK(n >= 0, GFCC_E_ARG, "n < 0");
+    GFCC_CHECK(drop_tol >= 0.0 && drop_tol < 1.0, GFCC_E_ARG, "drop_tol must be in [0, 1)");
+    if (n > 0) {
+      GFCC_CHECK(X, GFCC_E_ARG, "null X");
+      mor_extend(c, n, X, drop_tol, as_stream(stream), nullptr, nullptr);
+    }
+    if (m_out) *m_out = mor_size(c);
+  });
+}
+
+static void check_pq(gfcc_ctx* c, int64_t n, const int64_t* v, const char* what) {
+  GFCC_CHECK(v, GFCC_E_ARG, std::string("null ") + what);
+  for (int64_t k = 0; k < n; ++k)
+    GFCC_CHECK(v[k] >= 0 && v[k] < c->o, GFCC_E_ARG, std::string(what) + " out of range");
+}
+
+gfcc_status gfcc_mor_model(gfcc_ctx* c, int64_t np, const int64_t* p, int64_t nq, const int64_t* q,
+                           int64_t n_omega, const double* omega, double eta, double* G, void* stream) {
+  return guarded([&] {
+    GFCC_CHECK(c, GFCC_E_ARG, "null context");
+    GFCC_CHECK(np >= 1 && n_omega >= 0 && (q == nullptr || nq >= 1), GFCC_E_ARG, "bad sizes");
+    if (n_omega == 0) return;
+    check_pq(c, np, p, "p");
+    if (q) check_pq(c, nq, q, "q");
+    GFCC_CHECK(omega && G, GFCC_E_ARG, "null argument");
+    for (int64_t k = 0; k < n_omega; ++k) GFCC_CHECK(std::isfinite(omega[k]), GFCC_E_ARG, "non-finite omega");
+    mor_model(c, np, p, q ? nq : np, q, q == nullptr, n_omega, omega, eta, G, as_stream(stream));
+  });
+}
+
+gfcc_status gfcc_mor_export(gfcc_ctx* c, int32_t which, double* dst, int64_t* m_out, void* stream) {
+  return guarded([&] {
+    GFCC_CHECK(c, GFCC_E_ARG, "null context");
+    GFCC_CHECK(which == 0 || which == 1, GFCC_E_ARG, "which must be 0 (Hhat) or 1 (basis)");
+    if (m_out) *m_out = mor_size(c);
+    if (dst) {
+      hipStream_t s = as_stream(stream);
+      mor_export(c, which, dst, s);
+      GFCC_HIP(hipStreamSynchronize(s));
+    }
+  });
+}
+
+gfcc_status gfcc_mor_greens(gfcc_ctx* c, int64_t np, const int64_t* p, int64_t n_omega, const double* omega,
+                            double eta, const gfcc_mor_opts* opts, double* G, int32_t* level_of,
+                            gfcc_mor_report* report, void* stream) {
+  bool all_conv = true;
+  gfcc_status st = guarded([&] {
+    GFCC_CHECK(c, GFCC_E_ARG, "null context");
+    GFCC_CHECK(opts && opts->struct_size >= sizeof(gfcc_mor_opts), GFCC_E_ARG, "bad options struct");
+    GFCC_CHECK(opts->solve.struct_size >= sizeof(gfcc_solve_opts), GFCC_E_ARG, "bad solve options struct");
+    GFCC_CHECK(np >= 1 && n_omega >= 1, GFCC_E_ARG, "np and n_omega must be >= 1");
+    check_pq(c, np, p, "p");
+    GFCC_CHECK(omega && G, GFCC_E_ARG, "null argument");
+    GFCC_CHECK(opts->tol > 0.0 && opts->drop_tol >= 0.0 && opts->drop_tol < 1.0 && opts->max_levels >= 0,
+               GFCC_E_ARG, "bad tol / drop_tol / max_levels");
+    const gfcc_solve_opts& so = opts->solve;
+    GFCC_CHECK(so.tol > 0.0 && so.restart >= 1 && so.max_iter >= 1, GFCC_E_ARG, "bad solve tolerance/restart/max_iter");
+    GFCC_CHECK(so.precond >= GFCC_PC_NONE && so.precond <= GFCC_PC_MLP, GFCC_E_ARG, "bad preconditioner");
+    GFCC_CHECK(so.precision >= GFCC_FP64 && so.precision <= GFCC_BF16_IR, GFCC_E_ARG, "bad precision");
+    for (int64_t k = 0; k < n_omega; ++k) GFCC_CHECK(std::isfinite(omega[k]), GFCC_E_ARG, "non-finite omega");
+    if (n_omega >= 3) {
+      const double dw = (omega[n_omega - 1] - omega[0]) / double(n_omega - 1);
+      GFCC_CHECK(dw > 0.0, GFCC_E_ARG, "omega must be ascending");
+      for (int64_t k = 0; k < n_omega; ++k)
+        GFCC_CHECK(std::fabs(omega[k] - (omega[0] + double(k) * dw)) <= 1e-9 * (std::fabs(dw) + std::fabs(omega[k])),
+                   GFCC_E_ARG, "omega must be a uniform grid");
+    }
+    mor_greens(c, np, p, n_omega, omega, eta, opts, G, level_of, report, as_stream(stream), &all_conv);
+  });
+  if (st == GFCC_OK && !all_conv) return GFCC_W_NOCONV;
+  return st;
+}
+
 gfcc_status gfcc_prof_enable(gfcc_ctx* c, int enable) {
   return guarded([&] {
     GFCC_CHECK(c, GFCC_E_ARG, "null context");

@@ -5,6 +5,7 @@
 
 #include "gfcc_internal.h"
 #include "mlp.h"
+#include "mor.h"
 
 struct gfcc_prof_entry {
   int64_t count = 0;
@@ -67,6 +68,9 @@ struct gfcc_ctx {
 
   // learned preconditioner (created by training or by setting weights)
   std::unique_ptr<gfcc::Mlp> mlp;
+
+  // model-order reduction basis and projected operator
+  std::unique_ptr<gfcc::Mor> mor;
 };
 
 namespace gfcc {
@@ -96,6 +100,18 @@ void from_planes(gfcc_ctx* c, int64_t nb, const double* planes, double* xi, hipS
 // G[r][k] = c_{q_k} . x_r (planes), complex interleaved output
 void greens_planes(gfcc_ctx* c, int64_t nb, const double* planes, int64_t nq, const int64_t* q_dev,
                    double* G, hipStream_t s);
+
+// model-order reduction (mor.hip)
+void mor_reset(gfcc_ctx* c);
+int64_t mor_size(gfcc_ctx* c);
+int64_t mor_extend(gfcc_ctx* c, int64_t nb, const double* X, double drop_tol, hipStream_t s, double* t_basis,
+                   double* t_project);
+void mor_model(gfcc_ctx* c, int64_t np, const int64_t* p, int64_t nq, const int64_t* q, bool diag, int64_t nw,
+               const double* w, double eta, double* G, hipStream_t s);
+void mor_export(gfcc_ctx* c, int which, double* dst, hipStream_t s);
+void mor_greens(gfcc_ctx* c, int64_t np, const int64_t* p, int64_t nw, const double* w, double eta,
+                const gfcc_mor_opts* o, double* G, int32_t* level_of, gfcc_mor_report* rep, hipStream_t s,
+                bool* all_converged);
 
 // tile autotuner (tune.hip)
 void tune_load(gfcc_ctx* c, const char* path);

@@ -26,7 +26,8 @@ BLOCKS = ["FOO", "FVV", "FOV", "WOOOO", "WOOOV", "WOVOO", "WOVVO", "WOVOV", "DIA
 SYMBOLS = ["gfcc_build_intermediates", "gfcc_dims", "gfcc_export", "gfcc_sigma", "gfcc_solve_batch",
            "gfcc_greens", "gfcc_prof_enable", "gfcc_prof_get", "gfcc_destroy", "gfcc_strerror",
            "gfcc_last_error", "gfcc_mlp_train", "gfcc_mlp_set_weights", "gfcc_mlp_get_weights",
-           "gfcc_mlp_forward", "gfcc_mlp_loss_grad", "gfcc_mlp_features", "gfcc_mlp_apply"]
+           "gfcc_mlp_forward", "gfcc_mlp_loss_grad", "gfcc_mlp_features", "gfcc_mlp_apply",
+           "gfcc_mor_reset", "gfcc_mor_extend", "gfcc_mor_model", "gfcc_mor_export", "gfcc_mor_greens"]
 
 
 class GfccSystem(ctypes.Structure):
@@ -57,6 +58,18 @@ class MlpReport(ctypes.Structure):
     _fields_ = [("n_pairs", ctypes.c_int64), ("steps", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("loss_first", ctypes.c_double), ("loss_final", ctypes.c_double),
                 ("data_seconds", ctypes.c_double), ("train_seconds", ctypes.c_double)]
+
+
+class MorOpts(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_size_t), ("tol", ctypes.c_double), ("drop_tol", ctypes.c_double),
+                ("max_levels", ctypes.c_int32), ("reserved", ctypes.c_int32), ("solve", SolveOpts)]
+
+
+class MorReport(ctypes.Structure):
+    _fields_ = [("levels", ctypes.c_int32), ("m", ctypes.c_int32), ("n_solved", ctypes.c_int32),
+                ("converged", ctypes.c_int32), ("per_level", ctypes.c_int32 * 16),
+                ("max_mid_err", ctypes.c_double), ("t_solve", ctypes.c_double), ("t_basis", ctypes.c_double),
+                ("t_project", ctypes.c_double), ("t_model", ctypes.c_double)]
 
 
 class GfccError(RuntimeError):
@@ -101,6 +114,14 @@ def load():
     L.gfcc_mlp_apply.argtypes = [vp, i64, vp, vp, dbl, vp, vp]
     for name in ["gfcc_mlp_train", "gfcc_mlp_set_weights", "gfcc_mlp_get_weights", "gfcc_mlp_forward",
                  "gfcc_mlp_loss_grad", "gfcc_mlp_features", "gfcc_mlp_apply"]:
+        getattr(L, name).restype = ctypes.c_int
+    L.gfcc_mor_reset.argtypes = [vp]
+    L.gfcc_mor_extend.argtypes = [vp, i64, vp, dbl, ctypes.POINTER(i64), vp]
+    L.gfcc_mor_model.argtypes = [vp, i64, vp, i64, vp, i64, vp, dbl, vp, vp]
+    L.gfcc_mor_export.argtypes = [vp, ctypes.c_int32, vp, ctypes.POINTER(i64), vp]
+    L.gfcc_mor_greens.argtypes = [vp, i64, vp, i64, vp, dbl, ctypes.POINTER(MorOpts), vp, vp,
+                                  ctypes.POINTER(MorReport), vp]
+    for name in ["gfcc_mor_reset", "gfcc_mor_extend", "gfcc_mor_model", "gfcc_mor_export", "gfcc_mor_greens"]:
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -304,3 +325,68 @@ class Context:
         _check(self._lib.gfcc_mlp_apply(self._h, R.shape[0], _ptr(R), w_h.ctypes.data_as(ctypes.c_void_p), eta,
                                         _ptr(U), _stream()), "gfcc_mlp_apply")
         return U
+
+    # ---------------------------------------------------------------- model-order reduction
+    def mor_reset(self):
+        _check(self._lib.gfcc_mor_reset(self._h), "gfcc_mor_reset")
+
+    def mor_extend(self, X, drop_tol=1e-10):
+        """Gram-Schmidt Re/Im of complex vectors X [n, D] into the basis; returns the basis size."""
+        import torch
+        X = torch.as_tensor(X).to(self.device, torch.complex128).contiguous()
+        m = ctypes.c_int64()
+        _check(self._lib.gfcc_mor_extend(self._h, X.shape[0], _ptr(X), drop_tol, ctypes.byref(m), _stream()),
+               "gfcc_mor_extend")
+        return m.value
+
+    def mor_model(self, p, omega, eta, q=None):
+        """Model G: [n_omega, np] (q None: diagonal) or [n_omega, np, nq] complex128 device tensor."""
+        import torch
+        p_h = np.ascontiguousarray(np.asarray(p, dtype=np.int64))
+        w_h = np.ascontiguousarray(np.asarray(omega, dtype=np.float64))
+        if q is None:
+            q_h, nq, shape = None, p_h.size, (w_h.size, p_h.size)
+        else:
+            q_h = np.ascontiguousarray(np.asarray(q, dtype=np.int64))
+            nq, shape = q_h.size, (w_h.size, p_h.size, q_h.size)
+        G = torch.empty(shape, dtype=torch.complex128, device=self.device)
+        _check(self._lib.gfcc_mor_model(self._h, p_h.size, p_h.ctypes.data_as(ctypes.c_void_p), nq,
+                                        q_h.ctypes.data_as(ctypes.c_void_p) if q_h is not None else None, w_h.size,
+                                        w_h.ctypes.data_as(ctypes.c_void_p), eta, _ptr(G), _stream()),
+               "gfcc_mor_model")
+        return G
+
+    def mor_export(self, which="HHAT"):
+        import torch
+        wi = {"HHAT": 0, "BASIS": 1}[which]
+        m = ctypes.c_int64()
+        _check(self._lib.gfcc_mor_export(self._h, wi, None, ctypes.byref(m), _stream()), "gfcc_mor_export")
+        shape = (m.value, m.value) if wi == 0 else (m.value, self.dim)
+        out = torch.empty(shape, dtype=torch.float64, device=self.device)
+        if m.value > 0:
+            _check(self._lib.gfcc_mor_export(self._h, wi, _ptr(out), ctypes.byref(m), _stream()), "gfcc_mor_export")
+        return out
+
+    def mor_greens(self, p, omega, eta, tol=1e-8, drop_tol=1e-10, max_levels=0, solve_tol=1e-10, restart=30,
+                   max_iter=3000, batch=0, precond="jacobi", precision="fp64", use_graph=False, tune_cache=None,
+                   ir_inner_rtol=0.0):
+        """Level loop on the uniform grid omega; returns (G [n_omega, np] device, report dict, level_of)."""
+        import torch
+        p_h = np.ascontiguousarray(np.asarray(p, dtype=np.int64))
+        w_h = np.ascontiguousarray(np.asarray(omega, dtype=np.float64))
+        so = SolveOpts(ctypes.sizeof(SolveOpts), solve_tol, restart, max_iter, batch, PRECONDS[precond],
+                       PRECISIONS[precision], int(use_graph), tune_cache.encode() if tune_cache else None,
+                       ir_inner_rtol)
+        o = MorOpts(ctypes.sizeof(MorOpts), tol, drop_tol, max_levels, 0, so)
+        rep = MorReport()
+        lev = np.zeros(w_h.size, dtype=np.int32)
+        G = torch.zeros((w_h.size, p_h.size), dtype=torch.complex128, device=self.device)
+        st = self._lib.gfcc_mor_greens(self._h, p_h.size, p_h.ctypes.data_as(ctypes.c_void_p), w_h.size,
+                                       w_h.ctypes.data_as(ctypes.c_void_p), eta, ctypes.byref(o), _ptr(G),
+                                       lev.ctypes.data_as(ctypes.c_void_p), ctypes.byref(rep), _stream())
+        _check(st, "gfcc_mor_greens")
+        report = dict(levels=rep.levels, m=rep.m, n_solved=rep.n_solved, converged=bool(rep.converged),
+                      per_level=[rep.per_level[i] for i in range(min(rep.levels, 16))],
+                      max_mid_err=rep.max_mid_err, t_solve=rep.t_solve, t_basis=rep.t_basis,
+                      t_project=rep.t_project, t_model=rep.t_model, all_solves_converged=(st == 0))
+        return G, report, lev
