@@ -246,14 +246,15 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
 // NW = WGM x WGN waves, each computing a (BM/WGM) x (BN/WGN) sub-tile; two LDS
 // stages so that one barrier per K-step separates "store next" from "read
 // current"; global loads for step k+1 are issued before the MFMAs of step k.
-template <typename T, int BM, int BN, int WGM, int WGN, bool VEC>
+template <typename T, int BM, int BN, int WGM, int WGN, int KM, bool VEC>
 __global__ __launch_bounds__(64 * WGM * WGN) void gemm_db_kernel(GemmArgs g) {
   using MF = Mfma<T>;
   constexpr int NT = 64 * WGM * WGN;
   constexpr int EPC = 16 / int(sizeof(T));
-  constexpr int BK = 8 * EPC;
+  constexpr int CPR = 8 * KM;  // 16-byte chunks per K-row of a stage
+  constexpr int BK = CPR * EPC;
   constexpr int LDK = BK + EPC;
-  constexpr int RPP = NT / 8;
+  constexpr int RPP = NT / CPR;
   constexpr int PA = BM / RPP, PB = BN / RPP;
   constexpr int WM = BM / WGM, WN = BN / WGN, FM = WM / 16, FN = WN / 16;
   constexpr int FE = (MF::KS == 32) ? 8 : 1;
@@ -289,8 +290,8 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_db_kernel(GemmArgs g) {
   const T* A = static_cast<const T*>(g.A) + (g.k_split > 0 ? kbase : rmap(g.az, z));
   const T* B = static_cast<const T*>(g.B) + (g.k_split > 0 ? kbase : rmap(g.bz, z));
 
-  const int lrow = tid >> 3;
-  const int lchunk = tid & 7;
+  const int lrow = tid / CPR;
+  const int lchunk = tid % CPR;
   int64_t aoff[PA], boff[PB];
 #pragma unroll
   for (int p = 0; p < PA; ++p) {
@@ -388,16 +389,16 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_db_kernel(GemmArgs g) {
   }
 }
 
-template <typename T, int BM, int BN, int WGM, int WGN>
+template <typename T, int BM, int BN, int WGM, int WGN, int KM = 1>
 static void launch_db(const GemmArgs& a, bool vec, hipStream_t s) {
   const int64_t tiles = ((a.M + BM - 1) / BM) * ((a.N + BN - 1) / BN);
   GFCC_CHECK(tiles < (int64_t(1) << 31) && a.batch < 65536, GFCC_E_ARG, "GEMM grid too large");
   GFCC_CHECK(!a.b_ncontig, GFCC_E_ARG, "double-buffered tiles need a K-contiguous B");
   dim3 grid(unsigned(tiles), 1, unsigned(a.batch));
   if (vec)
-    hipLaunchKernelGGL((gemm_db_kernel<T, BM, BN, WGM, WGN, true>), grid, dim3(64 * WGM * WGN), 0, s, a);
+    hipLaunchKernelGGL((gemm_db_kernel<T, BM, BN, WGM, WGN, KM, true>), grid, dim3(64 * WGM * WGN), 0, s, a);
   else
-    hipLaunchKernelGGL((gemm_db_kernel<T, BM, BN, WGM, WGN, false>), grid, dim3(64 * WGM * WGN), 0, s, a);
+    hipLaunchKernelGGL((gemm_db_kernel<T, BM, BN, WGM, WGN, KM, false>), grid, dim3(64 * WGM * WGN), 0, s, a);
   GFCC_HIP(hipGetLastError());
 }
 
@@ -431,6 +432,7 @@ static void dispatch(const GemmArgs& a, int cfg, bool vec, hipStream_t s) {
     case TILE_DB_256x128: launch_db<T, 256, 128, 4, 2>(a, vec, s); break;
     case TILE_DB_128x256: launch_db<T, 128, 256, 2, 4>(a, vec, s); break;
     case TILE_DB_256x256: launch_db<T, 256, 256, 4, 2>(a, vec, s); break;
+    case TILE_DB_128x128_K2: launch_db<T, 128, 128, 2, 2, 2>(a, vec, s); break;
     default: throw Error{GFCC_E_ARG, "bad tile config"};
   }
 }
@@ -496,7 +498,7 @@ void gemm_auto(Prec p, const GemmArgs& a, Scratch& scr, int scr_slot, hipStream_
 
 const char* tile_name(int cfg) {
   static const char* n[] = {"128x128", "64x64", "128x64", "64x128", "db128x128", "db256x128", "db128x256",
-                            "db256x256"};
+                            "db256x256", "db128x128k2"};
   return (cfg >= 0 && cfg < N_TILE_CFG) ? n[cfg] : "?";
 }
 

@@ -680,6 +680,12 @@ void solve_batch(gfcc_ctx* c, int64_t nrhs, const int64_t* p, const double* omeg
       for (auto& kv : g) (void)hipGraphExecDestroy(kv.second);
     }
   } graph_guard{graphs};
+  struct CaptureStream {
+    hipStream_t s = nullptr;
+    ~CaptureStream() {
+      if (s) (void)hipStreamDestroy(s);
+    }
+  } cap;
   uint64_t graph_gen = alloc_generation();
   while (!active.empty() || !pending.empty()) {
     const int na = int(active.size());
@@ -690,7 +696,7 @@ void solve_batch(gfcc_ctx* c, int64_t nrhs, const int64_t* p, const double* omeg
       // (and a plain preconditioner) it is captured once per window size --
       // when that size repeats, so every buffer is already sized and the
       // capture holds kernels only -- and replayed afterwards.
-      auto iteration = [&]() {
+      auto iteration = [&](hipStream_t s) {
         if (!use_mlp) {
           hipLaunchKernelGGL(precond_kernel, dim3(nch, na), dim3(VT), 0, s, d, act, c->ws_in.as<double>(),
                              c->diag.as<double>(), mode, flex);
@@ -753,27 +759,41 @@ void solve_batch(gfcc_ctx* c, int64_t nrhs, const int64_t* p, const double* omeg
         graph_gen = alloc_generation();
       }
       if (!graphable) {
-        iteration();
+        iteration(s);
       } else {
         const std::pair<int, const void*> gk{na, d_act.p};
         auto it = graphs.find(gk);
         if (it != graphs.end()) {
           GFCC_HIP(hipGraphLaunch(it->second, s));
         } else if (seen_sizes.count(gk)) {
-          hipGraph_t gr;
+          // Record on a library stream: the caller's stream may be the legacy
+          // default stream, which cannot be captured.  Recording executes
+          // nothing; the graph is launched on the caller's stream.
+          if (!cap.s) GFCC_HIP(hipStreamCreateWithFlags(&cap.s, hipStreamNonBlocking));
+          hipGraph_t gr = nullptr;
           const uint64_t gen0 = alloc_generation();
-          GFCC_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-          iteration();
-          GFCC_HIP(hipStreamEndCapture(s, &gr));
-          GFCC_CHECK(alloc_generation() == gen0, GFCC_E_STATE, "allocation during graph capture");
+          GFCC_HIP(hipStreamBeginCapture(cap.s, hipStreamCaptureModeThreadLocal));
+          try {
+            iteration(cap.s);
+          } catch (...) {
+            if (hipStreamEndCapture(cap.s, &gr) == hipSuccess && gr) (void)hipGraphDestroy(gr);
+            (void)hipGetLastError();
+            throw;
+          }
+          GFCC_HIP(hipStreamEndCapture(cap.s, &gr));
+          if (alloc_generation() != gen0) {
+            (void)hipGraphDestroy(gr);
+            throw Error{GFCC_E_STATE, "allocation during graph capture"};
+          }
           hipGraphExec_t ex;
-          GFCC_HIP(hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0));
-          GFCC_HIP(hipGraphDestroy(gr));
+          const hipError_t ie = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
+          (void)hipGraphDestroy(gr);
+          GFCC_HIP(ie);
           graphs[gk] = ex;
           GFCC_HIP(hipGraphLaunch(ex, s));
         } else {
           seen_sizes.insert(gk);
-          iteration();
+          iteration(s);
         }
       }
       GFCC_HIP(hipMemcpyAsync(hflags.data(), d_flags.p, na * sizeof(int), hipMemcpyDeviceToHost, s));
