@@ -36,7 +36,13 @@ void tune_load(gfcc_ctx* c, const char* path) {
     const size_t cp = t.find("\"cfg\": ", e);
     if (cp == std::string::npos) break;
     const int cfg = std::atoi(t.c_str() + cp + 7);
-    if (cfg >= 0 && cfg < N_TILE_CFG) c->tuned[key] = cfg;
+    if (cfg >= 0 && cfg < N_TILE_CFG) {
+      c->tuned[key] = cfg;
+      const size_t mp = t.find("\"ms\": ", cp);
+      const size_t next = t.find("\"key\": \"", cp);
+      if (mp != std::string::npos && (next == std::string::npos || mp < next))
+        c->tuned_ms[key] = float(std::atof(t.c_str() + mp + 6));
+    }
     pos = cp;
   }
 }
