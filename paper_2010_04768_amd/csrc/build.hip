@@ -296,18 +296,16 @@ void build_intermediates(gfcc_ctx* c, const gfcc_system* sys, hipStream_t s) {
     const int p2[4] = {3, 0, 2, 1};  // (mf|ne): in dims (m,f,n,e)
     permute(ovov, p2, -1.0, z, 1.0, s);
   }
-  c->t2p.ensure(oov * c->vp * 8, s);
+  c->ktw = c->vp + c->o_pad;
+  const int64_t ktw = c->ktw;
+  c->TW.ensure(oov * ktw * 8, s);
   {
-    TView t = tview_s(c->t2p.as<double>(), {o, o, v, v}, {o * v * c->vp, v * c->vp, c->vp, 1});  // [i][j][a][e]
+    TView t = tview_s(c->TW.as<double>(), {o, o, v, v}, {o * v * ktw, v * ktw, ktw, 1});  // [i][j][a][e]
     const int p[4] = {0, 1, 3, 2};
     permute(T2, p, 1.0, t, 0.0, s);
-  }
-  c->WovooT.ensure(oov * c->o_pad * 8, s);
-  {
-    TView t = tview_s(c->WovooT.as<double>(), {o, o, v, o},
-                      {o * v * c->o_pad, v * c->o_pad, c->o_pad, 1});  // [i][j][a][m]
-    const int p[4] = {2, 3, 1, 0};
-    permute(Wovoo, p, 1.0, t, 0.0, s);
+    TView w = tview_s(c->TW.as<double>() + c->vp, {o, o, v, o}, {o * v * ktw, v * ktw, ktw, 1});  // [i][j][a][m]
+    const int q[4] = {2, 3, 1, 0};
+    permute(Wovoo, q, 1.0, w, 0.0, s);
   }
   c->FooT.ensure(o * c->o_pad * 8, s);
   {
@@ -404,6 +402,7 @@ void build_lowprec(gfcc_ctx* c, int which, hipStream_t s) {
   mk(L.Wov, c->Wov, ov * c->kp, L.sWov);
   mk(L.W4T, c->W4T, c->oo * c->op2, L.sW4T);
   mk(L.Zm, c->Zm, c->v * c->ldz, L.sZm);
+  mk(L.TW, c->TW, c->oov * c->ktw, L.sTW);
   GFCC_HIP(hipStreamSynchronize(s));
   L.built = true;
 }

@@ -31,8 +31,9 @@ struct gfcc_ctx {
   gfcc::DBuf Wvo, Wov, X1;
   gfcc::DBuf W4T;     // [(i,j)][op2]     W4T[(i,j)][(m,n)] = Woooo[m,n,i,j]
   gfcc::DBuf Zm;      // [v][ldz]         Zm[e][(m,n,f)] = 2(me|nf) - (mf|ne)
-  gfcc::DBuf t2p;     // [(i,j,a)][vp]    t2p[(i,j,a)][e] = t2[i,j,e,a]
-  gfcc::DBuf WovooT;  // [(i,j,a)][o_pad] WovooT[(i,j,a)][m] = Wovoo[m,a,i,j]
+  // [(i,j,a)][ktw]: columns [0, v) t2[i,j,e,a] (three-body), [vp, vp + o) Wovoo[m,a,i,j] (2h1p <- 1h)
+  gfcc::DBuf TW;
+  int64_t ktw = 0;    // vp + o_pad
   gfcc::DBuf FvvM;    // [a][vp]
   gfcc::DBuf FooT;    // [i][o_pad]       FooT[i][m] = Foo[m,i]
   gfcc::DBuf d1b;     // [(i,j,a)]        Fvv[a,a] - Foo[i,i] - Foo[j,j]
@@ -44,13 +45,13 @@ struct gfcc_ctx {
   // reduced-precision copies of the two-body operands: [0] FP32, [1] BF16
   struct LowPrec {
     bool built = false;
-    gfcc::DBuf X1, Wvo, Wov, W4T, Zm;
-    double sX1 = 1, sWvo = 1, sWov = 1, sW4T = 1, sZm = 1;  // stored = value * s
+    gfcc::DBuf X1, Wvo, Wov, W4T, Zm, TW;
+    double sX1 = 1, sWvo = 1, sWov = 1, sW4T = 1, sZm = 1, sTW = 1;  // stored = value * s
   } lp[2];
 
   // workspaces
   gfcc::Scratch scr;
-  gfcc::DBuf ws_RT, ws_Ra, ws_R, ws_z;      // sigma operand copies
+  gfcc::DBuf ws_RT, ws_Ra, ws_R, ws_z, ws_zr;  // sigma operand copies
   gfcc::DBuf ws_in, ws_out;                 // planes for gfcc_sigma / gfcc_greens
 
   // kernel timing
@@ -116,7 +117,11 @@ void mor_greens(gfcc_ctx* c, int64_t np, const int64_t* p, int64_t nw, const dou
 // tile autotuner (tune.hip)
 void tune_load(gfcc_ctx* c, const char* path);
 void tune_save(gfcc_ctx* c, const char* path);
+// time every tile configuration on the sigma GEMM shapes of a P-plane batch
+// (ring, hole-hole ladder, three-body + 2h1p<-1h) and keep the fastest
 void tune_ring(gfcc_ctx* c, Prec p, int64_t P, hipStream_t s);
+// tuned tile for a shape, else the closest tuned shape of the same precision and K, else the default
+int tuned_cfg(gfcc_ctx* c, Prec p, int64_t M, int64_t N, int64_t K);
 
 // timing helpers (no-ops when profiling is off)
 void prof_begin(gfcc_ctx* c, const char* name, hipStream_t s);

@@ -73,24 +73,19 @@ static unsigned blocks_for(int64_t n) {
   return unsigned(std::min<int64_t>(std::max<int64_t>((n + 255) / 256, 1), 4096));
 }
 
-static int ring_cfg(gfcc_ctx* c, Prec p, int64_t M, int64_t N, int64_t K) {
-  char key[96];
-  snprintf(key, sizeof key, "%d:%lld:%lld:%lld", int(p), (long long)M, (long long)N, (long long)K);
-  auto it = c->tuned.find(key);
-  if (it != c->tuned.end()) return it->second;
-  // a tuned entry for the same precision and N, K with a large M serves any large M
-  if (M >= 1024) {
-    char pre[96];
-    snprintf(pre, sizeof pre, "%d:", int(p));
-    char suf[64];
-    snprintf(suf, sizeof suf, ":%lld:%lld", (long long)N, (long long)K);
-    for (const auto& kv : c->tuned) {
-      const std::string& k = kv.first;
-      if (k.rfind(pre, 0) == 0 && k.size() > strlen(suf) && k.compare(k.size() - strlen(suf), strlen(suf), suf) == 0)
-        return kv.second;
-    }
+// A[p][k] of the fused three-body + 2h1p<-1h GEMM: [z_p (v) | 0 | r1_p (o) | 0], row stride ktw
+template <typename T>
+__global__ void make_zr_kernel(const double* __restrict__ z, const double* __restrict__ x, T* __restrict__ A,
+                               int64_t v, int64_t vp, int64_t o, int64_t ktw, int64_t Dp) {
+  const int64_t p = blockIdx.x;
+  for (int64_t k = threadIdx.x; k < ktw; k += blockDim.x) {
+    double val = 0.0;
+    if (k < v)
+      val = z[p * vp + k];
+    else if (k >= vp && k < vp + o)
+      val = x[p * Dp + (k - vp)];
+    A[p * ktw + k] = cvt<T>(val);
   }
-  return gemm_default_cfg(M, N, K);
 }
 
 template <typename T>
@@ -156,7 +151,7 @@ void sigma_planes(gfcc_ctx* c, int64_t P, const double* x, double* y, gfcc_preci
     g.C = y + op;
     g.cm = two(o, Dp, ov);
     g.cn = lin(1);
-    const int cfg = ring_cfg(c, rp, g.M, g.N, g.K);
+    const int cfg = tuned_cfg(c, rp, g.M, g.N, g.K);
     // P1a
     if (lowp) {
       g.A = c->ws_R.p;
@@ -205,7 +200,7 @@ void sigma_planes(gfcc_ctx* c, int64_t P, const double* x, double* y, gfcc_preci
     g.cn = two(v, Dp, 1);
     g.alpha = sW4T;
     g.beta = 1.0;
-    gemm(rp, g, gemm_default_cfg(g.M, g.N, g.K), s);
+    gemm(rp, g, tuned_cfg(c, rp, g.M, g.N, g.K), s);
   }
   // ---- three-body: z[p][e] = sum_(mnf) Zm[e][(m,n,f)] r2[p][(m,n,f)];  s2 -= z . t2
   {
@@ -228,37 +223,41 @@ void sigma_planes(gfcc_ctx* c, int64_t P, const double* x, double* y, gfcc_preci
     g.alpha = sZm;
     g.beta = 0.0;
     gemm_auto(rp, g, c->scr, 0, s);
+  }
+  // ---- three-body second half and 2h1p <- 1h in one GEMM:
+  //      s2[p][(i,j,a)] -= sum_e z[p][e] t2[i,j,e,a] + sum_m r1[p][m] Wovoo[m,a,i,j]
+  {
+    const int64_t ktw = c->ktw;
+    c->ws_zr.ensure(size_t(P * ktw * esz), s);
+    switch (rp) {
+      case Prec::F64:
+        hipLaunchKernelGGL((make_zr_kernel<double>), dim3(unsigned(P)), dim3(256), 0, s, c->ws_z.as<double>(), x,
+                           c->ws_zr.as<double>(), v, c->vp, o, ktw, Dp);
+        break;
+      case Prec::F32:
+        hipLaunchKernelGGL((make_zr_kernel<float>), dim3(unsigned(P)), dim3(256), 0, s, c->ws_z.as<double>(), x,
+                           c->ws_zr.as<float>(), v, c->vp, o, ktw, Dp);
+        break;
+      case Prec::BF16:
+        hipLaunchKernelGGL((make_zr_kernel<__bf16>), dim3(unsigned(P)), dim3(256), 0, s, c->ws_z.as<double>(), x,
+                           c->ws_zr.as<__bf16>(), v, c->vp, o, ktw, Dp);
+        break;
+    }
+    GFCC_HIP(hipGetLastError());
     GemmArgs h;
-    h.A = c->ws_z.p;
-    h.am = lin(c->vp);
-    h.B = c->t2p.p;
-    h.bm = lin(c->vp);
+    h.A = c->ws_zr.p;
+    h.am = lin(ktw);
+    h.B = lowp ? L.TW.p : c->TW.p;
+    h.bm = lin(ktw);
     h.M = P;
     h.N = oov;
-    h.K = v;
+    h.K = ktw;
     h.C = y + op;
     h.cm = lin(Dp);
     h.cn = lin(1);
-    h.alpha = -1.0;
+    h.alpha = lowp ? -1.0 / L.sTW : -1.0;
     h.beta = 1.0;
-    gemm(Prec::F64, h, gemm_default_cfg(h.M, h.N, h.K), s);
-  }
-  // ---- 2h1p <- 1h: s2[p][(i,j,a)] -= sum_m r1[p][m] WovooT[(i,j,a)][m]   (FP64)
-  {
-    GemmArgs g;
-    g.A = x;
-    g.am = lin(Dp);
-    g.B = c->WovooT.p;
-    g.bm = lin(c->o_pad);
-    g.M = P;
-    g.N = oov;
-    g.K = o;
-    g.C = y + op;
-    g.cm = lin(Dp);
-    g.cn = lin(1);
-    g.alpha = -1.0;
-    g.beta = 1.0;
-    gemm(Prec::F64, g, gemm_default_cfg(g.M, g.N, g.K), s);
+    gemm(rp, h, tuned_cfg(c, rp, h.M, h.N, h.K), s);
   }
   // ---- 1h rows: s1[p][i] = sum_k x[p][k] Uop[i][k]   (FP64)
   {

@@ -1,9 +1,11 @@
-// Tile autotuner for the ring GEMMs.  The paper's tensor layer relies on a
+// Tile autotuner for the sigma GEMMs.  The paper's tensor layer relies on a
 // few tens of kernels tuned by vendor libraries, code generation plus
 // autotuning, or hand tuning (Tensor Algebra for Many-body Methods); here every
-// tile configuration of the MFMA GEMM is timed with HIP events on the actual
-// ring-GEMM shape (M = vector rows, N = K = o*v) and the fastest is kept per
-// (precision, M, N, K).  Results persist in a small JSON file.
+// tile configuration of the MFMA GEMM is timed with HIP events on the sigma's
+// GEMM shapes (ring: M = vector rows, N = K = o*v; hole-hole ladder; three-body
+// + 2h1p<-1h) and the fastest is kept per (precision, M, N, K).  Results
+// persist in a small JSON file.
+#include <cmath>
 #include <cstdio>
 #include <fstream>
 #include <sstream>
@@ -60,22 +62,40 @@ void tune_save(gfcc_ctx* c, const char* path) {
   f << "]}\n";
 }
 
-// Time all tile configurations for the ring GEMM with P planes in precision p.
-void tune_ring(gfcc_ctx* c, Prec p, int64_t P, hipStream_t s) {
-  const int64_t M = P * c->o, N = c->ov, K = c->ov;
+template <typename T>
+__global__ void fill_kernel(T* p, int64_t n, double val) {
+  for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < n; t += int64_t(gridDim.x) * blockDim.x)
+    p[t] = T(float(val));
+}
+
+static void fill(Prec p, void* dst, int64_t n, double val, hipStream_t s) {
+  const dim3 g(unsigned(std::min<int64_t>((n + 255) / 256, 4096)));
+  switch (p) {
+    case Prec::F64: hipLaunchKernelGGL(fill_kernel<double>, g, dim3(256), 0, s, static_cast<double*>(dst), n, val); break;
+    case Prec::F32: hipLaunchKernelGGL(fill_kernel<float>, g, dim3(256), 0, s, static_cast<float*>(dst), n, val); break;
+    case Prec::BF16: hipLaunchKernelGGL(fill_kernel<__bf16>, g, dim3(256), 0, s, static_cast<__bf16*>(dst), n, val); break;
+  }
+  GFCC_HIP(hipGetLastError());
+}
+
+// Time every tile configuration on C[M][N] = A[M][K] B[N][K]^T (both operands
+// K-contiguous, filled with a constant) and keep the fastest.
+static void tune_shape(gfcc_ctx* c, Prec p, int64_t M, int64_t N, int64_t K, hipStream_t s) {
   const std::string key = tune_key(p, M, N, K);
-  if (c->tuned.count(key)) return;
+  if (c->tuned.count(key) || M <= 0 || N <= 0 || K <= 0) return;
   const int64_t esz = (p == Prec::F64) ? 8 : (p == Prec::F32 ? 4 : 2);
-  if (p != Prec::F64) build_lowprec(c, p == Prec::BF16 ? 1 : 0, s);
-  DBuf a, cbuf;
-  a.ensure(size_t(M) * K * esz, s);
-  cbuf.ensure(size_t(M) * N * 8, s);
-  const void* B = (p == Prec::F64) ? c->X1.p : (p == Prec::F32 ? c->lp[0].X1.p : c->lp[1].X1.p);
+  const int64_t ldk = round_up(K, 8);
+  DBuf a, b, cbuf;
+  a.ensure(size_t(M * ldk * esz), s);
+  b.ensure(size_t(N * ldk * esz), s);
+  cbuf.ensure(size_t(M * N) * 8, s);
+  fill(p, a.p, M * ldk, 0.5, s);
+  fill(p, b.p, N * ldk, 0.25, s);
   GemmArgs g;
   g.A = a.p;
-  g.am = lin(K);
-  g.B = B;
-  g.bm = lin(c->kp);
+  g.am = lin(ldk);
+  g.B = b.p;
+  g.bm = lin(ldk);
   g.C = cbuf.as<double>();
   g.cm = lin(N);
   g.cn = lin(1);
@@ -106,6 +126,34 @@ void tune_ring(gfcc_ctx* c, Prec p, int64_t P, hipStream_t s) {
   (void)hipEventDestroy(e1);
   c->tuned[key] = best;
   c->tuned_ms[key] = best_ms;
+}
+
+void tune_ring(gfcc_ctx* c, Prec p, int64_t P, hipStream_t s) {
+  if (p != Prec::F64) build_lowprec(c, p == Prec::BF16 ? 1 : 0, s);
+  tune_shape(c, p, P * c->o, c->ov, c->ov, s);  // ring
+  tune_shape(c, p, c->oo, P * c->v, c->oo, s);  // hole-hole ladder
+  tune_shape(c, p, P, c->oov, c->ktw, s);       // three-body + 2h1p <- 1h
+}
+
+int tuned_cfg(gfcc_ctx* c, Prec p, int64_t M, int64_t N, int64_t K) {
+  const std::string key = tune_key(p, M, N, K);
+  auto it = c->tuned.find(key);
+  if (it != c->tuned.end()) return it->second;
+  // closest tuned shape with the same precision and K (within a factor 4 overall)
+  double best = std::log(4.0);
+  int cfg = gemm_default_cfg(M, N, K);
+  for (const auto& kv : c->tuned) {
+    int pp = 0;
+    long long m2 = 0, n2 = 0, k2 = 0;
+    if (std::sscanf(kv.first.c_str(), "%d:%lld:%lld:%lld", &pp, &m2, &n2, &k2) != 4) continue;
+    if (pp != int(p) || k2 != K || m2 <= 0 || n2 <= 0) continue;
+    const double d = std::fabs(std::log(double(M) / double(m2))) + std::fabs(std::log(double(N) / double(n2)));
+    if (d <= best) {
+      best = d;
+      cfg = kv.second;
+    }
+  }
+  return cfg;
 }
 
 }  // namespace gfcc
