@@ -14,7 +14,13 @@
 // group, Implementation Details, here at slot granularity).
 //
 // Orthogonalisation is classical Gram-Schmidt applied twice (CGS2), FP64,
-// with the complex inner product <u, w> = sum conj(u) w.  Givens rotations as
+// with the complex inner product <u, w> = sum conj(u) w.  The second
+// projection's coefficients come from the Gram matrix of the basis:
+// V^H (w - V h1) = h1 - G h1 with G = V^H V, so one pass over the basis forms
+// h1 = V^H w together with the new column of G (<V_j, V_k>), and a second pass
+// forms w - V (2 h1 - G h1) and its norm -- the same projections as
+// re-reading the basis for an explicit second pass, two reads of it instead
+// of four.  Givens rotations as
 // in the oracle.  In GMRES-IR mode (FP32/BF16 sigma) the inner cycle stops at
 // a tolerance relative to the cycle's starting residual that the reduced
 // precision operator can deliver; the restart's FP64 true residual drives the
@@ -38,6 +44,7 @@ constexpr int VT = 256;         // threads per vector-kernel block
 constexpr int VE = 8;           // elements per thread
 constexpr int CH = VT * VE;     // elements per chunk
 constexpr int MAXM = 64;        // maximum restart length
+constexpr int PS = 2 * (MAXM + 1);  // partial-dot stride per chunk
 
 __device__ __forceinline__ double wave_sum(double x) {
 #pragma unroll
@@ -59,7 +66,8 @@ struct SolverDev {
   double* ctol;    // [B]  cycle tolerance (absolute)
   double* res;     // [B]  residual estimate |g_{k+1}|
   int* flag;       // [B]  1: cycle done
-  cplx* part;      // [na][nch][MAXM+1] partial dots
+  cplx* part;      // [na][nch][PS] partial dots: <V_j, w> at j, <V_j, V_k> at MAXM+1+j
+  cplx* Gm;        // [B][m][m+1]   Gm[s][k][j] = <V_j, V_k>, j <= k
   cplx* h;         // [na][MAXM+1]
   double* npart;   // [na][nch]
   double* norm;    // [na]
@@ -132,9 +140,8 @@ __global__ void precond_kernel(SolverDev d, const int* act, double* win, const d
   }
 }
 
-// pass = 0: w = z u + sigma  -> V[k+1], then partial <V_j, w>, j <= k
-// pass = 1: w -= sum_j h_j V_j (in place), then partial <V_j, w>
-// pass = 2: w -= sum_j h_j V_j, then partial ||w||^2
+// pass 0: w = z u + sigma -> V[k+1]; partial <V_j, w> and <V_j, V_k>, j <= k
+// pass 2: w -= sum_j h_j V_j (in place); partial ||w||^2
 __global__ __launch_bounds__(VT) void arnoldi_kernel(SolverDev d, const int* act, const double* win,
                                                      const double* wout, int pass) {
   const int q = blockIdx.y;
@@ -183,6 +190,7 @@ __global__ __launch_bounds__(VT) void arnoldi_kernel(SolverDev d, const int* act
         }
       }
     }
+    double acc = 0.0;
 #pragma unroll
     for (int e = 0; e < VE; ++e) {
       const int64_t t = i0 + threadIdx.x + e * VT;
@@ -190,12 +198,8 @@ __global__ __launch_bounds__(VT) void arnoldi_kernel(SolverDev d, const int* act
         wr[t] = xr[e];
         wi[t] = xi[e];
       }
+      acc += xr[e] * xr[e] + xi[e] * xi[e];
     }
-  }
-  if (pass == 2) {
-    double acc = 0.0;
-#pragma unroll
-    for (int e = 0; e < VE; ++e) acc += xr[e] * xr[e] + xi[e] * xi[e];
     __shared__ double red[VT / 64];
     acc = wave_sum(acc);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
@@ -207,12 +211,24 @@ __global__ __launch_bounds__(VT) void arnoldi_kernel(SolverDev d, const int* act
     }
     return;
   }
-  __shared__ double lds[VT / 64][MAXM + 1][2];
+  // pass 0: dots with every basis vector of w and of V_k
+  double kr[VE], ki[VE];
+  {
+    const double* vr = vec(d, s, k, 0);
+    const double* vi = vec(d, s, k, 1);
+#pragma unroll
+    for (int e = 0; e < VE; ++e) {
+      const int64_t t = i0 + threadIdx.x + e * VT;
+      kr[e] = (t < d.Dp) ? vr[t] : 0.0;
+      ki[e] = (t < d.Dp) ? vi[t] : 0.0;
+    }
+  }
+  __shared__ double lds[VT / 64][MAXM + 1][4];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   for (int j = 0; j <= k; ++j) {
     const double* vr = vec(d, s, j, 0);
     const double* vi = vec(d, s, j, 1);
-    double a = 0.0, b = 0.0;
+    double a = 0.0, b = 0.0, ga = 0.0, gb = 0.0;
 #pragma unroll
     for (int e = 0; e < VE; ++e) {
       const int64_t t = i0 + threadIdx.x + e * VT;
@@ -220,45 +236,76 @@ __global__ __launch_bounds__(VT) void arnoldi_kernel(SolverDev d, const int* act
         const double ur = vr[t], ui = vi[t];
         a += ur * xr[e] + ui * xi[e];  // conj(v) w
         b += ur * xi[e] - ui * xr[e];
+        ga += ur * kr[e] + ui * ki[e];  // conj(v) V_k
+        gb += ur * ki[e] - ui * kr[e];
       }
     }
     a = wave_sum(a);
     b = wave_sum(b);
+    ga = wave_sum(ga);
+    gb = wave_sum(gb);
     if (lane == 0) {
       lds[wv][j][0] = a;
       lds[wv][j][1] = b;
+      lds[wv][j][2] = ga;
+      lds[wv][j][3] = gb;
     }
   }
   __syncthreads();
   if (int(threadIdx.x) <= k) {
-    double a = 0, b = 0;
+    double a = 0, b = 0, ga = 0, gb = 0;
     for (int w = 0; w < VT / 64; ++w) {
       a += lds[w][threadIdx.x][0];
       b += lds[w][threadIdx.x][1];
+      ga += lds[w][threadIdx.x][2];
+      gb += lds[w][threadIdx.x][3];
     }
-    d.part[(int64_t(q) * d.nch + blockIdx.x) * (MAXM + 1) + threadIdx.x] = cplx{a, b};
+    cplx* pp = d.part + (int64_t(q) * d.nch + blockIdx.x) * PS;
+    pp[threadIdx.x] = cplx{a, b};
+    pp[MAXM + 1 + threadIdx.x] = cplx{ga, gb};
   }
 }
 
-// h = sum over chunks; H(:, k) = h (pass 0) or += h (pass 1)
-__global__ void reduce_h_kernel(SolverDev d, const int* act, int pass) {
+// Per slot: h1 = sum of the chunk partials of <V_j, w>, the new Gram column
+// G(j, k) = <V_j, V_k>, then h = h1 + (h1 - G h1) -> d.h and H(:, k).
+__global__ void reduce_hg_kernel(SolverDev d, const int* act) {
   const int q = blockIdx.x;
   const int s = act[q];
   const int k = d.kk[s];
+  const int m = d.m;
   const int j = threadIdx.x;
-  if (j > k) return;
-  double a = 0, b = 0;
-  for (int c = 0; c < d.nch; ++c) {
-    const cplx p = d.part[(int64_t(q) * d.nch + c) * (MAXM + 1) + j];
-    a += p.re;
-    b += p.im;
+  __shared__ cplx h1[MAXM + 1];
+  cplx* Gk = d.Gm + (int64_t(s) * m + k) * (m + 1);
+  if (j <= k) {
+    double a = 0, b = 0, ga = 0, gb = 0;
+    for (int c = 0; c < d.nch; ++c) {
+      const cplx* pp = d.part + (int64_t(q) * d.nch + c) * PS;
+      a += pp[j].re;
+      b += pp[j].im;
+      ga += pp[MAXM + 1 + j].re;
+      gb += pp[MAXM + 1 + j].im;
+    }
+    h1[j] = cplx{a, b};
+    Gk[j] = cplx{ga, gb};
   }
-  d.h[int64_t(q) * (MAXM + 1) + j] = cplx{a, b};
-  cplx* Hc = d.H + (int64_t(s) * d.m + k) * (d.m + 1);
-  if (pass == 0)
-    Hc[j] = cplx{a, b};
-  else
-    Hc[j] = cplx{Hc[j].re + a, Hc[j].im + b};
+  __syncthreads();
+  if (j > k) return;
+  // (G h1)_j = sum_i G(j, i) h1_i; column i of Gm holds G(0..i, i); G(j, i) = conj(G(i, j))
+  double gr = 0.0, gi = 0.0;
+  for (int i = 0; i <= k; ++i) {
+    cplx gji;
+    if (j <= i) {
+      gji = d.Gm[(int64_t(s) * m + i) * (m + 1) + j];
+    } else {
+      const cplx gij = d.Gm[(int64_t(s) * m + j) * (m + 1) + i];
+      gji = cplx{gij.re, -gij.im};
+    }
+    gr += gji.re * h1[i].re - gji.im * h1[i].im;
+    gi += gji.re * h1[i].im + gji.im * h1[i].re;
+  }
+  const cplx h = cplx{2.0 * h1[j].re - gr, 2.0 * h1[j].im - gi};
+  d.h[int64_t(q) * (MAXM + 1) + j] = h;
+  d.H[(int64_t(s) * m + k) * (m + 1) + j] = h;
 }
 
 // ||w||, H(k+1, k), Givens rotation, residual estimate, cycle flag
@@ -569,7 +616,7 @@ void solve_batch(gfcc_ctx* c, int64_t nrhs, const int64_t* p, const double* omeg
   B = int(std::min<int64_t>(B, nrhs));
 
   // device state
-  DBuf bV, bZ, bX, bH, bcs, bsn, bg, by, bz, bkk, bctol, bres, bflag, bpart, bh, bnpart, bnorm;
+  DBuf bV, bZ, bX, bH, bcs, bsn, bg, by, bz, bkk, bctol, bres, bflag, bpart, bGm, bh, bnpart, bnorm;
   bV.ensure(size_t(B) * (m + 1) * 2 * Dp * 8, s);
   if (flex) bZ.ensure(size_t(B) * m * 2 * Dp * 8, s);
   bX.ensure(size_t(B) * 2 * Dp * 8, s);
@@ -583,7 +630,8 @@ void solve_batch(gfcc_ctx* c, int64_t nrhs, const int64_t* p, const double* omeg
   bctol.ensure(size_t(B) * 8, s);
   bres.ensure(size_t(B) * 8, s);
   bflag.ensure(size_t(B) * sizeof(int), s);
-  bpart.ensure(size_t(B) * nch * (MAXM + 1) * sizeof(cplx), s);
+  bpart.ensure(size_t(B) * nch * PS * sizeof(cplx), s);
+  bGm.ensure(size_t(B) * m * (m + 1) * sizeof(cplx), s);
   bh.ensure(size_t(B) * (MAXM + 1) * sizeof(cplx), s);
   bnpart.ensure(size_t(B) * nch * 8, s);
   bnorm.ensure(size_t(B) * 8, s);
@@ -605,6 +653,7 @@ void solve_batch(gfcc_ctx* c, int64_t nrhs, const int64_t* p, const double* omeg
   d.res = bres.as<double>();
   d.flag = bflag.as<int>();
   d.part = bpart.as<cplx>();
+  d.Gm = bGm.as<cplx>();
   d.h = bh.as<cplx>();
   d.npart = bnpart.as<double>();
   d.norm = bnorm.as<double>();
@@ -739,10 +788,7 @@ void solve_batch(gfcc_ctx* c, int64_t nrhs, const int64_t* p, const double* omeg
         prof_begin(c, "arnoldi", s);
         hipLaunchKernelGGL(arnoldi_kernel, dim3(nch, na), dim3(VT), 0, s, d, act, c->ws_in.as<double>(),
                            c->ws_out.as<double>(), 0);
-        hipLaunchKernelGGL(reduce_h_kernel, dim3(na), dim3(MAXM + 1), 0, s, d, act, 0);
-        hipLaunchKernelGGL(arnoldi_kernel, dim3(nch, na), dim3(VT), 0, s, d, act, c->ws_in.as<double>(),
-                           c->ws_out.as<double>(), 1);
-        hipLaunchKernelGGL(reduce_h_kernel, dim3(na), dim3(MAXM + 1), 0, s, d, act, 1);
+        hipLaunchKernelGGL(reduce_hg_kernel, dim3(na), dim3(MAXM + 1), 0, s, d, act);
         hipLaunchKernelGGL(arnoldi_kernel, dim3(nch, na), dim3(VT), 0, s, d, act, c->ws_in.as<double>(),
                            c->ws_out.as<double>(), 2);
         GFCC_HIP(hipGetLastError());
