@@ -432,7 +432,6 @@ static void dispatch(const GemmArgs& a, int cfg, bool vec, hipStream_t s) {
     case TILE_DB_256x128: launch_db<T, 256, 128, 4, 2>(a, vec, s); break;
     case TILE_DB_128x256: launch_db<T, 128, 256, 2, 4>(a, vec, s); break;
     case TILE_DB_256x256: launch_db<T, 256, 256, 4, 2>(a, vec, s); break;
-    case TILE_DB_128x128_K2: launch_db<T, 128, 128, 2, 2, 2>(a, vec, s); break;
     default: throw Error{GFCC_E_ARG, "bad tile config"};
   }
 }
@@ -498,7 +497,7 @@ void gemm_auto(Prec p, const GemmArgs& a, Scratch& scr, int scr_slot, hipStream_
 
 const char* tile_name(int cfg) {
   static const char* n[] = {"128x128", "64x64", "128x64", "64x128", "db128x128", "db256x128", "db128x256",
-                            "db256x256", "db128x128k2"};
+                            "db256x256"};
   return (cfg >= 0 && cfg < N_TILE_CFG) ? n[cfg] : "?";
 }
 

@@ -114,9 +114,7 @@ enum TileCfg : int {
   TILE_128x128 = 0, TILE_64x64 = 1, TILE_128x64 = 2, TILE_64x128 = 3,
   // double-buffered LDS, one barrier per K-step (K-contiguous B only)
   TILE_DB_128x128 = 4, TILE_DB_256x128 = 5, TILE_DB_128x256 = 6, TILE_DB_256x256 = 7,
-  // double-buffered 128x128 with twice the K depth per stage (longer prefetch distance)
-  TILE_DB_128x128_K2 = 8,
-  N_TILE_CFG = 9
+  N_TILE_CFG = 8
 };
 const char* tile_name(int cfg);
 
