@@ -17,6 +17,7 @@
 // dealt round-robin over the 8 XCDs) and walks tile-rows in groups so that
 // concurrently running tiles share operand panels in that XCD's L2.
 #include <algorithm>
+#include <type_traits>
 
 #include "gfcc_internal.h"
 
@@ -24,37 +25,80 @@ namespace gfcc {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
+typedef float v16f __attribute__((ext_vector_type(16)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef unsigned int u4 __attribute__((ext_vector_type(4)));
 
 template <typename T> struct Mfma;
+// Every shape below describes its lane layout to the double-buffered kernel:
+// a 16x16 (or 32x32) block of C per instruction (BLK), K per instruction (KS),
+// the operand row and first K element a lane supplies (frow, fk) and where
+// accumulator r of a lane lands in the C block (orow, ocol).
 template <> struct Mfma<double> {
   using acc_t = v4d;
   using frag_t = double;
   static constexpr int KS = 4;       // K per instruction
+  static constexpr int BLK = 16, NACC = 4;
   static constexpr bool ROW_INTERLEAVED = true;  // D[(l/16) + 4r][l%16]
   __device__ static inline acc_t mma(frag_t a, frag_t b, acc_t c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
+  __device__ static inline int frow(int l) { return l & 15; }
+  __device__ static inline int fk(int l) { return l >> 4; }
+  __device__ static inline int orow(int l, int r) { return (l >> 4) + 4 * r; }
+  __device__ static inline int ocol(int l) { return l & 15; }
 };
 template <> struct Mfma<float> {
   using acc_t = v4f;
   using frag_t = float;
   static constexpr int KS = 4;
+  static constexpr int BLK = 16, NACC = 4;
   static constexpr bool ROW_INTERLEAVED = false;  // D[4(l/16) + r][l%16]
   __device__ static inline acc_t mma(frag_t a, frag_t b, acc_t c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
+  __device__ static inline int frow(int l) { return l & 15; }
+  __device__ static inline int fk(int l) { return l >> 4; }
+  __device__ static inline int orow(int l, int r) { return 4 * (l >> 4) + r; }
+  __device__ static inline int ocol(int l) { return l & 15; }
 };
 template <> struct Mfma<__bf16> {
   using acc_t = v4f;
   using frag_t = v8bf;
   static constexpr int KS = 32;
+  static constexpr int BLK = 16, NACC = 4;
   static constexpr bool ROW_INTERLEAVED = false;
   __device__ static inline acc_t mma(frag_t a, frag_t b, acc_t c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
   }
+  __device__ static inline int frow(int l) { return l & 15; }
+  __device__ static inline int fk(int l) { return (l >> 4) * 8; }
+  __device__ static inline int orow(int l, int r) { return 4 * (l >> 4) + r; }
+  __device__ static inline int ocol(int l) { return l & 15; }
 };
+// 32x32x16 BF16: half the instructions and fragment loads per flop of the 16x16x32 form
+struct Mfma32Bf16 {
+  using acc_t = v16f;
+  using frag_t = v8bf;
+  static constexpr int KS = 16;
+  static constexpr int BLK = 32, NACC = 16;
+  __device__ static inline acc_t mma(frag_t a, frag_t b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+  }
+  __device__ static inline int frow(int l) { return l & 31; }
+  __device__ static inline int fk(int l) { return (l >> 5) * 8; }
+  __device__ static inline int orow(int l, int r) { return 8 * (r >> 2) + 4 * (l >> 5) + (r & 3); }
+  __device__ static inline int ocol(int l) { return l & 31; }
+};
+
+// Workgroups are dealt round-robin over the 8 XCDs (workgroup b runs on XCD
+// b % 8).  Give XCD x a contiguous range of tiles: with ntiles = 8q + r, XCDs
+// x < r take q + 1 tiles and the others q; a bijection on [0, ntiles).
+__device__ __forceinline__ int64_t xcd_remap(int64_t bid, int64_t ntiles) {
+  const int64_t q = ntiles >> 3, r = ntiles & 7;
+  const int64_t x = bid & 7, idx = bid >> 3;
+  return (x < r) ? x * (q + 1) + idx : r * (q + 1) + (x - r) * q + idx;
+}
 
 __device__ __forceinline__ int64_t rmap(const RowMap& m, int64_t r) {
   return (r / m.div) * m.hi + (r % m.div) * m.lo;
@@ -85,7 +129,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
   const int64_t tiles_n = (g.N + BN - 1) / BN;
   const int64_t ntiles = tiles_m * tiles_n;
   int64_t bid = blockIdx.x;
-  if ((ntiles & 7) == 0) bid = (bid & 7) * (ntiles >> 3) + (bid >> 3);
+  bid = xcd_remap(bid, ntiles);
   constexpr int64_t GROUP = 8;
   const int64_t per_group = GROUP * tiles_n;
   const int64_t grp = bid / per_group;
@@ -246,9 +290,8 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
 // NW = WGM x WGN waves, each computing a (BM/WGM) x (BN/WGN) sub-tile; two LDS
 // stages so that one barrier per K-step separates "store next" from "read
 // current"; global loads for step k+1 are issued before the MFMAs of step k.
-template <typename T, int BM, int BN, int WGM, int WGN, int KM, bool VEC>
+template <typename T, typename MF, int BM, int BN, int WGM, int WGN, int KM, bool VEC>
 __global__ __launch_bounds__(64 * WGM * WGN) void gemm_db_kernel(GemmArgs g) {
-  using MF = Mfma<T>;
   constexpr int NT = 64 * WGM * WGN;
   constexpr int EPC = 16 / int(sizeof(T));
   constexpr int CPR = 8 * KM;  // 16-byte chunks per K-row of a stage
@@ -256,9 +299,9 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_db_kernel(GemmArgs g) {
   constexpr int LDK = BK + EPC;
   constexpr int RPP = NT / CPR;
   constexpr int PA = BM / RPP, PB = BN / RPP;
-  constexpr int WM = BM / WGM, WN = BN / WGN, FM = WM / 16, FN = WN / 16;
-  constexpr int FE = (MF::KS == 32) ? 8 : 1;
+  constexpr int WM = BM / WGM, WN = BN / WGN, FM = WM / MF::BLK, FN = WN / MF::BLK;
   static_assert(PA >= 1 && PB >= 1 && BM % RPP == 0 && BN % RPP == 0, "tile/thread mismatch");
+  static_assert(FM >= 1 && FN >= 1 && WM % MF::BLK == 0 && WN % MF::BLK == 0, "wave tile/MFMA mismatch");
 
   __shared__ __attribute__((aligned(16))) T As[2][BM * LDK];
   __shared__ __attribute__((aligned(16))) T Bs[2][BN * LDK];
@@ -273,7 +316,7 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_db_kernel(GemmArgs g) {
   const int64_t tiles_n = (g.N + BN - 1) / BN;
   const int64_t ntiles = tiles_m * tiles_n;
   int64_t bid = blockIdx.x;
-  if ((ntiles & 7) == 0) bid = (bid & 7) * (ntiles >> 3) + (bid >> 3);
+  bid = xcd_remap(bid, ntiles);
   constexpr int64_t GROUP = 4;
   const int64_t per_group = GROUP * tiles_n;
   const int64_t grp = bid / per_group;
@@ -337,11 +380,11 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_db_kernel(GemmArgs g) {
 #pragma unroll
   for (int a = 0; a < FM; ++a)
 #pragma unroll
-    for (int b = 0; b < FN; ++b) acc[a][b] = typename MF::acc_t{0, 0, 0, 0};
+    for (int b = 0; b < FN; ++b) acc[a][b] = typename MF::acc_t{};
 
   const int nk = int((Kz + BK - 1) / BK);
-  const int fr = lane & 15;
-  const int fk = (lane >> 4) * FE;
+  const int fr = MF::frow(lane);
+  const int fk = MF::fk(lane);
   load_tiles(0);
   store_tiles(0);
   __syncthreads();
@@ -353,10 +396,10 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_db_kernel(GemmArgs g) {
       typename MF::frag_t af[FM], bf[FN];
 #pragma unroll
       for (int a = 0; a < FM; ++a)
-        af[a] = *reinterpret_cast<const typename MF::frag_t*>(&As[cur][(wm0 + a * 16 + fr) * LDK + ks + fk]);
+        af[a] = *reinterpret_cast<const typename MF::frag_t*>(&As[cur][(wm0 + a * MF::BLK + fr) * LDK + ks + fk]);
 #pragma unroll
       for (int b = 0; b < FN; ++b)
-        bf[b] = *reinterpret_cast<const typename MF::frag_t*>(&Bs[cur][(wn0 + b * 16 + fr) * LDK + ks + fk]);
+        bf[b] = *reinterpret_cast<const typename MF::frag_t*>(&Bs[cur][(wn0 + b * MF::BLK + fr) * LDK + ks + fk]);
 #pragma unroll
       for (int a = 0; a < FM; ++a)
 #pragma unroll
@@ -367,19 +410,17 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_db_kernel(GemmArgs g) {
   }
 
   double* C = g.C + rmap(g.cz, z);
-  const int jl = lane & 15;
-  const int ih = lane >> 4;
+  const int jl = MF::ocol(lane);
 #pragma unroll
   for (int b = 0; b < FN; ++b) {
-    const int64_t j = j0 + wn0 + b * 16 + jl;
+    const int64_t j = j0 + wn0 + b * MF::BLK + jl;
     if (j >= g.N) continue;
     const int64_t cj = rmap(g.cn, j);
 #pragma unroll
     for (int a = 0; a < FM; ++a) {
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int ii = MF::ROW_INTERLEAVED ? (ih + 4 * r) : (4 * ih + r);
-        const int64_t i = i0 + wm0 + a * 16 + ii;
+      for (int r = 0; r < MF::NACC; ++r) {
+        const int64_t i = i0 + wm0 + a * MF::BLK + MF::orow(lane, r);
         if (i >= g.M) continue;
         double* p = C + rmap(g.cm, i) + cj;
         const double v = g.alpha * double(acc[a][b][r]);
@@ -389,16 +430,16 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_db_kernel(GemmArgs g) {
   }
 }
 
-template <typename T, int BM, int BN, int WGM, int WGN, int KM = 1>
+template <typename T, int BM, int BN, int WGM, int WGN, int KM = 1, typename MF = Mfma<T>>
 static void launch_db(const GemmArgs& a, bool vec, hipStream_t s) {
   const int64_t tiles = ((a.M + BM - 1) / BM) * ((a.N + BN - 1) / BN);
   GFCC_CHECK(tiles < (int64_t(1) << 31) && a.batch < 65536, GFCC_E_ARG, "GEMM grid too large");
   GFCC_CHECK(!a.b_ncontig, GFCC_E_ARG, "double-buffered tiles need a K-contiguous B");
   dim3 grid(unsigned(tiles), 1, unsigned(a.batch));
   if (vec)
-    hipLaunchKernelGGL((gemm_db_kernel<T, BM, BN, WGM, WGN, KM, true>), grid, dim3(64 * WGM * WGN), 0, s, a);
+    hipLaunchKernelGGL((gemm_db_kernel<T, MF, BM, BN, WGM, WGN, KM, true>), grid, dim3(64 * WGM * WGN), 0, s, a);
   else
-    hipLaunchKernelGGL((gemm_db_kernel<T, BM, BN, WGM, WGN, KM, false>), grid, dim3(64 * WGM * WGN), 0, s, a);
+    hipLaunchKernelGGL((gemm_db_kernel<T, MF, BM, BN, WGM, WGN, KM, false>), grid, dim3(64 * WGM * WGN), 0, s, a);
   GFCC_HIP(hipGetLastError());
 }
 
@@ -432,6 +473,19 @@ static void dispatch(const GemmArgs& a, int cfg, bool vec, hipStream_t s) {
     case TILE_DB_256x128: launch_db<T, 256, 128, 4, 2>(a, vec, s); break;
     case TILE_DB_128x256: launch_db<T, 128, 256, 2, 4>(a, vec, s); break;
     case TILE_DB_256x256: launch_db<T, 256, 256, 4, 2>(a, vec, s); break;
+    // 32x32 MFMA blocks (BF16; other types run the 16x16 kernel of the same tile)
+    case TILE_DB32_256x256:
+      if constexpr (std::is_same<T, __bf16>::value) launch_db<T, 256, 256, 4, 2, 1, Mfma32Bf16>(a, vec, s);
+      else launch_db<T, 256, 256, 4, 2>(a, vec, s);
+      break;
+    case TILE_DB32_256x128:
+      if constexpr (std::is_same<T, __bf16>::value) launch_db<T, 256, 128, 4, 2, 1, Mfma32Bf16>(a, vec, s);
+      else launch_db<T, 256, 128, 4, 2>(a, vec, s);
+      break;
+    case TILE_DB32_128x128:
+      if constexpr (std::is_same<T, __bf16>::value) launch_db<T, 128, 128, 2, 2, 1, Mfma32Bf16>(a, vec, s);
+      else launch_db<T, 128, 128, 2, 2>(a, vec, s);
+      break;
     default: throw Error{GFCC_E_ARG, "bad tile config"};
   }
 }
@@ -497,7 +551,7 @@ void gemm_auto(Prec p, const GemmArgs& a, Scratch& scr, int scr_slot, hipStream_
 
 const char* tile_name(int cfg) {
   static const char* n[] = {"128x128", "64x64", "128x64", "64x128", "db128x128", "db256x128", "db128x256",
-                            "db256x256"};
+                            "db256x256", "db32_256x256", "db32_256x128", "db32_128x128"};
   return (cfg >= 0 && cfg < N_TILE_CFG) ? n[cfg] : "?";
 }
 

@@ -114,7 +114,9 @@ enum TileCfg : int {
   TILE_128x128 = 0, TILE_64x64 = 1, TILE_128x64 = 2, TILE_64x128 = 3,
   // double-buffered LDS, one barrier per K-step (K-contiguous B only)
   TILE_DB_128x128 = 4, TILE_DB_256x128 = 5, TILE_DB_128x256 = 6, TILE_DB_256x256 = 7,
-  N_TILE_CFG = 8
+  // double-buffered with 32x32x16 BF16 MFMA blocks (other types: the 16x16 kernel of the same tile)
+  TILE_DB32_256x256 = 8, TILE_DB32_256x128 = 9, TILE_DB32_128x128 = 10,
+  N_TILE_CFG = 11
 };
 const char* tile_name(int cfg);
 
