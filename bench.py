@@ -55,6 +55,13 @@ def parse():
                     help="GEMM tile autotuner cache ('' disables tuning); the warmup step fills it")
     ap.add_argument("--graph", type=int, default=1, help="1: replay the inner iteration as a hipGraph")
     ap.add_argument("--no-mor", action="store_true", help="skip the model-order-reduction pass")
+    ap.add_argument("--mlp-study", action="store_true",
+                    help="instead of the benchmark: learned preconditioner vs Jacobi on the 90/420/1800 system "
+                         "(sampled right-hand sides), one JSON line")
+    ap.add_argument("--mlp-steps", type=int, default=400)
+    ap.add_argument("--mlp-max-iter", type=int, default=600)
+    ap.add_argument("--mlp-tol", type=float, default=1e-8,
+                    help="study tolerance (restarted GMRES(30) + Jacobi stalls near 1e-3 after 150 iterations here)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-baseline", action="store_true", help="skip the plain FP64 batched baseline")
     ap.add_argument("--profile-run", action="store_true",
@@ -70,6 +77,9 @@ def main():
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); every right-hand side is "
               "independent, so more GPUs would each take a share of the (p, omega) queue.", file=sys.stderr)
         sys.exit(2)
+    if args.mlp_study:
+        mlp_study(args)
+        return
     import torch
 
     from paper_2010_04768_amd import gfcc
@@ -247,6 +257,75 @@ def mor_pass(args, gfcc, eps_d, L_d, t1_d, t2_d, plist, omegas, wl, form, Gref):
             "omega_solved": rep["n_solved"], "per_level": rep["per_level"], "converged": rep["converged"],
             "t_solve": rep["t_solve"], "t_basis": rep["t_basis"], "t_project": rep["t_project"],
             "t_model": rep["t_model"]}
+
+
+def mlp_study(args):
+    """Learned FGMRES preconditioner against Jacobi on the 90/420/1800 system (30 highest p,
+    256 omega on [-1.2, -0.3], eta 0.005): train on Jacobi solves (the benchmark's form, FP64 true
+    residuals at every restart; restart 64) at 8 training omega (one p each, to 1e-4), then solve 16
+    other (p, omega) right-hand sides with BF16 sigma + FP64 refinement toward --mlp-tol for at most
+    --mlp-max-iter iterations: Jacobi and the network at restart 30, Jacobi at restart 64.  When no
+    training solve converges the network is not trained and that is reported."""
+    import torch
+
+    from paper_2010_04768_amd import gfcc
+    from synth import make_workload
+
+    torch.cuda.set_device(0)
+    t0 = time.perf_counter()
+    wl = make_workload("learned-o90v420")
+    s, omegas, plist = wl.systems[0], wl.omegas[0], wl.p_lists[0]
+    log(f"system o={s.n_occ} v={s.n_vir} Q={s.n_chol} D={s.dim} generated in {time.perf_counter() - t0:.0f}s")
+    t = time.perf_counter()
+    ctx = gfcc.Context(s.eps, s.L, s.t1, s.t2)  # Lambda = T^dagger: l1, l2 not passed
+    torch.cuda.synchronize()
+    log(f"intermediates built in {time.perf_counter() - t:.1f}s")
+    del s
+    tw = omegas[::32]  # 8 training omega, one p each
+    tp = np.array([plist[(5 * i) % len(plist)] for i in range(len(tw))])
+    ew = omegas[4::16]
+    ep = np.array([plist[(7 * i) % len(plist)] for i in range(len(ew))])
+    log(f"training data: {args.form} Jacobi solves of {len(tw)} right-hand sides, then {args.mlp_steps} Adam steps")
+    out = {"metric": "learned preconditioner vs Jacobi (inner iterations, true FP64 residual, time)",
+           "workload": "learned-o90v420 (n_occ=90 n_vir=420 N_chol=1800, eta=0.005), 8 training and "
+                       "16 evaluation right-hand sides", "tol": args.mlp_tol, "forms": {}}
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    try:
+        out["training"] = ctx.mlp_train(tp, tw, wl.eta, width=256, steps=args.mlp_steps, batch=8192,
+                                        pair_restart=64, lr=1e-3, seed=0, max_pairs=128, data_tol=1e-4,
+                                        data_max_iter=1200, data_precision=args.form)
+        trained = True
+    except gfcc.GfccError as e:  # no training solve converged: report it, evaluate Jacobi only
+        out["training"] = {"error": str(e)}
+        trained = False
+    torch.cuda.synchronize()
+    log(f"training: {out['training']} ({time.perf_counter() - t:.1f}s)")
+    forms = [("jacobi", "jacobi", 30), ("jacobi_restart64", "jacobi", 64)]
+    if trained:
+        forms.insert(1, ("mlp", "mlp", 30))
+    G0 = None
+    for name, pc, rs in forms:
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        G, info, _ = ctx.solve(ep, ew, wl.eta, tol=args.mlp_tol, precision=args.form, precond=pc, restart=rs,
+                               max_iter=args.mlp_max_iter)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        G = G.cpu().numpy()[:, 0]
+        rr = [i["true_rel_resid"] for i in info]
+        out["forms"][name] = {
+            "seconds": dt, "iters_mean": float(np.mean([i["iters"] for i in info])),
+            "restarts_mean": float(np.mean([i["restarts"] for i in info])),
+            "converged": int(sum(i["status"] in (0, 4) for i in info)),
+            "true_rel_resid_median": float(np.median(rr)), "true_rel_resid_max": float(max(rr))}
+        if G0 is None:
+            G0 = G
+        else:
+            out["forms"][name]["g_max_rel_diff_vs_jacobi"] = float(np.max(np.abs(G - G0) / np.abs(G0)))
+        log(f"{name}: {out['forms'][name]}")
+    ctx.close()
+    print(json.dumps(out), flush=True)
 
 
 def traffic_for(prec, tune_cache):

@@ -169,6 +169,11 @@ typedef struct {
   double lr;            /* Adam learning rate */
   uint64_t seed;        /* initialisation and sampling seed */
   int32_t max_pairs;    /* cap on stored (residual, error) pairs */
+  int32_t data_max_iter; /* iteration cap of each data-generating solve (0: 4000) */
+  double data_tol;      /* tolerance of the data-generating solves (0: 1e-11); X* must be
+                           accurate well below the residuals of the recorded pairs */
+  int32_t data_precision; /* gfcc_precision of the data-generating solves (their restart
+                             residuals are FP64 true residuals in every precision) */
   int32_t reserved;
 } gfcc_mlp_opts;
 
@@ -181,8 +186,8 @@ typedef struct {
 } gfcc_mlp_report;
 
 /* Train the network on pairs the solver generates itself: FP64 Jacobi GMRES
- * solves of the given (p, omega) right-hand sides with restart length
- * opts->pair_restart record, at every restart, the true residual r_k and the
+ * solves of the given (p, omega) right-hand sides (tolerance opts->data_tol) with restart
+ * length opts->pair_restart record, at every restart, the true residual r_k and the
  * iterate x_k; after convergence e_k = X* - x_k (so A e_k = r_k).  Minibatches
  * of elements are sampled on the GPU; loss = mean |y - t|^2 with
  * t = e sD/n - jh; Adam.  p, omega, report: host.  Blocking. */

@@ -190,6 +190,8 @@ gfcc_status gfcc_solve_batch(gfcc_ctx* c, int64_t nrhs, const int64_t* p, const 
     GFCC_CHECK(q != nullptr || nq == 1, GFCC_E_ARG, "q == NULL requires nq == 1");
     GFCC_CHECK(nq >= 1, GFCC_E_ARG, "nq < 1");
     for (int64_t r = 0; r < nrhs; ++r) GFCC_CHECK(p[r] >= 0 && p[r] < c->o, GFCC_E_ARG, "p out of range");
+    for (int64_t r = 0; r < nrhs; ++r) GFCC_CHECK(std::isfinite(omega[r]), GFCC_E_ARG, "non-finite omega");
+    GFCC_CHECK(std::isfinite(eta), GFCC_E_ARG, "non-finite eta");
     if (q)
       for (int64_t k = 0; k < nq; ++k) GFCC_CHECK(q[k] >= 0 && q[k] < c->o, GFCC_E_ARG, "q out of range");
     GFCC_CHECK(opts->tol > 0.0 && opts->restart >= 1 && opts->max_iter >= 1, GFCC_E_ARG, "bad tolerance/restart/max_iter");
@@ -348,11 +350,13 @@ gfcc_status gfcc_mlp_train(gfcc_ctx* c, int64_t nrhs, const int64_t* p, const do
     rec.cap = mo->max_pairs;
     gfcc_solve_opts so{};
     so.struct_size = sizeof(so);
-    so.tol = 1e-11;
+    so.tol = mo->data_tol > 0.0 ? mo->data_tol : 1e-11;
     so.restart = mo->pair_restart;
-    so.max_iter = 4000;
+    so.max_iter = mo->data_max_iter > 0 ? mo->data_max_iter : 4000;
     so.precond = GFCC_PC_JACOBI;
-    so.precision = GFCC_FP64;
+    GFCC_CHECK(mo->data_precision >= GFCC_FP64 && mo->data_precision <= GFCC_BF16_IR, GFCC_E_ARG,
+               "bad data_precision");
+    so.precision = static_cast<gfcc_precision>(mo->data_precision);
     std::vector<gfcc_rhs_info> inf(static_cast<size_t>(nrhs));
     bool conv = true;
     solve_batch(c, nrhs, p, omega, eta, 1, nullptr, &so, bG.as<double>(), nullptr, inf.data(), s, &conv, &rec);

@@ -381,6 +381,9 @@ void build_intermediates(gfcc_ctx* c, const gfcc_system* sys, hipStream_t s) {
     ein("qa,klac->qklc", -1.0, T1, ul, 1.0, c2, scr, s);
     GFCC_HIP(hipStreamSynchronize(s));  // temporaries are freed on return
   }
+  // the contraction engine's staging buffers hold integral-sized copies; the solver needs
+  // only small split-K partials from them, so give the memory back
+  for (auto& b : scr.b) b.release();
   (void)ovv;
 }
 

@@ -155,3 +155,16 @@ def test_level_loop_benchmark_shape():
         assert err.max() <= 1e-8
     finally:
         ctx.close()
+
+
+def test_level_loop_degenerate_grids(tiny):
+    """One or two frequencies: no level structure, every point solved directly."""
+    s, im, ctx, direct = tiny
+    for ws in (np.array([-0.55]), np.array([-0.9, -0.3])):
+        G, rep, lev = ctx.mor_greens([0, 2], ws, ETA, tol=1e-8, solve_tol=1e-13, precision="fp64")
+        assert rep["levels"] == 1 and list(lev) == [1] * len(ws)
+        G = G.cpu().numpy()
+        for k, w in enumerate(ws):
+            for i, p in enumerate((0, 2)):
+                g = O.left_vector(s, p) @ direct(p, w)
+                assert abs(G[k, i] - g) <= 1e-10 * abs(g)

@@ -190,3 +190,30 @@ def test_argument_errors():
         ctx.solve([0], [-0.5], 0.01, q=[9])
     G, info, _ = ctx.solve([], [], 0.01)
     assert G.shape[0] == 0
+
+
+def test_solve_edge_cases():
+    """max_iter exhaustion reports status 1 without failing the call; duplicate right-hand
+    sides in one window agree; a window larger than the request; restart 4; bad omega."""
+    s = _sys(5, 7, 9)
+    im = O.intermediates(s)
+    ctx = gfcc.Context.from_system(s)
+    G, info, _ = ctx.solve([1, 3], [-0.6, -0.4], 0.01, tol=1e-14, max_iter=2)
+    assert all(i["status"] == 1 and i["iters"] == 2 and i["true_rel_resid"] > 1e-14 for i in info)
+    p = [2, 2, 4, 2]
+    w = [-0.7, -0.7, -0.3, -0.7]
+    G, info, _ = ctx.solve(p, w, 0.01, tol=1e-12, batch=64)
+    G = G.cpu().numpy()[:, 0]
+    assert all(i["status"] == 0 for i in info)
+    assert G[0] == G[1] == G[3]
+    G2, info2, _ = ctx.solve(p, w, 0.01, tol=1e-12, restart=4, max_iter=4000)
+    assert all(i["status"] == 0 for i in info2)
+    for r in (0, 2):
+        x, _, _ = O.solve(s, im, p[r], w[r], 0.01, tol=1e-13)
+        gref = O.left_vector(s, p[r]) @ x
+        assert abs(G2.cpu().numpy()[r, 0] - gref) <= 1e-10 * abs(gref)
+    with pytest.raises(gfcc.GfccError):
+        ctx.solve([0], [float("nan")], 0.01)
+    with pytest.raises(gfcc.GfccError):
+        ctx.solve([0], [-0.5], float("inf"))
+    ctx.close()
