@@ -486,6 +486,15 @@ static void dispatch(const GemmArgs& a, int cfg, bool vec, hipStream_t s) {
       if constexpr (std::is_same<T, __bf16>::value) launch_db<T, 128, 128, 2, 2, 1, Mfma32Bf16>(a, vec, s);
       else launch_db<T, 128, 128, 2, 2>(a, vec, s);
       break;
+    // 16 waves of 64x64 (BF16): four waves per SIMD hide the global-load latency of the next K stage
+    case TILE_DB32_256x256_W16:
+      if constexpr (std::is_same<T, __bf16>::value) launch_db<T, 256, 256, 4, 4, 1, Mfma32Bf16>(a, vec, s);
+      else launch_db<T, 256, 256, 4, 2>(a, vec, s);
+      break;
+    case TILE_DB_256x256_W16:
+      if constexpr (std::is_same<T, __bf16>::value) launch_db<T, 256, 256, 4, 4>(a, vec, s);
+      else launch_db<T, 256, 256, 4, 2>(a, vec, s);
+      break;
     default: throw Error{GFCC_E_ARG, "bad tile config"};
   }
 }
@@ -551,7 +560,7 @@ void gemm_auto(Prec p, const GemmArgs& a, Scratch& scr, int scr_slot, hipStream_
 
 const char* tile_name(int cfg) {
   static const char* n[] = {"128x128", "64x64", "128x64", "64x128", "db128x128", "db256x128", "db128x256",
-                            "db256x256", "db32_256x256", "db32_256x128", "db32_128x128"};
+                            "db256x256", "db32_256x256", "db32_256x128", "db32_128x128", "db32_256x256w16", "db256x256w16"};
   return (cfg >= 0 && cfg < N_TILE_CFG) ? n[cfg] : "?";
 }
 

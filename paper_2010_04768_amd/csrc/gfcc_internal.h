@@ -116,7 +116,9 @@ enum TileCfg : int {
   TILE_DB_128x128 = 4, TILE_DB_256x128 = 5, TILE_DB_128x256 = 6, TILE_DB_256x256 = 7,
   // double-buffered with 32x32x16 BF16 MFMA blocks (other types: the 16x16 kernel of the same tile)
   TILE_DB32_256x256 = 8, TILE_DB32_256x128 = 9, TILE_DB32_128x128 = 10,
-  N_TILE_CFG = 11
+  // 256x256 with 16 waves of 64x64 (BF16; other types: the 8-wave kernel of the same tile)
+  TILE_DB32_256x256_W16 = 11, TILE_DB_256x256_W16 = 12,
+  N_TILE_CFG = 13
 };
 const char* tile_name(int cfg);
 
