@@ -38,7 +38,15 @@ void tune_load(gfcc_ctx* c, const char* path) {
     const size_t cp = t.find("\"cfg\": ", e);
     if (cp == std::string::npos) break;
     const int cfg = std::atoi(t.c_str() + cp + 7);
-    if (cfg >= 0 && cfg < N_TILE_CFG) {
+    // an entry written by a build with another tile table names a different tile: skip it
+    const size_t np = t.find("\"name\": \"", cp);
+    const size_t nxt = t.find("\"key\": \"", cp);
+    bool same_tile = false;
+    if (cfg >= 0 && cfg < N_TILE_CFG && np != std::string::npos && (nxt == std::string::npos || np < nxt)) {
+      const size_t ne = t.find('"', np + 9);
+      same_tile = ne != std::string::npos && t.compare(np + 9, ne - (np + 9), tile_name(cfg)) == 0;
+    }
+    if (same_tile) {
       c->tuned[key] = cfg;
       const size_t mp = t.find("\"ms\": ", cp);
       const size_t next = t.find("\"key\": \"", cp);
