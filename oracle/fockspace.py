@@ -249,10 +249,10 @@ class IPBruteForce:
             Hso[:, mu] = evec.T @ sig
         self.Hso = Hso
 
-        # b_p and c_q for occupied alpha orbitals
-        self.b_so = np.zeros((o, Dso))
-        self.c_so = np.zeros((o, Dso))
-        for p in range(o):
+        # b_p and c_q for every alpha spin orbital (occupied p < o, virtual p >= o)
+        self.b_so = np.zeros((n, Dso))
+        self.c_so = np.zeros((n, Dso))
+        for p in range(n):
             Ap = op_matrix([(1.0, [(False, p)])], detsN, idxM)
             self.b_so[p] = evec.T @ (emTM @ Ap @ eTN @ phi)
             Aqd = op_matrix([(1.0, [(True, p)])], detsM, idxN)

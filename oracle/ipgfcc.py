@@ -267,22 +267,42 @@ def explicit_matrix(im):
 # --------------------------------------------------------------------------
 
 def rhs(sys, p):
-    """b_p = abar_p |Phi> for occupied p: the 1h unit vector e_p (a_p commutes with T)."""
+    """b_p = abar_p |Phi> projected on the 1h + 2h1p space, p in [0, o + v).
+
+    abar_p = e^-T a_p e^T = a_p + [a_p, T]; the next commutator vanishes
+    because [a_p, T] only holds occupied annihilators, which commute with T.
+    * occupied p: a_p commutes with T, so b_p is the 1h unit vector e_p;
+    * virtual p (a = p - o): a_p|Phi> = 0 and [a_p, T]|Phi> gives
+      b(1h)[i] = t_i^a and, in the doublet basis, b(2h1p)[i,j,b] = t_ij^ab.
+    """
+    o, v = sys.n_occ, sys.n_vir
     b = np.zeros(sys.dim)
-    b[p] = 1.0
+    if p < o:
+        b[p] = 1.0
+        return b
+    a = p - o
+    b[:o] = sys.t1[:, a]
+    b[o:] = sys.t2[:, :, a, :].reshape(-1)
     return b
 
 
 def left_vector(sys, q):
-    """c_q[mu] = <Phi|(1 + Lambda) abar_q^+ |mu> for occupied q (spin-adapted).
+    """c_q[mu] = <Phi|(1 + Lambda) abar_q^+ |mu> (spin-adapted), q in [0, o + v).
 
-    abar_q^+ = a_q^+ - sum_a t_q^a a_a^+ - 1/2 sum_jab t_qj^ab a_a^+ a_b^+ a_j
+    Occupied q: abar_q^+ = a_q^+ - sum_a t_q^a a_a^+ - 1/2 sum_jab t_qj^ab a_a^+ a_b^+ a_j
     (higher commutators vanish).  Spin-summed over the doublet basis:
       c(1h)[i]      = d_qi - sum_a l_ia t_qa - sum_jab (2 l_ij^ab - l_ij^ba) t_qj^ab
       c(2h1p)[k,l,c] = 2 d_qk l_lc - d_ql l_kc - sum_a t_qa (2 l_kl^ac - l_kl^ca)
+    Virtual q (a = q - o): a_q^+ commutes with T, so abar_q^+ = a_q^+ and only
+    Lambda contributes:
+      c(1h)[i] = l_i^a,   c(2h1p)[k,l,c] = 2 l_kl^ac - l_kl^ca
     """
     o, v = sys.n_occ, sys.n_vir
     t1, t2, l1, l2 = sys.t1, sys.t2, sys.l1, sys.l2
+    if q >= o:
+        a = q - o
+        c2 = 2.0 * l2[:, :, a, :] - l2[:, :, :, a]
+        return np.concatenate([l1[:, a], c2.reshape(-1)])
     c1 = np.zeros(o)
     c1[q] = 1.0
     c1 -= l1 @ t1[q]

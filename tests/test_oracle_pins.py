@@ -68,7 +68,7 @@ def test_bruteforce_doublet_space_invariant_and_rhs():
     s = _sys(3, 3, 2)
     bf = IPBruteForce(s)
     assert bf.doublet_leak() < 1e-12
-    assert np.allclose(bf.b_sa, np.eye(3, s.dim), atol=1e-14)
+    assert np.allclose(bf.b_sa[:3], np.eye(3, s.dim), atol=1e-14)  # occupied p: b_p = e_p
     # spin-orbital and spin-adapted Green's functions agree
     for p, q in [(0, 0), (1, 2), (2, 1)]:
         assert abs(bf.greens_so(-0.4, 0.01, p, q) - bf.greens_sa(-0.4, 0.01, p, q)) < 1e-11
@@ -99,7 +99,7 @@ def test_hbar_matches_bruteforce_zero_integrals(bf_cache):
     bf = IPBruteForce(s)
     im = O.intermediates(s)
     assert np.abs(_dense(im) - bf.Hsa).max() < 1e-13
-    c = np.stack([O.left_vector(s, q) for q in range(3)])
+    c = np.stack([O.left_vector(s, q) for q in range(6)])  # occupied and virtual q
     assert np.abs(c - bf.c_sa).max() < 1e-13
 
 
@@ -113,7 +113,7 @@ def test_left_vectors_independent_lambda(bf_cache, shape):
     l2 = rng.normal(0, 0.1, s.t2.shape)
     s.l2 = l2 + l2.transpose(1, 0, 3, 2)
     bf = IPBruteForce(s)
-    c = np.stack([O.left_vector(s, q) for q in range(o)])
+    c = np.stack([O.left_vector(s, q) for q in range(o + v)])
     assert np.abs(c - bf.c_sa).max() < 1e-13
     im = O.intermediates(s)
     assert np.abs(_dense(im) - bf.Hsa).max() < 1e-12 * np.abs(bf.Hsa).max()
@@ -123,6 +123,31 @@ def test_left_vectors_independent_lambda(bf_cache, shape):
         g = O.left_vector(s, q) @ x
         gref = bf.greens_so(w, 0.02, p, q)
         assert abs(g - gref) < 1e-10 * max(1.0, abs(gref))
+
+
+@pytest.mark.parametrize("shape", [(2, 3), (3, 4)])
+def test_virtual_orbitals_rhs_left_and_greens(bf_cache, shape):
+    """Virtual p and q: b_p = [a_p, T]|Phi> and c_q from Lambda alone, against the
+    brute force (Lambda independent of T), and G_qp for every occupied/virtual pairing."""
+    o, v = shape
+    s = _sys(o, v, 9)
+    rng = np.random.default_rng(6)
+    s.l1 = rng.normal(0, 0.1, s.t1.shape)
+    l2 = rng.normal(0, 0.1, s.t2.shape)
+    s.l2 = l2 + l2.transpose(1, 0, 3, 2)
+    bf = IPBruteForce(s)
+    for p in range(o, o + v):
+        b = O.rhs(s, p)
+        assert np.abs(b).max() > 1e-3  # correlation gives virtual orbitals an ionised component
+        assert np.abs(b - bf.b_sa[p]).max() < 1e-13
+        assert np.abs(O.left_vector(s, p) - bf.c_sa[p]).max() < 1e-13
+    im = O.intermediates(s)
+    for p, q, w in [(o, 0, -0.6), (0, o + v - 1, -0.35), (o + v - 1, o, -0.8)]:
+        x, _, _ = O.solve(s, im, p, w, 0.02, tol=1e-13)
+        g = O.left_vector(s, q) @ x
+        gref = bf.greens_sa(w, 0.02, p, q)
+        assert abs(g - gref) < 1e-10 * max(1e-3, abs(gref)), (p, q)
+        assert abs(gref - bf.greens_so(w, 0.02, p, q)) < 1e-12 * max(1e-3, abs(gref))
 
 
 def test_lambda_zero_left_vector_is_unit():
