@@ -1,8 +1,8 @@
 /*
  * gfcc.h -- C ABI of the MI355X IP-GFCCSD linear-solve library (libgfcc.so).
  *
- * Operation (arXiv 2010.04768, Theory section): for occupied orbitals p, q and real
- * frequencies omega, the retarded ionisation (IP) term of the coupled-cluster
+ * Operation (arXiv 2010.04768, Theory section): for orbitals p, q (occupied or
+ * virtual; the benchmarks use occupied ones) and real frequencies omega, the retarded ionisation (IP) term of the coupled-cluster
  * Green's function in the GFCCSD truncation,
  *
  *     G_qp(omega) = c_q^T X_p(omega),   (omega + Hbar_N - i*eta) X_p = b_p,
@@ -11,8 +11,10 @@
  * c^T X of the model-order-reduction equations), where
  *   Hbar_N  = connected similarity-transformed Hamiltonian e^-T H e^T - E0,
  *             restricted to the 1h + 2h1p space of X_p (the X_p expansion),
- *   b_p     = abar_p |Phi>  (= the 1h unit vector e_p for occupied p),
- *   c_q     = <Phi|(1 + Lambda) abar_q^+ restricted to the same space,
+ *   b_p     = abar_p |Phi>  (= the 1h unit vector e_p for occupied p; for virtual
+ *             p = o + a it is [a_a, T]|Phi>: t_i^a on 1h, t_ij^ab on 2h1p),
+ *   c_q     = <Phi|(1 + Lambda) abar_q^+ restricted to the same space (for
+ *             virtual q = o + a: l_i^a on 1h, 2 l_kl^ac - l_kl^ca on 2h1p),
  * with T and Lambda truncated at singles and doubles.  The systems are solved
  * by restarted GMRES (GFCC Workflow and Bottlenecks section), optionally right-preconditioned.
  *
@@ -124,7 +126,8 @@ typedef struct {
 } gfcc_solve_opts;
 
 /* Per right-hand side result (host memory). status: 0 converged, 1 max_iter,
- * 2 breakdown, 3 non-finite, 4 converged after falling back to Jacobi. */
+ * 2 breakdown, 3 non-finite, 4 converged after falling back to Jacobi.
+ * true_rel_resid = |b_p - (omega + Hbar_N - i*eta) X| / |b_p| in FP64. */
 typedef struct {
   int32_t status, iters, restarts, reserved;
   double true_rel_resid;
@@ -133,6 +136,8 @@ typedef struct {
 /* Solve (omega_r + Hbar_N - i*eta) X_r = b_{p_r} for r < nrhs and form
  * G[r][k] = c_{q_k}^T X_r.  p, omega: host arrays [nrhs]; q: host [nq] or
  * NULL meaning q = p_r per right-hand side (then nq must be 1: G[r][0] = G_pp).
+ * p and q lie in [0, o + v).  A right-hand side with b_p = 0 (a virtual p no
+ * amplitude reaches) returns X = 0, G = 0, status 0 and no iterations.
  * G: device [nrhs][nq] complex interleaved.  X: device [nrhs][D] complex or
  * NULL (solutions are not kept).  info: host [nrhs].  eta is signed; the
  * operator is exactly (omega + Hbar_N - i*eta).  Right-hand sides are
@@ -144,7 +149,7 @@ gfcc_status gfcc_solve_batch(gfcc_ctx* ctx, int64_t nrhs, const int64_t* p, cons
                              double* G, double* X, gfcc_rhs_info* info, void* stream);
 
 /* G[r][k] = c_{q_k}^T X[r] (bilinear, no conjugation) for caller vectors X
- * [nrhs][D] complex; q host [nq]. G device [nrhs][nq] complex. */
+ * [nrhs][D] complex; q host [nq] in [0, o + v). G device [nrhs][nq] complex. */
 gfcc_status gfcc_greens(gfcc_ctx* ctx, int64_t nrhs, const double* X, int64_t nq, const int64_t* q,
                         double* G, void* stream);
 
@@ -258,7 +263,8 @@ gfcc_status gfcc_mor_extend(gfcc_ctx* ctx, int64_t n, const double* X, double dr
                             void* stream);
 
 /* Model Green's function at n_omega frequencies (host) for occupied p (host
- * [np]) and q (host [nq]); q == NULL: the diagonal q = p, G [n_omega][np],
+ * [np]; the model right-hand side is S^T e_p) and q (host [nq], occupied or
+ * virtual); q == NULL: the diagonal q = p, G [n_omega][np],
  * else G [n_omega][np][nq]; complex interleaved, device.  E_STATE when the
  * basis is empty or a model system is singular.  Blocking. */
 gfcc_status gfcc_mor_model(gfcc_ctx* ctx, int64_t np, const int64_t* p, int64_t nq, const int64_t* q,

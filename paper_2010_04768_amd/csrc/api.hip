@@ -161,7 +161,7 @@ gfcc_status gfcc_greens(gfcc_ctx* c, int64_t nrhs, const double* X, int64_t nq, 
     GFCC_CHECK(nrhs >= 0 && nq >= 0, GFCC_E_ARG, "negative size");
     if (nrhs == 0 || nq == 0) return;
     GFCC_CHECK(X && q && G, GFCC_E_ARG, "null argument");
-    for (int64_t k = 0; k < nq; ++k) GFCC_CHECK(q[k] >= 0 && q[k] < c->o, GFCC_E_ARG, "q out of range");
+    for (int64_t k = 0; k < nq; ++k) GFCC_CHECK(q[k] >= 0 && q[k] < c->o + c->v, GFCC_E_ARG, "q out of range");
     hipStream_t s = as_stream(stream);
     DBuf qd;
     qd.ensure(size_t(nq) * 8, s);
@@ -189,11 +189,11 @@ gfcc_status gfcc_solve_batch(gfcc_ctx* c, int64_t nrhs, const int64_t* p, const 
     GFCC_CHECK(p && omega && G && info, GFCC_E_ARG, "null argument");
     GFCC_CHECK(q != nullptr || nq == 1, GFCC_E_ARG, "q == NULL requires nq == 1");
     GFCC_CHECK(nq >= 1, GFCC_E_ARG, "nq < 1");
-    for (int64_t r = 0; r < nrhs; ++r) GFCC_CHECK(p[r] >= 0 && p[r] < c->o, GFCC_E_ARG, "p out of range");
+    for (int64_t r = 0; r < nrhs; ++r) GFCC_CHECK(p[r] >= 0 && p[r] < c->o + c->v, GFCC_E_ARG, "p out of range");
     for (int64_t r = 0; r < nrhs; ++r) GFCC_CHECK(std::isfinite(omega[r]), GFCC_E_ARG, "non-finite omega");
     GFCC_CHECK(std::isfinite(eta), GFCC_E_ARG, "non-finite eta");
     if (q)
-      for (int64_t k = 0; k < nq; ++k) GFCC_CHECK(q[k] >= 0 && q[k] < c->o, GFCC_E_ARG, "q out of range");
+      for (int64_t k = 0; k < nq; ++k) GFCC_CHECK(q[k] >= 0 && q[k] < c->o + c->v, GFCC_E_ARG, "q out of range");
     GFCC_CHECK(opts->tol > 0.0 && opts->restart >= 1 && opts->max_iter >= 1, GFCC_E_ARG, "bad tolerance/restart/max_iter");
     GFCC_CHECK(opts->precond >= GFCC_PC_NONE && opts->precond <= GFCC_PC_MLP, GFCC_E_ARG, "bad preconditioner");
     GFCC_CHECK(opts->precision >= GFCC_FP64 && opts->precision <= GFCC_BF16_IR, GFCC_E_ARG, "bad precision");
@@ -331,7 +331,7 @@ gfcc_status gfcc_mlp_train(gfcc_ctx* c, int64_t nrhs, const int64_t* p, const do
     GFCC_CHECK(mo->struct_size >= sizeof(gfcc_mlp_opts), GFCC_E_ARG, "bad options struct");
     GFCC_CHECK(mo->steps >= 0 && mo->batch >= 1 && mo->pair_restart >= 1 && mo->max_pairs >= 1 && mo->lr > 0.0,
                GFCC_E_ARG, "bad training options");
-    for (int64_t r = 0; r < nrhs; ++r) GFCC_CHECK(p[r] >= 0 && p[r] < c->o, GFCC_E_ARG, "p out of range");
+    for (int64_t r = 0; r < nrhs; ++r) GFCC_CHECK(p[r] >= 0 && p[r] < c->o + c->v, GFCC_E_ARG, "p out of range");
     hipStream_t s = as_stream(stream);
     const auto t0 = std::chrono::steady_clock::now();
     mlp_init(c, mo->width, mo->seed, s);
@@ -432,10 +432,11 @@ gfcc_status gfcc_mor_extend(gfcc_ctx* c, int64_t n, const double* X, double drop
   });
 }
 
-static void check_pq(gfcc_ctx* c, int64_t n, const int64_t* v, const char* what) {
+// orbital indices in [0, limit)
+static void check_pq(int64_t limit, int64_t n, const int64_t* v, const char* what) {
   GFCC_CHECK(v, GFCC_E_ARG, std::string("null ") + what);
   for (int64_t k = 0; k < n; ++k)
-    GFCC_CHECK(v[k] >= 0 && v[k] < c->o, GFCC_E_ARG, std::string(what) + " out of range");
+    GFCC_CHECK(v[k] >= 0 && v[k] < limit, GFCC_E_ARG, std::string(what) + " out of range");
 }
 
 gfcc_status gfcc_mor_model(gfcc_ctx* c, int64_t np, const int64_t* p, int64_t nq, const int64_t* q,
@@ -444,8 +445,8 @@ gfcc_status gfcc_mor_model(gfcc_ctx* c, int64_t np, const int64_t* p, int64_t nq
     GFCC_CHECK(c, GFCC_E_ARG, "null context");
     GFCC_CHECK(np >= 1 && n_omega >= 0 && (q == nullptr || nq >= 1), GFCC_E_ARG, "bad sizes");
     if (n_omega == 0) return;
-    check_pq(c, np, p, "p");
-    if (q) check_pq(c, nq, q, "q");
+    check_pq(c->o, np, p, "p (occupied: the model right-hand side is S^T e_p)");
+    if (q) check_pq(c->o + c->v, nq, q, "q");
     GFCC_CHECK(omega && G, GFCC_E_ARG, "null argument");
     for (int64_t k = 0; k < n_omega; ++k) GFCC_CHECK(std::isfinite(omega[k]), GFCC_E_ARG, "non-finite omega");
     mor_model(c, np, p, q ? nq : np, q, q == nullptr, n_omega, omega, eta, G, as_stream(stream));
@@ -474,7 +475,7 @@ gfcc_status gfcc_mor_greens(gfcc_ctx* c, int64_t np, const int64_t* p, int64_t n
     GFCC_CHECK(opts && opts->struct_size >= sizeof(gfcc_mor_opts), GFCC_E_ARG, "bad options struct");
     GFCC_CHECK(opts->solve.struct_size >= sizeof(gfcc_solve_opts), GFCC_E_ARG, "bad solve options struct");
     GFCC_CHECK(np >= 1 && n_omega >= 1, GFCC_E_ARG, "np and n_omega must be >= 1");
-    check_pq(c, np, p, "p");
+    check_pq(c->o, np, p, "p (occupied)");
     GFCC_CHECK(omega && G, GFCC_E_ARG, "null argument");
     GFCC_CHECK(opts->tol > 0.0 && opts->drop_tol >= 0.0 && opts->drop_tol < 1.0 && opts->max_levels >= 0,
                GFCC_E_ARG, "bad tol / drop_tol / max_levels");

@@ -43,6 +43,14 @@ static void add_diag(double* p, int64_t n, int64_t stride, const double* src, do
 }
 
 // Exact diagonal of Hbar_N over the plane layout.
+// flag = 1 when a[0:n] and b[0:n] differ anywhere
+__global__ void differ_kernel(const double* __restrict__ a, const double* __restrict__ b, int64_t n, int* flag) {
+  bool d = false;
+  for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < n; t += int64_t(gridDim.x) * blockDim.x)
+    d = d || (a[t] != b[t]);
+  if (d) *flag = 1;
+}
+
 __global__ void diag_kernel(double* __restrict__ dg, int64_t o, int64_t v, int64_t o_pad, int64_t kp,
                             const double* __restrict__ Foo, const double* __restrict__ Fvv,
                             const double* __restrict__ Woooo, const double* __restrict__ Wvo,
@@ -80,6 +88,7 @@ void build_intermediates(gfcc_ctx* c, const gfcc_system* sys, hipStream_t s) {
   double* t2 = const_cast<double*>(sys->t2);
   double* l1 = const_cast<double*>(sys->l1 ? sys->l1 : sys->t1);
   double* l2 = const_cast<double*>(sys->l2 ? sys->l2 : sys->t2);
+
   const double* eps = sys->eps;
 
   const int64_t nn = n * n;
@@ -381,6 +390,26 @@ void build_intermediates(gfcc_ctx* c, const gfcc_system* sys, hipStream_t s) {
     ein("qa,klac->qklc", -1.0, T1, ul, 1.0, c2, scr, s);
     GFCC_HIP(hipStreamSynchronize(s));  // temporaries are freed on return
   }
+  // ---- amplitudes for virtual-orbital right-hand sides and left vectors
+  c->t1c.ensure(ov * 8, s);
+  c->l1c.ensure(ov * 8, s);
+  GFCC_HIP(hipMemcpyAsync(c->t1c.p, t1, size_t(ov) * 8, hipMemcpyDeviceToDevice, s));
+  GFCC_HIP(hipMemcpyAsync(c->l1c.p, l1, size_t(ov) * 8, hipMemcpyDeviceToDevice, s));
+  if (l2 != t2) {  // keep l2 only when it differs from t2 (Lambda = T^dagger reuses TW)
+    DBuf dflag;
+    dflag.ensure(sizeof(int), s);
+    GFCC_HIP(hipMemsetAsync(dflag.p, 0, sizeof(int), s));
+    hipLaunchKernelGGL(differ_kernel, dim3(1024), dim3(256), 0, s, l2, t2, n_oovv, dflag.as<int>());
+    GFCC_HIP(hipGetLastError());
+    int differ = 0;
+    GFCC_HIP(hipMemcpyAsync(&differ, dflag.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    GFCC_HIP(hipStreamSynchronize(s));
+    if (differ) {
+      c->l2c.ensure(n_oovv * 8, s);
+      GFCC_HIP(hipMemcpyAsync(c->l2c.p, l2, size_t(n_oovv) * 8, hipMemcpyDeviceToDevice, s));
+    }
+  }
+  GFCC_HIP(hipStreamSynchronize(s));
   // the contraction engine's staging buffers hold integral-sized copies; the solver needs
   // only small split-K partials from them, so give the memory back
   for (auto& b : scr.b) b.release();

@@ -41,6 +41,11 @@ struct gfcc_ctx {
   gfcc::DBuf Uop;     // [o][Dp]          1h rows of Hbar_N over a plane
   gfcc::DBuf diag;    // [Dp]             exact diagonal (1.0 in padding)
   gfcc::DBuf left;    // [o][Dp]          c_q rows
+  // amplitudes kept for the right-hand sides and left vectors of virtual
+  // orbitals; t2 itself is the first v columns of TW
+  gfcc::DBuf t1c;     // [o][v]
+  gfcc::DBuf l1c;     // [o][v]
+  gfcc::DBuf l2c;     // [o][o][v][v], empty when l2 equals t2 (then TW serves)
 
   // reduced-precision copies of the two-body operands: [0] FP32, [1] BF16
   struct LowPrec {
@@ -98,6 +103,11 @@ void sigma_planes(gfcc_ctx* c, int64_t nplanes, const double* x, double* y, gfcc
 // interleaved complex [nb][D] <-> planes [2 nb][Dp]
 void to_planes(gfcc_ctx* c, int64_t nb, const double* xi, double* planes, hipStream_t s);
 void from_planes(gfcc_ctx* c, int64_t nb, const double* planes, double* xi, hipStream_t s);
+// b_p (real plane) for orbitals orb_dev[0:n] in [0, o + v): e_p for occupied p,
+// [a_p, T]|Phi> for virtual p; out [n][Dp]
+void make_rhs_rows(gfcc_ctx* c, int64_t n, const int64_t* orb_dev, double* out, hipStream_t s);
+// c_q (real plane) for orbitals orb_dev[0:n] in [0, o + v); out [n][Dp]
+void make_left_rows(gfcc_ctx* c, int64_t n, const int64_t* orb_dev, double* out, hipStream_t s);
 // G[r][k] = c_{q_k} . x_r (planes), complex interleaved output
 void greens_planes(gfcc_ctx* c, int64_t nb, const double* planes, int64_t nq, const int64_t* q_dev,
                    double* G, hipStream_t s);

@@ -63,14 +63,6 @@ __global__ void export_basis_kernel(const double* __restrict__ S, double* __rest
     out[b * D + t] = S[b * Dp + ((t < o) ? t : (t - o + o_pad))];
 }
 
-__global__ void gather_rows_kernel(const double* __restrict__ src, const int64_t* __restrict__ q, double* dst,
-                                   int64_t Dp) {
-  const int64_t k = blockIdx.y;
-  const double* s = src + q[k] * Dp;
-  for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < Dp; t += int64_t(gridDim.x) * blockDim.x)
-    dst[k * Dp + t] = s[t];
-}
-
 __device__ inline double2 cmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
@@ -371,9 +363,7 @@ void mor_model(gfcc_ctx* c, int64_t np, const int64_t* p, int64_t nq, const int6
   GFCC_HIP(hipMemcpyAsync(pd + np, q, size_t(nq) * 8, hipMemcpyHostToDevice, s));
   GFCC_HIP(hipMemcpyAsync(wd, w, size_t(nw) * 8, hipMemcpyHostToDevice, s));
   M.rows.ensure(size_t(nq * Dp) * 8, s);
-  hipLaunchKernelGGL(gather_rows_kernel, dim3(nblocks(Dp), unsigned(nq)), dim3(256), 0, s, c->left.as<double>(),
-                     pd + np, M.rows.as<double>(), Dp);
-  GFCC_HIP(hipGetLastError());
+  make_left_rows(c, nq, pd + np, M.rows.as<double>(), s);
   M.Ch.ensure(size_t(m * nq) * 8, s);
   GemmArgs g;  // chat[j][k] = s_j . c_{q_k}
   g.A = M.S.p;

@@ -318,22 +318,84 @@ void from_planes(gfcc_ctx* c, int64_t nb, const double* planes, double* xi, hipS
   GFCC_HIP(hipGetLastError());
 }
 
-// G[r][k] = c_{q_k} . x_r  (re from plane 2r, im from plane 2r+1)
-__global__ void gather_rows_kernel(const double* __restrict__ src, const int64_t* __restrict__ q, double* dst,
-                                   int64_t Dp) {
-  const int64_t k = blockIdx.y;
-  const double* s = src + q[k] * Dp;
-  for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < Dp; t += int64_t(gridDim.x) * blockDim.x)
-    dst[k * Dp + t] = s[t];
+// Right-hand sides b_p = abar_p|Phi> on the 1h + 2h1p space as real planes
+// (Theory section, the linear system for X_p): occupied p gives the unit vector
+// e_p; virtual p (a = p - o) gives [a_p, T]|Phi>: b(1h)_i = t_i^a and, in the
+// doublet basis, b(2h1p)_ijb = t_ij^ab.
+__global__ void rhs_rows_kernel(const int64_t* __restrict__ orb, const double* __restrict__ t1,
+                                const double* __restrict__ TW, int64_t ktw, double* __restrict__ out, int64_t o,
+                                int64_t v, int64_t o_pad, int64_t Dp) {
+  const int64_t r = blockIdx.y;
+  const int64_t p = orb[r];
+  const int64_t oov = o * o * v;
+  double* row = out + r * Dp;
+  for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < Dp; t += int64_t(gridDim.x) * blockDim.x) {
+    double val = 0.0;
+    if (p < o) {
+      val = (t == p) ? 1.0 : 0.0;
+    } else {
+      const int64_t a = p - o;
+      if (t < o)
+        val = t1[t * v + a];
+      else if (t >= o_pad && t - o_pad < oov)
+        val = TW[(t - o_pad) * ktw + a];  // t2[i, j, a, b] at row (i, j, b)
+    }
+    row[t] = val;
+  }
 }
 
+// Left vectors c_q = <Phi|(1 + Lambda) abar_q^+ as real planes: occupied q from the
+// rows built with the intermediates; virtual q (a = q - o): abar_q^+ = a_q^+ and
+// c(1h)_i = l_i^a, c(2h1p)_klc = 2 l_kl^ac - l_kl^ca.
+__global__ void left_rows_kernel(const int64_t* __restrict__ orb, const double* __restrict__ left_occ,
+                                 const double* __restrict__ l1, const double* __restrict__ l2,
+                                 const double* __restrict__ TW, int64_t ktw, double* __restrict__ out, int64_t o,
+                                 int64_t v, int64_t o_pad, int64_t Dp) {
+  const int64_t r = blockIdx.y;
+  const int64_t q = orb[r];
+  const int64_t oov = o * o * v;
+  double* row = out + r * Dp;
+  for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < Dp; t += int64_t(gridDim.x) * blockDim.x) {
+    double val = 0.0;
+    if (q < o) {
+      val = left_occ[q * Dp + t];
+    } else {
+      const int64_t a = q - o;
+      if (t < o) {
+        val = l1[t * v + a];
+      } else if (t >= o_pad && t - o_pad < oov) {
+        const int64_t idx = t - o_pad, kl = idx / v, cc = idx % v;  // (k, l, c)
+        if (l2)
+          val = 2.0 * l2[(kl * v + a) * v + cc] - l2[(kl * v + cc) * v + a];
+        else  // l2 = t2: l2[k, l, a, c] at TW row (k, l, c), column a
+          val = 2.0 * TW[idx * ktw + a] - TW[(kl * v + a) * ktw + cc];
+      }
+    }
+    row[t] = val;
+  }
+}
+
+void make_rhs_rows(gfcc_ctx* c, int64_t n, const int64_t* orb_dev, double* out, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(rhs_rows_kernel, dim3(blocks_for(c->Dp), unsigned(n)), dim3(256), 0, s, orb_dev,
+                     c->t1c.as<double>(), c->TW.as<double>(), c->ktw, out, c->o, c->v, c->o_pad, c->Dp);
+  GFCC_HIP(hipGetLastError());
+}
+
+void make_left_rows(gfcc_ctx* c, int64_t n, const int64_t* orb_dev, double* out, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(left_rows_kernel, dim3(blocks_for(c->Dp), unsigned(n)), dim3(256), 0, s, orb_dev,
+                     c->left.as<double>(), c->l1c.as<double>(), c->l2c.p ? c->l2c.as<double>() : nullptr,
+                     c->TW.as<double>(), c->ktw, out, c->o, c->v, c->o_pad, c->Dp);
+  GFCC_HIP(hipGetLastError());
+}
+
+// G[r][k] = c_{q_k} . x_r  (re from plane 2r, im from plane 2r+1)
 void greens_planes(gfcc_ctx* c, int64_t nb, const double* planes, int64_t nq, const int64_t* q_dev, double* G,
                    hipStream_t s) {
   if (nb <= 0 || nq <= 0) return;
   double* rows = c->scr.get(3, nq * c->Dp, s);
-  hipLaunchKernelGGL(gather_rows_kernel, dim3(blocks_for(c->Dp), unsigned(nq)), dim3(256), 0, s, c->left.as<double>(),
-                     q_dev, rows, c->Dp);
-  GFCC_HIP(hipGetLastError());
+  make_left_rows(c, nq, q_dev, rows, s);
   GemmArgs g;
   g.A = planes;
   g.am = lin(c->Dp);

@@ -80,12 +80,17 @@ __device__ __forceinline__ double* vec(const SolverDev& d, int s, int j, int c) 
   return d.V + ((int64_t(s) * (d.m + 1) + j) * 2 + c) * d.Dp;
 }
 
-// ---- new right-hand sides: V0 = e_p, X = 0, g = (1, 0, ...), k = 0
-__global__ void init_slots_kernel(SolverDev d, const int* slots, const int* ps, const cplx* zs, const double* ctol,
+// ---- new right-hand sides: V0 = b / |b|, X = 0, g = (|b|, 0, ...), k = 0.
+// b = e_p when brow[q] < 0 (occupied p), else row brow[q] of `brows`.
+__global__ void init_slots_kernel(SolverDev d, const int* slots, const int* ps, const int* brow,
+                                  const double* brows, const double* bnorm, const cplx* zs, const double* ctol,
                                   int n) {
   const int q = blockIdx.y;
   if (q >= n) return;
   const int s = slots[q];
+  const int br = brow[q];
+  const double bn = br < 0 ? 1.0 : bnorm[br];
+  const double* b = br < 0 ? nullptr : brows + int64_t(br) * d.Dp;
   const int64_t i0 = int64_t(blockIdx.x) * CH;
   for (int c = 0; c < 2; ++c) {
     double* v0 = vec(d, s, 0, c);
@@ -93,7 +98,9 @@ __global__ void init_slots_kernel(SolverDev d, const int* slots, const int* ps, 
     for (int e = threadIdx.x; e < CH; e += VT) {
       const int64_t t = i0 + e;
       if (t < d.Dp) {
-        v0[t] = (c == 0 && t == ps[q]) ? 1.0 : 0.0;
+        double val = 0.0;
+        if (c == 0) val = b ? b[t] / bn : (t == ps[q] ? 1.0 : 0.0);
+        v0[t] = val;
         x[t] = 0.0;
       }
     }
@@ -102,9 +109,9 @@ __global__ void init_slots_kernel(SolverDev d, const int* slots, const int* ps, 
     d.kk[s] = 0;
     d.z[s] = zs[q];
     d.ctol[s] = ctol[q];
-    d.res[s] = 1.0;
+    d.res[s] = bn;
     d.flag[s] = 0;
-    for (int j = 0; j <= d.m; ++j) d.g[int64_t(s) * (d.m + 1) + j] = cplx{j == 0 ? 1.0 : 0.0, 0.0};
+    for (int j = 0; j <= d.m; ++j) d.g[int64_t(s) * (d.m + 1) + j] = cplx{j == 0 ? bn : 0.0, 0.0};
   }
 }
 
@@ -446,13 +453,14 @@ __global__ void xupdate_kernel(SolverDev d, const int* fin, double* xout, const 
   }
 }
 
-// r = e_p - z x - sigma(x) -> V[0]; partial ||r||^2
-__global__ void residual_kernel(SolverDev d, const int* fin, const int* pfin, const double* xin,
-                                const double* sig) {
+// r = b - z x - sigma(x) -> V[0]; partial ||r||^2 (b = e_p when brow < 0)
+__global__ void residual_kernel(SolverDev d, const int* fin, const int* pfin, const int* brow, const double* brows,
+                                const double* xin, const double* sig) {
   const int q = blockIdx.y;
   const int s = fin[q];
   const cplx z = d.z[s];
   const int p = pfin[q];
+  const double* bp = brow[q] < 0 ? nullptr : brows + int64_t(brow[q]) * d.Dp;
   double* r0 = vec(d, s, 0, 0);
   double* r1 = vec(d, s, 0, 1);
   const double* xr = xin + (int64_t(q) * 2) * d.Dp;
@@ -465,7 +473,10 @@ __global__ void residual_kernel(SolverDev d, const int* fin, const int* pfin, co
     const double a = xr[t], b = xr[d.Dp + t];
     double rr = -(z.re * a - z.im * b) - sr[t];
     const double ri = -(z.re * b + z.im * a) - sr[d.Dp + t];
-    if (t == p) rr += 1.0;
+    if (bp)
+      rr += bp[t];
+    else if (t == p)
+      rr += 1.0;
     r0[t] = rr;
     r1[t] = ri;
     acc += rr * rr + ri * ri;
@@ -521,13 +532,14 @@ __global__ void restart_kernel(SolverDev d, const int* slots, const double* beta
   }
 }
 
-// G[row][k] = c_{q_k} . x  for finished slots (q_k = qlist[k] or the slot's own p)
-__global__ void gdot_kernel(SolverDev d, const int* slots, const int64_t* rows, const int* pown, const int64_t* qlist,
+// G[row][k] = c_{q_k} . x  for finished slots; the left vector is row
+// qrow[k] of `left`, or row crow[f] (the slot's own p) when qrow is null
+__global__ void gdot_kernel(SolverDev d, const int* slots, const int64_t* rows, const int* crow, const int64_t* qrow,
                             int nq, const double* left, double* G) {
   const int f = blockIdx.x;
   const int kq = blockIdx.y;
   const int s = slots[f];
-  const int64_t qq = qlist ? qlist[kq] : pown[f];
+  const int64_t qq = qrow ? qrow[kq] : crow[f];
   const double* c = left + qq * d.Dp;
   const double* xr = d.X + (int64_t(s) * 2) * d.Dp;
   const double* xi = xr + d.Dp;
@@ -555,6 +567,25 @@ __global__ void gdot_kernel(SolverDev d, const int* slots, const int64_t* rows, 
   }
 }
 
+// |row r| of rows [n][Dp]
+__global__ void row_norm_kernel(const double* rows, int64_t Dp, double* out) {
+  const int64_t r = blockIdx.x;
+  double acc = 0.0;
+  for (int64_t t = threadIdx.x; t < Dp; t += VT) {
+    const double x = rows[r * Dp + t];
+    acc += x * x;
+  }
+  __shared__ double red[VT / 64];
+  acc = wave_sum(acc);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0;
+    for (int w = 0; w < VT / 64; ++w) t += red[w];
+    out[r] = sqrt(t);
+  }
+}
+
 // copy X of finished slots to the caller's interleaved [nrhs][D] array
 __global__ void xout_kernel(SolverDev d, const int* slots, const int64_t* rows, double* Xo, int64_t D, int64_t o,
                             int64_t o_pad) {
@@ -577,6 +608,8 @@ struct HostSlot {
   int mlp = 0;             // 1 while the learned preconditioner is in use
   bool fell_back = false;  // switched to Jacobi after an MLP cycle stalled
   double beta = 1.0;       // residual at the start of the current cycle
+  double bn = 1.0;         // |b_p|
+  int brow = -1;           // row of b_p in the materialised right-hand sides (-1: e_p)
 };
 
 static double lp_cycle_rtol(gfcc_precision p) {
@@ -661,14 +694,68 @@ void solve_batch(gfcc_ctx* c, int64_t nrhs, const int64_t* p, const double* omeg
   d.Dp = Dp;
   d.nch = nch;
 
-  DBuf d_act, d_flags, d_res, d_list, d_plist, d_zlist, d_ctl, d_beta, d_rows, d_q;
+  DBuf d_act, d_flags, d_res, d_list, d_plist, d_brow, d_zlist, d_ctl, d_beta, d_rows, d_q;
   DBuf d_msrc, d_mzoff, d_mom, d_pmode;
   d_flags.ensure(size_t(B) * sizeof(int), s);
   d_res.ensure(size_t(B) * 8, s);
   d_beta.ensure(size_t(B) * 8, s);
+
+  // Right-hand sides of virtual orbitals, one materialised row per distinct
+  // orbital with its norm; occupied p keep the implicit unit vector e_p.
+  std::map<int64_t, int> brow_of;
+  std::vector<int64_t> borb;
+  for (int64_t r = 0; r < nrhs; ++r)
+    if (p[r] >= c->o && !brow_of.count(p[r])) {
+      brow_of[p[r]] = int(borb.size());
+      borb.push_back(p[r]);
+    }
+  DBuf d_borb, bB, bBn;
+  std::vector<double> bnorm_h(borb.size());
+  if (!borb.empty()) {
+    const int64_t nb = int64_t(borb.size());
+    upload(d_borb, borb, s);
+    bB.ensure(size_t(nb * Dp) * 8, s);
+    bBn.ensure(size_t(nb) * 8, s);
+    make_rhs_rows(c, nb, d_borb.as<int64_t>(), bB.as<double>(), s);
+    hipLaunchKernelGGL(row_norm_kernel, dim3(unsigned(nb)), dim3(VT), 0, s, bB.as<double>(), Dp, bBn.as<double>());
+    GFCC_HIP(hipGetLastError());
+    GFCC_HIP(hipMemcpyAsync(bnorm_h.data(), bBn.p, size_t(nb) * 8, hipMemcpyDeviceToHost, s));
+    GFCC_HIP(hipStreamSynchronize(s));
+  }
+  // Left vectors: the occupied rows built with the intermediates, or, when a
+  // virtual orbital is asked for, one materialised row per distinct orbital.
+  const double* lrows = c->left.as<double>();
+  std::map<int64_t, int64_t> lrow_of;
+  DBuf d_lorb, bL;
+  {
+    bool virt = false;
+    if (q) {
+      for (int64_t k = 0; k < nq; ++k) virt = virt || q[k] >= c->o;
+    } else {
+      virt = !borb.empty();
+    }
+    if (virt) {
+      std::vector<int64_t> lorb;
+      const int64_t nl_src = q ? nq : nrhs;
+      for (int64_t k = 0; k < nl_src; ++k) {
+        const int64_t orb = q ? q[k] : p[k];
+        if (!lrow_of.count(orb)) {
+          lrow_of[orb] = int64_t(lorb.size());
+          lorb.push_back(orb);
+        }
+      }
+      upload(d_lorb, lorb, s);
+      bL.ensure(lorb.size() * size_t(Dp) * 8, s);
+      make_left_rows(c, int64_t(lorb.size()), d_lorb.as<int64_t>(), bL.as<double>(), s);
+      lrows = bL.as<double>();
+    }
+  }
+  auto lrow = [&](int64_t orb) { return lrow_of.empty() ? orb : lrow_of.at(orb); };
   if (q) {
-    d_q.ensure(size_t(nq) * 8, s);
-    GFCC_HIP(hipMemcpyAsync(d_q.p, q, size_t(nq) * 8, hipMemcpyHostToDevice, s));
+    std::vector<int64_t> qr(static_cast<size_t>(nq));
+    for (int64_t k = 0; k < nq; ++k) qr[size_t(k)] = lrow(q[k]);
+    upload(d_q, qr, s);
+    GFCC_HIP(hipStreamSynchronize(s));
   }
 
   const double tol = opts->tol;
@@ -683,29 +770,44 @@ void solve_batch(gfcc_ctx* c, int64_t nrhs, const int64_t* p, const double* omeg
   bool ok_all = true;
 
   auto refill = [&]() {
-    std::vector<int> sl, pl;
+    std::vector<int> sl, pl, bl;
     std::vector<cplx> zl;
     std::vector<double> tl;
     while (!free_slots.empty() && next < nrhs) {
+      const int br = p[next] >= c->o ? brow_of.at(p[next]) : -1;
+      const double bn = br < 0 ? 1.0 : bnorm_h[size_t(br)];
+      if (!(bn > 0.0)) {  // b_p = 0 (no amplitude reaches this orbital): X = 0, G = 0
+        info[next] = gfcc_rhs_info{0, 0, 0, 0, 0.0};
+        GFCC_HIP(hipMemsetAsync(G + next * nq * 2, 0, size_t(nq) * 16, s));
+        if (Xout) GFCC_HIP(hipMemsetAsync(Xout + next * c->D * 2, 0, size_t(c->D) * 16, s));
+        ++next;
+        continue;
+      }
       const int sidx = free_slots.back();
       free_slots.pop_back();
       hs[sidx] = HostSlot{};
       hs[sidx].rhs = next;
       hs[sidx].mlp = use_mlp ? 1 : 0;
+      hs[sidx].bn = bn;
+      hs[sidx].beta = bn;
+      hs[sidx].brow = br;
       sl.push_back(sidx);
       pl.push_back(int(p[next]));
+      bl.push_back(br);
       zl.push_back(cplx{omega[next], -eta});
-      tl.push_back(std::max(0.5 * tol, rtol_lp));  // ||b|| = 1
+      tl.push_back(bn * std::max(0.5 * tol, rtol_lp));
       active.push_back(sidx);
       ++next;
     }
     if (sl.empty()) return;
     upload(d_list, sl, s);
     upload(d_plist, pl, s);
+    upload(d_brow, bl, s);
     upload(d_zlist, zl, s);
     upload(d_ctl, tl, s);
     hipLaunchKernelGGL(init_slots_kernel, dim3(nch, unsigned(sl.size())), dim3(VT), 0, s, d, d_list.as<int>(),
-                       d_plist.as<int>(), d_zlist.as<cplx>(), d_ctl.as<double>(), int(sl.size()));
+                       d_plist.as<int>(), d_brow.as<int>(), bB.as<double>(), bBn.as<double>(), d_zlist.as<cplx>(),
+                       d_ctl.as<double>(), int(sl.size()));
     GFCC_HIP(hipGetLastError());
     GFCC_HIP(hipStreamSynchronize(s));  // host vectors above go out of scope
   };
@@ -867,18 +969,22 @@ void solve_batch(gfcc_ctx* c, int64_t nrhs, const int64_t* p, const double* omeg
 
     // 5. finish the cycles of `fin`
     const int nf = int(fin.size());
-    std::vector<int> pf(nf);
-    for (int i = 0; i < nf; ++i) pf[i] = int(p[hs[fin[i]].rhs]);
+    std::vector<int> pf(nf), bf(nf);
+    for (int i = 0; i < nf; ++i) {
+      pf[i] = int(p[hs[fin[i]].rhs]);
+      bf[i] = hs[fin[i]].brow;
+    }
     upload(d_list, fin, s);
     upload(d_plist, pf, s);
+    upload(d_brow, bf, s);
     const int* fl = d_list.as<int>();
     hipLaunchKernelGGL(trisolve_kernel, dim3((nf + 63) / 64), dim3(64), 0, s, d, fl, nf);
     hipLaunchKernelGGL(xupdate_kernel, dim3(nch, nf), dim3(VT), 0, s, d, fl, c->ws_in.as<double>(),
                        c->diag.as<double>(), mode, flex);
     GFCC_HIP(hipGetLastError());
     sigma_planes(c, 2 * nf, c->ws_in.as<double>(), c->ws_out.as<double>(), GFCC_FP64, s);
-    hipLaunchKernelGGL(residual_kernel, dim3(nch, nf), dim3(VT), 0, s, d, fl, d_plist.as<int>(),
-                       c->ws_in.as<double>(), c->ws_out.as<double>());
+    hipLaunchKernelGGL(residual_kernel, dim3(nch, nf), dim3(VT), 0, s, d, fl, d_plist.as<int>(), d_brow.as<int>(),
+                       bB.as<double>(), c->ws_in.as<double>(), c->ws_out.as<double>());
     hipLaunchKernelGGL(rnorm_kernel, dim3(nf), dim3(64), 0, s, d, nf, d_beta.as<double>());
     GFCC_HIP(hipGetLastError());
     GFCC_HIP(hipMemcpyAsync(hbeta.data(), d_beta.p, nf * 8, hipMemcpyDeviceToHost, s));
@@ -890,13 +996,14 @@ void solve_batch(gfcc_ctx* c, int64_t nrhs, const int64_t* p, const double* omeg
     for (int i = 0; i < nf; ++i) {
       const int sl = fin[i];
       HostSlot& h = hs[sl];
-      const double beta = hbeta[i];
+      const double beta = hbeta[i];  // |r|
+      const double rel = beta / h.bn;
       const bool finite = std::isfinite(beta);
       gfcc_rhs_info& inf = info[h.rhs];
       inf.iters = h.iters;
       inf.restarts = h.restarts;
-      inf.true_rel_resid = beta;
-      if (finite && beta <= tol) {
+      inf.true_rel_resid = rel;
+      if (finite && rel <= tol) {
         inf.status = h.fell_back ? 4 : 0;
         if (rec) {  // keep X* of this right-hand side for the training pairs
           GFCC_HIP(hipMemcpyAsync(rec->xstar + h.rhs * 2 * Dp, d.X + int64_t(sl) * 2 * Dp, size_t(2 * Dp) * 8,
@@ -927,13 +1034,13 @@ void solve_batch(gfcc_ctx* c, int64_t nrhs, const int64_t* p, const double* omeg
         h.restarts += 1;
         again.push_back(sl);
         again_beta.push_back(beta);
-        again_tol.push_back(std::max(0.5 * tol, rtol_lp * beta));
+        again_tol.push_back(std::max(0.5 * tol * h.bn, rtol_lp * beta));
         continue;
       }
       if (inf.status != 0 && inf.status != 4) ok_all = false;
       done.push_back(sl);
       done_rows.push_back(h.rhs);
-      done_p.push_back(int(p[h.rhs]));
+      done_p.push_back(q ? 0 : int(lrow(p[h.rhs])));  // own left vector only when q == NULL
     }
     if (!again.empty()) {
       const int nr = int(again.size());
@@ -953,7 +1060,7 @@ void solve_batch(gfcc_ctx* c, int64_t nrhs, const int64_t* p, const double* omeg
       upload(d_plist, done_p, s);
       hipLaunchKernelGGL(gdot_kernel, dim3(nd, unsigned(nq)), dim3(VT), 0, s, d, d_list.as<int>(),
                          d_rows.as<int64_t>(), d_plist.as<int>(), q ? d_q.as<int64_t>() : nullptr, int(nq),
-                         c->left.as<double>(), G);
+                         lrows, G);
       if (Xout)
         hipLaunchKernelGGL(xout_kernel, dim3(std::min<int64_t>((c->D + 255) / 256, 1024), nd), dim3(256), 0, s, d,
                            d_list.as<int>(), d_rows.as<int64_t>(), Xout, c->D, c->o, c->o_pad);

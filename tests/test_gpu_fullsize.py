@@ -69,3 +69,24 @@ def test_fullsize_solve_bench_configuration(full):
         assert np.linalg.norm(res) <= 1.05 * wl.tol, np.linalg.norm(res)
         g_or = O.left_vector(s, P[r]) @ x
         assert abs(G[r] - g_or) <= 1e-12 * abs(g_or)
+
+
+def test_fullsize_virtual_orbitals(full):
+    """Virtual p (b_p = [a_p, T]|Phi>) and virtual q at the full size, BF16 GMRES-IR:
+    the oracle's true residual of X_gpu relative to |b_p|, and G against c_q^T X_gpu."""
+    wl, s, im, ctx = full
+    o, v = s.n_occ, s.n_vir
+    P = [o, o + 117, o + v - 1, 5]
+    W = [-0.62, -0.5, -0.71, -0.55]
+    Q = [5, o, o + 117]
+    G, info, X = ctx.solve(P, W, wl.eta, q=Q, tol=wl.tol, precision="bf16", batch=128, want_x=True)
+    assert all(i["status"] == 0 for i in info), info
+    G = G.cpu().numpy()
+    C = np.stack([O.left_vector(s, q) for q in Q])
+    for r in (0, 1, 3):
+        x = X[r].cpu().numpy()
+        b = O.rhs(s, P[r])
+        res = b - O.shifted_operator(im, W[r], wl.eta)(x)
+        assert np.linalg.norm(res) <= 1.05 * wl.tol * np.linalg.norm(b), np.linalg.norm(res)
+        g = C @ x
+        assert np.abs(G[r] - g).max() <= 1e-12 * np.abs(g).max()
