@@ -148,6 +148,39 @@ gfcc_status gfcc_solve_batch(gfcc_ctx* ctx, int64_t nrhs, const int64_t* p, cons
                              double eta, int64_t nq, const int64_t* q, const gfcc_solve_opts* opts,
                              double* G, double* X, gfcc_rhs_info* info, void* stream);
 
+/* ---------------------------------------------------------------------------
+ * Multi-shift GMRES (the shifted systems solved together over many frequencies,
+ * Introduction and Theory sections).  The Krylov space of (omega - i*eta +
+ * Hbar_N) and b_p is the same for every omega, so one real Arnoldi basis per
+ * orbital p (FP64, no preconditioner, no restart) gives the GMRES iterate of
+ * every frequency.  Each (p, omega) ends when its FP64 true residual
+ * |b_p - (omega + Hbar_N - i*eta) X| / |b_p| <= tol (formed from the stored
+ * sigma products, without another sigma). */
+typedef struct {
+  size_t struct_size;      /* sizeof(gfcc_shift_opts) */
+  double tol;              /* relative residual per (p, omega) */
+  int32_t max_dim;         /* Krylov dimension cap per orbital, <= 512; 0 = 160 */
+  int32_t batch;           /* orbitals in flight; 0 = as many as fit in 40% of free memory */
+  int32_t verify;          /* 1 = accept on the FP64 true residual, 0 = on the Givens estimate */
+  int32_t use_fallback;    /* 1 = (p, omega) not converged within max_dim are solved again by
+                              gfcc_solve_batch with `fallback` */
+  gfcc_solve_opts fallback;
+} gfcc_shift_opts;
+
+/* For every orbital p[i] (host [np], in [0, o + v)) and every frequency omega[k]
+ * (host [n_omega]) solve (omega_k + Hbar_N - i*eta) X = b_p.  G (device):
+ * [np][n_omega][nq] complex interleaved, G = c_q^T X for q (host [nq], in
+ * [0, o + v)), or q = NULL and nq = 1 for G_pp.  X (device, nullable):
+ * [np][n_omega][D] complex.  info (host [np][n_omega]): status as for
+ * gfcc_solve_batch (1: not converged within max_dim and no fallback), iters =
+ * basis size used (plus fallback iterations), true_rel_resid.  Memory: per
+ * orbital in flight (2 max_dim + 1) planes of (o + o*o*v) doubles.  Blocking;
+ * returns GFCC_W_NOCONV if any (p, omega) did not converge. */
+gfcc_status gfcc_solve_shifts(gfcc_ctx* ctx, int64_t np, const int64_t* p, int64_t n_omega,
+                              const double* omega, double eta, int64_t nq, const int64_t* q,
+                              const gfcc_shift_opts* opts, double* G, double* X, gfcc_rhs_info* info,
+                              void* stream);
+
 /* G[r][k] = c_{q_k}^T X[r] (bilinear, no conjugation) for caller vectors X
  * [nrhs][D] complex; q host [nq] in [0, o + v). G device [nrhs][nq] complex. */
 gfcc_status gfcc_greens(gfcc_ctx* ctx, int64_t nrhs, const double* X, int64_t nq, const int64_t* q,

@@ -324,6 +324,38 @@ gfcc_status gfcc_mlp_apply(gfcc_ctx* c, int64_t nvec, const double* R, const dou
   });
 }
 
+gfcc_status gfcc_solve_shifts(gfcc_ctx* c, int64_t np, const int64_t* p, int64_t n_omega, const double* omega,
+                              double eta, int64_t nq, const int64_t* q, const gfcc_shift_opts* opts, double* G,
+                              double* X, gfcc_rhs_info* info, void* stream) {
+  bool all_conv = true;
+  gfcc_status st = guarded([&] {
+    GFCC_CHECK(c, GFCC_E_ARG, "null context");
+    GFCC_CHECK(opts && opts->struct_size >= sizeof(gfcc_shift_opts), GFCC_E_ARG, "bad options struct");
+    GFCC_CHECK(np >= 0 && n_omega >= 0, GFCC_E_ARG, "negative size");
+    if (np == 0 || n_omega == 0) return;
+    GFCC_CHECK(p && omega && G && info, GFCC_E_ARG, "null argument");
+    GFCC_CHECK(q != nullptr || nq == 1, GFCC_E_ARG, "q == NULL requires nq == 1");
+    GFCC_CHECK(nq >= 1, GFCC_E_ARG, "nq < 1");
+    for (int64_t r = 0; r < np; ++r) GFCC_CHECK(p[r] >= 0 && p[r] < c->o + c->v, GFCC_E_ARG, "p out of range");
+    if (q)
+      for (int64_t k = 0; k < nq; ++k) GFCC_CHECK(q[k] >= 0 && q[k] < c->o + c->v, GFCC_E_ARG, "q out of range");
+    for (int64_t k = 0; k < n_omega; ++k) GFCC_CHECK(std::isfinite(omega[k]), GFCC_E_ARG, "non-finite omega");
+    GFCC_CHECK(std::isfinite(eta), GFCC_E_ARG, "non-finite eta");
+    GFCC_CHECK(opts->tol > 0.0 && opts->max_dim >= 0 && opts->max_dim <= 512 && opts->batch >= 0, GFCC_E_ARG,
+               "bad tol / max_dim / batch");
+    if (opts->use_fallback) {
+      const gfcc_solve_opts& f = opts->fallback;
+      GFCC_CHECK(f.struct_size >= sizeof(gfcc_solve_opts), GFCC_E_ARG, "bad fallback options struct");
+      GFCC_CHECK(f.tol > 0.0 && f.restart >= 1 && f.max_iter >= 1, GFCC_E_ARG, "bad fallback tolerance/restart/max_iter");
+      GFCC_CHECK(f.precond >= GFCC_PC_NONE && f.precond <= GFCC_PC_MLP, GFCC_E_ARG, "bad fallback preconditioner");
+      GFCC_CHECK(f.precision >= GFCC_FP64 && f.precision <= GFCC_BF16_IR, GFCC_E_ARG, "bad fallback precision");
+    }
+    solve_shifts(c, np, p, n_omega, omega, eta, nq, q, opts, G, X, info, as_stream(stream), &all_conv);
+  });
+  if (st == GFCC_OK && !all_conv) return GFCC_W_NOCONV;
+  return st;
+}
+
 gfcc_status gfcc_mlp_train(gfcc_ctx* c, int64_t nrhs, const int64_t* p, const double* omega, double eta,
                            const gfcc_mlp_opts* mo, gfcc_mlp_report* rep, void* stream) {
   return guarded([&] {

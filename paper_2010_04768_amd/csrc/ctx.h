@@ -93,6 +93,10 @@ struct PairRec {
 void solve_batch(gfcc_ctx* c, int64_t nrhs, const int64_t* p, const double* omega, double eta, int64_t nq,
                  const int64_t* q, const gfcc_solve_opts* opts, double* G, double* X, gfcc_rhs_info* info,
                  hipStream_t s, bool* all_converged, PairRec* rec);
+// multi-shift GMRES over all frequencies of each orbital (shifts.hip)
+void solve_shifts(gfcc_ctx* c, int64_t np, const int64_t* p, int64_t nw, const double* omega, double eta,
+                  int64_t nq, const int64_t* q, const gfcc_shift_opts* o, double* G, double* X,
+                  gfcc_rhs_info* info, hipStream_t s, bool* all_converged);
 
 // Vectors inside the library are "planes": for nb complex vectors, 2*nb planes
 // of Dp doubles (re of vector 0, im of vector 0, re of vector 1, ...).

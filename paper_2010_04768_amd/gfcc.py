@@ -27,7 +27,8 @@ SYMBOLS = ["gfcc_build_intermediates", "gfcc_dims", "gfcc_export", "gfcc_sigma",
            "gfcc_greens", "gfcc_prof_enable", "gfcc_prof_get", "gfcc_destroy", "gfcc_strerror",
            "gfcc_last_error", "gfcc_mlp_train", "gfcc_mlp_set_weights", "gfcc_mlp_get_weights",
            "gfcc_mlp_forward", "gfcc_mlp_loss_grad", "gfcc_mlp_features", "gfcc_mlp_apply",
-           "gfcc_mor_reset", "gfcc_mor_extend", "gfcc_mor_model", "gfcc_mor_export", "gfcc_mor_greens"]
+           "gfcc_mor_reset", "gfcc_mor_extend", "gfcc_mor_model", "gfcc_mor_export", "gfcc_mor_greens",
+           "gfcc_solve_shifts"]
 
 
 class GfccSystem(ctypes.Structure):
@@ -46,6 +47,12 @@ class SolveOpts(ctypes.Structure):
 class RhsInfo(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("iters", ctypes.c_int32), ("restarts", ctypes.c_int32),
                 ("reserved", ctypes.c_int32), ("true_rel_resid", ctypes.c_double)]
+
+
+class ShiftOpts(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_size_t), ("tol", ctypes.c_double), ("max_dim", ctypes.c_int32),
+                ("batch", ctypes.c_int32), ("verify", ctypes.c_int32), ("use_fallback", ctypes.c_int32),
+                ("fallback", SolveOpts)]
 
 
 class MlpOpts(ctypes.Structure):
@@ -116,6 +123,9 @@ def load():
     for name in ["gfcc_mlp_train", "gfcc_mlp_set_weights", "gfcc_mlp_get_weights", "gfcc_mlp_forward",
                  "gfcc_mlp_loss_grad", "gfcc_mlp_features", "gfcc_mlp_apply"]:
         getattr(L, name).restype = ctypes.c_int
+    L.gfcc_solve_shifts.argtypes = [vp, i64, vp, i64, vp, dbl, i64, vp, ctypes.POINTER(ShiftOpts), vp, vp,
+                                    ctypes.POINTER(RhsInfo), vp]
+    L.gfcc_solve_shifts.restype = ctypes.c_int
     L.gfcc_mor_reset.argtypes = [vp]
     L.gfcc_mor_extend.argtypes = [vp, i64, vp, dbl, ctypes.POINTER(i64), vp]
     L.gfcc_mor_model.argtypes = [vp, i64, vp, i64, vp, i64, vp, dbl, vp, vp]
@@ -241,6 +251,45 @@ class Context:
         _check(st, "gfcc_solve_batch")
         infos = [dict(status=info[r].status, iters=info[r].iters, restarts=info[r].restarts,
                       true_rel_resid=info[r].true_rel_resid) for r in range(n)]
+        return G, infos, X
+
+    def solve_shifts(self, p: Sequence[int], omega: Sequence[float], eta: float,
+                     q: Optional[Sequence[int]] = None, tol=1e-8, max_dim=160, batch=0, verify=True,
+                     want_x=False, fallback: Optional[dict] = None):
+        """Multi-shift GMRES: one Krylov basis per orbital for all frequencies.
+
+        Returns (G [np, n_omega, nq] complex128 device tensor, info [np][n_omega] dicts, X
+        [np, n_omega, D] or None).  `fallback`: keyword arguments of `solve` (tol, restart,
+        max_iter, batch, precond, precision, use_graph, ir_inner_rtol) for the (p, omega) that
+        do not converge within max_dim basis vectors; None leaves them with status 1."""
+        import torch
+        p_h = np.ascontiguousarray(np.asarray(p, dtype=np.int64))
+        w_h = np.ascontiguousarray(np.asarray(omega, dtype=np.float64))
+        npp, nw = p_h.size, w_h.size
+        if q is None:
+            q_h, nq = None, 1
+        else:
+            q_h = np.ascontiguousarray(np.asarray(q, dtype=np.int64))
+            nq = q_h.size
+        G = torch.zeros((npp, nw, nq), dtype=torch.complex128, device=self.device)
+        X = torch.zeros((npp, nw, self.dim), dtype=torch.complex128, device=self.device) if want_x else None
+        info = (RhsInfo * max(npp * nw, 1))()
+        f = dict(tol=tol, restart=30, max_iter=2000, batch=0, precond="jacobi", precision="fp64",
+                 use_graph=False, ir_inner_rtol=0.0)
+        if fallback:
+            f.update(fallback)
+        fo = SolveOpts(ctypes.sizeof(SolveOpts), f["tol"], f["restart"], f["max_iter"], f["batch"],
+                       PRECONDS[f["precond"]], PRECISIONS[f["precision"]], int(f["use_graph"]), None,
+                       f["ir_inner_rtol"])
+        opts = ShiftOpts(ctypes.sizeof(ShiftOpts), tol, max_dim, batch, int(verify), int(fallback is not None), fo)
+        st = self._lib.gfcc_solve_shifts(
+            self._h, npp, p_h.ctypes.data_as(ctypes.c_void_p), nw, w_h.ctypes.data_as(ctypes.c_void_p), eta, nq,
+            q_h.ctypes.data_as(ctypes.c_void_p) if q_h is not None else None, ctypes.byref(opts), _ptr(G), _ptr(X),
+            info, _stream())
+        _check(st, "gfcc_solve_shifts")
+        infos = [[dict(status=info[i * nw + k].status, iters=info[i * nw + k].iters,
+                       restarts=info[i * nw + k].restarts, true_rel_resid=info[i * nw + k].true_rel_resid)
+                  for k in range(nw)] for i in range(npp)]
         return G, infos, X
 
     def greens(self, X, q):
