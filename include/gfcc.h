@@ -165,6 +165,8 @@ typedef struct {
   int32_t use_fallback;    /* 1 = (p, omega) not converged within max_dim are solved again by
                               gfcc_solve_batch with `fallback` */
   gfcc_solve_opts fallback;
+  const char* tune_cache;  /* host path of the tile autotuner JSON cache (FP64 sigma shapes of the
+                              orbital window); NULL = no tuning */
 } gfcc_shift_opts;
 
 /* For every orbital p[i] (host [np], in [0, o + v)) and every frequency omega[k]

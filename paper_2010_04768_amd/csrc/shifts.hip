@@ -232,13 +232,17 @@ __global__ void ms_scale_kernel(MsDev d) {
     v[t] *= f;
 }
 
-// Residual planes R[2k], R[2k+1] (re, im of shift k) += b; row norms.
-__global__ void ms_resid_kernel(double* R, int64_t Dp, int nk, const double* b, int p, double* out) {
-  const int k = blockIdx.x;
-  double* rr = R + (int64_t(2) * k) * Dp;
-  double* ri = rr + Dp;
+// Residual planes R[2k], R[2k+1] (re, im of shift k = blockIdx.y) plus b: partial
+// squared norms of RB slices of the plane, out[k][blockIdx.x].
+constexpr int RB = 64;
+__global__ void ms_resid_kernel(const double* R, int64_t Dp, const double* b, int p, double* out) {
+  const int k = blockIdx.y;
+  const double* rr = R + (int64_t(2) * k) * Dp;
+  const double* ri = rr + Dp;
+  const int64_t len = (Dp + RB - 1) / RB;
+  const int64_t t0 = int64_t(blockIdx.x) * len, t1 = std::min<int64_t>(Dp, t0 + len);
   double acc = 0.0;
-  for (int64_t t = threadIdx.x; t < Dp; t += VT) {
+  for (int64_t t = t0 + threadIdx.x; t < t1; t += VT) {
     const double bt = b ? b[t] : (t == p ? 1.0 : 0.0);
     const double a = rr[t] + bt, c = ri[t];
     acc += a * a + c * c;
@@ -250,9 +254,8 @@ __global__ void ms_resid_kernel(double* R, int64_t Dp, int nk, const double* b, 
   if (threadIdx.x == 0) {
     double t = 0.0;
     for (int u = 0; u < VT / 64; ++u) t += red[u];
-    out[k] = sqrt(t);
+    out[int64_t(k) * RB + blockIdx.x] = t;
   }
-  (void)nk;
 }
 
 // |row r| of rows [n][Dp]
@@ -295,7 +298,8 @@ struct Shift {
 
 // Upper Hessenberg column j (rows 0..j+1) of the real basis, shifted by z.
 void apply_column(Shift& sh, const std::vector<double>& H, int ldH, int j) {
-  std::vector<cd> col(size_t(j) + 2);
+  thread_local std::vector<cd> col;
+  col.resize(size_t(j) + 2);
   for (int i = 0; i <= j + 1; ++i) col[size_t(i)] = cd(H[size_t(j) * ldH + i], 0.0);
   col[size_t(j)] += sh.z;
   for (int i = 0; i < j; ++i) {
@@ -548,7 +552,7 @@ void solve_shifts(gfcc_ctx* c, int64_t np, const int64_t* p, int64_t nw, const d
       if (o->verify) {
         bcoef.ensure(size_t(4 * KC * ldc) * 8, s);
         bR.ensure(size_t(2 * KC * Dp) * 8, s);
-        brn.ensure(size_t(KC) * 8, s);
+        brn.ensure(size_t(KC) * RB * 8, s);
         for (int64_t k0 = 0; k0 < nw; k0 += KC) {
           const int64_t kc = std::min(KC, nw - k0);
           std::vector<double> cf(size_t(4 * kc * ldc), 0.0);  // [Cv | Cw] row blocks
@@ -568,11 +572,17 @@ void solve_shifts(gfcc_ctx* c, int64_t np, const int64_t* p, int64_t nw, const d
           GFCC_HIP(hipMemcpyAsync(bcoef.p, cf.data(), cf.size() * 8, hipMemcpyHostToDevice, s));
           comb(bcoef.as<double>(), ldc, 2 * kc, m, Vs, 0.0, bR.as<double>());
           comb(bcoef.as<double>() + 2 * kc * ldc, ldc, 2 * kc, m, Ws, 1.0, bR.as<double>());
-          hipLaunchKernelGGL(ms_resid_kernel, dim3(unsigned(kc)), dim3(VT), 0, s, bR.as<double>(), Dp, int(kc),
-                             bptr, int(p[S.pi]), brn.as<double>());
+          hipLaunchKernelGGL(ms_resid_kernel, dim3(RB, unsigned(kc)), dim3(VT), 0, s, bR.as<double>(), Dp, bptr,
+                             int(p[S.pi]), brn.as<double>());
           GFCC_HIP(hipGetLastError());
-          GFCC_HIP(hipMemcpyAsync(rel.data() + k0, brn.p, size_t(kc) * 8, hipMemcpyDeviceToHost, s));
+          std::vector<double> part(size_t(kc) * RB);
+          GFCC_HIP(hipMemcpyAsync(part.data(), brn.p, part.size() * 8, hipMemcpyDeviceToHost, s));
           GFCC_HIP(hipStreamSynchronize(s));  // cf goes out of scope
+          for (int64_t k = 0; k < kc; ++k) {
+            double t = 0.0;
+            for (int u = 0; u < RB; ++u) t += part[size_t(k * RB + u)];
+            rel[size_t(k0 + k)] = std::sqrt(t);
+          }
         }
         for (auto& r : rel) r /= S.bn;
       } else {
@@ -658,6 +668,11 @@ void solve_shifts(gfcc_ctx* c, int64_t np, const int64_t* p, int64_t nw, const d
     return true;
   };
 
+  if (o->tune_cache) {  // FP64 sigma tiles for a full orbital window
+    tune_load(c, o->tune_cache);
+    tune_ring(c, Prec::F64, int64_t(B), s);
+    tune_save(c, o->tune_cache);
+  }
   refill();
   std::vector<double> hh(size_t(B) * (KMAX + 1)), hn(static_cast<size_t>(B));
   while (!active.empty()) {

@@ -52,7 +52,7 @@ class RhsInfo(ctypes.Structure):
 class ShiftOpts(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_size_t), ("tol", ctypes.c_double), ("max_dim", ctypes.c_int32),
                 ("batch", ctypes.c_int32), ("verify", ctypes.c_int32), ("use_fallback", ctypes.c_int32),
-                ("fallback", SolveOpts)]
+                ("fallback", SolveOpts), ("tune_cache", ctypes.c_char_p)]
 
 
 class MlpOpts(ctypes.Structure):
@@ -255,7 +255,7 @@ class Context:
 
     def solve_shifts(self, p: Sequence[int], omega: Sequence[float], eta: float,
                      q: Optional[Sequence[int]] = None, tol=1e-8, max_dim=160, batch=0, verify=True,
-                     want_x=False, fallback: Optional[dict] = None):
+                     want_x=False, fallback: Optional[dict] = None, tune_cache=None):
         """Multi-shift GMRES: one Krylov basis per orbital for all frequencies.
 
         Returns (G [np, n_omega, nq] complex128 device tensor, info [np][n_omega] dicts, X
@@ -281,7 +281,8 @@ class Context:
         fo = SolveOpts(ctypes.sizeof(SolveOpts), f["tol"], f["restart"], f["max_iter"], f["batch"],
                        PRECONDS[f["precond"]], PRECISIONS[f["precision"]], int(f["use_graph"]), None,
                        f["ir_inner_rtol"])
-        opts = ShiftOpts(ctypes.sizeof(ShiftOpts), tol, max_dim, batch, int(verify), int(fallback is not None), fo)
+        opts = ShiftOpts(ctypes.sizeof(ShiftOpts), tol, max_dim, batch, int(verify), int(fallback is not None), fo,
+                         tune_cache.encode() if tune_cache else None)
         st = self._lib.gfcc_solve_shifts(
             self._h, npp, p_h.ctypes.data_as(ctypes.c_void_p), nw, w_h.ctypes.data_as(ctypes.c_void_p), eta, nq,
             q_h.ctypes.data_as(ctypes.c_void_p) if q_h is not None else None, ctypes.byref(opts), _ptr(G), _ptr(X),
