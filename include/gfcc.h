@@ -183,6 +183,17 @@ gfcc_status gfcc_solve_shifts(gfcc_ctx* ctx, int64_t np, const int64_t* p, int64
                               const gfcc_shift_opts* opts, double* G, double* X, gfcc_rhs_info* info,
                               void* stream);
 
+/* Spectral function from the diagonal of the retarded G (Theory section, the
+ * trace of its imaginary part): A[k] = sgn(eta)/pi * sum_p Im G_pp(omega_k).
+ * With the operator (omega + Hbar_N - i*eta) and eta > 0, Im G_pp > 0 at the
+ * poles, so this equals the paper's -(1/pi) Im of the +i*eta form; eta < 0
+ * conjugates G and the sign keeps A the same.  G: device [np][ld] complex
+ * interleaved, element (p, k) = G_pp(omega_k), ld >= n_omega (e.g. the G of
+ * gfcc_solve_shifts with q = NULL, or of gfcc_solve_batch ordered p-major).
+ * A: device [n_omega].  Needs no context.  Enqueued on `stream`. */
+gfcc_status gfcc_spectral(int64_t np, int64_t n_omega, const double* G, int64_t ld, double eta, double* A,
+                          void* stream);
+
 /* G[r][k] = c_{q_k}^T X[r] (bilinear, no conjugation) for caller vectors X
  * [nrhs][D] complex; q host [nq] in [0, o + v). G device [nrhs][nq] complex. */
 gfcc_status gfcc_greens(gfcc_ctx* ctx, int64_t nrhs, const double* X, int64_t nq, const int64_t* q,

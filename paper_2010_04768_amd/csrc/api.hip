@@ -154,6 +154,17 @@ gfcc_status gfcc_sigma(gfcc_ctx* c, int64_t nrhs, const double* X, double* Y, gf
   });
 }
 
+gfcc_status gfcc_spectral(int64_t np, int64_t n_omega, const double* G, int64_t ld, double eta, double* A,
+                          void* stream) {
+  return guarded([&] {
+    GFCC_CHECK(np >= 0 && n_omega >= 0 && ld >= n_omega, GFCC_E_ARG, "bad sizes (need ld >= n_omega)");
+    if (n_omega == 0) return;
+    GFCC_CHECK(A && (G || np == 0), GFCC_E_ARG, "null argument");
+    GFCC_CHECK(std::isfinite(eta) && eta != 0.0, GFCC_E_ARG, "eta must be finite and non-zero");
+    spectral(np, n_omega, G, ld, eta, A, as_stream(stream));
+  });
+}
+
 gfcc_status gfcc_greens(gfcc_ctx* c, int64_t nrhs, const double* X, int64_t nq, const int64_t* q, double* G,
                         void* stream) {
   return guarded([&] {

@@ -112,6 +112,8 @@ void from_planes(gfcc_ctx* c, int64_t nb, const double* planes, double* xi, hipS
 void make_rhs_rows(gfcc_ctx* c, int64_t n, const int64_t* orb_dev, double* out, hipStream_t s);
 // c_q (real plane) for orbitals orb_dev[0:n] in [0, o + v); out [n][Dp]
 void make_left_rows(gfcc_ctx* c, int64_t n, const int64_t* orb_dev, double* out, hipStream_t s);
+// A[k] = sgn(eta)/pi sum_p Im G[p][k] for G [np][ld] complex (device)
+void spectral(int64_t np, int64_t nw, const double* G, int64_t ld, double eta, double* A, hipStream_t s);
 // G[r][k] = c_{q_k} . x_r (planes), complex interleaved output
 void greens_planes(gfcc_ctx* c, int64_t nb, const double* planes, int64_t nq, const int64_t* q_dev,
                    double* G, hipStream_t s);

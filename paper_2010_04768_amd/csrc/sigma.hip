@@ -412,6 +412,29 @@ void greens_planes(gfcc_ctx* c, int64_t nb, const double* planes, int64_t nq, co
   gemm_auto(Prec::F64, g, c->scr, 0, s);
 }
 
+// Spectral function (Theory section, trace of the imaginary part of the
+// retarded G): A[k] = sgn(eta) / pi * sum_p Im G[p][k].  With the operator
+// (omega + Hbar_N - i eta) and eta > 0 the poles give Im G_pp > 0, so the sign
+// keeps A >= 0 for either sign of eta (G(omega, -eta) = conj G(omega, eta)).
+__global__ void spectral_kernel(const double* __restrict__ G, int64_t np, int64_t ld, double scale,
+                                double* __restrict__ A) {
+  const int64_t k = blockIdx.x;
+  double acc = 0.0;
+  for (int64_t p = threadIdx.x; p < np; p += blockDim.x) acc += G[(p * ld + k) * 2 + 1];
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+  __shared__ double red[4];
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) A[k] = scale * (red[0] + red[1] + red[2] + red[3]);
+}
+
+void spectral(int64_t np, int64_t nw, const double* G, int64_t ld, double eta, double* A, hipStream_t s) {
+  if (nw <= 0) return;
+  const double scale = (eta < 0.0 ? -1.0 : 1.0) / M_PI;
+  hipLaunchKernelGGL(spectral_kernel, dim3(unsigned(nw)), dim3(256), 0, s, G, np, ld, scale, A);
+  GFCC_HIP(hipGetLastError());
+}
+
 // ------------------------------------------------------------------ timing
 
 void prof_begin(gfcc_ctx* c, const char* name, hipStream_t s) {

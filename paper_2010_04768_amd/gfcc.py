@@ -28,7 +28,7 @@ SYMBOLS = ["gfcc_build_intermediates", "gfcc_dims", "gfcc_export", "gfcc_sigma",
            "gfcc_last_error", "gfcc_mlp_train", "gfcc_mlp_set_weights", "gfcc_mlp_get_weights",
            "gfcc_mlp_forward", "gfcc_mlp_loss_grad", "gfcc_mlp_features", "gfcc_mlp_apply",
            "gfcc_mor_reset", "gfcc_mor_extend", "gfcc_mor_model", "gfcc_mor_export", "gfcc_mor_greens",
-           "gfcc_solve_shifts"]
+           "gfcc_solve_shifts", "gfcc_spectral"]
 
 
 class GfccSystem(ctypes.Structure):
@@ -126,6 +126,8 @@ def load():
     L.gfcc_solve_shifts.argtypes = [vp, i64, vp, i64, vp, dbl, i64, vp, ctypes.POINTER(ShiftOpts), vp, vp,
                                     ctypes.POINTER(RhsInfo), vp]
     L.gfcc_solve_shifts.restype = ctypes.c_int
+    L.gfcc_spectral.argtypes = [i64, i64, vp, i64, dbl, vp, vp]
+    L.gfcc_spectral.restype = ctypes.c_int
     L.gfcc_mor_reset.argtypes = [vp]
     L.gfcc_mor_extend.argtypes = [vp, i64, vp, dbl, ctypes.POINTER(i64), vp]
     L.gfcc_mor_model.argtypes = [vp, i64, vp, i64, vp, i64, vp, dbl, vp, vp]
@@ -152,6 +154,17 @@ def _stream():
 
 def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def spectral(G, eta):
+    """A[k] = sgn(eta)/pi * sum_p Im G[p, k] on the GPU; G: [np, n_omega] (or [np, n_omega, 1]) complex
+    device tensor of diagonal elements G_pp(omega_k).  Returns a float64 device tensor [n_omega]."""
+    import torch
+    G = G.reshape(G.shape[0], -1).to(dtype=torch.complex128).contiguous()
+    A = torch.empty(G.shape[1], dtype=torch.float64, device=G.device)
+    _check(load().gfcc_spectral(G.shape[0], G.shape[1], _ptr(G), G.shape[1], float(eta), _ptr(A), _stream()),
+           "gfcc_spectral")
+    return A
 
 
 class Context:

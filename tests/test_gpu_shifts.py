@@ -174,3 +174,19 @@ def test_shifts_benchmark_shape():
             assert np.linalg.norm(res) <= 1.05 * wl.tol * np.linalg.norm(b)
     finally:
         ctx.close()
+
+
+def test_spectral_function(tiny):
+    """A(omega) on the GPU from the multi-shift G_pp equals the oracle's spectral function of the
+    oracle's G, and is unchanged when eta changes sign (G -> conj G)."""
+    s, im, ctx, direct = tiny
+    P = [0, 1, 2, 3]
+    Go = np.array([[O.left_vector(s, p) @ direct(p, w) for p in P] for w in WS])  # [omega][p]
+    Ao = O.spectral_function(Go)
+    G, info, _ = ctx.solve_shifts(P, WS, ETA, tol=1e-12)
+    A = gfcc.spectral(G, ETA).cpu().numpy()
+    assert np.abs(A - Ao).max() <= 1e-9 * np.abs(Ao).max()
+    Gm, _, _ = ctx.solve_shifts(P, WS, -ETA, tol=1e-12)
+    Am = gfcc.spectral(Gm, -ETA).cpu().numpy()
+    assert np.abs(Am - Ao).max() <= 1e-9 * np.abs(Ao).max()
+    assert np.all(A > 0)
