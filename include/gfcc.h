@@ -194,6 +194,20 @@ gfcc_status gfcc_solve_shifts(gfcc_ctx* ctx, int64_t np, const int64_t* p, int64
 gfcc_status gfcc_spectral(int64_t np, int64_t n_omega, const double* G, int64_t ld, double eta, double* A,
                           void* stream);
 
+/* Right-hand sides of several systems in one persistent solve (uneven
+ * convergence across systems, the paper's dynamic pickup of work by idle
+ * process groups in Implementation Details, here at slot granularity): right-hand
+ * side r belongs to system sys[r] (host [nrhs], index into ctxs[0:nsys], distinct
+ * contexts, nsys <= 16).  Each system gets a share of the slot window in
+ * proportion to its right-hand sides (opts->batch = total window, 0 = auto);
+ * all systems advance together, one inner iteration of every system per step,
+ * and the ring GEMMs of up to four systems run as one grouped launch.  p, omega,
+ * q, G, info as for gfcc_solve_batch (q must be valid for every system);
+ * solutions are not returned.  Blocking. */
+gfcc_status gfcc_solve_multi(int32_t nsys, gfcc_ctx* const* ctxs, int64_t nrhs, const int32_t* sys,
+                             const int64_t* p, const double* omega, double eta, int64_t nq, const int64_t* q,
+                             const gfcc_solve_opts* opts, double* G, gfcc_rhs_info* info, void* stream);
+
 /* G[r][k] = c_{q_k}^T X[r] (bilinear, no conjugation) for caller vectors X
  * [nrhs][D] complex; q host [nq] in [0, o + v). G device [nrhs][nq] complex. */
 gfcc_status gfcc_greens(gfcc_ctx* ctx, int64_t nrhs, const double* X, int64_t nq, const int64_t* q,

@@ -335,6 +335,46 @@ gfcc_status gfcc_mlp_apply(gfcc_ctx* c, int64_t nvec, const double* R, const dou
   });
 }
 
+gfcc_status gfcc_solve_multi(int32_t nsys, gfcc_ctx* const* ctxs, int64_t nrhs, const int32_t* sys,
+                             const int64_t* p, const double* omega, double eta, int64_t nq, const int64_t* q,
+                             const gfcc_solve_opts* opts, double* G, gfcc_rhs_info* info, void* stream) {
+  bool all_conv = true;
+  gfcc_status st = guarded([&] {
+    GFCC_CHECK(nsys >= 1 && nsys <= 16 && ctxs, GFCC_E_ARG, "nsys must be in [1, 16]");
+    for (int k = 0; k < nsys; ++k) {
+      GFCC_CHECK(ctxs[k], GFCC_E_ARG, "null context");
+      for (int j = 0; j < k; ++j) GFCC_CHECK(ctxs[j] != ctxs[k], GFCC_E_ARG, "a context appears twice");
+    }
+    GFCC_CHECK(opts && opts->struct_size >= sizeof(gfcc_solve_opts), GFCC_E_ARG, "bad options struct");
+    GFCC_CHECK(nrhs >= 0, GFCC_E_ARG, "nrhs < 0");
+    if (nrhs == 0) return;
+    GFCC_CHECK(sys && p && omega && G && info, GFCC_E_ARG, "null argument");
+    GFCC_CHECK(q != nullptr || nq == 1, GFCC_E_ARG, "q == NULL requires nq == 1");
+    GFCC_CHECK(nq >= 1, GFCC_E_ARG, "nq < 1");
+    for (int64_t r = 0; r < nrhs; ++r) {
+      GFCC_CHECK(sys[r] >= 0 && sys[r] < nsys, GFCC_E_ARG, "system index out of range");
+      const gfcc_ctx* c = ctxs[sys[r]];
+      GFCC_CHECK(p[r] >= 0 && p[r] < c->o + c->v, GFCC_E_ARG, "p out of range");
+      GFCC_CHECK(std::isfinite(omega[r]), GFCC_E_ARG, "non-finite omega");
+    }
+    GFCC_CHECK(std::isfinite(eta), GFCC_E_ARG, "non-finite eta");
+    if (q)
+      for (int k = 0; k < nsys; ++k)
+        for (int64_t j = 0; j < nq; ++j)
+          GFCC_CHECK(q[j] >= 0 && q[j] < ctxs[k]->o + ctxs[k]->v, GFCC_E_ARG, "q out of range for a system");
+    GFCC_CHECK(opts->tol > 0.0 && opts->restart >= 1 && opts->max_iter >= 1, GFCC_E_ARG, "bad tolerance/restart/max_iter");
+    GFCC_CHECK(opts->precond >= GFCC_PC_NONE && opts->precond <= GFCC_PC_MLP, GFCC_E_ARG, "bad preconditioner");
+    GFCC_CHECK(opts->precision >= GFCC_FP64 && opts->precision <= GFCC_BF16_IR, GFCC_E_ARG, "bad precision");
+    if (opts->precond == GFCC_PC_MLP)
+      for (int k = 0; k < nsys; ++k)
+        GFCC_CHECK(ctxs[k]->mlp && ctxs[k]->mlp->trained, GFCC_E_STATE,
+                   "GFCC_PC_MLP needs trained or loaded network weights on every system");
+    solve_multi(nsys, ctxs, nrhs, sys, p, omega, eta, nq, q, opts, G, info, as_stream(stream), &all_conv);
+  });
+  if (st == GFCC_OK && !all_conv) return GFCC_W_NOCONV;
+  return st;
+}
+
 gfcc_status gfcc_solve_shifts(gfcc_ctx* c, int64_t np, const int64_t* p, int64_t n_omega, const double* omega,
                               double eta, int64_t nq, const int64_t* q, const gfcc_shift_opts* opts, double* G,
                               double* X, gfcc_rhs_info* info, void* stream) {

@@ -93,6 +93,10 @@ struct PairRec {
 void solve_batch(gfcc_ctx* c, int64_t nrhs, const int64_t* p, const double* omega, double eta, int64_t nq,
                  const int64_t* q, const gfcc_solve_opts* opts, double* G, double* X, gfcc_rhs_info* info,
                  hipStream_t s, bool* all_converged, PairRec* rec);
+// right-hand sides of several systems (ctxs[sys[r]]) in one persistent loop
+void solve_multi(int nsys, gfcc_ctx* const* ctxs, int64_t nrhs, const int32_t* sys, const int64_t* p,
+                 const double* omega, double eta, int64_t nq, const int64_t* q, const gfcc_solve_opts* opts,
+                 double* G, gfcc_rhs_info* info, hipStream_t s, bool* all_converged);
 // multi-shift GMRES over all frequencies of each orbital (shifts.hip)
 void solve_shifts(gfcc_ctx* c, int64_t np, const int64_t* p, int64_t nw, const double* omega, double eta,
                   int64_t nq, const int64_t* q, const gfcc_shift_opts* o, double* G, double* X,
@@ -104,6 +108,14 @@ void build_intermediates(gfcc_ctx* c, const gfcc_system* sys, hipStream_t s);
 void build_lowprec(gfcc_ctx* c, int which, hipStream_t s);
 void sigma_planes(gfcc_ctx* c, int64_t nplanes, const double* x, double* y, gfcc_precision prec,
                   hipStream_t s);
+// sigma for several systems at once (the ring GEMMs of all in grouped launches)
+struct SigmaJob {
+  gfcc_ctx* c;
+  int64_t P;
+  const double* x;
+  double* y;
+};
+void sigma_group(const SigmaJob* jobs, int nj, gfcc_precision prec, hipStream_t s);
 // interleaved complex [nb][D] <-> planes [2 nb][Dp]
 void to_planes(gfcc_ctx* c, int64_t nb, const double* xi, double* planes, hipStream_t s);
 void from_planes(gfcc_ctx* c, int64_t nb, const double* planes, double* xi, hipStream_t s);

@@ -105,7 +105,7 @@ __device__ __forceinline__ int64_t rmap(const RowMap& m, int64_t r) {
 }
 
 template <typename T, int BM, int BN, bool VEC, bool BNC>
-__global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
+__device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t braw) {
   using MF = Mfma<T>;
   constexpr int EPC = 16 / int(sizeof(T));   // elements per 16-byte chunk
   constexpr int BK = 8 * EPC;                // 8 chunks per row: 16 fp64, 32 fp32, 64 bf16
@@ -128,7 +128,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
   const int64_t tiles_m = (g.M + BM - 1) / BM;
   const int64_t tiles_n = (g.N + BN - 1) / BN;
   const int64_t ntiles = tiles_m * tiles_n;
-  int64_t bid = blockIdx.x;
+  int64_t bid = braw;
   bid = xcd_remap(bid, ntiles);
   constexpr int64_t GROUP = 8;
   const int64_t per_group = GROUP * tiles_n;
@@ -286,12 +286,17 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
   }
 }
 
+template <typename T, int BM, int BN, bool VEC, bool BNC>
+__global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
+  gemm_tile<T, BM, BN, VEC, BNC>(g, blockIdx.x);
+}
+
 // Double-buffered variant for the large ring GEMMs (both operands K-contiguous):
 // NW = WGM x WGN waves, each computing a (BM/WGM) x (BN/WGN) sub-tile; two LDS
 // stages so that one barrier per K-step separates "store next" from "read
 // current"; global loads for step k+1 are issued before the MFMAs of step k.
 template <typename T, typename MF, int BM, int BN, int WGM, int WGN, int KM, bool VEC>
-__global__ __launch_bounds__(64 * WGM * WGN) void gemm_db_kernel(GemmArgs g) {
+__device__ __forceinline__ void gemm_db_tile(const GemmArgs& g, int64_t braw) {
   constexpr int NT = 64 * WGM * WGN;
   constexpr int EPC = 16 / int(sizeof(T));
   constexpr int CPR = 8 * KM;  // 16-byte chunks per K-row of a stage
@@ -315,7 +320,7 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_db_kernel(GemmArgs g) {
   const int64_t tiles_m = (g.M + BM - 1) / BM;
   const int64_t tiles_n = (g.N + BN - 1) / BN;
   const int64_t ntiles = tiles_m * tiles_n;
-  int64_t bid = blockIdx.x;
+  int64_t bid = braw;
   bid = xcd_remap(bid, ntiles);
   constexpr int64_t GROUP = 4;
   const int64_t per_group = GROUP * tiles_n;
@@ -430,6 +435,40 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_db_kernel(GemmArgs g) {
   }
 }
 
+template <typename T, typename MF, int BM, int BN, int WGM, int WGN, int KM, bool VEC>
+__global__ __launch_bounds__(64 * WGM * WGN) void gemm_db_kernel(GemmArgs g) {
+  gemm_db_tile<T, MF, BM, BN, WGM, WGN, KM, VEC>(g, blockIdx.x);
+}
+
+// Grouped launch: group gi owns blocks [start[gi], start[gi+1]); starts are
+// multiples of 8 so a group's blocks keep the XCD round-robin of a plain launch.
+template <int BM, int BN>
+__device__ __forceinline__ int64_t group_of(const GemmGroup& gg, int64_t* local) {
+  int gi = 0;
+  while (gi + 1 < gg.ng && int64_t(blockIdx.x) >= gg.start[gi + 1]) ++gi;
+  const GemmArgs& g = gg.g[gi];
+  const int64_t l = int64_t(blockIdx.x) - gg.start[gi];
+  const int64_t ntiles = ((g.M + BM - 1) / BM) * ((g.N + BN - 1) / BN);
+  *local = l;
+  return l < ntiles ? gi : -1;
+}
+
+template <typename T, typename MF, int BM, int BN, int WGM, int WGN, int KM, bool VEC>
+__global__ __launch_bounds__(64 * WGM * WGN) void gemm_db_grouped_kernel(GemmGroup gg) {
+  int64_t local = 0;
+  const int64_t gi = group_of<BM, BN>(gg, &local);
+  if (gi < 0) return;  // padding block of a group
+  gemm_db_tile<T, MF, BM, BN, WGM, WGN, KM, VEC>(gg.g[gi], local);
+}
+
+template <typename T, int BM, int BN, bool VEC>
+__global__ __launch_bounds__(256) void gemm_grouped_kernel(GemmGroup gg) {
+  int64_t local = 0;
+  const int64_t gi = group_of<BM, BN>(gg, &local);
+  if (gi < 0) return;
+  gemm_tile<T, BM, BN, VEC, false>(gg.g[gi], local);
+}
+
 template <typename T, int BM, int BN, int WGM, int WGN, int KM = 1, typename MF = Mfma<T>>
 static void launch_db(const GemmArgs& a, bool vec, hipStream_t s) {
   const int64_t tiles = ((a.M + BM - 1) / BM) * ((a.N + BN - 1) / BN);
@@ -494,6 +533,78 @@ static void dispatch(const GemmArgs& a, int cfg, bool vec, hipStream_t s) {
     case TILE_DB_256x256_W16:
       if constexpr (std::is_same<T, __bf16>::value) launch_db<T, 256, 256, 4, 4>(a, vec, s);
       else launch_db<T, 256, 256, 4, 2>(a, vec, s);
+      break;
+    default: throw Error{GFCC_E_ARG, "bad tile config"};
+  }
+}
+
+template <typename T, int BM, int BN, int WGM, int WGN, int KM = 1, typename MF = Mfma<T>>
+static void launch_db_grouped(const GemmGroup& gg, bool vec, hipStream_t s) {
+  dim3 grid(unsigned(gg.start[gg.ng]), 1, 1);
+  if (vec)
+    hipLaunchKernelGGL((gemm_db_grouped_kernel<T, MF, BM, BN, WGM, WGN, KM, true>), grid, dim3(64 * WGM * WGN), 0, s,
+                       gg);
+  else
+    hipLaunchKernelGGL((gemm_db_grouped_kernel<T, MF, BM, BN, WGM, WGN, KM, false>), grid, dim3(64 * WGM * WGN), 0,
+                       s, gg);
+  GFCC_HIP(hipGetLastError());
+}
+
+template <typename T, int BM, int BN>
+static void launch_grouped(const GemmGroup& gg, bool vec, hipStream_t s) {
+  dim3 grid(unsigned(gg.start[gg.ng]), 1, 1);
+  if (vec)
+    hipLaunchKernelGGL((gemm_grouped_kernel<T, BM, BN, true>), grid, dim3(256), 0, s, gg);
+  else
+    hipLaunchKernelGGL((gemm_grouped_kernel<T, BM, BN, false>), grid, dim3(256), 0, s, gg);
+  GFCC_HIP(hipGetLastError());
+}
+
+// tile sizes of a configuration
+static void tile_dims(int cfg, int* bm, int* bn) {
+  switch (cfg) {
+    case TILE_128x128: case TILE_DB_128x128: case TILE_DB32_128x128: *bm = 128; *bn = 128; return;
+    case TILE_64x64: *bm = 64; *bn = 64; return;
+    case TILE_128x64: *bm = 128; *bn = 64; return;
+    case TILE_64x128: *bm = 64; *bn = 128; return;
+    case TILE_DB_256x128: case TILE_DB32_256x128: *bm = 256; *bn = 128; return;
+    case TILE_DB_128x256: *bm = 128; *bn = 256; return;
+    case TILE_DB_256x256: case TILE_DB32_256x256: case TILE_DB32_256x256_W16: case TILE_DB_256x256_W16:
+      *bm = 256; *bn = 256; return;
+    default: throw Error{GFCC_E_ARG, "bad tile config"};
+  }
+}
+
+template <typename T>
+static void dispatch_grouped(const GemmGroup& gg, int cfg, bool vec, hipStream_t s) {
+  switch (cfg) {
+    case TILE_128x128: launch_grouped<T, 128, 128>(gg, vec, s); break;
+    case TILE_64x64: launch_grouped<T, 64, 64>(gg, vec, s); break;
+    case TILE_128x64: launch_grouped<T, 128, 64>(gg, vec, s); break;
+    case TILE_64x128: launch_grouped<T, 64, 128>(gg, vec, s); break;
+    case TILE_DB_128x128: launch_db_grouped<T, 128, 128, 2, 2>(gg, vec, s); break;
+    case TILE_DB_256x128: launch_db_grouped<T, 256, 128, 4, 2>(gg, vec, s); break;
+    case TILE_DB_128x256: launch_db_grouped<T, 128, 256, 2, 4>(gg, vec, s); break;
+    case TILE_DB_256x256: launch_db_grouped<T, 256, 256, 4, 2>(gg, vec, s); break;
+    case TILE_DB32_256x256:
+      if constexpr (std::is_same<T, __bf16>::value) launch_db_grouped<T, 256, 256, 4, 2, 1, Mfma32Bf16>(gg, vec, s);
+      else launch_db_grouped<T, 256, 256, 4, 2>(gg, vec, s);
+      break;
+    case TILE_DB32_256x128:
+      if constexpr (std::is_same<T, __bf16>::value) launch_db_grouped<T, 256, 128, 4, 2, 1, Mfma32Bf16>(gg, vec, s);
+      else launch_db_grouped<T, 256, 128, 4, 2>(gg, vec, s);
+      break;
+    case TILE_DB32_128x128:
+      if constexpr (std::is_same<T, __bf16>::value) launch_db_grouped<T, 128, 128, 2, 2, 1, Mfma32Bf16>(gg, vec, s);
+      else launch_db_grouped<T, 128, 128, 2, 2>(gg, vec, s);
+      break;
+    case TILE_DB32_256x256_W16:
+      if constexpr (std::is_same<T, __bf16>::value) launch_db_grouped<T, 256, 256, 4, 4, 1, Mfma32Bf16>(gg, vec, s);
+      else launch_db_grouped<T, 256, 256, 4, 2>(gg, vec, s);
+      break;
+    case TILE_DB_256x256_W16:
+      if constexpr (std::is_same<T, __bf16>::value) launch_db_grouped<T, 256, 256, 4, 4>(gg, vec, s);
+      else launch_db_grouped<T, 256, 256, 4, 2>(gg, vec, s);
       break;
     default: throw Error{GFCC_E_ARG, "bad tile config"};
   }
@@ -586,6 +697,38 @@ void gemm(Prec p, const GemmArgs& a, int cfg, hipStream_t s) {
     case Prec::F64: dispatch<double>(a, cfg, vec, s); break;
     case Prec::F32: dispatch<float>(a, cfg, vec, s); break;
     case Prec::BF16: dispatch<__bf16>(a, cfg, vec, s); break;
+  }
+}
+
+void gemm_grouped(Prec p, const GemmArgs* a, int ng, int cfg, hipStream_t s) {
+  GFCC_CHECK(ng >= 0 && ng <= MAX_GEMM_GROUPS, GFCC_E_ARG, "too many GEMM groups");
+  const int64_t esz = (p == Prec::F64) ? 8 : (p == Prec::F32 ? 4 : 2);
+  const int64_t epc = 16 / esz;
+  int bm = 0, bn = 0;
+  tile_dims(cfg, &bm, &bn);
+  GemmGroup gg;
+  gg.ng = 0;
+  gg.start[0] = 0;
+  bool vec = true;
+  for (int i = 0; i < ng; ++i) {
+    const GemmArgs& x = a[i];
+    if (x.M <= 0 || x.N <= 0) continue;
+    GFCC_CHECK(x.K >= 0 && x.batch == 1 && x.k_split == 0 && !x.b_ncontig, GFCC_E_ARG,
+               "grouped GEMM: batch 1, no split-K, K-contiguous B");
+    GFCC_CHECK(x.am.div > 0 && x.bm.div > 0 && x.cm.div > 0 && x.cn.div > 0, GFCC_E_ARG, "bad row map");
+    vec = vec && aligned_map(x.am, epc) && aligned_map(x.bm, epc) && (reinterpret_cast<uintptr_t>(x.A) % 16 == 0) &&
+          (reinterpret_cast<uintptr_t>(x.B) % 16 == 0);
+    const int64_t tiles = ((x.M + bm - 1) / bm) * ((x.N + bn - 1) / bn);
+    gg.g[gg.ng] = x;
+    gg.start[gg.ng + 1] = gg.start[gg.ng] + (tiles + 7) / 8 * 8;
+    gg.ng += 1;
+  }
+  if (gg.ng == 0) return;
+  GFCC_CHECK(gg.start[gg.ng] < (int64_t(1) << 31), GFCC_E_ARG, "GEMM grid too large");
+  switch (p) {
+    case Prec::F64: dispatch_grouped<double>(gg, cfg, vec, s); break;
+    case Prec::F32: dispatch_grouped<float>(gg, cfg, vec, s); break;
+    case Prec::BF16: dispatch_grouped<__bf16>(gg, cfg, vec, s); break;
   }
 }
 

@@ -109,6 +109,14 @@ struct GemmArgs {
   int64_t k_split = 0;
 };
 
+// Several independent GEMMs (same precision and tile) in one launch.
+constexpr int MAX_GEMM_GROUPS = 4;
+struct GemmGroup {
+  GemmArgs g[MAX_GEMM_GROUPS];
+  int64_t start[MAX_GEMM_GROUPS + 1];  // first block of each group (multiples of 8)
+  int ng = 0;
+};
+
 // Tile configurations; the autotuner picks one per (shape, precision).
 enum TileCfg : int {
   TILE_128x128 = 0, TILE_64x64 = 1, TILE_128x64 = 2, TILE_64x128 = 3,
@@ -123,6 +131,8 @@ enum TileCfg : int {
 const char* tile_name(int cfg);
 
 void gemm(Prec p, const GemmArgs& a, int cfg, hipStream_t s);
+// ng <= MAX_GEMM_GROUPS GEMMs (batch 1, no split-K, K-contiguous B) in one grouped launch
+void gemm_grouped(Prec p, const GemmArgs* a, int ng, int cfg, hipStream_t s);
 // GEMM whose tile grid is too small to fill the GPU: split K over `slices`,
 // reduce the partials (deterministic order) into C with alpha/beta.
 void gemm_splitk(Prec p, const GemmArgs& a, int slices, double* part, hipStream_t s);

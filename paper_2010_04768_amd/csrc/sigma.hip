@@ -100,7 +100,13 @@ static void make_operands(gfcc_ctx* c, int64_t P, const double* x, T* RT, T* R, 
   GFCC_HIP(hipGetLastError());
 }
 
-void sigma_planes(gfcc_ctx* c, int64_t P, const double* x, double* y, gfcc_precision prec, hipStream_t s) {
+// phases of one sigma: operand copies, the three ring GEMMs, everything else
+enum : int { PH_OPS = 1, PH_RING = 2, PH_REST = 4, PH_ALL = 7 };
+
+// With ring_out != nullptr the ring phase returns its three GEMMs (and tile)
+// instead of launching them, for a grouped launch over several systems.
+static void sigma_impl(gfcc_ctx* c, int64_t P, const double* x, double* y, gfcc_precision prec, hipStream_t s,
+                       int phases, GemmArgs* ring_out, int* ring_cfg) {
   if (P <= 0) return;
   const int64_t o = c->o, v = c->v, ov = c->ov, oo = c->oo, oov = c->oov;
   const int64_t Dp = c->Dp, op = c->o_pad, kp = c->kp;
@@ -115,18 +121,21 @@ void sigma_planes(gfcc_ctx* c, int64_t P, const double* x, double* y, gfcc_preci
   if (lowp) c->ws_R.ensure(size_t(P * ps * esz), s);
   c->ws_z.ensure(size_t(P * c->vp * 8), s);
 
-  prof_begin(c, "sigma", s);
-  switch (rp) {
-    case Prec::F64:
-      make_operands<double>(c, P, x, c->ws_RT.as<double>(), nullptr, c->ws_Ra.as<double>(), ps, y, s);
-      break;
-    case Prec::F32:
-      make_operands<float>(c, P, x, c->ws_RT.as<float>(), c->ws_R.as<float>(), c->ws_Ra.as<float>(), ps, y, s);
-      break;
-    case Prec::BF16:
-      make_operands<__bf16>(c, P, x, c->ws_RT.as<__bf16>(), c->ws_R.as<__bf16>(), c->ws_Ra.as<__bf16>(), ps, y,
-                             s);
-      break;
+  const bool whole = phases == PH_ALL;
+  if (whole) prof_begin(c, "sigma", s);
+  if (phases & PH_OPS) {
+    switch (rp) {
+      case Prec::F64:
+        make_operands<double>(c, P, x, c->ws_RT.as<double>(), nullptr, c->ws_Ra.as<double>(), ps, y, s);
+        break;
+      case Prec::F32:
+        make_operands<float>(c, P, x, c->ws_RT.as<float>(), c->ws_R.as<float>(), c->ws_Ra.as<float>(), ps, y, s);
+        break;
+      case Prec::BF16:
+        make_operands<__bf16>(c, P, x, c->ws_RT.as<__bf16>(), c->ws_R.as<__bf16>(), c->ws_Ra.as<__bf16>(), ps, y,
+                               s);
+        break;
+    }
   }
   const auto& L = c->lp[li];
   const void* X1 = lowp ? L.X1.p : c->X1.p;
@@ -143,7 +152,7 @@ void sigma_planes(gfcc_ctx* c, int64_t P, const double* x, double* y, gfcc_preci
   const double ring_bytes = double(ov) * double(kp) * esz + 2.0 * double(P) * double(o) * double(ov) * (esz + 8.0);
 
   // ---- ring terms
-  {
+  if (phases & PH_RING) {
     GemmArgs g;
     g.M = P * o;
     g.N = ov;
@@ -164,27 +173,32 @@ void sigma_planes(gfcc_ctx* c, int64_t P, const double* x, double* y, gfcc_preci
     g.bm = lin(kp);
     g.alpha = sX1;
     g.beta = 1.0;  // y2 holds the diagonal one-body part
-    prof_begin(c, ring_name, s);
-    gemm(rp, g, cfg, s);
-    prof_end(c, ring_name, s, ring_flops, ring_bytes);
+    auto run = [&](int k) {
+      if (ring_out) {
+        ring_out[k] = g;
+        *ring_cfg = cfg;
+        return;
+      }
+      prof_begin(c, ring_name, s);
+      gemm(rp, g, cfg, s);
+      prof_end(c, ring_name, s, ring_flops, ring_bytes);
+    };
+    run(0);
     // P1b
     g.A = c->ws_RT.p;
     g.am = two(o, ps, ov);
     g.B = Wvo;
     g.alpha = -sWvo;
     g.beta = 1.0;
-    prof_begin(c, ring_name, s);
-    gemm(rp, g, cfg, s);
-    prof_end(c, ring_name, s, ring_flops, ring_bytes);
+    run(1);
     // P2: rows (p, j), cols (i, a) -> s2[p][i][j][a]
     g.B = Wov;
     g.alpha = -sWov;
     g.cm = two(o, Dp, v);
     g.cn = two(v, ov, 1);
-    prof_begin(c, ring_name, s);
-    gemm(rp, g, cfg, s);
-    prof_end(c, ring_name, s, ring_flops, ring_bytes);
+    run(2);
   }
+  if (!(phases & PH_REST)) return;
   // ---- hole-hole ladder: s2[p][(i,j)][a] += sum_(mn) W4T[(i,j)][(m,n)] Ra[(p,a)][(m,n)]
   {
     GemmArgs g;
@@ -279,7 +293,44 @@ void sigma_planes(gfcc_ctx* c, int64_t P, const double* x, double* y, gfcc_preci
   const double total_flops = 3.0 * ring_flops + 2.0 * double(P) * (double(oo) * oo * v + 2.0 * oov * v +
                                                                     double(oov) * v + double(oov) * o +
                                                                     2.0 * double(oov) * o + double(Dp) * o);
-  prof_end(c, "sigma", s, total_flops, 0.0);
+  if (whole) prof_end(c, "sigma", s, total_flops, 0.0);
+}
+
+void sigma_planes(gfcc_ctx* c, int64_t P, const double* x, double* y, gfcc_precision prec, hipStream_t s) {
+  sigma_impl(c, P, x, y, prec, s, PH_ALL, nullptr, nullptr);
+}
+
+// Several systems: operand copies per system, each ring term of all systems in
+// one grouped launch (tile of the largest system), the remaining terms per system.
+void sigma_group(const SigmaJob* jobs, int nj, gfcc_precision prec, hipStream_t s) {
+  int live = 0;
+  for (int j = 0; j < nj; ++j) live += jobs[j].P > 0 ? 1 : 0;
+  if (live <= 1 || nj > MAX_GEMM_GROUPS) {
+    for (int j = 0; j < nj; ++j) sigma_planes(jobs[j].c, jobs[j].P, jobs[j].x, jobs[j].y, prec, s);
+    return;
+  }
+  const Prec rp = prec == GFCC_FP64 ? Prec::F64 : (prec == GFCC_BF16_IR ? Prec::BF16 : Prec::F32);
+  GemmArgs ring[3][MAX_GEMM_GROUPS];
+  int ng = 0, cfg = 0;
+  double best = -1.0;
+  for (int j = 0; j < nj; ++j) {
+    const SigmaJob& J = jobs[j];
+    if (J.P <= 0) continue;
+    sigma_impl(J.c, J.P, J.x, J.y, prec, s, PH_OPS, nullptr, nullptr);
+    GemmArgs g3[3];
+    int cj = 0;
+    sigma_impl(J.c, J.P, J.x, J.y, prec, s, PH_RING, g3, &cj);
+    for (int t = 0; t < 3; ++t) ring[t][ng] = g3[t];
+    const double size = double(g3[0].M) * double(g3[0].N);
+    if (size > best) {
+      best = size;
+      cfg = cj;
+    }
+    ++ng;
+  }
+  for (int t = 0; t < 3; ++t) gemm_grouped(rp, ring[t], ng, cfg, s);
+  for (int j = 0; j < nj; ++j)
+    if (jobs[j].P > 0) sigma_impl(jobs[j].c, jobs[j].P, jobs[j].x, jobs[j].y, prec, s, PH_REST, nullptr, nullptr);
 }
 
 // ------------------------------------------------------------------ layout conversions

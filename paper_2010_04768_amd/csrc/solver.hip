@@ -30,6 +30,7 @@
 #include <deque>
 #include <map>
 #include <set>
+#include <string>
 #include <vector>
 
 #include "ctx.h"
@@ -626,108 +627,129 @@ static void upload(DBuf& b, const std::vector<T>& v, hipStream_t s) {
   if (!v.empty()) GFCC_HIP(hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
 }
 
-void solve_batch(gfcc_ctx* c, int64_t nrhs, const int64_t* p, const double* omega, double eta, int64_t nq,
-                 const int64_t* q, const gfcc_solve_opts* opts, double* G, double* Xout, gfcc_rhs_info* info,
-                 hipStream_t s, bool* all_converged, PairRec* rec) {
-  const int m = std::min<int>(opts->restart, MAXM);
-  const gfcc_precision prec = opts->precision;
-  const bool use_mlp = opts->precond == GFCC_PC_MLP;
-  GFCC_CHECK(!use_mlp || (c->mlp && c->mlp->trained), GFCC_E_STATE,
-             "GFCC_PC_MLP needs trained or loaded network weights");
-  const int mode = use_mlp ? GFCC_PC_JACOBI : opts->precond;  // Jacobi is also the MLP fallback
-  const int flex = use_mlp ? 1 : 0;
-  const int64_t Dp = c->Dp;
-  const int nch = int((Dp + CH - 1) / CH);
-  int B = opts->batch > 0 ? opts->batch : 0;
-  if (B == 0) {
-    size_t freeb = 0, totalb = 0;
-    GFCC_HIP(hipMemGetInfo(&freeb, &totalb));
-    const double per_slot = double(m + 2 + (flex ? m : 0)) * 2.0 * Dp * 8.0 + 6.0 * 2.0 * Dp * 8.0;
-    const int64_t fit = int64_t(0.5 * double(freeb) / per_slot);
-    B = int(std::max<int64_t>(1, std::min<int64_t>({fit, 128, nrhs})));
-  }
-  B = int(std::min<int64_t>(B, nrhs));
-
-  // device state
+// One system's share of the solve: a window of B slots on its context, the
+// queue of its right-hand sides (global indices) and the device state.
+struct Lane {
+  gfcc_ctx* c = nullptr;
+  std::vector<int64_t> rows;
+  size_t next = 0;
+  int B = 0, nch = 0;
+  int64_t Dp = 0;
   DBuf bV, bZ, bX, bH, bcs, bsn, bg, by, bz, bkk, bctol, bres, bflag, bpart, bGm, bh, bnpart, bnorm;
-  bV.ensure(size_t(B) * (m + 1) * 2 * Dp * 8, s);
-  if (flex) bZ.ensure(size_t(B) * m * 2 * Dp * 8, s);
-  bX.ensure(size_t(B) * 2 * Dp * 8, s);
-  bH.ensure(size_t(B) * m * (m + 1) * sizeof(cplx), s);
-  bcs.ensure(size_t(B) * m * sizeof(cplx), s);
-  bsn.ensure(size_t(B) * m * sizeof(cplx), s);
-  bg.ensure(size_t(B) * (m + 1) * sizeof(cplx), s);
-  by.ensure(size_t(B) * m * sizeof(cplx), s);
-  bz.ensure(size_t(B) * sizeof(cplx), s);
-  bkk.ensure(size_t(B) * sizeof(int), s);
-  bctol.ensure(size_t(B) * 8, s);
-  bres.ensure(size_t(B) * 8, s);
-  bflag.ensure(size_t(B) * sizeof(int), s);
-  bpart.ensure(size_t(B) * nch * PS * sizeof(cplx), s);
-  bGm.ensure(size_t(B) * m * (m + 1) * sizeof(cplx), s);
-  bh.ensure(size_t(B) * (MAXM + 1) * sizeof(cplx), s);
-  bnpart.ensure(size_t(B) * nch * 8, s);
-  bnorm.ensure(size_t(B) * 8, s);
-  c->ws_in.ensure(size_t(2 * B) * Dp * 8, s);
-  c->ws_out.ensure(size_t(2 * B) * Dp * 8, s);
-
-  SolverDev d;
-  d.V = bV.as<double>();
-  d.Z = flex ? bZ.as<double>() : nullptr;
-  d.X = bX.as<double>();
-  d.H = bH.as<cplx>();
-  d.cs = bcs.as<cplx>();
-  d.sn = bsn.as<cplx>();
-  d.g = bg.as<cplx>();
-  d.y = by.as<cplx>();
-  d.z = bz.as<cplx>();
-  d.kk = bkk.as<int>();
-  d.ctol = bctol.as<double>();
-  d.res = bres.as<double>();
-  d.flag = bflag.as<int>();
-  d.part = bpart.as<cplx>();
-  d.Gm = bGm.as<cplx>();
-  d.h = bh.as<cplx>();
-  d.npart = bnpart.as<double>();
-  d.norm = bnorm.as<double>();
-  d.m = m;
-  d.Dp = Dp;
-  d.nch = nch;
-
+  SolverDev d{};
   DBuf d_act, d_flags, d_res, d_list, d_plist, d_brow, d_zlist, d_ctl, d_beta, d_rows, d_q;
   DBuf d_msrc, d_mzoff, d_mom, d_pmode;
-  d_flags.ensure(size_t(B) * sizeof(int), s);
-  d_res.ensure(size_t(B) * 8, s);
-  d_beta.ensure(size_t(B) * 8, s);
-
-  // Right-hand sides of virtual orbitals, one materialised row per distinct
-  // orbital with its norm; occupied p keep the implicit unit vector e_p.
-  std::map<int64_t, int> brow_of;
-  std::vector<int64_t> borb;
-  for (int64_t r = 0; r < nrhs; ++r)
-    if (p[r] >= c->o && !brow_of.count(p[r])) {
-      brow_of[p[r]] = int(borb.size());
-      borb.push_back(p[r]);
-    }
+  std::map<int64_t, int> brow_of;  // virtual p -> row of bB
+  std::vector<double> bnorm_h;
   DBuf d_borb, bB, bBn;
-  std::vector<double> bnorm_h(borb.size());
-  if (!borb.empty()) {
-    const int64_t nb = int64_t(borb.size());
-    upload(d_borb, borb, s);
-    bB.ensure(size_t(nb * Dp) * 8, s);
-    bBn.ensure(size_t(nb) * 8, s);
-    make_rhs_rows(c, nb, d_borb.as<int64_t>(), bB.as<double>(), s);
-    hipLaunchKernelGGL(row_norm_kernel, dim3(unsigned(nb)), dim3(VT), 0, s, bB.as<double>(), Dp, bBn.as<double>());
-    GFCC_HIP(hipGetLastError());
-    GFCC_HIP(hipMemcpyAsync(bnorm_h.data(), bBn.p, size_t(nb) * 8, hipMemcpyDeviceToHost, s));
-    GFCC_HIP(hipStreamSynchronize(s));
-  }
-  // Left vectors: the occupied rows built with the intermediates, or, when a
-  // virtual orbital is asked for, one materialised row per distinct orbital.
-  const double* lrows = c->left.as<double>();
+  const double* lrows = nullptr;
   std::map<int64_t, int64_t> lrow_of;
   DBuf d_lorb, bL;
-  {
+  std::vector<HostSlot> hs;
+  std::vector<int> free_slots, active, pending;
+  std::vector<int> hflags;
+  std::vector<double> hres, hbeta;
+  int64_t lrow(int64_t orb) const { return lrow_of.empty() ? orb : lrow_of.at(orb); }
+};
+
+namespace {
+
+struct BatchRun {
+  const int64_t* p;
+  const double* omega;
+  double eta;
+  int64_t nq;
+  const int64_t* q;
+  const gfcc_solve_opts* opts;
+  double* G;
+  double* Xout;
+  gfcc_rhs_info* info;
+  PairRec* rec;
+  hipStream_t s;
+  int m = 0, mode = 0, flex = 0;
+  bool use_mlp = false;
+  gfcc_precision prec = GFCC_FP64;
+  double tol = 0.0, rtol_lp = 0.0;
+  bool ok_all = true;
+
+  // device buffers, right-hand-side rows and left rows of one lane
+  void setup(Lane& L) {
+    gfcc_ctx* c = L.c;
+    const int B = L.B;
+    const int64_t Dp = c->Dp;
+    L.Dp = Dp;
+    L.nch = int((Dp + CH - 1) / CH);
+    const int nch = L.nch;
+    L.bV.ensure(size_t(B) * (m + 1) * 2 * Dp * 8, s);
+    if (flex) L.bZ.ensure(size_t(B) * m * 2 * Dp * 8, s);
+    L.bX.ensure(size_t(B) * 2 * Dp * 8, s);
+    L.bH.ensure(size_t(B) * m * (m + 1) * sizeof(cplx), s);
+    L.bcs.ensure(size_t(B) * m * sizeof(cplx), s);
+    L.bsn.ensure(size_t(B) * m * sizeof(cplx), s);
+    L.bg.ensure(size_t(B) * (m + 1) * sizeof(cplx), s);
+    L.by.ensure(size_t(B) * m * sizeof(cplx), s);
+    L.bz.ensure(size_t(B) * sizeof(cplx), s);
+    L.bkk.ensure(size_t(B) * sizeof(int), s);
+    L.bctol.ensure(size_t(B) * 8, s);
+    L.bres.ensure(size_t(B) * 8, s);
+    L.bflag.ensure(size_t(B) * sizeof(int), s);
+    L.bpart.ensure(size_t(B) * nch * PS * sizeof(cplx), s);
+    L.bGm.ensure(size_t(B) * m * (m + 1) * sizeof(cplx), s);
+    L.bh.ensure(size_t(B) * (MAXM + 1) * sizeof(cplx), s);
+    L.bnpart.ensure(size_t(B) * nch * 8, s);
+    L.bnorm.ensure(size_t(B) * 8, s);
+    c->ws_in.ensure(size_t(2 * B) * Dp * 8, s);
+    c->ws_out.ensure(size_t(2 * B) * Dp * 8, s);
+    SolverDev& d = L.d;
+    d.V = L.bV.as<double>();
+    d.Z = flex ? L.bZ.as<double>() : nullptr;
+    d.X = L.bX.as<double>();
+    d.H = L.bH.as<cplx>();
+    d.cs = L.bcs.as<cplx>();
+    d.sn = L.bsn.as<cplx>();
+    d.g = L.bg.as<cplx>();
+    d.y = L.by.as<cplx>();
+    d.z = L.bz.as<cplx>();
+    d.kk = L.bkk.as<int>();
+    d.ctol = L.bctol.as<double>();
+    d.res = L.bres.as<double>();
+    d.flag = L.bflag.as<int>();
+    d.part = L.bpart.as<cplx>();
+    d.Gm = L.bGm.as<cplx>();
+    d.h = L.bh.as<cplx>();
+    d.npart = L.bnpart.as<double>();
+    d.norm = L.bnorm.as<double>();
+    d.m = m;
+    d.Dp = Dp;
+    d.nch = nch;
+    L.d_flags.ensure(size_t(B) * sizeof(int), s);
+    L.d_res.ensure(size_t(B) * 8, s);
+    L.d_beta.ensure(size_t(B) * 8, s);
+
+    // Right-hand sides of virtual orbitals, one materialised row per distinct
+    // orbital with its norm; occupied p keep the implicit unit vector e_p.
+    std::vector<int64_t> borb;
+    for (int64_t r : L.rows)
+      if (p[r] >= c->o && !L.brow_of.count(p[r])) {
+        L.brow_of[p[r]] = int(borb.size());
+        borb.push_back(p[r]);
+      }
+    L.bnorm_h.assign(borb.size(), 0.0);
+    if (!borb.empty()) {
+      const int64_t nb = int64_t(borb.size());
+      upload(L.d_borb, borb, s);
+      L.bB.ensure(size_t(nb * Dp) * 8, s);
+      L.bBn.ensure(size_t(nb) * 8, s);
+      make_rhs_rows(c, nb, L.d_borb.as<int64_t>(), L.bB.as<double>(), s);
+      hipLaunchKernelGGL(row_norm_kernel, dim3(unsigned(nb)), dim3(VT), 0, s, L.bB.as<double>(), Dp,
+                         L.bBn.as<double>());
+      GFCC_HIP(hipGetLastError());
+      GFCC_HIP(hipMemcpyAsync(L.bnorm_h.data(), L.bBn.p, size_t(nb) * 8, hipMemcpyDeviceToHost, s));
+      GFCC_HIP(hipStreamSynchronize(s));
+    }
+    // Left vectors: the occupied rows built with the intermediates, or, when a
+    // virtual orbital is asked for, one materialised row per distinct orbital.
+    L.lrows = c->left.as<double>();
     bool virt = false;
     if (q) {
       for (int64_t k = 0; k < nq; ++k) virt = virt || q[k] >= c->o;
@@ -736,258 +758,189 @@ void solve_batch(gfcc_ctx* c, int64_t nrhs, const int64_t* p, const double* omeg
     }
     if (virt) {
       std::vector<int64_t> lorb;
-      const int64_t nl_src = q ? nq : nrhs;
-      for (int64_t k = 0; k < nl_src; ++k) {
-        const int64_t orb = q ? q[k] : p[k];
-        if (!lrow_of.count(orb)) {
-          lrow_of[orb] = int64_t(lorb.size());
+      auto add = [&](int64_t orb) {
+        if (!L.lrow_of.count(orb)) {
+          L.lrow_of[orb] = int64_t(lorb.size());
           lorb.push_back(orb);
         }
-      }
-      upload(d_lorb, lorb, s);
-      bL.ensure(lorb.size() * size_t(Dp) * 8, s);
-      make_left_rows(c, int64_t(lorb.size()), d_lorb.as<int64_t>(), bL.as<double>(), s);
-      lrows = bL.as<double>();
+      };
+      if (q)
+        for (int64_t k = 0; k < nq; ++k) add(q[k]);
+      else
+        for (int64_t r : L.rows) add(p[r]);
+      upload(L.d_lorb, lorb, s);
+      L.bL.ensure(lorb.size() * size_t(Dp) * 8, s);
+      make_left_rows(c, int64_t(lorb.size()), L.d_lorb.as<int64_t>(), L.bL.as<double>(), s);
+      L.lrows = L.bL.as<double>();
     }
-  }
-  auto lrow = [&](int64_t orb) { return lrow_of.empty() ? orb : lrow_of.at(orb); };
-  if (q) {
-    std::vector<int64_t> qr(static_cast<size_t>(nq));
-    for (int64_t k = 0; k < nq; ++k) qr[size_t(k)] = lrow(q[k]);
-    upload(d_q, qr, s);
+    if (q) {
+      std::vector<int64_t> qr(static_cast<size_t>(nq));
+      for (int64_t k = 0; k < nq; ++k) qr[size_t(k)] = L.lrow(q[k]);
+      upload(L.d_q, qr, s);
+    }
+    L.hs.assign(size_t(B), HostSlot{});
+    for (int i = B - 1; i >= 0; --i) L.free_slots.push_back(i);
+    L.hflags.assign(size_t(B), 0);
+    L.hres.assign(size_t(B), 0.0);
+    L.hbeta.assign(size_t(B), 0.0);
     GFCC_HIP(hipStreamSynchronize(s));
   }
 
-  const double tol = opts->tol;
-  const double rtol_lp = (prec == GFCC_FP64) ? 0.0
-                         : (opts->ir_inner_rtol > 0.0 ? opts->ir_inner_rtol : lp_cycle_rtol(prec));
-  std::vector<HostSlot> hs(B);
-  std::vector<int> free_slots;
-  for (int i = B - 1; i >= 0; --i) free_slots.push_back(i);
-  std::vector<int> active;
-  int64_t next = 0;
-  for (int64_t r = 0; r < nrhs; ++r) info[r] = gfcc_rhs_info{1, 0, 0, 0, 0.0};
-  bool ok_all = true;
-
-  auto refill = [&]() {
+  void refill(Lane& L) {
+    gfcc_ctx* c = L.c;
     std::vector<int> sl, pl, bl;
     std::vector<cplx> zl;
     std::vector<double> tl;
-    while (!free_slots.empty() && next < nrhs) {
-      const int br = p[next] >= c->o ? brow_of.at(p[next]) : -1;
-      const double bn = br < 0 ? 1.0 : bnorm_h[size_t(br)];
+    while (!L.free_slots.empty() && L.next < L.rows.size()) {
+      const int64_t r = L.rows[L.next];
+      const int br = p[r] >= c->o ? L.brow_of.at(p[r]) : -1;
+      const double bn = br < 0 ? 1.0 : L.bnorm_h[size_t(br)];
       if (!(bn > 0.0)) {  // b_p = 0 (no amplitude reaches this orbital): X = 0, G = 0
-        info[next] = gfcc_rhs_info{0, 0, 0, 0, 0.0};
-        GFCC_HIP(hipMemsetAsync(G + next * nq * 2, 0, size_t(nq) * 16, s));
-        if (Xout) GFCC_HIP(hipMemsetAsync(Xout + next * c->D * 2, 0, size_t(c->D) * 16, s));
-        ++next;
+        info[r] = gfcc_rhs_info{0, 0, 0, 0, 0.0};
+        GFCC_HIP(hipMemsetAsync(G + r * nq * 2, 0, size_t(nq) * 16, s));
+        if (Xout) GFCC_HIP(hipMemsetAsync(Xout + r * c->D * 2, 0, size_t(c->D) * 16, s));
+        ++L.next;
         continue;
       }
-      const int sidx = free_slots.back();
-      free_slots.pop_back();
-      hs[sidx] = HostSlot{};
-      hs[sidx].rhs = next;
-      hs[sidx].mlp = use_mlp ? 1 : 0;
-      hs[sidx].bn = bn;
-      hs[sidx].beta = bn;
-      hs[sidx].brow = br;
+      const int sidx = L.free_slots.back();
+      L.free_slots.pop_back();
+      HostSlot& h = L.hs[size_t(sidx)];
+      h = HostSlot{};
+      h.rhs = r;
+      h.mlp = use_mlp ? 1 : 0;
+      h.bn = bn;
+      h.beta = bn;
+      h.brow = br;
       sl.push_back(sidx);
-      pl.push_back(int(p[next]));
+      pl.push_back(int(p[r]));
       bl.push_back(br);
-      zl.push_back(cplx{omega[next], -eta});
+      zl.push_back(cplx{omega[r], -eta});
       tl.push_back(bn * std::max(0.5 * tol, rtol_lp));
-      active.push_back(sidx);
-      ++next;
+      L.active.push_back(sidx);
+      ++L.next;
     }
     if (sl.empty()) return;
-    upload(d_list, sl, s);
-    upload(d_plist, pl, s);
-    upload(d_brow, bl, s);
-    upload(d_zlist, zl, s);
-    upload(d_ctl, tl, s);
-    hipLaunchKernelGGL(init_slots_kernel, dim3(nch, unsigned(sl.size())), dim3(VT), 0, s, d, d_list.as<int>(),
-                       d_plist.as<int>(), d_brow.as<int>(), bB.as<double>(), bBn.as<double>(), d_zlist.as<cplx>(),
-                       d_ctl.as<double>(), int(sl.size()));
+    upload(L.d_list, sl, s);
+    upload(L.d_plist, pl, s);
+    upload(L.d_brow, bl, s);
+    upload(L.d_zlist, zl, s);
+    upload(L.d_ctl, tl, s);
+    hipLaunchKernelGGL(init_slots_kernel, dim3(L.nch, unsigned(sl.size())), dim3(VT), 0, s, L.d, L.d_list.as<int>(),
+                       L.d_plist.as<int>(), L.d_brow.as<int>(), L.bB.as<double>(), L.bBn.as<double>(),
+                       L.d_zlist.as<cplx>(), L.d_ctl.as<double>(), int(sl.size()));
     GFCC_HIP(hipGetLastError());
     GFCC_HIP(hipStreamSynchronize(s));  // host vectors above go out of scope
-  };
-
-  if (opts->tune_cache) {  // pick ring-GEMM tiles for the full window (inner precision and FP64)
-    tune_load(c, opts->tune_cache);
-    const Prec ip = prec == GFCC_FP64 ? Prec::F64 : (prec == GFCC_FP32_IR ? Prec::F32 : Prec::BF16);
-    tune_ring(c, ip, 2 * int64_t(B), s);
-    if (ip != Prec::F64) tune_ring(c, Prec::F64, 2 * int64_t(B), s);
-    tune_save(c, opts->tune_cache);
   }
-  refill();
-  std::vector<int> hflags(B);
-  std::vector<double> hres(B), hbeta(B);
-  std::vector<int> pending;  // slots whose cycle ended, waiting for a batched finish
-  std::map<std::pair<int, const void*>, hipGraphExec_t> graphs;
-  std::set<std::pair<int, const void*>> seen_sizes;
-  struct GraphGuard {
-    std::map<std::pair<int, const void*>, hipGraphExec_t>& g;
-    ~GraphGuard() {
-      for (auto& kv : g) (void)hipGraphExecDestroy(kv.second);
-    }
-  } graph_guard{graphs};
-  struct CaptureStream {
-    hipStream_t s = nullptr;
-    ~CaptureStream() {
-      if (s) (void)hipStreamDestroy(s);
-    }
-  } cap;
-  uint64_t graph_gen = alloc_generation();
-  while (!active.empty() || !pending.empty()) {
-    const int na = int(active.size());
-    if (na > 0) {
-      upload(d_act, active, s);
-      const int* act = d_act.as<int>();
-      // One inner iteration: precondition, sigma, CGS2, Givens.  With use_graph
-      // (and a plain preconditioner) it is captured once per window size --
-      // when that size repeats, so every buffer is already sized and the
-      // capture holds kernels only -- and replayed afterwards.
-      auto iteration = [&](hipStream_t s) {
-        if (!use_mlp) {
-          hipLaunchKernelGGL(precond_kernel, dim3(nch, na), dim3(VT), 0, s, d, act, c->ws_in.as<double>(),
-                             c->diag.as<double>(), mode, flex);
-          GFCC_HIP(hipGetLastError());
-        } else {
-          std::vector<int> sidx(na), pm(B);
-          std::vector<int64_t> zoff(na);
-          std::vector<double> om(na);
-          for (int i = 0; i < na; ++i) {
-            const int sl = active[i];
-            sidx[i] = sl * (m + 1) + hs[sl].k;
-            zoff[i] = ((int64_t(sl) * m + hs[sl].k) * 2) * Dp;
-            om[i] = omega[hs[sl].rhs];
-          }
-          for (int sl = 0; sl < B; ++sl) pm[sl] = hs[sl].mlp;
-          upload(d_msrc, sidx, s);
-          upload(d_mzoff, zoff, s);
-          upload(d_mom, om, s);
-          upload(d_pmode, pm, s);
-          MlpApplyArgs a;
-          a.src = d.V;
-          a.src_idx = d_msrc.as<int>();
-          a.slots = act;
-          a.mode = d_pmode.as<int>();
-          a.omega = d_mom.as<double>();
-          a.nrm = nullptr;
-          a.nrm_const = 1.0 / std::sqrt(double(c->D));  // Krylov vectors have unit norm
-          a.eta = eta;
-          a.dst = c->ws_in.as<double>();
-          a.zdst = d.Z;
-          a.zoff = d_mzoff.as<int64_t>();
-          prof_begin(c, "mlp", s);
-          mlp_apply(c, a, na, s);
-          prof_end(c, "mlp", s, 2.0 * double(na) * double(c->D) *
-                                    (double(MLP_F) * c->mlp->width + double(c->mlp->width) * c->mlp->width +
-                                     2.0 * c->mlp->width), 0.0);
-          GFCC_HIP(hipStreamSynchronize(s));  // host vectors above go out of scope
-        }
-        sigma_planes(c, 2 * na, c->ws_in.as<double>(), c->ws_out.as<double>(), prec, s);
-        prof_begin(c, "arnoldi", s);
-        hipLaunchKernelGGL(arnoldi_kernel, dim3(nch, na), dim3(VT), 0, s, d, act, c->ws_in.as<double>(),
-                           c->ws_out.as<double>(), 0);
-        hipLaunchKernelGGL(reduce_hg_kernel, dim3(na), dim3(MAXM + 1), 0, s, d, act);
-        hipLaunchKernelGGL(arnoldi_kernel, dim3(nch, na), dim3(VT), 0, s, d, act, c->ws_in.as<double>(),
-                           c->ws_out.as<double>(), 2);
-        GFCC_HIP(hipGetLastError());
-        hipLaunchKernelGGL(givens_kernel, dim3(na), dim3(64), 0, s, d, act, d_flags.as<int>(), d_res.as<double>(), 1);
-        hipLaunchKernelGGL(scale_kernel, dim3(nch, na), dim3(VT), 0, s, d, act);
-        GFCC_HIP(hipGetLastError());
-        prof_end(c, "arnoldi", s, 0.0, 0.0);
-      };
-      const bool graphable = opts->use_graph && !use_mlp && !c->prof_on;
-      if (graphable && graph_gen != alloc_generation()) {  // a buffer moved: drop stale graphs
-        for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
-        graphs.clear();
-        seen_sizes.clear();
-        graph_gen = alloc_generation();
-      }
-      if (!graphable) {
-        iteration(s);
-      } else {
-        const std::pair<int, const void*> gk{na, d_act.p};
-        auto it = graphs.find(gk);
-        if (it != graphs.end()) {
-          GFCC_HIP(hipGraphLaunch(it->second, s));
-        } else if (seen_sizes.count(gk)) {
-          // Record on a library stream: the caller's stream may be the legacy
-          // default stream, which cannot be captured.  Recording executes
-          // nothing; the graph is launched on the caller's stream.
-          if (!cap.s) GFCC_HIP(hipStreamCreateWithFlags(&cap.s, hipStreamNonBlocking));
-          hipGraph_t gr = nullptr;
-          const uint64_t gen0 = alloc_generation();
-          GFCC_HIP(hipStreamBeginCapture(cap.s, hipStreamCaptureModeThreadLocal));
-          try {
-            iteration(cap.s);
-          } catch (...) {
-            if (hipStreamEndCapture(cap.s, &gr) == hipSuccess && gr) (void)hipGraphDestroy(gr);
-            (void)hipGetLastError();
-            throw;
-          }
-          GFCC_HIP(hipStreamEndCapture(cap.s, &gr));
-          if (alloc_generation() != gen0) {
-            (void)hipGraphDestroy(gr);
-            throw Error{GFCC_E_STATE, "allocation during graph capture"};
-          }
-          hipGraphExec_t ex;
-          const hipError_t ie = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
-          (void)hipGraphDestroy(gr);
-          GFCC_HIP(ie);
-          graphs[gk] = ex;
-          GFCC_HIP(hipGraphLaunch(ex, s));
-        } else {
-          seen_sizes.insert(gk);
-          iteration(s);
-        }
-      }
-      GFCC_HIP(hipMemcpyAsync(hflags.data(), d_flags.p, na * sizeof(int), hipMemcpyDeviceToHost, s));
-      GFCC_HIP(hipMemcpyAsync(hres.data(), d_res.p, na * 8, hipMemcpyDeviceToHost, s));
-      GFCC_HIP(hipStreamSynchronize(s));
-      std::vector<int> still;
-      for (int i = 0; i < na; ++i) {
-        const int sl = active[i];
-        hs[sl].iters += 1;
-        hs[sl].k += 1;
-        if (hflags[i] != 0 || hs[sl].iters >= opts->max_iter)
-          pending.push_back(sl);
-        else
-          still.push_back(sl);
-      }
-      active.swap(still);
-    }
-    // finish cycles in groups: wait until half of the live slots are pending
-    // (slots advance in near lock-step, so this costs little latency) so the
-    // FP64 true-residual sigma runs on a wide batch
-    if (pending.empty()) continue;
-    if (!active.empty() && pending.size() * 2 < active.size() + pending.size()) continue;
-    std::vector<int> fin;
-    fin.swap(pending);
 
-    // 5. finish the cycles of `fin`
+  // preconditioner step of one inner iteration: u = M^-1 V[k] into ws_in
+  void pre(Lane& L, hipStream_t st) {
+    gfcc_ctx* c = L.c;
+    const int na = int(L.active.size());
+    const int* act = L.d_act.as<int>();
+    SolverDev& d = L.d;
+    if (!use_mlp) {
+      hipLaunchKernelGGL(precond_kernel, dim3(L.nch, na), dim3(VT), 0, st, d, act, c->ws_in.as<double>(),
+                         c->diag.as<double>(), mode, flex);
+      GFCC_HIP(hipGetLastError());
+      return;
+    }
+    std::vector<int> sidx(na), pm(L.B);
+    std::vector<int64_t> zoff(na);
+    std::vector<double> om(na);
+    for (int i = 0; i < na; ++i) {
+      const int sl = L.active[size_t(i)];
+      sidx[i] = sl * (m + 1) + L.hs[size_t(sl)].k;
+      zoff[i] = ((int64_t(sl) * m + L.hs[size_t(sl)].k) * 2) * L.Dp;
+      om[i] = omega[L.hs[size_t(sl)].rhs];
+    }
+    for (int sl = 0; sl < L.B; ++sl) pm[sl] = L.hs[size_t(sl)].mlp;
+    upload(L.d_msrc, sidx, st);
+    upload(L.d_mzoff, zoff, st);
+    upload(L.d_mom, om, st);
+    upload(L.d_pmode, pm, st);
+    MlpApplyArgs a;
+    a.src = d.V;
+    a.src_idx = L.d_msrc.as<int>();
+    a.slots = act;
+    a.mode = L.d_pmode.as<int>();
+    a.omega = L.d_mom.as<double>();
+    a.nrm = nullptr;
+    a.nrm_const = 1.0 / std::sqrt(double(c->D));  // Krylov vectors have unit norm
+    a.eta = eta;
+    a.dst = c->ws_in.as<double>();
+    a.zdst = d.Z;
+    a.zoff = L.d_mzoff.as<int64_t>();
+    prof_begin(c, "mlp", st);
+    mlp_apply(c, a, na, st);
+    prof_end(c, "mlp", st, 2.0 * double(na) * double(c->D) *
+                               (double(MLP_F) * c->mlp->width + double(c->mlp->width) * c->mlp->width +
+                                2.0 * c->mlp->width), 0.0);
+    GFCC_HIP(hipStreamSynchronize(st));  // host vectors above go out of scope
+  }
+
+  // CGS2 Arnoldi step and Givens update after the sigma
+  void post(Lane& L, hipStream_t st) {
+    gfcc_ctx* c = L.c;
+    const int na = int(L.active.size());
+    const int* act = L.d_act.as<int>();
+    SolverDev& d = L.d;
+    prof_begin(c, "arnoldi", st);
+    hipLaunchKernelGGL(arnoldi_kernel, dim3(L.nch, na), dim3(VT), 0, st, d, act, c->ws_in.as<double>(),
+                       c->ws_out.as<double>(), 0);
+    hipLaunchKernelGGL(reduce_hg_kernel, dim3(na), dim3(MAXM + 1), 0, st, d, act);
+    hipLaunchKernelGGL(arnoldi_kernel, dim3(L.nch, na), dim3(VT), 0, st, d, act, c->ws_in.as<double>(),
+                       c->ws_out.as<double>(), 2);
+    GFCC_HIP(hipGetLastError());
+    hipLaunchKernelGGL(givens_kernel, dim3(na), dim3(64), 0, st, d, act, L.d_flags.as<int>(), L.d_res.as<double>(),
+                       1);
+    hipLaunchKernelGGL(scale_kernel, dim3(L.nch, na), dim3(VT), 0, st, d, act);
+    GFCC_HIP(hipGetLastError());
+    prof_end(c, "arnoldi", st, 0.0, 0.0);
+  }
+
+  // one inner iteration of every lane with active slots
+  void iteration(std::vector<Lane*>& live, hipStream_t st) {
+    for (Lane* L : live) pre(*L, st);
+    if (live.size() == 1) {
+      Lane& L = *live[0];
+      sigma_planes(L.c, 2 * int64_t(L.active.size()), L.c->ws_in.as<double>(), L.c->ws_out.as<double>(), prec, st);
+    } else {
+      std::vector<SigmaJob> jobs;
+      for (Lane* L : live)
+        jobs.push_back(SigmaJob{L->c, 2 * int64_t(L->active.size()), L->c->ws_in.as<double>(),
+                                L->c->ws_out.as<double>()});
+      sigma_group(jobs.data(), int(jobs.size()), prec, st);
+    }
+    for (Lane* L : live) post(*L, st);
+  }
+
+  // finish the cycles of the pending slots of one lane (true residual, restart or G)
+  void finish(Lane& L) {
+    gfcc_ctx* c = L.c;
+    SolverDev& d = L.d;
+    const int64_t Dp = L.Dp;
+    std::vector<int> fin;
+    fin.swap(L.pending);
     const int nf = int(fin.size());
     std::vector<int> pf(nf), bf(nf);
     for (int i = 0; i < nf; ++i) {
-      pf[i] = int(p[hs[fin[i]].rhs]);
-      bf[i] = hs[fin[i]].brow;
+      pf[i] = int(p[L.hs[size_t(fin[i])].rhs]);
+      bf[i] = L.hs[size_t(fin[i])].brow;
     }
-    upload(d_list, fin, s);
-    upload(d_plist, pf, s);
-    upload(d_brow, bf, s);
-    const int* fl = d_list.as<int>();
+    upload(L.d_list, fin, s);
+    upload(L.d_plist, pf, s);
+    upload(L.d_brow, bf, s);
+    const int* fl = L.d_list.as<int>();
     hipLaunchKernelGGL(trisolve_kernel, dim3((nf + 63) / 64), dim3(64), 0, s, d, fl, nf);
-    hipLaunchKernelGGL(xupdate_kernel, dim3(nch, nf), dim3(VT), 0, s, d, fl, c->ws_in.as<double>(),
+    hipLaunchKernelGGL(xupdate_kernel, dim3(L.nch, nf), dim3(VT), 0, s, d, fl, c->ws_in.as<double>(),
                        c->diag.as<double>(), mode, flex);
     GFCC_HIP(hipGetLastError());
     sigma_planes(c, 2 * nf, c->ws_in.as<double>(), c->ws_out.as<double>(), GFCC_FP64, s);
-    hipLaunchKernelGGL(residual_kernel, dim3(nch, nf), dim3(VT), 0, s, d, fl, d_plist.as<int>(), d_brow.as<int>(),
-                       bB.as<double>(), c->ws_in.as<double>(), c->ws_out.as<double>());
-    hipLaunchKernelGGL(rnorm_kernel, dim3(nf), dim3(64), 0, s, d, nf, d_beta.as<double>());
+    hipLaunchKernelGGL(residual_kernel, dim3(L.nch, nf), dim3(VT), 0, s, d, fl, L.d_plist.as<int>(),
+                       L.d_brow.as<int>(), L.bB.as<double>(), c->ws_in.as<double>(), c->ws_out.as<double>());
+    hipLaunchKernelGGL(rnorm_kernel, dim3(nf), dim3(64), 0, s, d, nf, L.d_beta.as<double>());
     GFCC_HIP(hipGetLastError());
-    GFCC_HIP(hipMemcpyAsync(hbeta.data(), d_beta.p, nf * 8, hipMemcpyDeviceToHost, s));
+    GFCC_HIP(hipMemcpyAsync(L.hbeta.data(), L.d_beta.p, nf * 8, hipMemcpyDeviceToHost, s));
     GFCC_HIP(hipStreamSynchronize(s));
 
     std::vector<int> done, again, done_p;
@@ -995,8 +948,8 @@ void solve_batch(gfcc_ctx* c, int64_t nrhs, const int64_t* p, const double* omeg
     std::vector<double> again_beta, again_tol;
     for (int i = 0; i < nf; ++i) {
       const int sl = fin[i];
-      HostSlot& h = hs[sl];
-      const double beta = hbeta[i];  // |r|
+      HostSlot& h = L.hs[size_t(sl)];
+      const double beta = L.hbeta[size_t(i)];  // |r|
       const double rel = beta / h.bn;
       const bool finite = std::isfinite(beta);
       gfcc_rhs_info& inf = info[h.rhs];
@@ -1040,7 +993,7 @@ void solve_batch(gfcc_ctx* c, int64_t nrhs, const int64_t* p, const double* omeg
       if (inf.status != 0 && inf.status != 4) ok_all = false;
       done.push_back(sl);
       done_rows.push_back(h.rhs);
-      done_p.push_back(q ? 0 : int(lrow(p[h.rhs])));  // own left vector only when q == NULL
+      done_p.push_back(q ? 0 : int(L.lrow(p[h.rhs])));  // own left vector only when q == NULL
     }
     if (!again.empty()) {
       const int nr = int(again.size());
@@ -1048,34 +1001,236 @@ void solve_batch(gfcc_ctx* c, int64_t nrhs, const int64_t* p, const double* omeg
       upload(d_ag, again, s);
       upload(d_agb, again_beta, s);
       upload(d_agt, again_tol, s);
-      hipLaunchKernelGGL(restart_kernel, dim3(nch, nr), dim3(VT), 0, s, d, d_ag.as<int>(), d_agb.as<double>(),
+      hipLaunchKernelGGL(restart_kernel, dim3(L.nch, nr), dim3(VT), 0, s, d, d_ag.as<int>(), d_agb.as<double>(),
                          d_agt.as<double>(), nr);
       GFCC_HIP(hipGetLastError());
       GFCC_HIP(hipStreamSynchronize(s));
     }
     if (!done.empty()) {
       const int nd = int(done.size());
-      upload(d_list, done, s);
-      upload(d_rows, done_rows, s);
-      upload(d_plist, done_p, s);
-      hipLaunchKernelGGL(gdot_kernel, dim3(nd, unsigned(nq)), dim3(VT), 0, s, d, d_list.as<int>(),
-                         d_rows.as<int64_t>(), d_plist.as<int>(), q ? d_q.as<int64_t>() : nullptr, int(nq),
-                         lrows, G);
+      upload(L.d_list, done, s);
+      upload(L.d_rows, done_rows, s);
+      upload(L.d_plist, done_p, s);
+      hipLaunchKernelGGL(gdot_kernel, dim3(nd, unsigned(nq)), dim3(VT), 0, s, d, L.d_list.as<int>(),
+                         L.d_rows.as<int64_t>(), L.d_plist.as<int>(), q ? L.d_q.as<int64_t>() : nullptr, int(nq),
+                         L.lrows, G);
       if (Xout)
         hipLaunchKernelGGL(xout_kernel, dim3(std::min<int64_t>((c->D + 255) / 256, 1024), nd), dim3(256), 0, s, d,
-                           d_list.as<int>(), d_rows.as<int64_t>(), Xout, c->D, c->o, c->o_pad);
+                           L.d_list.as<int>(), L.d_rows.as<int64_t>(), Xout, c->D, c->o, c->o_pad);
       GFCC_HIP(hipGetLastError());
       GFCC_HIP(hipStreamSynchronize(s));
       for (int sl : done) {
-        hs[sl].rhs = -1;
-        free_slots.push_back(sl);
+        L.hs[size_t(sl)].rhs = -1;
+        L.free_slots.push_back(sl);
       }
     }
-    for (int sl : again) active.push_back(sl);
-    refill();
+    for (int sl : again) L.active.push_back(sl);
+    refill(L);
   }
-  GFCC_HIP(hipStreamSynchronize(s));
-  *all_converged = ok_all;
+
+  void run(std::vector<Lane>& lanes) {
+    for (auto& L : lanes) setup(L);
+    if (opts->tune_cache) {  // ring-GEMM tiles for each full window (inner precision and FP64)
+      const Prec ip = prec == GFCC_FP64 ? Prec::F64 : (prec == GFCC_FP32_IR ? Prec::F32 : Prec::BF16);
+      for (auto& L : lanes) {
+        tune_load(L.c, opts->tune_cache);
+        tune_ring(L.c, ip, 2 * int64_t(L.B), s);
+        if (ip != Prec::F64) tune_ring(L.c, Prec::F64, 2 * int64_t(L.B), s);
+        tune_save(L.c, opts->tune_cache);
+      }
+    }
+    for (auto& L : lanes) refill(L);
+    const bool any_prof = std::any_of(lanes.begin(), lanes.end(), [](const Lane& L) { return L.c->prof_on; });
+    const bool graphable = opts->use_graph && !use_mlp && !any_prof;
+    std::map<std::string, hipGraphExec_t> graphs;
+    std::set<std::string> seen;
+    struct GraphGuard {
+      std::map<std::string, hipGraphExec_t>& g;
+      ~GraphGuard() {
+        for (auto& kv : g) (void)hipGraphExecDestroy(kv.second);
+      }
+    } graph_guard{graphs};
+    struct CaptureStream {
+      hipStream_t s = nullptr;
+      ~CaptureStream() {
+        if (s) (void)hipStreamDestroy(s);
+      }
+    } cap;
+    uint64_t graph_gen = alloc_generation();
+    for (;;) {
+      std::vector<Lane*> live;
+      bool work = false;
+      for (auto& L : lanes) {
+        if (!L.active.empty()) live.push_back(&L);
+        work = work || !L.active.empty() || !L.pending.empty();
+      }
+      if (!work) break;
+      if (!live.empty()) {
+        std::string key;
+        for (Lane* L : live) {
+          upload(L->d_act, L->active, s);
+          key += std::to_string(L->active.size()) + "@" + std::to_string(reinterpret_cast<uintptr_t>(L->d_act.p)) +
+                 ";";
+        }
+        // One inner iteration of every live lane: precondition, sigma (the ring
+        // GEMMs of all lanes in grouped launches), CGS2, Givens.  With use_graph
+        // (and a plain preconditioner) it is captured once per window shape --
+        // when that shape repeats, so every buffer is already sized and the
+        // capture holds kernels only -- and replayed afterwards.
+        if (graphable && graph_gen != alloc_generation()) {  // a buffer moved: drop stale graphs
+          for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
+          graphs.clear();
+          seen.clear();
+          graph_gen = alloc_generation();
+        }
+        if (!graphable) {
+          iteration(live, s);
+        } else {
+          auto it = graphs.find(key);
+          if (it != graphs.end()) {
+            GFCC_HIP(hipGraphLaunch(it->second, s));
+          } else if (seen.count(key)) {
+            // Record on a library stream: the caller's stream may be the legacy
+            // default stream, which cannot be captured.  Recording executes
+            // nothing; the graph is launched on the caller's stream.
+            if (!cap.s) GFCC_HIP(hipStreamCreateWithFlags(&cap.s, hipStreamNonBlocking));
+            hipGraph_t gr = nullptr;
+            const uint64_t gen0 = alloc_generation();
+            GFCC_HIP(hipStreamBeginCapture(cap.s, hipStreamCaptureModeThreadLocal));
+            try {
+              iteration(live, cap.s);
+            } catch (...) {
+              if (hipStreamEndCapture(cap.s, &gr) == hipSuccess && gr) (void)hipGraphDestroy(gr);
+              (void)hipGetLastError();
+              throw;
+            }
+            GFCC_HIP(hipStreamEndCapture(cap.s, &gr));
+            if (alloc_generation() != gen0) {
+              (void)hipGraphDestroy(gr);
+              throw Error{GFCC_E_STATE, "allocation during graph capture"};
+            }
+            hipGraphExec_t ex;
+            const hipError_t ie = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(gr);
+            GFCC_HIP(ie);
+            graphs[key] = ex;
+            GFCC_HIP(hipGraphLaunch(ex, s));
+          } else {
+            seen.insert(key);
+            iteration(live, s);
+          }
+        }
+        for (Lane* L : live) {
+          const size_t na = L->active.size();
+          GFCC_HIP(hipMemcpyAsync(L->hflags.data(), L->d_flags.p, na * sizeof(int), hipMemcpyDeviceToHost, s));
+          GFCC_HIP(hipMemcpyAsync(L->hres.data(), L->d_res.p, na * 8, hipMemcpyDeviceToHost, s));
+        }
+        GFCC_HIP(hipStreamSynchronize(s));
+        for (Lane* L : live) {
+          std::vector<int> still;
+          for (size_t i = 0; i < L->active.size(); ++i) {
+            const int sl = L->active[i];
+            HostSlot& h = L->hs[size_t(sl)];
+            h.iters += 1;
+            h.k += 1;
+            if (L->hflags[i] != 0 || h.iters >= opts->max_iter)
+              L->pending.push_back(sl);
+            else
+              still.push_back(sl);
+          }
+          L->active.swap(still);
+        }
+      }
+      // finish cycles in groups: wait until half of a lane's live slots are
+      // pending (slots advance in near lock-step, so this costs little
+      // latency) so the FP64 true-residual sigma runs on a wide batch
+      for (auto& L : lanes) {
+        if (L.pending.empty()) continue;
+        if (!L.active.empty() && L.pending.size() * 2 < L.active.size() + L.pending.size()) continue;
+        finish(L);
+      }
+    }
+    GFCC_HIP(hipStreamSynchronize(s));
+  }
+};
+
+BatchRun make_run(const int64_t* p, const double* omega, double eta, int64_t nq, const int64_t* q,
+                  const gfcc_solve_opts* opts, double* G, double* Xout, gfcc_rhs_info* info, hipStream_t s,
+                  PairRec* rec) {
+  BatchRun R{p, omega, eta, nq, q, opts, G, Xout, info, rec, s};
+  R.m = std::min<int>(opts->restart, MAXM);
+  R.prec = opts->precision;
+  R.use_mlp = opts->precond == GFCC_PC_MLP;
+  R.mode = R.use_mlp ? GFCC_PC_JACOBI : opts->precond;  // Jacobi is also the MLP fallback
+  R.flex = R.use_mlp ? 1 : 0;
+  R.tol = opts->tol;
+  R.rtol_lp = (R.prec == GFCC_FP64) ? 0.0
+              : (opts->ir_inner_rtol > 0.0 ? opts->ir_inner_rtol : lp_cycle_rtol(R.prec));
+  return R;
+}
+
+double slot_bytes(const gfcc_ctx* c, int m, int flex) {
+  return double(m + 2 + (flex ? m : 0)) * 2.0 * double(c->Dp) * 8.0 + 6.0 * 2.0 * double(c->Dp) * 8.0;
+}
+
+}  // namespace
+
+void solve_batch(gfcc_ctx* c, int64_t nrhs, const int64_t* p, const double* omega, double eta, int64_t nq,
+                 const int64_t* q, const gfcc_solve_opts* opts, double* G, double* Xout, gfcc_rhs_info* info,
+                 hipStream_t s, bool* all_converged, PairRec* rec) {
+  const bool use_mlp = opts->precond == GFCC_PC_MLP;
+  GFCC_CHECK(!use_mlp || (c->mlp && c->mlp->trained), GFCC_E_STATE,
+             "GFCC_PC_MLP needs trained or loaded network weights");
+  for (int64_t r = 0; r < nrhs; ++r) info[r] = gfcc_rhs_info{1, 0, 0, 0, 0.0};
+  BatchRun R = make_run(p, omega, eta, nq, q, opts, G, Xout, info, s, rec);
+  int B = opts->batch > 0 ? opts->batch : 0;
+  if (B == 0) {
+    size_t freeb = 0, totalb = 0;
+    GFCC_HIP(hipMemGetInfo(&freeb, &totalb));
+    const int64_t fit = int64_t(0.5 * double(freeb) / slot_bytes(c, R.m, R.flex));
+    B = int(std::max<int64_t>(1, std::min<int64_t>({fit, 128, nrhs})));
+  }
+  std::vector<Lane> lanes(1);
+  lanes[0].c = c;
+  lanes[0].B = int(std::min<int64_t>(B, nrhs));
+  lanes[0].rows.resize(static_cast<size_t>(nrhs));
+  for (int64_t r = 0; r < nrhs; ++r) lanes[0].rows[size_t(r)] = r;
+  R.run(lanes);
+  *all_converged = R.ok_all;
+}
+
+// Right-hand sides of several systems in one persistent loop: one lane per
+// system, the window split in proportion to each system's right-hand sides.
+void solve_multi(int nsys, gfcc_ctx* const* ctxs, int64_t nrhs, const int32_t* sys, const int64_t* p,
+                 const double* omega, double eta, int64_t nq, const int64_t* q, const gfcc_solve_opts* opts,
+                 double* G, gfcc_rhs_info* info, hipStream_t s, bool* all_converged) {
+  for (int64_t r = 0; r < nrhs; ++r) info[r] = gfcc_rhs_info{1, 0, 0, 0, 0.0};
+  BatchRun R = make_run(p, omega, eta, nq, q, opts, G, nullptr, info, s, nullptr);
+  std::vector<Lane> lanes(static_cast<size_t>(nsys));
+  for (int k = 0; k < nsys; ++k) lanes[size_t(k)].c = ctxs[k];
+  for (int64_t r = 0; r < nrhs; ++r) lanes[size_t(sys[r])].rows.push_back(r);
+  std::vector<Lane> used;
+  for (auto& L : lanes)
+    if (!L.rows.empty()) used.push_back(std::move(L));
+  if (used.empty()) {
+    *all_converged = true;
+    return;
+  }
+  int64_t Btot = opts->batch > 0 ? opts->batch : std::min<int64_t>(nrhs, 128 * int64_t(used.size()));
+  size_t freeb = 0, totalb = 0;
+  GFCC_HIP(hipMemGetInfo(&freeb, &totalb));
+  for (;;) {  // window share of each system ~ its right-hand sides, within half of free memory
+    double bytes = 0.0;
+    for (auto& L : used) {
+      L.B = int(std::max<int64_t>(1, std::min<int64_t>(int64_t(L.rows.size()),
+                                                        int64_t(double(Btot) * double(L.rows.size()) / double(nrhs)))));
+      bytes += double(L.B) * slot_bytes(L.c, R.m, R.flex);
+    }
+    if (bytes <= 0.5 * double(freeb) || Btot <= int64_t(used.size())) break;
+    Btot = std::max<int64_t>(int64_t(used.size()), Btot * 3 / 4);
+  }
+  R.run(used);
+  *all_converged = R.ok_all;
 }
 
 }  // namespace gfcc

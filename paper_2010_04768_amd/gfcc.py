@@ -28,7 +28,7 @@ SYMBOLS = ["gfcc_build_intermediates", "gfcc_dims", "gfcc_export", "gfcc_sigma",
            "gfcc_last_error", "gfcc_mlp_train", "gfcc_mlp_set_weights", "gfcc_mlp_get_weights",
            "gfcc_mlp_forward", "gfcc_mlp_loss_grad", "gfcc_mlp_features", "gfcc_mlp_apply",
            "gfcc_mor_reset", "gfcc_mor_extend", "gfcc_mor_model", "gfcc_mor_export", "gfcc_mor_greens",
-           "gfcc_solve_shifts", "gfcc_spectral"]
+           "gfcc_solve_shifts", "gfcc_spectral", "gfcc_solve_multi"]
 
 
 class GfccSystem(ctypes.Structure):
@@ -126,6 +126,9 @@ def load():
     L.gfcc_solve_shifts.argtypes = [vp, i64, vp, i64, vp, dbl, i64, vp, ctypes.POINTER(ShiftOpts), vp, vp,
                                     ctypes.POINTER(RhsInfo), vp]
     L.gfcc_solve_shifts.restype = ctypes.c_int
+    L.gfcc_solve_multi.argtypes = [ctypes.c_int32, vp, i64, vp, vp, vp, dbl, i64, vp, ctypes.POINTER(SolveOpts),
+                                   vp, ctypes.POINTER(RhsInfo), vp]
+    L.gfcc_solve_multi.restype = ctypes.c_int
     L.gfcc_spectral.argtypes = [i64, i64, vp, i64, dbl, vp, vp]
     L.gfcc_spectral.restype = ctypes.c_int
     L.gfcc_mor_reset.argtypes = [vp]
@@ -165,6 +168,37 @@ def spectral(G, eta):
     _check(load().gfcc_spectral(G.shape[0], G.shape[1], _ptr(G), G.shape[1], float(eta), _ptr(A), _stream()),
            "gfcc_spectral")
     return A
+
+
+def solve_multi(ctxs, sys, p, omega, eta, q=None, tol=1e-8, restart=30, max_iter=2000, batch=0,
+                precond="jacobi", precision="fp64", use_graph=False, ir_inner_rtol=0.0, tune_cache=None):
+    """Right-hand sides of several systems (contexts) in one persistent solve: right-hand side r
+    belongs to ctxs[sys[r]].  Returns (G [nrhs, nq] complex128 device tensor, info list)."""
+    import torch
+    s_h = np.ascontiguousarray(np.asarray(sys, dtype=np.int32))
+    p_h = np.ascontiguousarray(np.asarray(p, dtype=np.int64))
+    w_h = np.ascontiguousarray(np.asarray(omega, dtype=np.float64))
+    assert s_h.shape == p_h.shape == w_h.shape
+    n = p_h.size
+    if q is None:
+        q_h, nq = None, 1
+    else:
+        q_h = np.ascontiguousarray(np.asarray(q, dtype=np.int64))
+        nq = q_h.size
+    G = torch.zeros((n, nq), dtype=torch.complex128, device=ctxs[0].device)
+    info = (RhsInfo * max(n, 1))()
+    handles = (ctypes.c_void_p * len(ctxs))(*[c._h.value for c in ctxs])
+    opts = SolveOpts(ctypes.sizeof(SolveOpts), tol, restart, max_iter, batch, PRECONDS[precond],
+                     PRECISIONS[precision], int(use_graph), tune_cache.encode() if tune_cache else None,
+                     ir_inner_rtol)
+    st = load().gfcc_solve_multi(len(ctxs), handles, n, s_h.ctypes.data_as(ctypes.c_void_p),
+                                 p_h.ctypes.data_as(ctypes.c_void_p), w_h.ctypes.data_as(ctypes.c_void_p), eta, nq,
+                                 q_h.ctypes.data_as(ctypes.c_void_p) if q_h is not None else None,
+                                 ctypes.byref(opts), _ptr(G), info, _stream())
+    _check(st, "gfcc_solve_multi")
+    infos = [dict(status=info[r].status, iters=info[r].iters, restarts=info[r].restarts,
+                  true_rel_resid=info[r].true_rel_resid) for r in range(n)]
+    return G, infos
 
 
 class Context:
