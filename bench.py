@@ -61,6 +61,12 @@ def parse():
     ap.add_argument("--mlp-study", action="store_true",
                     help="instead of the benchmark: learned preconditioner vs Jacobi on the 90/420/1800 system "
                          "(sampled right-hand sides), one JSON line")
+    ap.add_argument("--multi-study", action="store_true",
+                    help="instead of the benchmark: the three-system mixed-precision workload (20/100/400, "
+                         "40/180/720, 60/300/1200; sampled p x omega), one persistent solve vs one solve per "
+                         "system, BF16-IR, per-system G error vs FP64; one JSON line")
+    ap.add_argument("--multi-p", type=int, default=8, help="orbitals per system in the multi-system study")
+    ap.add_argument("--multi-omega", type=int, default=16, help="frequencies per system in the multi-system study")
     ap.add_argument("--mlp-steps", type=int, default=400)
     ap.add_argument("--mlp-max-iter", type=int, default=600)
     ap.add_argument("--mlp-tol", type=float, default=1e-8,
@@ -82,6 +88,9 @@ def main():
         sys.exit(2)
     if args.mlp_study:
         mlp_study(args)
+        return
+    if args.multi_study:
+        multi_study(args)
         return
     import torch
 
@@ -308,6 +317,85 @@ def mor_pass(args, gfcc, eps_d, L_d, t1_d, t2_d, plist, omegas, wl, form, Gref):
             "omega_solved": rep["n_solved"], "per_level": rep["per_level"], "converged": rep["converged"],
             "t_solve": rep["t_solve"], "t_basis": rep["t_basis"], "t_project": rep["t_project"],
             "t_model": rep["t_model"]}
+
+
+def multi_study(args):
+    """Three systems of uneven size and convergence (the mixed-precision workload, eta 0.01, omega on
+    [-1.2, -0.3]): --multi-p highest occupied p x --multi-omega frequencies per system, BF16 sigma +
+    FP64 refinement to tol 1e-8, Jacobi, restart 30, graph replay.  Timed: one gfcc_solve_multi over all
+    right-hand sides (window 128 in all) against one gfcc_solve_batch per system in turn (window 42 each);
+    both after one untimed warm-up that fills the tile cache.  G of every system is checked against its
+    FP64 solve (tol 1e-11, untimed)."""
+    import torch
+
+    from paper_2010_04768_amd import gfcc
+    from synth import make_workload
+
+    torch.cuda.set_device(0)
+    wl = make_workload("mixed-3sys", n_omega=128)
+    ctxs = [gfcc.Context.from_system(s) for s in wl.systems]
+    torch.cuda.synchronize()
+    S, P, W = [], [], []
+    for k, s in enumerate(wl.systems):
+        ps = list(range(s.n_occ - args.multi_p, s.n_occ))
+        ws = wl.omegas[k][:: max(1, len(wl.omegas[k]) // args.multi_omega)][: args.multi_omega]
+        for p in ps:
+            for w in ws:
+                S.append(k)
+                P.append(p)
+                W.append(w)
+    S, P, W = np.array(S), np.array(P), np.array(W)
+    log(f"multi-system study: {len(S)} right-hand sides, per system {[int((S == k).sum()) for k in range(3)]}, "
+        f"dims {[s.dim for s in wl.systems]}")
+    kw = dict(tol=wl.tol, precision="bf16", batch=128, use_graph=True, tune_cache=args.tune_cache or None)
+
+    def one_launch():
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        G, info = gfcc.solve_multi(ctxs, S, P, W, wl.eta, **kw)
+        torch.cuda.synchronize()
+        return G.cpu().numpy()[:, 0], info, time.perf_counter() - t0
+
+    def per_system():
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        G = np.zeros(len(S), dtype=complex)
+        info = [None] * len(S)
+        for k, c in enumerate(ctxs):
+            idx = np.nonzero(S == k)[0]
+            Gk, ik, _ = c.solve(P[idx], W[idx], wl.eta, **dict(kw, batch=128 // len(ctxs)))
+            G[idx] = Gk.cpu().numpy()[:, 0]
+            for j, r in enumerate(idx):
+                info[r] = ik[j]
+        torch.cuda.synchronize()
+        return G, info, time.perf_counter() - t0
+
+    one_launch()
+    per_system()
+    Gm, im_, tm = one_launch()
+    Gs, is_, ts = per_system()
+    log(f"one launch {tm:.2f}s, per system {ts:.2f}s")
+    out = {"metric": "multi-system solve (BF16-IR), one persistent launch vs one solve per system",
+           "workload": "mixed-3sys (20/100/400, 40/180/720, 60/300/1200), eta 0.01, sampled "
+                       f"{args.multi_p} p x {args.multi_omega} omega per system", "n_rhs": int(len(S)),
+           "one_launch_s": tm, "per_system_s": ts, "speedup": ts / tm, "systems": []}
+    for k, c in enumerate(ctxs):
+        idx = np.nonzero(S == k)[0]
+        Gr, ir, _ = c.solve(P[idx], W[idx], wl.eta, tol=1e-11, precision="fp64", max_iter=3000)
+        Gr = Gr.cpu().numpy()[:, 0]
+        e_m = float(np.max(np.abs(Gm[idx] - Gr) / np.abs(Gr)))
+        e_s = float(np.max(np.abs(Gs[idx] - Gr) / np.abs(Gr)))
+        s = wl.systems[k]
+        out["systems"].append({"o": s.n_occ, "v": s.n_vir, "Q": s.n_chol, "n_rhs": int(len(idx)),
+                               "g_max_rel_err_one_launch": e_m, "g_max_rel_err_per_system": e_s,
+                               "iters_mean": float(np.mean([im_[r]["iters"] for r in idx])),
+                               "converged": int(sum(im_[r]["status"] == 0 for r in idx))})
+        log(f"system {k}: {out['systems'][-1]}")
+    out["rhs_per_s_one_launch"] = len(S) / tm
+    out["rhs_per_s_per_system"] = len(S) / ts
+    print(json.dumps(out), flush=True)
+    for c in ctxs:
+        c.close()
 
 
 def mlp_study(args):
