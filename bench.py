@@ -29,10 +29,10 @@ PEAK = {"fp64": 78.6e12, "fp32": 157.3e12, "bf16": 2.5e15}
 # HBM bytes per 128-slot ring-GEMM launch from rocprofv3 FETCH_SIZE / WRITE_SIZE passes
 # (profiles/ring_gemm_o40v200_bf16ir.md; copy-kernel scale 2.0 for FETCH_SIZE, 1.0 for
 # WRITE_SIZE).  Valid only for the GEMM source they were taken on.
-TRAFFIC = {"gemm_src_sha256_16": "4eb52ff1288cbbbf",
-           "bf16": {"fetch_GB": 2.956, "write_GB": 0.656, "tile": "db32_256x256w16", "key": "2:10240:8000:8000",
+TRAFFIC = {"gemm_src_sha256_16": "0a24a5c2e6a5af6f",
+           "bf16": {"fetch_GB": 2.995, "write_GB": 0.656, "tile": "db32_256x256w16", "key": "2:10240:8000:8000",
                     "launch": "128 slots, M=10240 N=K=8000"},
-           "fp64": {"fetch_GB": 12.04, "write_GB": 0.745, "tile": "db256x128", "key": "0:10240:8000:8000",
+           "fp64": {"fetch_GB": 12.02, "write_GB": 0.746, "tile": "db256x128", "key": "0:10240:8000:8000",
                     "launch": "128 slots, M=10240 N=K=8000"}}
 DTYPE = {"fp64": "f64", "fp32": "f32+f64", "bf16": "bf16+f64"}
 
