@@ -157,6 +157,15 @@ static void to_matrix(const TView& src, const std::string& sl, const std::string
   permute(src, perm, 1.0, out, 0.0, s);
 }
 
+// Large products go to the double-buffered 256x128 tile (the one the tuner picks for the
+// FP64 ring GEMMs); the rest to the default tile or split-K.
+static void contract_gemm(const GemmArgs& g, Scratch& scr, hipStream_t s) {
+  if (g.M >= 2048 && g.N >= 2048 && g.batch == 1 && !g.b_ncontig)
+    gemm(Prec::F64, g, TILE_DB_256x128, s);
+  else
+    gemm_auto(Prec::F64, g, scr, 3, s);
+}
+
 void ein(const char* spec, double alpha, const TView& A, const TView& B, double beta,
          const TView& C, Scratch& scr, hipStream_t s) {
   std::string sp(spec);
@@ -232,7 +241,7 @@ void ein(const char* spec, double alpha, const TView& A, const TView& B, double 
     g.cn = lin(1);
     g.alpha = alpha;
     g.beta = beta;
-    gemm_auto(Prec::F64, g, scr, 3, s);
+    contract_gemm(g, scr, s);
     return;
   }
   double* tmp = scr.get(2, M * N, s);
@@ -241,7 +250,7 @@ void ein(const char* spec, double alpha, const TView& A, const TView& B, double 
   g.cn = lin(1);
   g.alpha = 1.0;
   g.beta = 0.0;
-  gemm_auto(Prec::F64, g, scr, 3, s);
+  contract_gemm(g, scr, s);
   // permute-accumulate tmp[ml nl] into C[lc]
   std::string tl = ml + nl;
   TView tv;
