@@ -123,6 +123,12 @@ typedef struct {
   const char* tune_cache;   /* host path of the tile autotuner JSON cache; NULL = no tuning */
   double ir_inner_rtol;     /* GMRES-IR: inner cycle stops at this fraction of the cycle's starting
                                residual; 0 = default for the precision (ignored for FP64) */
+  const char* checkpoint;   /* host path of a resume file, or NULL: every finished right-hand side
+                               appends (index, p, omega, eta, G row, info) to it, and a later call
+                               with the same request restores the rows it holds instead of solving
+                               them (gfcc_solve_batch and gfcc_solve_multi; ignored by the solves
+                               that model-order reduction and the multi-shift fallback run).
+                               Restored rows get no X (zeros when X is requested). */
 } gfcc_solve_opts;
 
 /* Per right-hand side result (host memory). status: 0 converged, 1 max_iter,

@@ -439,7 +439,9 @@ void mor_greens(gfcc_ctx* c, int64_t np, const int64_t* p, int64_t nw, const dou
     std::vector<gfcc_rhs_info> info(static_cast<size_t>(nr));
     bool conv = true;
     const double t0 = now_s();
-    solve_batch(c, nr, P.data(), W.data(), eta, 1, nullptr, &o->solve, Gs.as<double>(), Xs.as<double>(), info.data(),
+    gfcc_solve_opts so = o->solve;
+    so.checkpoint = nullptr;  // the level loop's own solves are not resumable rows of a request
+    solve_batch(c, nr, P.data(), W.data(), eta, 1, nullptr, &so, Gs.as<double>(), Xs.as<double>(), info.data(),
                 s, &conv, nullptr);
     std::vector<double> g(static_cast<size_t>(2 * nr));
     GFCC_HIP(hipMemcpyAsync(g.data(), Gs.p, size_t(nr) * 16, hipMemcpyDeviceToHost, s));

@@ -749,7 +749,9 @@ void solve_shifts(gfcc_ctx* c, int64_t np, const int64_t* p, int64_t nw, const d
     if (Xout) Xf.ensure(size_t(nf * D) * 16, s);
     std::vector<gfcc_rhs_info> inf(static_cast<size_t>(nf));
     bool conv = true;
-    solve_batch(c, nf, Pf.data(), Wf.data(), eta, nql, q, &o->fallback, Gf.as<double>(),
+    gfcc_solve_opts fo = o->fallback;
+    fo.checkpoint = nullptr;
+    solve_batch(c, nf, Pf.data(), Wf.data(), eta, nql, q, &fo, Gf.as<double>(),
                 Xout ? Xf.as<double>() : nullptr, inf.data(), s, &conv, nullptr);
     for (int64_t r = 0; r < nf; ++r) {
       const int64_t row = failed[size_t(r)].first * nw + failed[size_t(r)].second;

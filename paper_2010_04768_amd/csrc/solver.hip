@@ -25,8 +25,11 @@
 // a tolerance relative to the cycle's starting residual that the reduced
 // precision operator can deliver; the restart's FP64 true residual drives the
 // refinement.
+#include <unistd.h>
+
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <deque>
 #include <map>
 #include <set>
@@ -672,6 +675,87 @@ struct BatchRun {
   double tol = 0.0, rtol_lp = 0.0;
   bool ok_all = true;
 
+  // Resume file: one record per finished right-hand side, appended as it finishes.
+  struct CkptRec {
+    int64_t row, p, nq, qhash;
+    double omega, eta;
+    gfcc_rhs_info info;
+  };  // followed by 2 nq doubles (the G row)
+  FILE* ck = nullptr;
+  std::set<int64_t> restored;
+  int64_t qhash = 0;
+
+  // restore the rows a previous call recorded for this request, then open the file for appending
+  void ckpt_open(int64_t nrhs) {
+    if (!opts->checkpoint) return;
+    uint64_t h = 1469598103934665603ull;  // FNV-1a over (nq, q)
+    auto mix = [&](int64_t x) {
+      for (int b = 0; b < 8; ++b) {
+        h ^= uint64_t(x >> (8 * b)) & 0xffu;
+        h *= 1099511628211ull;
+      }
+    };
+    mix(nq);
+    for (int64_t k = 0; q && k < nq; ++k) mix(q[k]);
+    if (!q) mix(-1);
+    qhash = int64_t(h);
+    std::vector<double> gbuf;
+    std::vector<int64_t> rows;
+    long good = 0, total = 0;  // bytes of whole records / of the file
+    if (FILE* f = std::fopen(opts->checkpoint, "rb")) {
+      CkptRec r;
+      std::vector<double> g;
+      while (std::fread(&r, sizeof(r), 1, f) == 1) {
+        if (r.nq < 1 || r.nq > (int64_t(1) << 20)) break;  // not a record of this format
+        g.resize(size_t(2 * r.nq));
+        if (std::fread(g.data(), sizeof(double), g.size(), f) != g.size()) break;
+        good = std::ftell(f);
+        if (r.nq != nq) continue;
+        const bool same = r.row >= 0 && r.row < nrhs && r.p == p[r.row] && r.omega == omega[r.row] &&
+                          r.eta == eta && r.qhash == qhash;
+        if (!same || restored.count(r.row)) continue;
+        restored.insert(r.row);
+        info[r.row] = r.info;
+        if (r.info.status != 0 && r.info.status != 4) ok_all = false;
+        rows.push_back(r.row);
+        gbuf.insert(gbuf.end(), g.begin(), g.end());
+      }
+      std::fseek(f, 0, SEEK_END);
+      total = std::ftell(f);
+      std::fclose(f);
+    }
+    // a record torn by an interrupted write is cut off before appending
+    if (total > good) GFCC_CHECK(::truncate(opts->checkpoint, good) == 0, GFCC_E_ARG, "cannot trim checkpoint file");
+    for (size_t k = 0; k < rows.size(); ++k)
+      GFCC_HIP(hipMemcpyAsync(G + rows[k] * nq * 2, gbuf.data() + k * 2 * nq, size_t(nq) * 16,
+                              hipMemcpyHostToDevice, s));
+    GFCC_HIP(hipStreamSynchronize(s));  // gbuf goes out of scope
+    ck = std::fopen(opts->checkpoint, "ab");
+    GFCC_CHECK(ck, GFCC_E_ARG, std::string("cannot open checkpoint file ") + opts->checkpoint);
+  }
+
+  // append the finished rows (G already on the device)
+  void ckpt_write(const std::vector<int64_t>& rows) {
+    if (!ck || rows.empty()) return;
+    std::vector<double> g(rows.size() * size_t(2 * nq));
+    for (size_t k = 0; k < rows.size(); ++k)
+      GFCC_HIP(hipMemcpyAsync(g.data() + k * 2 * nq, G + rows[k] * nq * 2, size_t(nq) * 16,
+                              hipMemcpyDeviceToHost, s));
+    GFCC_HIP(hipStreamSynchronize(s));
+    for (size_t k = 0; k < rows.size(); ++k) {
+      const int64_t r = rows[k];
+      CkptRec rec{r, p[r], nq, qhash, omega[r], eta, info[r]};
+      std::fwrite(&rec, sizeof(rec), 1, ck);
+      std::fwrite(g.data() + k * 2 * nq, sizeof(double), size_t(2 * nq), ck);
+    }
+    std::fflush(ck);
+  }
+
+  void ckpt_close() {
+    if (ck) std::fclose(ck);
+    ck = nullptr;
+  }
+
   // device buffers, right-hand-side rows and left rows of one lane
   void setup(Lane& L) {
     gfcc_ctx* c = L.c;
@@ -791,14 +875,20 @@ struct BatchRun {
     std::vector<int> sl, pl, bl;
     std::vector<cplx> zl;
     std::vector<double> tl;
+    std::vector<int64_t> zero_rows;
     while (!L.free_slots.empty() && L.next < L.rows.size()) {
       const int64_t r = L.rows[L.next];
+      if (restored.count(r)) {  // finished in an earlier call (resume file)
+        ++L.next;
+        continue;
+      }
       const int br = p[r] >= c->o ? L.brow_of.at(p[r]) : -1;
       const double bn = br < 0 ? 1.0 : L.bnorm_h[size_t(br)];
       if (!(bn > 0.0)) {  // b_p = 0 (no amplitude reaches this orbital): X = 0, G = 0
         info[r] = gfcc_rhs_info{0, 0, 0, 0, 0.0};
         GFCC_HIP(hipMemsetAsync(G + r * nq * 2, 0, size_t(nq) * 16, s));
         if (Xout) GFCC_HIP(hipMemsetAsync(Xout + r * c->D * 2, 0, size_t(c->D) * 16, s));
+        zero_rows.push_back(r);
         ++L.next;
         continue;
       }
@@ -819,6 +909,7 @@ struct BatchRun {
       L.active.push_back(sidx);
       ++L.next;
     }
+    ckpt_write(zero_rows);
     if (sl.empty()) return;
     upload(L.d_list, sl, s);
     upload(L.d_plist, pl, s);
@@ -1019,6 +1110,7 @@ struct BatchRun {
                            L.d_list.as<int>(), L.d_rows.as<int64_t>(), Xout, c->D, c->o, c->o_pad);
       GFCC_HIP(hipGetLastError());
       GFCC_HIP(hipStreamSynchronize(s));
+      ckpt_write(done_rows);
       for (int sl : done) {
         L.hs[size_t(sl)].rhs = -1;
         L.free_slots.push_back(sl);
@@ -1028,7 +1120,12 @@ struct BatchRun {
     refill(L);
   }
 
-  void run(std::vector<Lane>& lanes) {
+  void run(std::vector<Lane>& lanes, int64_t nrhs) {
+    struct Closer {
+      BatchRun* r;
+      ~Closer() { r->ckpt_close(); }
+    } closer{this};
+    ckpt_open(nrhs);
     for (auto& L : lanes) setup(L);
     if (opts->tune_cache) {  // ring-GEMM tiles for each full window (inner precision and FP64)
       const Prec ip = prec == GFCC_FP64 ? Prec::F64 : (prec == GFCC_FP32_IR ? Prec::F32 : Prec::BF16);
@@ -1195,7 +1292,7 @@ void solve_batch(gfcc_ctx* c, int64_t nrhs, const int64_t* p, const double* omeg
   lanes[0].B = int(std::min<int64_t>(B, nrhs));
   lanes[0].rows.resize(static_cast<size_t>(nrhs));
   for (int64_t r = 0; r < nrhs; ++r) lanes[0].rows[size_t(r)] = r;
-  R.run(lanes);
+  R.run(lanes, nrhs);
   *all_converged = R.ok_all;
 }
 
@@ -1229,7 +1326,7 @@ void solve_multi(int nsys, gfcc_ctx* const* ctxs, int64_t nrhs, const int32_t* s
     if (bytes <= 0.5 * double(freeb) || Btot <= int64_t(used.size())) break;
     Btot = std::max<int64_t>(int64_t(used.size()), Btot * 3 / 4);
   }
-  R.run(used);
+  R.run(used, nrhs);
   *all_converged = R.ok_all;
 }
 

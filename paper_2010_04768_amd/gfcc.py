@@ -41,7 +41,7 @@ class SolveOpts(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_size_t), ("tol", ctypes.c_double), ("restart", ctypes.c_int32),
                 ("max_iter", ctypes.c_int32), ("batch", ctypes.c_int32), ("precond", ctypes.c_int),
                 ("precision", ctypes.c_int), ("use_graph", ctypes.c_int32), ("tune_cache", ctypes.c_char_p),
-                ("ir_inner_rtol", ctypes.c_double)]
+                ("ir_inner_rtol", ctypes.c_double), ("checkpoint", ctypes.c_char_p)]
 
 
 class RhsInfo(ctypes.Structure):
@@ -171,9 +171,11 @@ def spectral(G, eta):
 
 
 def solve_multi(ctxs, sys, p, omega, eta, q=None, tol=1e-8, restart=30, max_iter=2000, batch=0,
-                precond="jacobi", precision="fp64", use_graph=False, ir_inner_rtol=0.0, tune_cache=None):
+                precond="jacobi", precision="fp64", use_graph=False, ir_inner_rtol=0.0, tune_cache=None,
+                checkpoint=None):
     """Right-hand sides of several systems (contexts) in one persistent solve: right-hand side r
-    belongs to ctxs[sys[r]].  Returns (G [nrhs, nq] complex128 device tensor, info list)."""
+    belongs to ctxs[sys[r]].  Returns (G [nrhs, nq] complex128 device tensor, info list).
+    `checkpoint`: resume file (finished rows are appended; rows it already holds are restored)."""
     import torch
     s_h = np.ascontiguousarray(np.asarray(sys, dtype=np.int32))
     p_h = np.ascontiguousarray(np.asarray(p, dtype=np.int64))
@@ -190,7 +192,7 @@ def solve_multi(ctxs, sys, p, omega, eta, q=None, tol=1e-8, restart=30, max_iter
     handles = (ctypes.c_void_p * len(ctxs))(*[c._h.value for c in ctxs])
     opts = SolveOpts(ctypes.sizeof(SolveOpts), tol, restart, max_iter, batch, PRECONDS[precond],
                      PRECISIONS[precision], int(use_graph), tune_cache.encode() if tune_cache else None,
-                     ir_inner_rtol)
+                     ir_inner_rtol, checkpoint.encode() if checkpoint else None)
     st = load().gfcc_solve_multi(len(ctxs), handles, n, s_h.ctypes.data_as(ctypes.c_void_p),
                                  p_h.ctypes.data_as(ctypes.c_void_p), w_h.ctypes.data_as(ctypes.c_void_p), eta, nq,
                                  q_h.ctypes.data_as(ctypes.c_void_p) if q_h is not None else None,
@@ -273,7 +275,7 @@ class Context:
     # ---------------------------------------------------------------- solve
     def solve(self, p: Sequence[int], omega: Sequence[float], eta: float, q: Optional[Sequence[int]] = None,
               tol=1e-8, restart=30, max_iter=2000, batch=0, precond="jacobi", precision="fp64",
-              use_graph=False, want_x=False, ir_inner_rtol=0.0, tune_cache=None):
+              use_graph=False, want_x=False, ir_inner_rtol=0.0, tune_cache=None, checkpoint=None):
         """Returns (G [nrhs, nq] complex128 device tensor, info list of dicts, X or None)."""
         import torch
         p_h = np.ascontiguousarray(np.asarray(p, dtype=np.int64))
@@ -290,7 +292,8 @@ class Context:
         info = (RhsInfo * max(n, 1))()
         opts = SolveOpts(ctypes.sizeof(SolveOpts), tol, restart, max_iter, batch, PRECONDS[precond],
                          PRECISIONS[precision], int(use_graph),
-                         tune_cache.encode() if tune_cache else None, ir_inner_rtol)
+                         tune_cache.encode() if tune_cache else None, ir_inner_rtol,
+                         checkpoint.encode() if checkpoint else None)
         st = self._lib.gfcc_solve_batch(
             self._h, n, p_h.ctypes.data_as(ctypes.c_void_p), w_h.ctypes.data_as(ctypes.c_void_p), eta, nq,
             q_h.ctypes.data_as(ctypes.c_void_p) if q_h is not None else None, ctypes.byref(opts), _ptr(G),

@@ -52,3 +52,57 @@ def test_autotuner_cache_and_results(ctx, tmp_path):
     assert ent and all(0 <= e["cfg"] < 13 for e in ent)
     rel = (torch.abs(G1 - G0) / torch.abs(G0)).max().item()
     assert rel < 1e-10
+
+
+def test_repeat_runs_are_bitwise_identical(ctx):
+    """Determinism: the same request twice gives the same bits (restarted solver in FP64 and
+    BF16-IR, multi-shift solver, several systems in one solve with and without graph replay)."""
+    s, c = ctx
+    rng = np.random.default_rng(5)
+    p = rng.integers(0, s.n_occ, size=12)
+    w = rng.uniform(-1.2, -0.3, size=12)
+    for prec in ("fp64", "bf16"):
+        G1, _, _ = c.solve(p, w, 0.01, tol=1e-10, batch=5, precision=prec)
+        G2, _, _ = c.solve(p, w, 0.01, tol=1e-10, batch=5, precision=prec)
+        assert torch.equal(G1, G2), prec
+    S1, _, _ = c.solve_shifts([0, 3, 9], w[:6], 0.01, tol=1e-10)
+    S2, _, _ = c.solve_shifts([0, 3, 9], w[:6], 0.01, tol=1e-10)
+    assert torch.equal(S1, S2)
+    s2 = make_system(6, 20, 30, 778, sigma_L=0.1, sigma_t1=0.01)
+    c2 = gfcc.Context.from_system(s2)
+    try:
+        sys_ = np.array([0, 1] * 6)
+        pp = np.array([int(x) % 6 for x in p])
+        M1, _ = gfcc.solve_multi([c, c2], sys_, pp, w, 0.01, tol=1e-10, batch=6, precision="bf16")
+        M2, _ = gfcc.solve_multi([c, c2], sys_, pp, w, 0.01, tol=1e-10, batch=6, precision="bf16")
+        M3, _ = gfcc.solve_multi([c, c2], sys_, pp, w, 0.01, tol=1e-10, batch=6, precision="bf16", use_graph=True)
+        assert torch.equal(M1, M2) and torch.equal(M1, M3)
+    finally:
+        c2.close()
+
+
+def test_checkpoint_resume(ctx, tmp_path):
+    """Resume file: every finished right-hand side is appended; a repeated request restores all of
+    them without solving (same bits, same info); a truncated file restores its rows and solves the
+    rest; records of another request (other omega) are ignored."""
+    s, c = ctx
+    rng = np.random.default_rng(9)
+    p = rng.integers(0, s.n_occ, size=16)
+    w = rng.uniform(-1.2, -0.3, size=16)
+    ck = str(tmp_path / "ck.bin")
+    G0, i0, _ = c.solve(p, w, 0.01, tol=1e-10, batch=4, checkpoint=ck)
+    size = os.path.getsize(ck)
+    assert size % 16 == 0
+    rec = size // 16
+    G1, i1, _ = c.solve(p, w, 0.01, tol=1e-10, batch=4, checkpoint=ck)
+    assert torch.equal(G0, G1) and i0 == i1
+    assert os.path.getsize(ck) == size  # nothing was solved again
+    ck2 = str(tmp_path / "ck2.bin")
+    with open(ck, "rb") as f, open(ck2, "wb") as g:
+        g.write(f.read(6 * rec + rec // 2))  # six whole records and a torn one
+    G2, i2, _ = c.solve(p, w, 0.01, tol=1e-10, batch=4, checkpoint=ck2)
+    assert all(x["status"] == 0 for x in i2)
+    assert (torch.abs(G2 - G0) / torch.abs(G0)).max().item() < 1e-8
+    G3, i3, _ = c.solve(p, w + 0.01, 0.01, tol=1e-10, batch=4, checkpoint=ck)
+    assert all(x["iters"] > 0 for x in i3)
+    assert os.path.getsize(ck) == 2 * size
