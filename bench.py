@@ -26,14 +26,14 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK = {"fp64": 78.6e12, "fp32": 157.3e12, "bf16": 2.5e15}
-# HBM bytes per 128-slot ring-GEMM launch from rocprofv3 FETCH_SIZE / WRITE_SIZE passes
+# HBM bytes per 512-slot ring-GEMM launch from rocprofv3 FETCH_SIZE / WRITE_SIZE passes
 # (profiles/ring_gemm_o40v200_bf16ir.md; copy-kernel scale 2.0 for FETCH_SIZE, 1.0 for
 # WRITE_SIZE).  Valid only for the GEMM source they were taken on.
 TRAFFIC = {"gemm_src_sha256_16": "0a24a5c2e6a5af6f",
-           "bf16": {"fetch_GB": 2.995, "write_GB": 0.656, "tile": "db32_256x256w16", "key": "2:10240:8000:8000",
-                    "launch": "128 slots, M=10240 N=K=8000"},
-           "fp64": {"fetch_GB": 12.02, "write_GB": 0.746, "tile": "db256x128", "key": "0:10240:8000:8000",
-                    "launch": "128 slots, M=10240 N=K=8000"}}
+           "bf16": {"fetch_GB": 11.55, "write_GB": 2.623, "tile": "db32_256x256w16", "key": "2:40960:8000:8000",
+                    "launch": "512 slots, M=40960 N=K=8000"},
+           "fp64": {"fetch_GB": 47.05, "write_GB": 2.956, "tile": "db256x128", "key": "0:40960:8000:8000",
+                    "launch": "512 slots, M=40960 N=K=8000"}}
 DTYPE = {"fp64": "f64", "fp32": "f32+f64", "bf16": "bf16+f64"}
 
 
@@ -468,7 +468,7 @@ def mlp_study(args):
 
 
 def traffic_for(prec, tune_cache):
-    """Counter-measured HBM bytes (fetch + write) per 128-slot launch, or None when the GEMM
+    """Counter-measured HBM bytes (fetch + write) per 512-slot launch, or None when the GEMM
     source or the tile the autotuner chose differs from the profiled one."""
     import hashlib
     src = os.path.join(ROOT, "paper_2010_04768_amd", "csrc", "gemm.hip")

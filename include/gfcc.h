@@ -116,7 +116,7 @@ typedef struct {
   double tol;               /* on ||b - A x|| / ||b||, true FP64 residual */
   int32_t restart;          /* Krylov vectors per cycle (>= 1) */
   int32_t max_iter;         /* total inner iterations per right-hand side */
-  int32_t batch;            /* active right-hand sides per launch; 0 = auto from free HBM */
+  int32_t batch;            /* active right-hand sides per launch; 0 = auto: up to 512, within half of free HBM */
   gfcc_precond precond;
   gfcc_precision precision;
   int32_t use_graph;        /* capture one inner iteration in a hipGraph and replay it */

@@ -1285,7 +1285,7 @@ void solve_batch(gfcc_ctx* c, int64_t nrhs, const int64_t* p, const double* omeg
     size_t freeb = 0, totalb = 0;
     GFCC_HIP(hipMemGetInfo(&freeb, &totalb));
     const int64_t fit = int64_t(0.5 * double(freeb) / slot_bytes(c, R.m, R.flex));
-    B = int(std::max<int64_t>(1, std::min<int64_t>({fit, 128, nrhs})));
+    B = int(std::max<int64_t>(1, std::min<int64_t>({fit, 512, nrhs})));
   }
   std::vector<Lane> lanes(1);
   lanes[0].c = c;
