@@ -88,7 +88,11 @@ typedef struct {
 /* Build the per-system intermediates (blocks of Hbar_N, its exact diagonal,
  * the left vectors c_q for all occupied q, and reduced-precision copies) on
  * the GPU; the paper precomputes these constant intermediates before the
- * GFCC loop (Implementation Details).  Blocking.  *out receives a new context. */
+ * GFCC loop (Implementation Details).  The context also keeps copies of t1, l1
+ * and (only when its contents differ from t2) l2 for virtual-orbital right-hand
+ * sides and left vectors; nothing of *sys is referenced after the call.
+ * Blocking.  *out receives a new context (free it with gfcc_destroy).  Errors:
+ * E_ARG for bad dimensions or null pointers, E_OOM when device memory runs out. */
 gfcc_status gfcc_build_intermediates(const gfcc_system* sys, void* stream, gfcc_ctx** out);
 
 /* Dimensions of the context: D = o + o*o*v, o, v. Host pointers; any may be NULL. */
