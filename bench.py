@@ -69,6 +69,8 @@ def parse():
                          "system, BF16-IR, per-system G error vs FP64; one JSON line")
     ap.add_argument("--multi-p", type=int, default=8, help="orbitals per system in the multi-system study")
     ap.add_argument("--multi-omega", type=int, default=16, help="frequencies per system in the multi-system study")
+    ap.add_argument("--mlp-workload", default="learned-o90v420", choices=["learned-o90v420", "plain-o40v200"],
+                    help="system of the learned-preconditioner study")
     ap.add_argument("--mlp-steps", type=int, default=400)
     ap.add_argument("--mlp-max-iter", type=int, default=600)
     ap.add_argument("--mlp-tol", type=float, default=1e-8,
@@ -422,22 +424,23 @@ def mlp_study(args):
 
     torch.cuda.set_device(0)
     t0 = time.perf_counter()
-    wl = make_workload("learned-o90v420")
+    wl = make_workload(args.mlp_workload)
     s, omegas, plist = wl.systems[0], wl.omegas[0], wl.p_lists[0]
     log(f"system o={s.n_occ} v={s.n_vir} Q={s.n_chol} D={s.dim} generated in {time.perf_counter() - t0:.0f}s")
     t = time.perf_counter()
     ctx = gfcc.Context(s.eps, s.L, s.t1, s.t2)  # Lambda = T^dagger: l1, l2 not passed
     torch.cuda.synchronize()
     log(f"intermediates built in {time.perf_counter() - t:.1f}s")
+    dims = (s.n_occ, s.n_vir, s.n_chol)
     del s
-    tw = omegas[::32]  # 8 training omega, one p each
+    tw = omegas[:: len(omegas) // 8]  # 8 training omega, one p each
     tp = np.array([plist[(5 * i) % len(plist)] for i in range(len(tw))])
-    ew = omegas[4::16]
+    ew = omegas[len(omegas) // 64 :: len(omegas) // 16][:16]  # 16 other omega
     ep = np.array([plist[(7 * i) % len(plist)] for i in range(len(ew))])
     log(f"training data: {args.form} Jacobi solves of {len(tw)} right-hand sides, then {args.mlp_steps} Adam steps")
     out = {"metric": "learned preconditioner vs Jacobi (inner iterations, true FP64 residual, time)",
-           "workload": "learned-o90v420 (n_occ=90 n_vir=420 N_chol=1800, eta=0.005), 8 training and "
-                       "16 evaluation right-hand sides", "tol": args.mlp_tol, "forms": {}}
+           "workload": f"{args.mlp_workload} (n_occ={dims[0]} n_vir={dims[1]} N_chol={dims[2]}, eta={wl.eta}), "
+                       "8 training and 16 evaluation right-hand sides", "tol": args.mlp_tol, "forms": {}}
     torch.cuda.synchronize()
     t = time.perf_counter()
     try:
