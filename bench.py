@@ -72,6 +72,8 @@ def parse():
     ap.add_argument("--mlp-workload", default="learned-o90v420", choices=["learned-o90v420", "plain-o40v200"],
                     help="system of the learned-preconditioner study")
     ap.add_argument("--mlp-steps", type=int, default=400)
+    ap.add_argument("--mlp-pair-restart", type=int, default=64,
+                    help="restart length of the training solves (one (residual, iterate) pair per restart)")
     ap.add_argument("--mlp-max-iter", type=int, default=600)
     ap.add_argument("--mlp-tol", type=float, default=1e-8,
                     help="study tolerance (restarted GMRES(30) + Jacobi stalls near 1e-3 after 150 iterations here)")
@@ -445,7 +447,8 @@ def mlp_study(args):
     t = time.perf_counter()
     try:
         out["training"] = ctx.mlp_train(tp, tw, wl.eta, width=256, steps=args.mlp_steps, batch=8192,
-                                        pair_restart=64, lr=1e-3, seed=0, max_pairs=128, data_tol=1e-4,
+                                        pair_restart=args.mlp_pair_restart, lr=1e-3, seed=0, max_pairs=128,
+                                        data_tol=1e-4,
                                         data_max_iter=1200, data_precision=args.form)
         trained = True
     except gfcc.GfccError as e:  # no training solve converged: report it, evaluate Jacobi only

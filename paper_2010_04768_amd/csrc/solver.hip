@@ -1068,8 +1068,10 @@ struct BatchRun {
           rec->nrm.push_back(beta / std::sqrt(double(c->D)));
           rec->n += 1;
         }
-        // the learned preconditioner hands over to Jacobi when a cycle stalls
-        if (h.mlp && !(beta < 0.9 * h.beta)) {
+        // the learned preconditioner hands over to Jacobi when a cycle stalls: it cut the true
+        // residual by less than 10%, or it used the whole restart length without reaching
+        // its cycle target
+        if (h.mlp && (!(beta < 0.9 * h.beta) || h.k >= m)) {
           h.mlp = 0;
           h.fell_back = true;
         }
