@@ -72,6 +72,9 @@ def parse():
     ap.add_argument("--mlp-workload", default="learned-o90v420", choices=["learned-o90v420", "plain-o40v200"],
                     help="system of the learned-preconditioner study")
     ap.add_argument("--mlp-steps", type=int, default=400)
+    ap.add_argument("--mlp-data-tol", type=float, default=1e-4, help="tolerance of the training solves")
+    ap.add_argument("--mlp-data-precision", default="", choices=["", "fp64", "fp32", "bf16"],
+                    help="precision of the training solves (default: --form)")
     ap.add_argument("--mlp-pair-restart", type=int, default=64,
                     help="restart length of the training solves (one (residual, iterate) pair per restart)")
     ap.add_argument("--mlp-max-iter", type=int, default=600)
@@ -448,8 +451,8 @@ def mlp_study(args):
     try:
         out["training"] = ctx.mlp_train(tp, tw, wl.eta, width=256, steps=args.mlp_steps, batch=8192,
                                         pair_restart=args.mlp_pair_restart, lr=1e-3, seed=0, max_pairs=128,
-                                        data_tol=1e-4,
-                                        data_max_iter=1200, data_precision=args.form)
+                                        data_tol=args.mlp_data_tol,
+                                        data_max_iter=1200, data_precision=args.mlp_data_precision or args.form)
         trained = True
     except gfcc.GfccError as e:  # no training solve converged: report it, evaluate Jacobi only
         out["training"] = {"error": str(e)}
