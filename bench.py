@@ -442,7 +442,8 @@ def mlp_study(args):
     tp = np.array([plist[(5 * i) % len(plist)] for i in range(len(tw))])
     ew = omegas[len(omegas) // 64 :: len(omegas) // 16][:16]  # 16 other omega
     ep = np.array([plist[(7 * i) % len(plist)] for i in range(len(ew))])
-    log(f"training data: {args.form} Jacobi solves of {len(tw)} right-hand sides, then {args.mlp_steps} Adam steps")
+    log(f"training data: {args.mlp_data_precision or args.form} Jacobi solves of {len(tw)} right-hand sides "
+        f"(tol {args.mlp_data_tol}, restart {args.mlp_pair_restart}), then {args.mlp_steps} Adam steps")
     out = {"metric": "learned preconditioner vs Jacobi (inner iterations, true FP64 residual, time)",
            "workload": f"{args.mlp_workload} (n_occ={dims[0]} n_vir={dims[1]} N_chol={dims[2]}, eta={wl.eta}), "
                        "8 training and 16 evaluation right-hand sides", "tol": args.mlp_tol, "forms": {}}
