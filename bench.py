@@ -68,6 +68,8 @@ def parse():
                          "40/180/720, 60/300/1200; sampled p x omega), one persistent solve vs one solve per "
                          "system, BF16-IR, per-system G error vs FP64; one JSON line")
     ap.add_argument("--multi-p", type=int, default=8, help="orbitals per system in the multi-system study")
+    ap.add_argument("--multi-small", action="store_true",
+                    help="multi-system study on three different 20/100/400 systems (each too small to fill the GPU)")
     ap.add_argument("--multi-omega", type=int, default=16, help="frequencies per system in the multi-system study")
     ap.add_argument("--mlp-workload", default="learned-o90v420", choices=["learned-o90v420", "plain-o40v200"],
                     help="system of the learned-preconditioner study")
@@ -349,7 +351,8 @@ def multi_study(args):
     from synth import make_workload
 
     torch.cuda.set_device(0)
-    wl = make_workload("mixed-3sys", n_omega=128)
+    shapes = [(20, 100, 400)] * 3 if args.multi_small else None  # three different small systems
+    wl = make_workload("mixed-3sys", n_omega=128, shapes=shapes)
     ctxs = [gfcc.Context.from_system(s) for s in wl.systems]
     torch.cuda.synchronize()
     S, P, W = [], [], []
@@ -393,7 +396,8 @@ def multi_study(args):
     Gs, is_, ts = per_system()
     log(f"one launch {tm:.2f}s, per system {ts:.2f}s")
     out = {"metric": "multi-system solve (BF16-IR), one persistent launch vs one solve per system",
-           "workload": "mixed-3sys (20/100/400, 40/180/720, 60/300/1200), eta 0.01, sampled "
+           "workload": ("three different 20/100/400 systems" if args.multi_small else
+                        "mixed-3sys (20/100/400, 40/180/720, 60/300/1200)") + ", eta 0.01, sampled "
                        f"{args.multi_p} p x {args.multi_omega} omega per system", "n_rhs": int(len(S)),
            "one_launch_s": tm, "per_system_s": ts, "speedup": ts / tm, "systems": []}
     for k, c in enumerate(ctxs):
