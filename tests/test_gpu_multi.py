@@ -10,6 +10,7 @@ grouped launches.
 * the three-system mixed-precision workload (20/100/400, 40/180/720,
   60/300/1200): a sample of every system in one call, BF16 GMRES-IR against
   FP64 solves of each system to 1e-8;
+* virtual p in the queue, and the resume file;
 * argument errors.
 """
 import numpy as np
@@ -133,3 +134,23 @@ def test_multi_three_system_workload():
     finally:
         for c in ctxs:
             c.close()
+
+
+def test_multi_virtual_orbitals_and_resume(three, tmp_path):
+    """Virtual p in a multi-system queue (b_p = [a_p, T]|Phi>) against dense direct solves, and the
+    resume file: a repeated request restores every row bit for bit."""
+    ctxs = [c for _, _, c in three]
+    S = np.array([0, 1, 2, 0, 1, 2])
+    P = np.array([4, 5, 3, 19, 11, 1])  # virtual except the last
+    W = np.array([-0.7, -0.5, -0.3, -0.9, -0.4, -0.6])
+    ck = str(tmp_path / "multi.ckpt")
+    G, info = gfcc.solve_multi(ctxs, S, P, W, ETA, tol=1e-11, batch=4, checkpoint=ck)
+    assert all(x["status"] == 0 for x in info)
+    G = G.cpu().numpy()[:, 0]
+    for r in range(len(S)):
+        s, A, _ = three[S[r]]
+        x = np.linalg.solve((W[r] - 1j * ETA) * np.eye(s.dim) + A, O.rhs(s, P[r]))
+        g = O.left_vector(s, P[r]) @ x
+        assert abs(G[r] - g) <= 1e-8 * max(abs(g), 1e-4), r
+    G2, info2 = gfcc.solve_multi(ctxs, S, P, W, ETA, tol=1e-11, batch=4, checkpoint=ck)
+    assert np.array_equal(G2.cpu().numpy()[:, 0], G) and info2 == info
