@@ -67,6 +67,9 @@ def parse():
                     help="instead of the benchmark: the three-system mixed-precision workload (20/100/400, "
                          "40/180/720, 60/300/1200; sampled p x omega), one persistent solve vs one solve per "
                          "system, BF16-IR, per-system G error vs FP64; one JSON line")
+    ap.add_argument("--shifts-study", action="store_true",
+                    help="multi-shift GMRES on each system of the three-system workload (all occupied p, 128 "
+                         "omega), sampled G against FP64 restarted solves; one JSON line")
     ap.add_argument("--multi-p", type=int, default=8, help="orbitals per system in the multi-system study")
     ap.add_argument("--multi-small", action="store_true",
                     help="multi-system study on three different 20/100/400 systems (each too small to fill the GPU)")
@@ -102,6 +105,9 @@ def main():
         return
     if args.multi_study:
         multi_study(args)
+        return
+    if args.shifts_study:
+        shifts_study(args)
         return
     import torch
 
@@ -417,6 +423,59 @@ def multi_study(args):
     print(json.dumps(out), flush=True)
     for c in ctxs:
         c.close()
+
+
+def shifts_study(args):
+    """Multi-shift GMRES (FP64, one basis per orbital) on the 20/100/400, 40/180/720 and
+    60/300/1200 systems: every occupied p at all 128 frequencies, build + solve timed after an
+    untimed pass; 3 p x 4 omega per system re-solved by the restarted FP64 solver to tol 1e-11."""
+    import torch
+
+    from paper_2010_04768_amd import gfcc
+    from synth import make_workload
+
+    torch.cuda.set_device(0)
+    wl = make_workload("mixed-3sys", n_omega=128)
+    out = {"metric": "multi-shift GMRES omega-points/s per system (FP64 sigma, all occupied p x 128 omega)",
+           "workload": "mixed-3sys (20/100/400, 40/180/720, 60/300/1200), eta 0.01, tol 1e-8", "systems": []}
+    for k, s in enumerate(wl.systems):
+        ws, ps = wl.omegas[k], wl.p_lists[k]
+        eps_d, L_d = torch.from_numpy(s.eps).cuda(), torch.from_numpy(s.L).cuda()
+        t1_d, t2_d = torch.from_numpy(s.t1).cuda(), torch.from_numpy(s.t2).cuda()
+
+        def once():
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ctx = gfcc.Context(eps_d, L_d, t1_d, t2_d)
+            G, info, _ = ctx.solve_shifts(ps, ws, wl.eta, tol=wl.tol, max_dim=256,
+                                          fallback=dict(precond="jacobi", precision="fp64", tol=wl.tol),
+                                          tune_cache=args.tune_cache or None)
+            torch.cuda.synchronize()
+            return ctx, G, info, time.perf_counter() - t0
+
+        ctx, _, _, _ = once()
+        ctx.close()
+        ctx, G, info, dt = once()
+        G = G.cpu().numpy()[:, :, 0]
+        sp = [0, len(ps) // 2, len(ps) - 1]
+        sk = [0, 41, 85, 127]
+        P = np.repeat(np.asarray(ps)[sp], len(sk))
+        W = np.tile(ws[sk], len(sp))
+        Gr, ir, _ = ctx.solve(P, W, wl.eta, tol=1e-11, precision="fp64", max_iter=4000)
+        Gr = Gr.cpu().numpy()[:, 0].reshape(len(sp), len(sk))
+        err = float(np.max(np.abs(G[np.ix_(sp, sk)] - Gr) / np.abs(Gr)))
+        conv = sum(x["status"] == 0 for row in info for x in row)
+        dims = [max(x["iters"] for x in row) for row in info]
+        rec = {"o": s.n_occ, "v": s.n_vir, "Q": s.n_chol, "n_p": len(ps), "n_omega": len(ws), "step_s": dt,
+               "omega_points_per_s": len(ws) / dt if conv == len(ps) * len(ws) else 0.0, "converged": int(conv),
+               "basis_size_mean": float(np.mean(dims)), "basis_size_max": int(max(dims)),
+               "fallback_rhs": int(sum(x["restarts"] > 0 for row in info for x in row)),
+               "sampled_g_max_rel_err_vs_fp64": err}
+        out["systems"].append(rec)
+        log(f"system {k}: {rec}")
+        ctx.close()
+        del eps_d, L_d, t1_d, t2_d
+    print(json.dumps(out), flush=True)
 
 
 def mlp_study(args):
