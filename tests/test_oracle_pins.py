@@ -171,6 +171,26 @@ def test_closed_form_free_particles_o2():
             assert np.abs(G[w] - want).max() < 1e-12
 
 
+def test_spectral_function_free_particles():
+    """T = Lambda = L = 0: A(omega) is a sum of Lorentzians of width eta at the occupied orbital
+    energies, (1/pi) sum_i eta / ((omega - eps_i)^2 + eta^2) (Theory section, the spectral function
+    as the trace of Im G), positive, and each Lorentzian carries unit weight."""
+    o, v = 4, 16
+    s = make_system(o, v, 48, 22, t1=False, t2=False, lam=False, L_zero=True)
+    im = O.intermediates(s)
+    eta = 0.02
+    ws = np.array([-1.1, -0.7, -0.45, -0.3])
+    Gd = np.stack([O.greens(s, im, p, ws, eta, tol=1e-14)[:, 0] for p in range(o)], axis=1)  # [omega][p]
+    A = O.spectral_function(Gd)
+    want = np.array([np.sum(eta / ((w - s.eps[:o]) ** 2 + eta ** 2)) / np.pi for w in ws])
+    assert np.abs(A - want).max() < 1e-10 * want.max()
+    assert np.all(A > 0)
+    # unit weight per occupied orbital: the closed form integrates to o over a wide window
+    grid = np.linspace(-60.0, 60.0, 2_400_001)
+    dense = np.sum(eta / ((grid[:, None] - s.eps[None, :o]) ** 2 + eta ** 2), axis=1) / np.pi
+    assert abs(np.trapezoid(dense, grid) - o) < 2e-3
+
+
 def test_self_energy_fourth_order_in_L():
     """T = Lambda = 0, L -> sL: G - G0 = O(s^4) (ERIs are quadratic in L)."""
     o, v = 3, 6
