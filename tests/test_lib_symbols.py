@@ -42,3 +42,19 @@ def test_strerror_without_gpu():
     lib.gfcc_strerror.restype = ctypes.c_char_p
     assert lib.gfcc_strerror(0) == b"success"
     assert lib.gfcc_strerror(-1) == b"invalid argument"
+
+
+@pytest.mark.parametrize("lang,std", [("c", "-std=c99"), ("c++", "-std=c++17")])
+def test_header_is_plain_c_and_cpp(tmp_path, lang, std):
+    """The boundary header compiles on its own as C99 (no C++ in the ABI) and as C++."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc" if lang == "c" else "g++")
+    if cc is None:
+        pytest.skip("no host compiler")
+    src = tmp_path / "use_header.c"
+    src.write_text('#include "gfcc.h"\nint main(void) { gfcc_solve_opts o; gfcc_shift_opts s; '
+                   'gfcc_mor_opts m; (void)o; (void)s; (void)m; return 0; }\n')
+    r = subprocess.run([cc, std, "-Wall", "-Wextra", "-pedantic", "-Werror", "-fsyntax-only", "-x", lang,
+                        "-I", os.path.join(ROOT, "include"), str(src)], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
