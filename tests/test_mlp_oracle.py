@@ -69,3 +69,55 @@ def test_adam_decreases_loss_on_a_fit():
         L, g = M.loss_and_grad(p, X, T)
         M.adam_step(p, g, st, 1e-2)
     assert L < 0.3 * L0
+
+
+# ---- Adam (Kingma & Ba, Algorithm 1: biased moments m, v; bias corrections
+# 1 - beta^t; step lr * mhat / (sqrt(vhat) + eps)).  Pins independent of the
+# oracle's own formula: a two-step example worked by hand, and two closed forms.
+
+def _adam_run(p0, grads, lr, **kw):
+    p = {"w": np.array(p0, dtype=float)}
+    st = {}
+    for g in grads:
+        M.adam_step(p, {"w": np.array(g, dtype=float)}, st, lr, **kw)
+    return p["w"], st
+
+
+def test_adam_two_steps_worked_by_hand():
+    """p0 = 1, gradients 0.5 then -0.25, lr = 0.1, beta1 = 0.9, beta2 = 0.999, eps = 1e-8.
+    Step 1: m = 0.05, v = 0.00025, mhat = 0.5, vhat = 0.25,
+            p1 = 1 - 0.1 * 0.5 / (0.5 + 1e-8) = 0.90000000199999996000...
+    Step 2: m = 0.9*0.05 - 0.1*0.25 = 0.02, v = 0.999*0.00025 + 0.001*0.0625 = 0.00031225,
+            mhat = 0.02 / 0.19, vhat = 0.00031225 / 0.001999,
+            p2 = 0.87336629870784616255937..."""
+    w1, st1 = _adam_run([1.0], [[0.5]], 0.1)
+    assert abs(st1["m_w"][0] - 0.05) <= 4e-15 * 0.05 and abs(st1["v_w"][0] - 0.00025) <= 4e-15 * 0.00025
+    assert abs(w1[0] - 0.90000000199999996000) <= 1e-15
+    w2, st2 = _adam_run([1.0], [[0.5], [-0.25]], 0.1)
+    assert abs(st2["m_w"][0] - 0.02) <= 4e-15 * 0.02 and abs(st2["v_w"][0] - 0.00031225) <= 4e-15 * 0.00031225
+    assert st2["t"] == 2
+    assert abs(w2[0] - 0.87336629870784616256) <= 1e-15
+
+
+def test_adam_first_step_is_lr_times_sign_like():
+    """The bias corrections make the first step exactly lr * g / (|g| + eps) for every
+    parameter, whatever the betas.  eps = 0.1 so that eps inside the square root, or a
+    missing or misplaced bias correction, changes the result by far more than rounding."""
+    rng = np.random.default_rng(11)
+    g = rng.normal(size=50) * np.exp(rng.uniform(-3, 3, size=50))
+    p0 = rng.normal(size=50)
+    for b1, b2 in ((0.9, 0.999), (0.5, 0.9)):
+        w, _ = _adam_run(p0, [g], 0.03, b1=b1, b2=b2, eps=0.1)
+        assert np.allclose(w, p0 - 0.03 * g / (np.abs(g) + 0.1), rtol=0, atol=1e-15)
+
+
+def test_adam_constant_gradient_moves_linearly():
+    """With a constant gradient the bias-corrected moments equal g and g^2 at every step,
+    so t steps move each parameter by t * lr * g / (|g| + eps)."""
+    rng = np.random.default_rng(12)
+    g = rng.normal(size=20)
+    p0 = rng.normal(size=20)
+    w, st = _adam_run(p0, [g] * 7, 0.01, eps=0.05)
+    assert np.allclose(w, p0 - 7 * 0.01 * g / (np.abs(g) + 0.05), rtol=0, atol=1e-14)
+    # the biased first moment after t steps is (1 - beta1^t) g
+    assert np.allclose(st["m_w"], (1 - 0.9 ** 7) * g, rtol=1e-14, atol=0)
