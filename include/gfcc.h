@@ -110,8 +110,14 @@ typedef enum {
 } gfcc_block;
 gfcc_status gfcc_export(gfcc_ctx* ctx, gfcc_block which, double* dst, void* stream);
 
-/* Y[r] = Hbar_N X[r] for r < nrhs.  X, Y: [nrhs][D] complex interleaved; may
- * not alias.  prec selects the arithmetic of the two-body contractions. */
+/* The sigma product Y[r] = Hbar_N X[r] for r < nrhs: the action of the
+ * connected similarity-transformed Hamiltonian on the 1h + 2h1p expansion of
+ * X_p (Theory section, the linear system for X_p and the X_p expansion; the
+ * per-iteration O(o^3 v^2) work of the GMRES micro loop, GFCC Workflow and
+ * Bottlenecks, Algorithm 1).  X, Y: device [nrhs][D] complex interleaved; may
+ * not alias.  prec selects the arithmetic of the two-body contractions (FP32 or
+ * BF16 on MFMA with FP32 accumulation; the one-body terms stay FP64).  E_ARG for
+ * a bad precision or aliased/NULL buffers.  Enqueued on `stream`. */
 gfcc_status gfcc_sigma(gfcc_ctx* ctx, int64_t nrhs, const double* X, double* Y,
                        gfcc_precision prec, void* stream);
 
@@ -127,12 +133,18 @@ typedef struct {
   const char* tune_cache;   /* host path of the tile autotuner JSON cache; NULL = no tuning */
   double ir_inner_rtol;     /* GMRES-IR: inner cycle stops at this fraction of the cycle's starting
                                residual; 0 = default for the precision (ignored for FP64) */
-  const char* checkpoint;   /* host path of a resume file, or NULL: every finished right-hand side
-                               appends (index, p, omega, eta, G row, info) to it, and a later call
-                               with the same request restores the rows it holds instead of solving
-                               them (gfcc_solve_batch and gfcc_solve_multi; ignored by the solves
-                               that model-order reduction and the multi-shift fallback run).
-                               Restored rows get no X (zeros when X is requested). */
+  const char* checkpoint;   /* host path of a resume file, or NULL.  A new or empty file gets a
+                               header (magic, version, record size, a fingerprint of the request:
+                               each system's dimensions and exact diagonal, the system of each
+                               right-hand side, q, eta, tol, precision, precond, restart, max_iter);
+                               every finished right-hand side then appends (index, p, omega, eta,
+                               G row, info), and a later call with the same request restores the
+                               rows it holds instead of solving them.  A file without a valid
+                               header, or with another request's fingerprint, is refused with
+                               E_ARG and left unchanged; a torn last record is trimmed.
+                               gfcc_solve_batch and gfcc_solve_multi; ignored by the solves that
+                               model-order reduction and the multi-shift fallback run.  Restored
+                               rows get X = 0 when X is requested. */
 } gfcc_solve_opts;
 
 /* Per right-hand side result (host memory). status: 0 converged, 1 max_iter,
@@ -218,10 +230,17 @@ gfcc_status gfcc_solve_multi(int32_t nsys, gfcc_ctx* const* ctxs, int64_t nrhs, 
                              const int64_t* p, const double* omega, double eta, int64_t nq, const int64_t* q,
                              const gfcc_solve_opts* opts, double* G, gfcc_rhs_info* info, void* stream);
 
-/* G[r][k] = c_{q_k}^T X[r] (bilinear, no conjugation) for caller vectors X
- * [nrhs][D] complex; q host [nq] in [0, o + v). G device [nrhs][nq] complex. */
-gfcc_status gfcc_greens(gfcc_ctx* ctx, int64_t nrhs, const double* X, int64_t nq, const int64_t* q,
-                        double* G, void* stream);
+/* Green's function from caller solutions (Theory section: the compact form
+ * G_qp = <Phi|(1 + Lambda) abar_q^+ X_p|Phi>, evaluated as the bilinear product
+ * c_q^T X_p of the model-order-reduction equations, no conjugation):
+ * G[r][k] = c_{q_k}^T X[r] for vectors X [nrhs][D] complex interleaved (device).
+ * q: host [nq] in [0, o + v), the same list for every vector; or q = NULL with
+ * nq = 1, the diagonal form G[r][0] = c_{p_r}^T X[r] with p host [nrhs] in
+ * [0, o + v) (p is read only when q is NULL).  G: device [nrhs][nq] complex
+ * interleaved.  E_ARG for out-of-range orbitals or a NULL q without p or with
+ * nq != 1.  Blocking. */
+gfcc_status gfcc_greens(gfcc_ctx* ctx, int64_t nrhs, const int64_t* p, const double* X, int64_t nq,
+                        const int64_t* q, double* G, void* stream);
 
 /* ---------------------------------------------------------------------------
  * Learned preconditioner (GFCC_PC_MLP).  An elementwise network corrects the
@@ -273,6 +292,14 @@ gfcc_status gfcc_mlp_train(gfcc_ctx* ctx, int64_t nrhs, const int64_t* p, const 
  * params may be NULL to query the width only. */
 gfcc_status gfcc_mlp_set_weights(gfcc_ctx* ctx, int32_t width, const double* params, void* stream);
 gfcc_status gfcc_mlp_get_weights(gfcc_ctx* ctx, int32_t* width, double* params, void* stream);
+
+/* One Adam step (Kingma & Ba: beta1 = 0.9, beta2 = 0.999, eps = 1e-8, bias
+ * corrections 1 - beta^t) on the network weights with the caller's flat
+ * gradient grad [n_params] (device), the step the training loop takes after
+ * each minibatch gradient.  The moments and the step count t live in the
+ * context and start at zero when weights are set or training starts.
+ * E_STATE without a network.  Blocking. */
+gfcc_status gfcc_mlp_adam_step(gfcc_ctx* ctx, const double* grad, double lr, void* stream);
 
 /* FP64 network on caller features: Y[n][2] from X[n][8] (device). */
 gfcc_status gfcc_mlp_forward(gfcc_ctx* ctx, int64_t n, const double* X, double* Y, void* stream);

@@ -165,26 +165,39 @@ gfcc_status gfcc_spectral(int64_t np, int64_t n_omega, const double* G, int64_t 
   });
 }
 
-gfcc_status gfcc_greens(gfcc_ctx* c, int64_t nrhs, const double* X, int64_t nq, const int64_t* q, double* G,
-                        void* stream) {
+gfcc_status gfcc_greens(gfcc_ctx* c, int64_t nrhs, const int64_t* p, const double* X, int64_t nq,
+                        const int64_t* q, double* G, void* stream) {
   return guarded([&] {
     GFCC_CHECK(c, GFCC_E_ARG, "null context");
     GFCC_CHECK(nrhs >= 0 && nq >= 0, GFCC_E_ARG, "negative size");
     if (nrhs == 0 || nq == 0) return;
-    GFCC_CHECK(X && q && G, GFCC_E_ARG, "null argument");
-    for (int64_t k = 0; k < nq; ++k) GFCC_CHECK(q[k] >= 0 && q[k] < c->o + c->v, GFCC_E_ARG, "q out of range");
+    GFCC_CHECK(X && G, GFCC_E_ARG, "null argument");
+    GFCC_CHECK(q != nullptr || (nq == 1 && p != nullptr), GFCC_E_ARG, "q == NULL requires nq == 1 and p");
+    const int64_t norb = c->o + c->v;
+    if (q)
+      for (int64_t k = 0; k < nq; ++k) GFCC_CHECK(q[k] >= 0 && q[k] < norb, GFCC_E_ARG, "q out of range");
+    else
+      for (int64_t r = 0; r < nrhs; ++r) GFCC_CHECK(p[r] >= 0 && p[r] < norb, GFCC_E_ARG, "p out of range");
     hipStream_t s = as_stream(stream);
+    // q list (shared by every vector), or the diagonal form's own orbital per vector
+    const int64_t nlist = q ? nq : nrhs;
     DBuf qd;
-    qd.ensure(size_t(nq) * 8, s);
-    GFCC_HIP(hipMemcpyAsync(qd.p, q, size_t(nq) * 8, hipMemcpyHostToDevice, s));
+    qd.ensure(size_t(nlist) * 8, s);
+    GFCC_HIP(hipMemcpyAsync(qd.p, q ? q : p, size_t(nlist) * 8, hipMemcpyHostToDevice, s));
     const int64_t chunk = 64;
     for (int64_t r0 = 0; r0 < nrhs; r0 += chunk) {
       const int64_t nb = std::min(chunk, nrhs - r0);
       c->ws_in.ensure(size_t(2 * nb * c->Dp) * 8, s);
       to_planes(c, nb, X + r0 * c->D * 2, c->ws_in.as<double>(), s);
-      greens_planes(c, nb, c->ws_in.as<double>(), nq, qd.as<int64_t>(), G + r0 * nq * 2, s);
+      if (q) {
+        greens_planes(c, nb, c->ws_in.as<double>(), nq, qd.as<int64_t>(), G + r0 * nq * 2, s);
+      } else {
+        for (int64_t b = 0; b < nb; ++b)
+          greens_planes(c, 1, c->ws_in.as<double>() + 2 * b * c->Dp, 1, qd.as<int64_t>() + r0 + b,
+                        G + (r0 + b) * 2, s);
+      }
     }
-    GFCC_HIP(hipStreamSynchronize(s));  // qd and the host q are released on return
+    GFCC_HIP(hipStreamSynchronize(s));  // qd and the host lists are released on return
   });
 }
 
@@ -260,6 +273,18 @@ gfcc_status gfcc_mlp_get_weights(gfcc_ctx* c, int32_t* width, double* params, vo
     if (params)
       GFCC_HIP(hipMemcpyAsync(params, c->mlp->params.p, size_t(mlp_n_params(c->mlp->width)) * 8,
                               hipMemcpyDeviceToDevice, as_stream(stream)));
+  });
+}
+
+gfcc_status gfcc_mlp_adam_step(gfcc_ctx* c, const double* grad, double lr, void* stream) {
+  return guarded([&] {
+    GFCC_CHECK(c && grad, GFCC_E_ARG, "null argument");
+    GFCC_CHECK(std::isfinite(lr) && lr > 0.0, GFCC_E_ARG, "lr must be finite and positive");
+    GFCC_CHECK(c->mlp != nullptr, GFCC_E_STATE, "no network in this context");
+    hipStream_t s = as_stream(stream);
+    mlp_adam(c, grad, lr, s);
+    mlp_prepare_inference(c, s);
+    GFCC_HIP(hipStreamSynchronize(s));
   });
 }
 

@@ -68,6 +68,7 @@ void mlp_features(struct ::gfcc_ctx* c, int64_t nvec, const double* planes, cons
                   const double* nrm_dev, double eta, double* X, hipStream_t s);
 void mlp_train(struct ::gfcc_ctx* c, const MlpPairs& pairs, int64_t steps, int64_t N, double lr, uint64_t seed,
                double eta, gfcc_mlp_report* rep, hipStream_t s);
+void mlp_adam(struct ::gfcc_ctx* c, const double* grad, double lr, hipStream_t s);
 void mlp_pair_errors(double* E, const double* Xk, const double* Xstar, const int* rhs_dev, int64_t npairs,
                      int64_t Dp, hipStream_t s);
 

@@ -493,6 +493,19 @@ void mlp_features(gfcc_ctx* c, int64_t nvec, const double* planes, const double*
 
 // ------------------------------------------------------------------ training
 
+// One Adam step (Kingma & Ba): biased moments m, v with beta1 = 0.9, beta2 = 0.999,
+// bias corrections 1 - beta^t, step lr * mhat / (sqrt(vhat) + 1e-8).
+void mlp_adam(gfcc_ctx* c, const double* grad, double lr, hipStream_t s) {
+  Mlp& M = *c->mlp;
+  const int64_t np = mlp_n_params(M.width);
+  const double b1 = 0.9, b2 = 0.999, eps = 1e-8;
+  M.adam_t += 1;
+  const double c1 = 1.0 - std::pow(b1, double(M.adam_t)), c2 = 1.0 - std::pow(b2, double(M.adam_t));
+  hipLaunchKernelGGL(adam_kernel, dim3(nblk(np)), dim3(256), 0, s, M.params.as<double>(), grad, M.m.as<double>(),
+                     M.v.as<double>(), np, lr, b1, b2, eps, c1, c2);
+  GFCC_HIP(hipGetLastError());
+}
+
 void mlp_train(gfcc_ctx* c, const MlpPairs& pairs, int64_t steps, int64_t N, double lr, uint64_t seed, double eta,
                gfcc_mlp_report* rep, hipStream_t s) {
   Mlp& M = *c->mlp;
@@ -501,17 +514,12 @@ void mlp_train(gfcc_ctx* c, const MlpPairs& pairs, int64_t steps, int64_t N, dou
   double* T = M.ws.get(5, N * 2, s);
   M.grad.ensure(size_t(np) * 8, s);
   M.loss.ensure(size_t(std::max<int64_t>(steps, 1)) * 8, s);
-  const double b1 = 0.9, b2 = 0.999, eps = 1e-8;
   for (int64_t it = 0; it < steps; ++it) {
     hipLaunchKernelGGL(mlp_sample_kernel, dim3(nblk(N)), dim3(256), 0, s, pairs.R, pairs.E, pairs.omega, pairs.nrm,
                        pairs.n, c->diag.as<double>(), c->D, c->o, c->o_pad, c->Dp, eta, M.sD,
                        mix64_host(seed + 0x1000 * uint64_t(it)), N, X, T);
     mlp_loss_grad64(c, N, X, T, M.loss.as<double>() + it, M.grad.as<double>(), s);
-    M.adam_t += 1;
-    const double c1 = 1.0 - std::pow(b1, double(M.adam_t)), c2 = 1.0 - std::pow(b2, double(M.adam_t));
-    hipLaunchKernelGGL(adam_kernel, dim3(nblk(np)), dim3(256), 0, s, M.params.as<double>(), M.grad.as<double>(),
-                       M.m.as<double>(), M.v.as<double>(), np, lr, b1, b2, eps, c1, c2);
-    GFCC_HIP(hipGetLastError());
+    mlp_adam(c, M.grad.as<double>(), lr, s);
   }
   std::vector<double> L(size_t(std::max<int64_t>(steps, 1)));
   if (steps > 0)

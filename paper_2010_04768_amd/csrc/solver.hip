@@ -30,6 +30,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstring>
 #include <deque>
 #include <map>
 #include <set>
@@ -397,6 +398,12 @@ __global__ void scale_kernel(SolverDev d, const int* act) {
   }
 }
 
+// drop the current cycle of the listed slots (k = 0: the solution update adds nothing)
+__global__ void drop_cycle_kernel(SolverDev d, const int* slots, int n) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < n) d.kk[slots[q]] = 0;
+}
+
 // y = R^-1 g (upper triangular k x k) per finishing slot
 __global__ void trisolve_kernel(SolverDev d, const int* fin, int n) {
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
@@ -611,6 +618,7 @@ struct HostSlot {
   int k = 0;               // Krylov step (mirror of the device counter)
   int mlp = 0;             // 1 while the learned preconditioner is in use
   bool fell_back = false;  // switched to Jacobi after an MLP cycle stalled
+  bool nonfinite = false;  // the current cycle produced a non-finite value
   double beta = 1.0;       // residual at the start of the current cycle
   double bn = 1.0;         // |b_p|
   int brow = -1;           // row of b_p in the materialised right-hand sides (-1: e_p)
@@ -642,6 +650,7 @@ struct Lane {
   SolverDev d{};
   DBuf d_act, d_flags, d_res, d_list, d_plist, d_brow, d_zlist, d_ctl, d_beta, d_rows, d_q;
   DBuf d_msrc, d_mzoff, d_mom, d_pmode;
+  DBuf d_ag, d_agb, d_agt, d_drop;  // restart and dropped-cycle lists of cycle finishing
   std::map<int64_t, int> brow_of;  // virtual p -> row of bB
   std::vector<double> bnorm_h;
   DBuf d_borb, bB, bBn;
@@ -675,20 +684,75 @@ struct BatchRun {
   double tol = 0.0, rtol_lp = 0.0;
   bool ok_all = true;
 
-  // Resume file: one record per finished right-hand side, appended as it finishes.
+  // Resume file: a header (magic, version, record size, fingerprint of the
+  // request), then one record per finished right-hand side, appended as it finishes.
+  struct CkptHeader {
+    char magic[8];
+    int32_t version, rec_size;
+    uint64_t fingerprint;
+  };
   struct CkptRec {
     int64_t row, p, nq, qhash;
     double omega, eta;
     gfcc_rhs_info info;
   };  // followed by 2 nq doubles (the G row)
+  static constexpr char kMagic[8] = {'G', 'F', 'C', 'C', 'R', 'E', 'S', 'M'};
+  static constexpr int32_t kVersion = 2;
   FILE* ck = nullptr;
   std::set<int64_t> restored;
   int64_t qhash = 0;
+  const int32_t* sysv = nullptr;  // system of each right-hand side (several-system solves)
 
-  // restore the rows a previous call recorded for this request, then open the file for appending
-  void ckpt_open(int64_t nrhs) {
+  // FNV-1a over the request: every system's dimensions and a sample of its exact
+  // diagonal, the system of each right-hand side, the q list, eta and the solver
+  // options that change results (tolerance, precision, preconditioner, restart,
+  // max_iter).  p and omega are matched per record.
+  uint64_t fingerprint(const std::vector<Lane>& lanes, int64_t nrhs) {
+    uint64_t h = 1469598103934665603ull;
+    auto mix = [&](uint64_t x) {
+      for (int b = 0; b < 8; ++b) {
+        h ^= (x >> (8 * b)) & 0xffu;
+        h *= 1099511628211ull;
+      }
+    };
+    auto mixd = [&](double x) {
+      uint64_t u;
+      std::memcpy(&u, &x, 8);
+      mix(u);
+    };
+    mix(uint64_t(lanes.size()));
+    for (const Lane& L : lanes) {
+      const gfcc_ctx* c = L.c;
+      mix(uint64_t(c->o));
+      mix(uint64_t(c->v));
+      mix(uint64_t(c->Q));
+      const int64_t n = std::min<int64_t>(c->Dp, 2048);
+      std::vector<double> dg(size_t(2 * n));
+      GFCC_HIP(hipMemcpyAsync(dg.data(), c->diag.p, size_t(n) * 8, hipMemcpyDeviceToHost, s));
+      GFCC_HIP(hipMemcpyAsync(dg.data() + n, c->diag.as<double>() + (c->Dp - n), size_t(n) * 8,
+                              hipMemcpyDeviceToHost, s));
+      GFCC_HIP(hipStreamSynchronize(s));
+      for (double x : dg) mixd(x);
+    }
+    if (sysv)
+      for (int64_t r = 0; r < nrhs; ++r) mix(uint64_t(sysv[r]));
+    mix(uint64_t(nq));
+    for (int64_t k = 0; q && k < nq; ++k) mix(uint64_t(q[k]));
+    mixd(eta);
+    mixd(opts->tol);
+    mix(uint64_t(opts->precision));
+    mix(uint64_t(opts->precond));
+    mix(uint64_t(opts->restart));
+    mix(uint64_t(opts->max_iter));
+    return h;
+  }
+
+  // Restore the rows a previous call recorded for this request, then open the file
+  // for appending.  A file that is not a resume file, or belongs to another request,
+  // is refused with E_ARG and left untouched.
+  void ckpt_open(const std::vector<Lane>& lanes, int64_t nrhs) {
     if (!opts->checkpoint) return;
-    uint64_t h = 1469598103934665603ull;  // FNV-1a over (nq, q)
+    uint64_t h = 1469598103934665603ull;  // FNV-1a over (nq, q): matched per record
     auto mix = [&](int64_t x) {
       for (int b = 0; b < 8; ++b) {
         h ^= uint64_t(x >> (8 * b)) & 0xffu;
@@ -699,39 +763,72 @@ struct BatchRun {
     for (int64_t k = 0; q && k < nq; ++k) mix(q[k]);
     if (!q) mix(-1);
     qhash = int64_t(h);
+    CkptHeader want{};
+    std::memcpy(want.magic, kMagic, 8);
+    want.version = kVersion;
+    want.rec_size = int32_t(sizeof(CkptRec));
+    want.fingerprint = fingerprint(lanes, nrhs);
     std::vector<double> gbuf;
     std::vector<int64_t> rows;
-    long good = 0, total = 0;  // bytes of whole records / of the file
+    long good = 0, total = 0;  // bytes of the header and whole records / of the file
+    bool fresh = true;
     if (FILE* f = std::fopen(opts->checkpoint, "rb")) {
-      CkptRec r;
-      std::vector<double> g;
-      while (std::fread(&r, sizeof(r), 1, f) == 1) {
-        if (r.nq < 1 || r.nq > (int64_t(1) << 20)) break;  // not a record of this format
-        g.resize(size_t(2 * r.nq));
-        if (std::fread(g.data(), sizeof(double), g.size(), f) != g.size()) break;
-        good = std::ftell(f);
-        if (r.nq != nq) continue;
-        const bool same = r.row >= 0 && r.row < nrhs && r.p == p[r.row] && r.omega == omega[r.row] &&
-                          r.eta == eta && r.qhash == qhash;
-        if (!same || restored.count(r.row)) continue;
-        restored.insert(r.row);
-        info[r.row] = r.info;
-        if (r.info.status != 0 && r.info.status != 4) ok_all = false;
-        rows.push_back(r.row);
-        gbuf.insert(gbuf.end(), g.begin(), g.end());
-      }
       std::fseek(f, 0, SEEK_END);
       total = std::ftell(f);
+      std::fseek(f, 0, SEEK_SET);
+      if (total > 0) {
+        fresh = false;
+        CkptHeader got{};
+        const bool hdr = std::fread(&got, sizeof(got), 1, f) == 1 && std::memcmp(got.magic, kMagic, 8) == 0 &&
+                         got.version == kVersion && got.rec_size == int32_t(sizeof(CkptRec));
+        if (!hdr) {
+          std::fclose(f);
+          throw Error{GFCC_E_ARG, std::string("not a resume file of this library: ") + opts->checkpoint};
+        }
+        if (got.fingerprint != want.fingerprint) {
+          std::fclose(f);
+          throw Error{GFCC_E_ARG, std::string("resume file belongs to a different request (system, q, eta or "
+                                              "solver options): ") + opts->checkpoint};
+        }
+        good = long(sizeof(CkptHeader));
+        CkptRec r;
+        std::vector<double> g;
+        while (std::fread(&r, sizeof(r), 1, f) == 1) {
+          if (r.nq < 1 || r.nq > (int64_t(1) << 20)) break;  // torn or corrupt tail
+          g.resize(size_t(2 * r.nq));
+          if (std::fread(g.data(), sizeof(double), g.size(), f) != g.size()) break;
+          good = std::ftell(f);
+          if (r.nq != nq) continue;
+          const bool same = r.row >= 0 && r.row < nrhs && r.p == p[r.row] && r.omega == omega[r.row] &&
+                            r.eta == eta && r.qhash == qhash;
+          if (!same || restored.count(r.row)) continue;
+          restored.insert(r.row);
+          info[r.row] = r.info;
+          if (r.info.status != 0 && r.info.status != 4) ok_all = false;
+          rows.push_back(r.row);
+          gbuf.insert(gbuf.end(), g.begin(), g.end());
+        }
+      }
       std::fclose(f);
     }
-    // a record torn by an interrupted write is cut off before appending
-    if (total > good) GFCC_CHECK(::truncate(opts->checkpoint, good) == 0, GFCC_E_ARG, "cannot trim checkpoint file");
-    for (size_t k = 0; k < rows.size(); ++k)
+    // a record torn by an interrupted write is cut off (after a valid header) before appending
+    if (!fresh && total > good)
+      GFCC_CHECK(::truncate(opts->checkpoint, good) == 0, GFCC_E_ARG, "cannot trim resume file");
+    for (size_t k = 0; k < rows.size(); ++k) {
       GFCC_HIP(hipMemcpyAsync(G + rows[k] * nq * 2, gbuf.data() + k * 2 * nq, size_t(nq) * 16,
                               hipMemcpyHostToDevice, s));
+      if (Xout) {  // restored rows carry no solution
+        const int64_t D = lanes[0].c->D;
+        GFCC_HIP(hipMemsetAsync(Xout + rows[k] * D * 2, 0, size_t(D) * 16, s));
+      }
+    }
     GFCC_HIP(hipStreamSynchronize(s));  // gbuf goes out of scope
-    ck = std::fopen(opts->checkpoint, "ab");
-    GFCC_CHECK(ck, GFCC_E_ARG, std::string("cannot open checkpoint file ") + opts->checkpoint);
+    ck = std::fopen(opts->checkpoint, fresh ? "wb" : "ab");
+    GFCC_CHECK(ck, GFCC_E_ARG, std::string("cannot open resume file ") + opts->checkpoint);
+    if (fresh) {
+      std::fwrite(&want, sizeof(want), 1, ck);
+      std::fflush(ck);
+    }
   }
 
   // append the finished rows (G already on the device)
@@ -809,6 +906,10 @@ struct BatchRun {
     L.d_flags.ensure(size_t(B) * sizeof(int), s);
     L.d_res.ensure(size_t(B) * 8, s);
     L.d_beta.ensure(size_t(B) * 8, s);
+    // lists of at most B entries, sized once so that cycle finishing allocates nothing
+    for (DBuf* b : {&L.d_act, &L.d_list, &L.d_plist, &L.d_brow, &L.d_ag, &L.d_agt, &L.d_drop})
+      b->ensure(size_t(B) * 8, s);
+    for (DBuf* b : {&L.d_zlist, &L.d_ctl, &L.d_agb, &L.d_rows}) b->ensure(size_t(B) * 16, s);
 
     // Right-hand sides of virtual orbitals, one materialised row per distinct
     // orbital with its norm; occupied p keep the implicit unit vector e_p.
@@ -1022,6 +1123,20 @@ struct BatchRun {
     upload(L.d_plist, pf, s);
     upload(L.d_brow, bf, s);
     const int* fl = L.d_list.as<int>();
+    // A cycle of the learned preconditioner that went non-finite (e.g. non-finite
+    // network weights) is discarded: X keeps its value from before the cycle, the
+    // true residual below then shows no progress and Jacobi takes over.
+    std::vector<int> dropped;
+    for (int i = 0; i < nf; ++i) {
+      HostSlot& h = L.hs[size_t(fin[i])];
+      if (h.nonfinite && h.mlp) dropped.push_back(fin[i]);
+    }
+    if (!dropped.empty()) {
+      upload(L.d_drop, dropped, s);
+      hipLaunchKernelGGL(drop_cycle_kernel, dim3((unsigned(dropped.size()) + 63) / 64), dim3(64), 0, s, d,
+                         L.d_drop.as<int>(), int(dropped.size()));
+      GFCC_HIP(hipGetLastError());
+    }
     hipLaunchKernelGGL(trisolve_kernel, dim3((nf + 63) / 64), dim3(64), 0, s, d, fl, nf);
     hipLaunchKernelGGL(xupdate_kernel, dim3(L.nch, nf), dim3(VT), 0, s, d, fl, c->ws_in.as<double>(),
                        c->diag.as<double>(), mode, flex);
@@ -1042,6 +1157,8 @@ struct BatchRun {
       HostSlot& h = L.hs[size_t(sl)];
       const double beta = L.hbeta[size_t(i)];  // |r|
       const double rel = beta / h.bn;
+      const bool dropped_cycle = h.nonfinite && h.mlp;
+      h.nonfinite = false;
       const bool finite = std::isfinite(beta);
       gfcc_rhs_info& inf = info[h.rhs];
       inf.iters = h.iters;
@@ -1071,7 +1188,7 @@ struct BatchRun {
         // the learned preconditioner hands over to Jacobi when a cycle stalls: it cut the true
         // residual by less than 10%, or it used the whole restart length without reaching
         // its cycle target
-        if (h.mlp && (!(beta < 0.9 * h.beta) || h.k >= m)) {
+        if (h.mlp && (dropped_cycle || !(beta < 0.9 * h.beta) || h.k >= m)) {
           h.mlp = 0;
           h.fell_back = true;
         }
@@ -1090,12 +1207,11 @@ struct BatchRun {
     }
     if (!again.empty()) {
       const int nr = int(again.size());
-      DBuf d_ag, d_agb, d_agt;
-      upload(d_ag, again, s);
-      upload(d_agb, again_beta, s);
-      upload(d_agt, again_tol, s);
-      hipLaunchKernelGGL(restart_kernel, dim3(L.nch, nr), dim3(VT), 0, s, d, d_ag.as<int>(), d_agb.as<double>(),
-                         d_agt.as<double>(), nr);
+      upload(L.d_ag, again, s);
+      upload(L.d_agb, again_beta, s);
+      upload(L.d_agt, again_tol, s);
+      hipLaunchKernelGGL(restart_kernel, dim3(L.nch, nr), dim3(VT), 0, s, d, L.d_ag.as<int>(), L.d_agb.as<double>(),
+                         L.d_agt.as<double>(), nr);
       GFCC_HIP(hipGetLastError());
       GFCC_HIP(hipStreamSynchronize(s));
     }
@@ -1127,7 +1243,7 @@ struct BatchRun {
       BatchRun* r;
       ~Closer() { r->ckpt_close(); }
     } closer{this};
-    ckpt_open(nrhs);
+    ckpt_open(lanes, nrhs);
     for (auto& L : lanes) setup(L);
     if (opts->tune_cache) {  // ring-GEMM tiles for each full window (inner precision and FP64)
       const Prec ip = prec == GFCC_FP64 ? Prec::F64 : (prec == GFCC_FP32_IR ? Prec::F32 : Prec::BF16);
@@ -1232,6 +1348,7 @@ struct BatchRun {
             HostSlot& h = L->hs[size_t(sl)];
             h.iters += 1;
             h.k += 1;
+            if (L->hflags[i] == 3) h.nonfinite = true;
             if (L->hflags[i] != 0 || h.iters >= opts->max_iter)
               L->pending.push_back(sl);
             else
@@ -1305,6 +1422,7 @@ void solve_multi(int nsys, gfcc_ctx* const* ctxs, int64_t nrhs, const int32_t* s
                  double* G, gfcc_rhs_info* info, hipStream_t s, bool* all_converged) {
   for (int64_t r = 0; r < nrhs; ++r) info[r] = gfcc_rhs_info{1, 0, 0, 0, 0.0};
   BatchRun R = make_run(p, omega, eta, nq, q, opts, G, nullptr, info, s, nullptr);
+  R.sysv = sys;
   std::vector<Lane> lanes(static_cast<size_t>(nsys));
   for (int k = 0; k < nsys; ++k) lanes[size_t(k)].c = ctxs[k];
   for (int64_t r = 0; r < nrhs; ++r) lanes[size_t(sys[r])].rows.push_back(r);

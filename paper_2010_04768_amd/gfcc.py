@@ -28,7 +28,7 @@ SYMBOLS = ["gfcc_build_intermediates", "gfcc_dims", "gfcc_export", "gfcc_sigma",
            "gfcc_last_error", "gfcc_mlp_train", "gfcc_mlp_set_weights", "gfcc_mlp_get_weights",
            "gfcc_mlp_forward", "gfcc_mlp_loss_grad", "gfcc_mlp_features", "gfcc_mlp_apply",
            "gfcc_mor_reset", "gfcc_mor_extend", "gfcc_mor_model", "gfcc_mor_export", "gfcc_mor_greens",
-           "gfcc_solve_shifts", "gfcc_spectral", "gfcc_solve_multi"]
+           "gfcc_solve_shifts", "gfcc_spectral", "gfcc_solve_multi", "gfcc_mlp_adam_step"]
 
 
 class GfccSystem(ctypes.Structure):
@@ -102,7 +102,7 @@ def load():
     L.gfcc_sigma.argtypes = [vp, i64, vp, vp, ctypes.c_int, vp]
     L.gfcc_solve_batch.argtypes = [vp, i64, vp, vp, dbl, i64, vp, ctypes.POINTER(SolveOpts), vp, vp,
                                    ctypes.POINTER(RhsInfo), vp]
-    L.gfcc_greens.argtypes = [vp, i64, vp, i64, vp, vp, vp]
+    L.gfcc_greens.argtypes = [vp, i64, vp, vp, i64, vp, vp, vp]
     L.gfcc_prof_enable.argtypes = [vp, ctypes.c_int]
     L.gfcc_prof_get.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(i64), ctypes.POINTER(dbl),
                                 ctypes.POINTER(dbl), ctypes.POINTER(dbl)]
@@ -117,10 +117,11 @@ def load():
     L.gfcc_mlp_set_weights.argtypes = [vp, ctypes.c_int32, vp, vp]
     L.gfcc_mlp_get_weights.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), vp, vp]
     L.gfcc_mlp_forward.argtypes = [vp, i64, vp, vp, vp]
+    L.gfcc_mlp_adam_step.argtypes = [vp, vp, dbl, vp]
     L.gfcc_mlp_loss_grad.argtypes = [vp, i64, vp, vp, vp, vp, vp]
     L.gfcc_mlp_features.argtypes = [vp, i64, vp, vp, dbl, vp, vp]
     L.gfcc_mlp_apply.argtypes = [vp, i64, vp, vp, dbl, vp, vp]
-    for name in ["gfcc_mlp_train", "gfcc_mlp_set_weights", "gfcc_mlp_get_weights", "gfcc_mlp_forward",
+    for name in ["gfcc_mlp_train", "gfcc_mlp_set_weights", "gfcc_mlp_get_weights", "gfcc_mlp_forward", "gfcc_mlp_adam_step",
                  "gfcc_mlp_loss_grad", "gfcc_mlp_features", "gfcc_mlp_apply"]:
         getattr(L, name).restype = ctypes.c_int
     L.gfcc_solve_shifts.argtypes = [vp, i64, vp, i64, vp, dbl, i64, vp, ctypes.POINTER(ShiftOpts), vp, vp,
@@ -275,8 +276,9 @@ class Context:
     # ---------------------------------------------------------------- solve
     def solve(self, p: Sequence[int], omega: Sequence[float], eta: float, q: Optional[Sequence[int]] = None,
               tol=1e-8, restart=30, max_iter=2000, batch=0, precond="jacobi", precision="fp64",
-              use_graph=False, want_x=False, ir_inner_rtol=0.0, tune_cache=None, checkpoint=None):
-        """Returns (G [nrhs, nq] complex128 device tensor, info list of dicts, X or None)."""
+              use_graph=False, want_x=False, ir_inner_rtol=0.0, tune_cache=None, checkpoint=None, x_out=None):
+        """Returns (G [nrhs, nq] complex128 device tensor, info list of dicts, X or None).
+        `x_out`: caller buffer [nrhs, D] complex128 for X (with want_x; default: a new zero tensor)."""
         import torch
         p_h = np.ascontiguousarray(np.asarray(p, dtype=np.int64))
         w_h = np.ascontiguousarray(np.asarray(omega, dtype=np.float64))
@@ -288,7 +290,10 @@ class Context:
             q_h = np.ascontiguousarray(np.asarray(q, dtype=np.int64))
             nq = q_h.size
         G = torch.zeros((n, nq), dtype=torch.complex128, device=self.device)
-        X = torch.zeros((n, self.dim), dtype=torch.complex128, device=self.device) if want_x else None
+        X = None
+        if want_x:
+            X = x_out if x_out is not None else torch.zeros((n, self.dim), dtype=torch.complex128, device=self.device)
+            assert X.shape == (n, self.dim) and X.dtype == torch.complex128 and X.is_contiguous()
         info = (RhsInfo * max(n, 1))()
         opts = SolveOpts(ctypes.sizeof(SolveOpts), tol, restart, max_iter, batch, PRECONDS[precond],
                          PRECISIONS[precision], int(use_graph),
@@ -343,12 +348,21 @@ class Context:
                   for k in range(nw)] for i in range(npp)]
         return G, infos, X
 
-    def greens(self, X, q):
+    def greens(self, X, q=None, p=None):
+        """G [nrhs, nq] = c_q^T X for a list q, or with q None the diagonal form G[r, 0] = c_{p[r]}^T X[r]."""
         import torch
         X = X.to(device=self.device, dtype=torch.complex128).contiguous()
-        q_h = np.ascontiguousarray(np.asarray(q, dtype=np.int64))
-        G = torch.empty((X.shape[0], q_h.size), dtype=torch.complex128, device=self.device)
-        _check(self._lib.gfcc_greens(self._h, X.shape[0], _ptr(X), q_h.size, q_h.ctypes.data_as(ctypes.c_void_p),
+        if q is None:
+            p_h = np.ascontiguousarray(np.asarray(p, dtype=np.int64))
+            q_h, nq = None, 1
+        else:
+            p_h = None
+            q_h = np.ascontiguousarray(np.asarray(q, dtype=np.int64))
+            nq = q_h.size
+        G = torch.empty((X.shape[0], nq), dtype=torch.complex128, device=self.device)
+        _check(self._lib.gfcc_greens(self._h, X.shape[0], p_h.ctypes.data_as(ctypes.c_void_p) if p_h is not None
+                                     else None, _ptr(X), nq,
+                                     q_h.ctypes.data_as(ctypes.c_void_p) if q_h is not None else None,
                                      _ptr(G), _stream()), "gfcc_greens")
         return G
 
@@ -390,6 +404,13 @@ class Context:
         out = torch.empty(n, dtype=torch.float64, device=self.device)
         _check(self._lib.gfcc_mlp_get_weights(self._h, ctypes.byref(w), _ptr(out), _stream()), "gfcc_mlp_get_weights")
         return W, out
+
+    def mlp_adam_step(self, grad, lr):
+        """One Adam step on the network weights with the flat gradient `grad` (device or host)."""
+        import torch
+        g = torch.as_tensor(np.asarray(grad, dtype=np.float64) if not isinstance(grad, torch.Tensor) else grad)
+        g = g.to(self.device, torch.float64).contiguous()
+        _check(self._lib.gfcc_mlp_adam_step(self._h, _ptr(g), float(lr), _stream()), "gfcc_mlp_adam_step")
 
     def mlp_forward(self, X):
         import torch

@@ -106,3 +106,48 @@ def test_train_and_solve_with_learned_preconditioner(sysctx):
         gref = O.left_vector(s, p[r]) @ x
         assert abs(G[r] - gref) <= 1e-8 * abs(gref)
     print("iterations mlp", [i["iters"] for i in info], "jacobi", [i["iters"] for i in infoj])
+
+
+def test_adam_step_matches_oracle(sysctx):
+    """The library's Adam update against oracle.mlp.adam_step (itself pinned to a two-step
+    example worked by hand and to Adam's closed forms): three steps on fixed gradients of
+    different scales, elementwise to 1e-12 relative to the parameter scale."""
+    s, im, ctx, d, sD = sysctx
+    W = 64
+    p = _params(W, 3)
+    flat0 = M.flatten(p)
+    ctx.mlp_set_weights(W, flat0)  # also resets the moments and the step count
+    rng = np.random.default_rng(17)
+    grads = [rng.normal(size=flat0.size) * np.exp(rng.uniform(-4, 2, size=flat0.size)) for _ in range(3)]
+    ref = {"w": flat0.copy()}
+    st = {}
+    for k, g in enumerate(grads):
+        ctx.mlp_adam_step(g, 3e-3)
+        M.adam_step(ref, {"w": g}, st, 3e-3)
+        _, got = ctx.mlp_get_weights()
+        got = got.cpu().numpy()
+        err = np.abs(got - ref["w"]).max()
+        assert err <= 1e-12 * np.abs(ref["w"]).max(), (k, err)
+    # the update moved every parameter (a dropped step or a zero learning rate would not)
+    assert np.all(np.abs(ref["w"] - flat0) > 0)
+
+
+def test_nonfinite_network_falls_back_to_jacobi(sysctx):
+    """Failure injection: network weights with NaN make every learned-preconditioner cycle
+    non-finite.  The solver discards that cycle, hands the right-hand side to Jacobi (status 4)
+    and still reaches the oracle's G."""
+    s, im, ctx, d, sD = sysctx
+    W = 64
+    p = _params(W, 11)
+    p["W3"][0, 5] = np.nan
+    ctx.mlp_set_weights(W, M.flatten(p))
+    pl = [1, 4, 0]
+    wl = [-0.55, -0.95, -0.35]
+    G, info, _ = ctx.solve(pl, wl, 0.01, tol=1e-10, precond="mlp")
+    G = G.cpu().numpy()[:, 0]
+    for r in range(3):
+        assert info[r]["status"] == 4, info[r]
+        assert info[r]["true_rel_resid"] <= 1e-10
+        x, _, _ = O.solve(s, im, pl[r], wl[r], 0.01, tol=1e-13)
+        gref = O.left_vector(s, pl[r]) @ x
+        assert abs(G[r] - gref) <= 1e-8 * abs(gref)

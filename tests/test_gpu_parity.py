@@ -97,6 +97,11 @@ def test_greens_bilinear(cache):
     G = ctx.greens(torch.from_numpy(X), q).cpu().numpy()
     C = np.stack([O.left_vector(s, qq) for qq in q])
     assert _rel(G, X @ C.T) < 1e-12
+    # diagonal form (q = NULL): G[r] = c_{p_r}^T X[r], virtual orbitals included
+    pd = [3, 0, s.n_occ + 2, 4]
+    Gd = ctx.greens(torch.from_numpy(X), p=pd).cpu().numpy()[:, 0]
+    want = np.array([O.left_vector(s, pd[r]) @ X[r] for r in range(4)])
+    assert _rel(Gd, want) < 1e-12
 
 
 @pytest.mark.parametrize("precond", ["jacobi", "none"])

@@ -81,10 +81,14 @@ def test_repeat_runs_are_bitwise_identical(ctx):
         c2.close()
 
 
+HDR = 24  # resume-file header: magic, version, record size, request fingerprint
+
+
 def test_checkpoint_resume(ctx, tmp_path):
-    """Resume file: every finished right-hand side is appended; a repeated request restores all of
-    them without solving (same bits, same info); a truncated file restores its rows and solves the
-    rest; records of another request (other omega) are ignored."""
+    """Resume file: every finished right-hand side is appended after the header; a repeated
+    request restores all of them without solving (same bits, same info, zero X rows); a
+    truncated file restores its rows and solves the rest; records of other (p, omega) pairs
+    of the same request are ignored."""
     s, c = ctx
     rng = np.random.default_rng(9)
     p = rng.integers(0, s.n_occ, size=16)
@@ -92,17 +96,49 @@ def test_checkpoint_resume(ctx, tmp_path):
     ck = str(tmp_path / "ck.bin")
     G0, i0, _ = c.solve(p, w, 0.01, tol=1e-10, batch=4, checkpoint=ck)
     size = os.path.getsize(ck)
-    assert size % 16 == 0
-    rec = size // 16
-    G1, i1, _ = c.solve(p, w, 0.01, tol=1e-10, batch=4, checkpoint=ck)
+    assert (size - HDR) % 16 == 0
+    rec = (size - HDR) // 16
+    X = torch.full((16, c.dim), 7.0 + 1.0j, dtype=torch.complex128, device=c.device)
+    G1, i1, X1 = c.solve(p, w, 0.01, tol=1e-10, batch=4, checkpoint=ck, want_x=True, x_out=X)
     assert torch.equal(G0, G1) and i0 == i1
+    assert torch.count_nonzero(X1).item() == 0  # restored rows carry no solution: zeros, not stale data
     assert os.path.getsize(ck) == size  # nothing was solved again
     ck2 = str(tmp_path / "ck2.bin")
     with open(ck, "rb") as f, open(ck2, "wb") as g:
-        g.write(f.read(6 * rec + rec // 2))  # six whole records and a torn one
+        g.write(f.read(HDR + 6 * rec + rec // 2))  # header, six whole records and a torn one
     G2, i2, _ = c.solve(p, w, 0.01, tol=1e-10, batch=4, checkpoint=ck2)
     assert all(x["status"] == 0 for x in i2)
     assert (torch.abs(G2 - G0) / torch.abs(G0)).max().item() < 1e-8
     G3, i3, _ = c.solve(p, w + 0.01, 0.01, tol=1e-10, batch=4, checkpoint=ck)
     assert all(x["iters"] > 0 for x in i3)
-    assert os.path.getsize(ck) == 2 * size
+    assert os.path.getsize(ck) == 2 * size - HDR
+
+
+def test_checkpoint_refuses_foreign_and_mismatched_files(ctx, tmp_path):
+    """A file that is not a resume file, or one written for another system, tolerance,
+    precision or q list, is refused with an argument error and left byte for byte unchanged."""
+    s, c = ctx
+    p = [0, 1, 2, 3]
+    w = [-1.0, -0.8, -0.6, -0.4]
+    foreign = tmp_path / "results.txt"
+    foreign.write_bytes(b"omega G\n-1.0 0.5\n" * 40)
+    before = foreign.read_bytes()
+    with pytest.raises(gfcc.GfccError, match="not a resume file"):
+        c.solve(p, w, 0.01, tol=1e-10, checkpoint=str(foreign))
+    assert foreign.read_bytes() == before
+    ck = tmp_path / "ck.bin"
+    c.solve(p, w, 0.01, tol=1e-10, checkpoint=str(ck))
+    good = ck.read_bytes()
+    for kw in (dict(tol=1e-9), dict(tol=1e-10, precision="bf16"), dict(tol=1e-10, q=[0, 1]),
+               dict(tol=1e-10, restart=20)):
+        with pytest.raises(gfcc.GfccError, match="different request"):
+            c.solve(p, w, 0.01, checkpoint=str(ck), **kw)
+        assert ck.read_bytes() == good
+    s2 = make_system(10, 48, 60, 779, sigma_L=0.1, sigma_t1=0.01)  # same shape, other system
+    c2 = gfcc.Context.from_system(s2)
+    try:
+        with pytest.raises(gfcc.GfccError, match="different request"):
+            c2.solve(p, w, 0.01, tol=1e-10, checkpoint=str(ck))
+        assert ck.read_bytes() == good
+    finally:
+        c2.close()
