@@ -170,6 +170,19 @@ gfcc_status gfcc_solve_batch(gfcc_ctx* ctx, int64_t nrhs, const int64_t* p, cons
                              double eta, int64_t nq, const int64_t* q, const gfcc_solve_opts* opts,
                              double* G, double* X, gfcc_rhs_info* info, void* stream);
 
+/* gfcc_greens for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * arguments and results, with every intermediate (the vectors in plane layout,
+ * the left rows, the orbital list, split-K partials) in a fixed 64 MiB device
+ * array that the library holds on each GPU from load until the process ends.
+ * Calls no hipMalloc/hipFree.  E_ARG when the request does not fit the array
+ * (at least one vector's two planes plus the nq left rows, each o + o*o*v
+ * doubles, must fit), E_STATE when the context's device is not current.  Every
+ * call on a GPU shares that GPU's array: calls that overlap on one GPU (other
+ * streams, other threads) race.  Blocking. */
+gfcc_status gfcc_greens_noalloc(gfcc_ctx* ctx, int64_t nrhs, const int64_t* p, const double* X, int64_t nq,
+                                const int64_t* q, double* G, void* stream);
+
 /* ---------------------------------------------------------------------------
  * Multi-shift GMRES (the shifted systems solved together over many frequencies,
  * Introduction and Theory sections).  The Krylov space of (omega - i*eta +

@@ -4,6 +4,8 @@
 #include <cmath>
 #include <cstring>
 #include <exception>
+#include <map>
+#include <mutex>
 #include <string>
 
 #include "ctx.h"
@@ -12,6 +14,30 @@ namespace gfcc {
 static thread_local std::string g_last_error;
 void set_error(const std::string& msg) { g_last_error = msg; }
 }  // namespace gfcc
+
+// ---------------------------------------------------------------- fixed scratch
+// Device memory of the allocation-free entry points: one static array per GPU,
+// held from module load until the process ends.  In host code `scratch` only
+// names the symbol; its address on a device comes from hipGetSymbolAddress with
+// that device current, looked up once per device when a context is built there.
+namespace {
+constexpr size_t kFixedScratchBytes = size_t(64) << 20;  // 64 MiB
+__device__ __align__(256) unsigned char scratch[kFixedScratchBytes];
+
+std::mutex g_scratch_mu;
+std::map<int, void*> g_scratch_of_device;
+
+void* fixed_scratch_address(int dev) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  auto it = g_scratch_of_device.find(dev);
+  if (it != g_scratch_of_device.end()) return it->second;
+  void* ptr = nullptr;
+  GFCC_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+  GFCC_CHECK(ptr != nullptr, GFCC_E_HIP, "hipGetSymbolAddress returned no address for the fixed scratch");
+  g_scratch_of_device[dev] = ptr;
+  return ptr;
+}
+}  // namespace
 
 using namespace gfcc;
 
@@ -62,6 +88,8 @@ gfcc_status gfcc_build_intermediates(const gfcc_system* sys, void* stream, gfcc_
       c->ldz = round_up(c->oov, 8);
       c->lp_ps = round_up(c->oov, 8);
       hipStream_t s = as_stream(stream);
+      GFCC_HIP(hipGetDevice(&c->device));
+      c->fixed_scratch = fixed_scratch_address(c->device);
       build_intermediates(c, sys, s);
       GFCC_HIP(hipStreamSynchronize(s));
     } catch (...) {
@@ -198,6 +226,65 @@ gfcc_status gfcc_greens(gfcc_ctx* c, int64_t nrhs, const int64_t* p, const doubl
       }
     }
     GFCC_HIP(hipStreamSynchronize(s));  // qd and the host lists are released on return
+  });
+}
+
+// gfcc_greens without any device allocation: the vectors' planes, the left rows, the
+// orbital list and the split-K partials live in the fixed scratch array.
+gfcc_status gfcc_greens_noalloc(gfcc_ctx* c, int64_t nrhs, const int64_t* p, const double* X, int64_t nq,
+                                const int64_t* q, double* G, void* stream) {
+  return guarded([&] {
+    GFCC_CHECK(c, GFCC_E_ARG, "null context");
+    GFCC_CHECK(nrhs >= 0 && nq >= 0, GFCC_E_ARG, "negative size");
+    if (nrhs == 0 || nq == 0) return;
+    GFCC_CHECK(X && G, GFCC_E_ARG, "null argument");
+    GFCC_CHECK(q != nullptr || (nq == 1 && p != nullptr), GFCC_E_ARG, "q == NULL requires nq == 1 and p");
+    const int64_t norb = c->o + c->v;
+    if (q)
+      for (int64_t k = 0; k < nq; ++k) GFCC_CHECK(q[k] >= 0 && q[k] < norb, GFCC_E_ARG, "q out of range");
+    else
+      for (int64_t r = 0; r < nrhs; ++r) GFCC_CHECK(p[r] >= 0 && p[r] < norb, GFCC_E_ARG, "p out of range");
+    int dev = -1;
+    GFCC_HIP(hipGetDevice(&dev));
+    GFCC_CHECK(dev == c->device && c->fixed_scratch, GFCC_E_STATE,
+               "the context's device must be current for the allocation-free entry points");
+    hipStream_t s = as_stream(stream);
+    const int64_t Dp = c->Dp;
+    const size_t plane = size_t(Dp) * 8;
+    auto up = [](size_t b) { return (b + 255) / 256 * 256; };
+    // regions: orbital list | left rows | planes of nb vectors | split-K partials
+    const int64_t nrows = q ? nq : 1;   // the diagonal form takes one vector (and row) at a time
+    const int64_t nlist = q ? nq : 1;
+    const size_t list_b = up(size_t(nlist) * 8), rows_b = up(size_t(nrows) * plane);
+    auto need = [&](int64_t nb) {
+      return list_b + rows_b + up(size_t(2 * nb) * plane) + up(size_t(greens_part_doubles(c, nb, nrows)) * 8);
+    };
+    int64_t nb = q ? std::min<int64_t>(nrhs, 64) : 1;
+    while (nb > 1 && need(nb) > kFixedScratchBytes) --nb;
+    GFCC_CHECK(need(nb) <= kFixedScratchBytes, GFCC_E_ARG,
+               "request exceeds the fixed scratch of the allocation-free entry point: " +
+                   std::to_string(need(nb)) + " bytes needed, " + std::to_string(kFixedScratchBytes) + " available");
+    unsigned char* base = static_cast<unsigned char*>(c->fixed_scratch);
+    int64_t* list = reinterpret_cast<int64_t*>(base);
+    double* rows = reinterpret_cast<double*>(base + list_b);
+    double* planes = reinterpret_cast<double*>(base + list_b + rows_b);
+    double* part = reinterpret_cast<double*>(base + list_b + rows_b + up(size_t(2 * nb) * plane));
+    if (q) {
+      GFCC_HIP(hipMemcpyAsync(list, q, size_t(nq) * 8, hipMemcpyHostToDevice, s));
+      make_left_rows(c, nq, list, rows, s);
+    }
+    for (int64_t r0 = 0; r0 < nrhs; r0 += nb) {
+      const int64_t n = std::min(nb, nrhs - r0);
+      if (!q) {
+        GFCC_HIP(hipMemcpyAsync(list, p + r0, 8, hipMemcpyHostToDevice, s));
+        make_left_rows(c, 1, list, rows, s);
+      }
+      // the planes' padding must read as zero: the array keeps the previous call's contents
+      GFCC_HIP(hipMemsetAsync(planes, 0, size_t(2 * n) * plane, s));
+      to_planes(c, n, X + r0 * c->D * 2, planes, s);
+      greens_rows(c, n, planes, nrows, rows, G + r0 * nq * 2, part, s);
+    }
+    GFCC_HIP(hipStreamSynchronize(s));  // the host lists are only read by the copies above
   });
 }
 

@@ -77,6 +77,11 @@ struct gfcc_ctx {
 
   // model-order reduction basis and projected operator
   std::unique_ptr<gfcc::Mor> mor;
+
+  // device of the context and the address there of the library's fixed scratch
+  // array (the allocation-free entry points)
+  int device = -1;
+  void* fixed_scratch = nullptr;
 };
 
 namespace gfcc {
@@ -129,6 +134,10 @@ void spectral(int64_t np, int64_t nw, const double* G, int64_t ld, double eta, d
 // G[r][k] = c_{q_k} . x_r (planes), complex interleaved output
 void greens_planes(gfcc_ctx* c, int64_t nb, const double* planes, int64_t nq, const int64_t* q_dev,
                    double* G, hipStream_t s);
+// the same product with caller-provided left rows and split-K partials (no library buffers)
+int64_t greens_part_doubles(gfcc_ctx* c, int64_t nb, int64_t nq);
+void greens_rows(gfcc_ctx* c, int64_t nb, const double* planes, int64_t nq, const double* rows, double* G,
+                 double* part, hipStream_t s);
 
 // model-order reduction (mor.hip)
 void mor_reset(gfcc_ctx* c);

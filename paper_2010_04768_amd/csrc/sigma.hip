@@ -441,6 +441,38 @@ void make_left_rows(gfcc_ctx* c, int64_t n, const int64_t* orb_dev, double* out,
   GFCC_HIP(hipGetLastError());
 }
 
+// Split-K partials (doubles) of the G product for nb vectors and nq left rows; 0 when
+// the tile grid fills the GPU without splitting K.
+int64_t greens_part_doubles(gfcc_ctx* c, int64_t nb, int64_t nq) {
+  const int sl = splitk_slices(2 * nb, nq, c->Dp);
+  return sl > 1 ? int64_t(sl) * 2 * nb * nq : 0;
+}
+
+// G[r][k] = rows[k] . x_r with caller-provided left rows [nq][Dp] and split-K
+// partials (greens_part_doubles of them; nullptr when that is 0)
+void greens_rows(gfcc_ctx* c, int64_t nb, const double* planes, int64_t nq, const double* rows, double* G,
+                 double* part, hipStream_t s) {
+  if (nb <= 0 || nq <= 0) return;
+  GemmArgs g;
+  g.A = planes;
+  g.am = lin(c->Dp);
+  g.B = rows;
+  g.bm = lin(c->Dp);
+  g.M = 2 * nb;
+  g.N = nq;
+  g.K = c->Dp;
+  g.C = G;
+  g.cm = two(2, 2 * nq, 1);
+  g.cn = lin(2);
+  g.alpha = 1.0;
+  g.beta = 0.0;
+  const int sl = splitk_slices(g.M, g.N, g.K);
+  if (sl <= 1)
+    gemm(Prec::F64, g, gemm_default_cfg(g.M, g.N, g.K), s);
+  else
+    gemm_splitk(Prec::F64, g, sl, part, s);
+}
+
 // G[r][k] = c_{q_k} . x_r  (re from plane 2r, im from plane 2r+1)
 void greens_planes(gfcc_ctx* c, int64_t nb, const double* planes, int64_t nq, const int64_t* q_dev, double* G,
                    hipStream_t s) {

@@ -28,7 +28,8 @@ SYMBOLS = ["gfcc_build_intermediates", "gfcc_dims", "gfcc_export", "gfcc_sigma",
            "gfcc_last_error", "gfcc_mlp_train", "gfcc_mlp_set_weights", "gfcc_mlp_get_weights",
            "gfcc_mlp_forward", "gfcc_mlp_loss_grad", "gfcc_mlp_features", "gfcc_mlp_apply",
            "gfcc_mor_reset", "gfcc_mor_extend", "gfcc_mor_model", "gfcc_mor_export", "gfcc_mor_greens",
-           "gfcc_solve_shifts", "gfcc_spectral", "gfcc_solve_multi", "gfcc_mlp_adam_step"]
+           "gfcc_solve_shifts", "gfcc_spectral", "gfcc_solve_multi", "gfcc_mlp_adam_step",
+           "gfcc_greens_noalloc"]
 
 
 class GfccSystem(ctypes.Structure):
@@ -103,6 +104,8 @@ def load():
     L.gfcc_solve_batch.argtypes = [vp, i64, vp, vp, dbl, i64, vp, ctypes.POINTER(SolveOpts), vp, vp,
                                    ctypes.POINTER(RhsInfo), vp]
     L.gfcc_greens.argtypes = [vp, i64, vp, vp, i64, vp, vp, vp]
+    L.gfcc_greens_noalloc.argtypes = [vp, i64, vp, vp, i64, vp, vp, vp]
+    L.gfcc_greens_noalloc.restype = ctypes.c_int
     L.gfcc_prof_enable.argtypes = [vp, ctypes.c_int]
     L.gfcc_prof_get.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(i64), ctypes.POINTER(dbl),
                                 ctypes.POINTER(dbl), ctypes.POINTER(dbl)]
@@ -348,8 +351,9 @@ class Context:
                   for k in range(nw)] for i in range(npp)]
         return G, infos, X
 
-    def greens(self, X, q=None, p=None):
-        """G [nrhs, nq] = c_q^T X for a list q, or with q None the diagonal form G[r, 0] = c_{p[r]}^T X[r]."""
+    def greens(self, X, q=None, p=None, noalloc=False):
+        """G [nrhs, nq] = c_q^T X for a list q, or with q None the diagonal form G[r, 0] = c_{p[r]}^T X[r].
+        noalloc=True calls the allocation-free entry point (fixed device scratch)."""
         import torch
         X = X.to(device=self.device, dtype=torch.complex128).contiguous()
         if q is None:
@@ -360,10 +364,10 @@ class Context:
             q_h = np.ascontiguousarray(np.asarray(q, dtype=np.int64))
             nq = q_h.size
         G = torch.empty((X.shape[0], nq), dtype=torch.complex128, device=self.device)
-        _check(self._lib.gfcc_greens(self._h, X.shape[0], p_h.ctypes.data_as(ctypes.c_void_p) if p_h is not None
-                                     else None, _ptr(X), nq,
-                                     q_h.ctypes.data_as(ctypes.c_void_p) if q_h is not None else None,
-                                     _ptr(G), _stream()), "gfcc_greens")
+        fn, name = ((self._lib.gfcc_greens_noalloc, "gfcc_greens_noalloc") if noalloc
+                    else (self._lib.gfcc_greens, "gfcc_greens"))
+        _check(fn(self._h, X.shape[0], p_h.ctypes.data_as(ctypes.c_void_p) if p_h is not None else None, _ptr(X),
+                  nq, q_h.ctypes.data_as(ctypes.c_void_p) if q_h is not None else None, _ptr(G), _stream()), name)
         return G
 
     # ---------------------------------------------------------------- timing
