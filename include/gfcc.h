@@ -31,8 +31,9 @@
  *     Entry points return after enqueueing unless stated "blocking".
  *   - Nothing throws across the ABI; every function returns a gfcc_status.
  *     On failure gfcc_last_error() returns a thread-local message.
- *   - Input arrays are borrowed for the duration of the call only (the
- *     context copies what it keeps).  Output arrays are owned by the caller.
+ *   - Input arrays are borrowed for the duration of the call only, except the
+ *     amplitudes t2 and l2 of gfcc_system (borrowed until gfcc_destroy).
+ *     Output arrays are owned by the caller.
  */
 #ifndef GFCC_H
 #define GFCC_H
@@ -67,14 +68,19 @@ typedef enum {
   GFCC_PC_MLP = 2     /* learned residual->correction network, flexible GMRES; Jacobi fallback */
 } gfcc_precond;
 
-/* One closed-shell system.  Device pointers, FP64, borrowed for the call.
+/* One closed-shell system.  Device pointers, FP64.
  *   eps [n]            orbital energies (Fock matrix diag(eps)), occupied first
  *   L   [Q][n][n]      Cholesky vectors, symmetric in (p,q):
  *                      (pq|rs) = sum_Q L[Q][p][q] L[Q][r][s]   (Implementation Details: Cholesky ERIs)
- *   t1  [o][v], t2 [o][o][v][v]   ground-state amplitudes t_i^a, t_ij^ab
- *                      (t2[i][j][a][b] = t2[j][i][b][a])
- *   l1, l2             Lambda amplitudes in the same layout; NULL means
- *                      Lambda = T^dagger (l1 = t1, l2 = t2).               */
+ *   t1  [o][v], t2 [o][o][v][v]   ground-state amplitudes t_i^a, t_ij^ab, with the
+ *                      closed-shell pair symmetry t2[i][j][a][b] = t2[j][i][b][a]
+ *   l1, l2             Lambda amplitudes in the same layout (l2 with the same pair
+ *                      symmetry); NULL means Lambda = T^dagger (l1 = t1, l2 = t2).
+ * Ownership: eps, L, t1 and l1 are read during gfcc_build_intermediates only.
+ * t2, and l2 when it differs from t2, are BORROWED by the context: the sigma
+ * product and the virtual-orbital vectors read them in place (at the C60-shaped
+ * 120/600/3000 system t2 alone is 41.5 GB), so they must stay valid and unchanged
+ * until gfcc_destroy.                                                        */
 typedef struct {
   int64_t n_occ, n_vir, n_chol;
   const double* eps;
@@ -86,14 +92,40 @@ typedef struct {
 } gfcc_system;
 
 /* Build the per-system intermediates (blocks of Hbar_N, its exact diagonal,
- * the left vectors c_q for all occupied q, and reduced-precision copies) on
- * the GPU; the paper precomputes these constant intermediates before the
- * GFCC loop (Implementation Details).  The context also keeps copies of t1, l1
- * and (only when its contents differ from t2) l2 for virtual-orbital right-hand
- * sides and left vectors; nothing of *sys is referenced after the call.
- * Blocking.  *out receives a new context (free it with gfcc_destroy).  Errors:
- * E_ARG for bad dimensions or null pointers, E_OOM when device memory runs out. */
+ * the left vectors c_q for all occupied q; reduced-precision copies follow on
+ * first use) on the GPU; the paper precomputes these constant intermediates
+ * before the GFCC loop (Implementation Details).  The context copies t1 and l1
+ * and borrows t2 (and l2 when its contents differ from t2), see gfcc_system.
+ * Nothing of size o^2 v^2 is stored besides the ring matrix [Wovvo | Wovov]
+ * (2 (ov)^2 doubles); the build's own temporaries are chunked to the free device
+ * memory (gfcc_plan_memory gives the budget).  With the environment variable
+ * GFCC_VERBOSE set the byte budget per operand is printed to stderr before
+ * allocating.  Blocking.  *out receives a new context (free it with
+ * gfcc_destroy).  Errors: E_ARG for bad dimensions or null pointers, E_OOM when
+ * device memory runs out. */
 gfcc_status gfcc_build_intermediates(const gfcc_system* sys, void* stream, gfcc_ctx** out);
+
+/* Device-memory plan of one system in bytes (host arithmetic only, no GPU
+ * needed): the caller's inputs, each operand the context keeps in FP64 and in
+ * the reduced precision `prec`, the build's fixed temporaries and smallest
+ * chunk, and the solver's bytes per slot of a window (restart length,
+ * flexible = 1 for the learned preconditioner's FGMRES) with the sigma operand
+ * copies of `window` slots.  total = the borrowed t2/l2 + context (FP64 +
+ * reduced precision) + window slots + sigma workspace, what a solve holds;
+ * build_peak = all inputs (L included) + FP64 context + the build's fixed
+ * temporaries and smallest chunk. */
+typedef struct {
+  size_t struct_size;                    /* sizeof(gfcc_memory_plan) */
+  double input_L, input_t2, input_l2;    /* caller's buffers (L is read during the build only) */
+  double ring, ladder, wovoo, wooov;     /* [Wovvo|Wovov], Woooo, Wovoo, Wooov */
+  double cholesky, rows_1h, left;        /* Cholesky operands of the three-body term, 1h rows, c_q rows */
+  double vectors, small;                 /* diagonal and other O(D) arrays; one-body blocks */
+  double context_fp64, context_lowp;
+  double build_fixed, build_chunk_min;
+  double per_slot, sigma_workspace, total, build_peak;
+} gfcc_memory_plan;
+gfcc_status gfcc_plan_memory(int64_t n_occ, int64_t n_vir, int64_t n_chol, gfcc_precision prec, int32_t restart,
+                             int32_t flexible, int64_t window, int32_t lambda_given, gfcc_memory_plan* out);
 
 /* Dimensions of the context: D = o + o*o*v, o, v. Host pointers; any may be NULL. */
 gfcc_status gfcc_dims(const gfcc_ctx* ctx, int64_t* D, int64_t* n_occ, int64_t* n_vir);

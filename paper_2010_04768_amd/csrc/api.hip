@@ -83,10 +83,10 @@ gfcc_status gfcc_build_intermediates(const gfcc_system* sys, void* stream, gfcc_
       c->o_pad = round_up(c->o, 8);
       c->Dp = c->o_pad + round_up(c->oov, 8);
       c->kp = round_up(c->ov, 8);
+      c->k2 = 2 * c->kp;
       c->op2 = round_up(c->oo, 8);
       c->vp = round_up(c->v, 8);
-      c->ldz = round_up(c->oov, 8);
-      c->lp_ps = round_up(c->oov, 8);
+      c->Qp = round_up(c->Q, 8);
       hipStream_t s = as_stream(stream);
       GFCC_HIP(hipGetDevice(&c->device));
       c->fixed_scratch = fixed_scratch_address(c->device);
@@ -97,6 +97,39 @@ gfcc_status gfcc_build_intermediates(const gfcc_system* sys, void* stream, gfcc_
       throw;
     }
     *out = c;
+  });
+}
+
+gfcc_status gfcc_plan_memory(int64_t n_occ, int64_t n_vir, int64_t n_chol, gfcc_precision prec, int32_t restart,
+                             int32_t flexible, int64_t window, int32_t lambda_given, gfcc_memory_plan* out) {
+  return guarded([&] {
+    GFCC_CHECK(out && out->struct_size >= sizeof(gfcc_memory_plan), GFCC_E_ARG, "bad plan struct");
+    GFCC_CHECK(n_occ >= 1 && n_vir >= 1 && n_chol >= 1 && window >= 0 && restart >= 1, GFCC_E_ARG, "bad sizes");
+    GFCC_CHECK(prec >= GFCC_FP64 && prec <= GFCC_BF16_IR, GFCC_E_ARG, "bad precision");
+    const MemPlan p = plan_memory(n_occ, n_vir, n_chol, prec, restart, flexible, window, lambda_given != 0);
+    const size_t ss = out->struct_size;
+    *out = gfcc_memory_plan{};
+    out->struct_size = ss;
+    out->input_L = p.input_L;
+    out->input_t2 = p.input_t2;
+    out->input_l2 = p.input_l2;
+    out->ring = p.ring;
+    out->ladder = p.ladder;
+    out->wovoo = p.wovoo;
+    out->wooov = p.wooov;
+    out->cholesky = p.chol;
+    out->rows_1h = p.rows_1h;
+    out->left = p.left;
+    out->vectors = p.vectors;
+    out->small = p.small;
+    out->context_fp64 = p.context_fp64;
+    out->context_lowp = p.context_lowp;
+    out->build_fixed = p.build_fixed;
+    out->build_chunk_min = p.build_chunk_min;
+    out->per_slot = p.per_slot;
+    out->sigma_workspace = p.sigma_ws;
+    out->total = p.total;
+    out->build_peak = p.build_peak;
   });
 }
 
@@ -113,7 +146,8 @@ gfcc_status gfcc_export(gfcc_ctx* c, gfcc_block which, double* dst, void* stream
   return guarded([&] {
     GFCC_CHECK(c && dst, GFCC_E_ARG, "null argument");
     hipStream_t s = as_stream(stream);
-    const int64_t o = c->o, v = c->v, kp = c->kp;
+    const int64_t o = c->o, v = c->v, kp = c->kp, k2 = c->k2;
+    const int id4[4] = {0, 1, 2, 3};
     auto copy = [&](const DBuf& b, int64_t n) {
       GFCC_HIP(hipMemcpyAsync(dst, b.p, size_t(n) * 8, hipMemcpyDeviceToDevice, s));
     };
@@ -121,29 +155,43 @@ gfcc_status gfcc_export(gfcc_ctx* c, gfcc_block which, double* dst, void* stream
       case GFCC_FOO: copy(c->Foo, o * o); break;
       case GFCC_FVV: copy(c->Fvv, v * v); break;
       case GFCC_FOV: copy(c->Fov, o * v); break;
-      case GFCC_WOOOO: copy(c->Woooo, o * o * o * o); break;
-      case GFCC_WOOOV: copy(c->Wooov, o * o * o * v); break;
-      case GFCC_WOVOO: copy(c->Wovoo, o * v * o * o); break;
-      case GFCC_WOVVO: {
-        TView in = tview_s(c->Wvo.as<double>(), {o, v, v, o}, {v, kp, 1, v * kp});
-        TView out = tview(dst, {o, v, v, o});
-        const int id[4] = {0, 1, 2, 3};
-        permute(in, id, 1.0, out, 0.0, s);
+      case GFCC_WOOOO: {  // W4T[(i,j)][(m,n)] -> [m][n][i][j]
+        const int64_t op2 = c->op2;
+        TView in = tview_s(c->W4T.as<double>(), {o, o, o, o}, {o, 1, o * op2, op2});
+        permute(in, id4, 1.0, tview(dst, {o, o, o, o}), 0.0, s);
         break;
       }
-      case GFCC_WOVOV: {
-        TView in = tview_s(c->Wov.as<double>(), {o, v, o, v}, {v, kp, v * kp, 1});
-        TView out = tview(dst, {o, v, o, v});
-        const int id[4] = {0, 1, 2, 3};
-        permute(in, id, 1.0, out, 0.0, s);
-        // remove the folded off-diagonal Foo term  d_ae Foo_off[m,j]
+      case GFCC_WOOOV: copy(c->Wooov, o * o * o * v); break;
+      case GFCC_WOVOO: {  // WovooT[(i,j,a)][m] -> [m][a][i][j]
+        const int64_t op = c->o_pad;
+        TView in = tview_s(c->WovooT.as<double>(), {o, v, o, o}, {1, op, o * v * op, v * op});
+        permute(in, id4, 1.0, tview(dst, {o, v, o, o}), 0.0, s);
+        break;
+      }
+      case GFCC_WOVVO: {  // WW[(j,a)][(m,e)] -> [m][a][e][j]
+        TView in = tview_s(c->WW.as<double>(), {o, v, v, o}, {v, k2, 1, v * k2});
+        permute(in, id4, 1.0, tview(dst, {o, v, v, o}), 0.0, s);
+        break;
+      }
+      case GFCC_WOVOV: {  // WW[(j,a)][kp + (m,e)] -> [m][a][j][e], without the folded one-body terms
+        TView in = tview_s(c->WW.as<double>() + kp, {o, v, o, v}, {v, k2, v * k2, 1});
+        permute(in, id4, 1.0, tview(dst, {o, v, o, v}), 0.0, s);
+        // remove  Foo_off[m,j] d_ae
         const int id3[3] = {0, 1, 2}, id2[2] = {0, 1};
-        TView foo_b = tview_s(c->Foo.as<double>(), {o, v, o}, {1, 0, o});
-        TView foo_d = tview_s(c->Foo.as<double>(), {o, v}, {o + 1, 0});
-        TView o_ae = tview_s(dst, {o, v, o}, {v, o * v + 1, v * o * v});  // [j][a][m] at [m][a][j][a]
-        TView o_d = tview_s(dst, {o, v}, {v * o * v + v, o * v + 1});      // m = j
+        const double* Foo = c->Foo.as<double>();
+        const double* Fvv = c->Fvv.as<double>();
+        TView foo_b = tview_s(const_cast<double*>(Foo), {o, v, o}, {1, 0, o});  // [j][a][m] -> Foo[m][j]
+        TView foo_d = tview_s(const_cast<double*>(Foo), {o, v}, {o + 1, 0});    // [j][a]    -> Foo[j][j]
+        TView o_ae = tview_s(dst, {o, v, o}, {v, o * v + 1, v * o * v});        // [j][a][m] at [m][a][j][a]
+        TView o_d = tview_s(dst, {o, v}, {v * o * v + v, o * v + 1});            // m = j, e = a
         permute(foo_b, id3, -1.0, o_ae, 1.0, s);
         permute(foo_d, id2, 1.0, o_d, 1.0, s);
+        // remove -1/2 Fvv_off[a,e] d_jm
+        TView fvv_b = tview_s(const_cast<double*>(Fvv), {o, v, v}, {0, v, 1});  // [j][a][e] -> Fvv[a][e]
+        TView fvv_d = tview_s(const_cast<double*>(Fvv), {o, v}, {0, v + 1});    // [j][a]    -> Fvv[a][a]
+        TView o_jm = tview_s(dst, {o, v, v}, {v * o * v + v, o * v, 1});        // [j][a][e] at [j][a][j][e]
+        permute(fvv_b, id3, 0.5, o_jm, 1.0, s);
+        permute(fvv_d, id2, -0.5, o_d, 1.0, s);
         break;
       }
       case GFCC_DIAG:

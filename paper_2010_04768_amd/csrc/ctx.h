@@ -18,45 +18,43 @@ struct gfcc_ctx {
   int64_t ov = 0, oo = 0, oov = 0;
   int64_t o_pad = 0;  // start of the 2h1p block inside a plane
   int64_t Dp = 0;     // plane length (re or im part of one vector)
-  int64_t kp = 0;     // padded row length of [ov][ov] ring matrices
+  int64_t kp = 0;     // padded length of an (m,e) index range: round8(o v)
+  int64_t k2 = 0;     // row length of the ring matrix: 2 kp
   int64_t op2 = 0;    // padded row length of [o^2][o^2] / [v][o^2] operands
   int64_t vp = 0;     // padded row length for K = v operands
-  int64_t ldz = 0;    // row length of the three-body matrix [v][o^2 v]
-  int64_t lp_ps = 0;  // plane stride of reduced-precision vector copies
+  int64_t Qp = 0;     // padded Cholesky rank (rows of Q-innermost operands)
+
+  // borrowed inputs (caller memory, valid until gfcc_destroy): t2, and l2 when
+  // Lambda is not T^dagger (else nullptr)
+  const double* t2 = nullptr;
+  const double* l2 = nullptr;
 
   // FP64 blocks (natural layouts, see gfcc_export)
-  gfcc::DBuf Foo, Fvv, Fov, Woooo, Wooov, Wovoo;
-  // ring matrices [(j,a)][(m,e)] with row stride kp:
-  //   Wvo = Wovvo[m,a,e,j],  Wov = Wovov[m,a,j,e],  X1 = 2 Wvo - Wov
-  gfcc::DBuf Wvo, Wov, X1;
+  gfcc::DBuf Foo, Fvv, Fov, Wooov;
+  // ring matrix WW[(j,a)][0:kp) = Wovvo[m,a,e,j], WW[(j,a)][kp:2kp) = Wovov[m,a,j,e] (+ folds),
+  // columns (m,e); sigma's first ring product reads whole rows against [2R - RT | -R]
+  gfcc::DBuf WW;
   gfcc::DBuf W4T;     // [(i,j)][op2]     W4T[(i,j)][(m,n)] = Woooo[m,n,i,j]
-  gfcc::DBuf Zm;      // [v][ldz]         Zm[e][(m,n,f)] = 2(me|nf) - (mf|ne)
-  // [(i,j,a)][ktw]: columns [0, v) t2[i,j,e,a] (three-body), [vp, vp + o) Wovoo[m,a,i,j] (2h1p <- 1h)
-  gfcc::DBuf TW;
-  int64_t ktw = 0;    // vp + o_pad
-  gfcc::DBuf FvvM;    // [a][vp]
-  gfcc::DBuf FooT;    // [i][o_pad]       FooT[i][m] = Foo[m,i]
+  gfcc::DBuf WovooT;  // [(i,j,a)][o_pad] WovooT[(i,j,a)][m] = Wovoo[m,a,i,j]
+  gfcc::DBuf LovC;    // [Q][kp]          L[Q][m][o+e] at column (m,e) (three-body, first half)
+  gfcc::DBuf LovT;    // [v][o][Qp]       L[Q][m][o+e] at [e][m][Q]   (three-body, second half)
   gfcc::DBuf d1b;     // [(i,j,a)]        Fvv[a,a] - Foo[i,i] - Foo[j,j]
-  // note: X1 and Wov also carry the off-diagonal one-body terms (see build.hip)
   gfcc::DBuf Uop;     // [o][Dp]          1h rows of Hbar_N over a plane
   gfcc::DBuf diag;    // [Dp]             exact diagonal (1.0 in padding)
   gfcc::DBuf left;    // [o][Dp]          c_q rows
-  // amplitudes kept for the right-hand sides and left vectors of virtual
-  // orbitals; t2 itself is the first v columns of TW
-  gfcc::DBuf t1c;     // [o][v]
+  gfcc::DBuf t1c;     // [o][v]           amplitudes for virtual-orbital right-hand sides
   gfcc::DBuf l1c;     // [o][v]
-  gfcc::DBuf l2c;     // [o][o][v][v], empty when l2 equals t2 (then TW serves)
 
-  // reduced-precision copies of the two-body operands: [0] FP32, [1] BF16
+  // reduced-precision copies of the two-body operands with power-of-two scales: [0] FP32, [1] BF16
   struct LowPrec {
     bool built = false;
-    gfcc::DBuf X1, Wvo, Wov, W4T, Zm, TW;
-    double sX1 = 1, sWvo = 1, sWov = 1, sW4T = 1, sZm = 1, sTW = 1;  // stored = value * s
+    gfcc::DBuf WW, W4T, WovooT, t2, LovC;
+    double sWW = 1, sW4T = 1, sWovooT = 1, st2 = 1, sLovC = 1;  // stored = value * s
   } lp[2];
 
   // workspaces
   gfcc::Scratch scr;
-  gfcc::DBuf ws_RT, ws_Ra, ws_R, ws_z, ws_zr;  // sigma operand copies
+  gfcc::DBuf ws_A1, ws_RT, ws_Ra, ws_r1, ws_U, ws_z, ws_zl;  // sigma operand copies
   gfcc::DBuf ws_in, ws_out;                 // planes for gfcc_sigma / gfcc_greens
 
   // kernel timing
@@ -106,6 +104,18 @@ void solve_multi(int nsys, gfcc_ctx* const* ctxs, int64_t nrhs, const int32_t* s
 void solve_shifts(gfcc_ctx* c, int64_t np, const int64_t* p, int64_t nw, const double* omega, double eta,
                   int64_t nq, const int64_t* q, const gfcc_shift_opts* o, double* G, double* X,
                   gfcc_rhs_info* info, hipStream_t s, bool* all_converged);
+
+// Device-memory plan of one system (bytes): what the context keeps, what the
+// caller's inputs hold, what the build needs on top, and the solver's share.
+struct MemPlan {
+  double input_L, input_t2, input_l2;
+  double ring, ladder, wovoo, wooov, chol, rows_1h, left, vectors, small;
+  double context_fp64, context_lowp;
+  double build_fixed, build_chunk_min;
+  double per_slot, sigma_ws, total, build_peak;
+};
+MemPlan plan_memory(int64_t o, int64_t v, int64_t Q, int prec, int restart, int flexible, int64_t window,
+                    bool lambda_given);
 
 // Vectors inside the library are "planes": for nb complex vectors, 2*nb planes
 // of Dp doubles (re of vector 0, im of vector 0, re of vector 1, ...).

@@ -12,12 +12,19 @@
 // Hbar_N is real; a complex vector is two real planes, so every term is a
 // real GEMM whose N dimension runs over (vector, re/im, index).
 //
-// The three ring terms are the hot spot (12 o^3 v^2 flops per complex vector):
-//   P1a: s2[(p,i)][(j,a)]  = R [(p,i)][(m,e)] . X1 [(j,a)][(m,e)]^T   (R = r2 rows)
-//   P1b: s2[(p,i)][(j,a)] -= RT[(p,i)][(m,e)] . Wvo[(j,a)][(m,e)]^T   (RT[i][m][e] = r2[m][i][e])
-//   P2 : s2[(p,j)][(i,a)] -= RT[(p,j)][(m,e)] . Wov[(i,a)][(m,e)]^T   (scattered store)
-// In FP32/BF16 mode these three and the hole-hole ladder and z contraction
-// read reduced-precision copies; the one-body terms stay FP64.
+// The ring terms are the hot spot (12 o^3 v^2 flops per complex vector), two GEMMs
+// against the ring matrix WW[(j,a)] = [Wovvo | Wovov] (one-body terms folded in):
+//   P1: s2[(p,i)][(j,a)] += [2R - RT | -R][(p,i)] . WW[(j,a)]^T    (K = 2 o v)
+//       (2 Wovvo - Wovov) R - Wovvo RT = Wovvo (2R - RT) - Wovov R,  R[(p,i)][(m,e)] = r2[i][m][e],
+//       RT[(p,i)][(m,e)] = r2[m][i][e]
+//   P2: s2[(p,j)][(i,a)] -= RT[(p,j)] . Wovov[(i,a)]^T                 (scattered store)
+// The three-body z goes through the Cholesky vectors: with
+//   U[(p,m)][Q] = sum_(n,f) (2R - RT)[(p,m)][(n,f)] L[Q][n][o+f]   (the first half of P1's operand)
+//   z[p][e]     = sum_(m,Q) U[(p,m)][Q] L[Q][m][o+e]
+// and s2[p][(i,j,a)] -= sum_e z[p][e] t2[j][i][a][e] (t_ij^ea = t_ji^ae) reads the
+// caller's t2 in place, one occupied i per batch.
+// In FP32/BF16 mode the ring, ladder, U, three-body and 2h1p <- 1h products read
+// reduced-precision copies; the one-body diagonal, z and the 1h rows stay FP64.
 #include <algorithm>
 #include <cstring>
 #include <string>
@@ -31,22 +38,39 @@ template <> __device__ __forceinline__ double cvt<double>(double x) { return x; 
 template <> __device__ __forceinline__ float cvt<float>(double x) { return float(x); }
 template <> __device__ __forceinline__ __bf16 cvt<__bf16>(double x) { return __bf16(float(x)); }
 
-// RT[p][i*ov + m*v + e] = x[p*Dp + o_pad + m*ov + i*v + e]   (and R when R != nullptr)
-// and the FP64 diagonal one-body part  y2[p][t] = d1b[t] x2[p][t]  (initialises y2)
+// Per plane p and element t = (i, m, e) of the 2h1p block:
+//   A1[(p,i)][(m,e)] = 2 r[i][m][e] - r[m][i][e],  A1[(p,i)][kp + (m,e)] = -r[i][m][e]  (row stride k2)
+//   RT[(p,i)][(m,e)] = r[m][i][e]                                                      (row stride kp)
+//   y2[p][t] = d1b[t] x2[p][t]   (FP64 diagonal one-body part; initialises y2)
+// and r1l[p][m] = r1[p][m] (reduced-precision copy of the 1h part, row stride o_pad).
 template <typename T>
-__global__ void make_rt_kernel(const double* __restrict__ x, T* __restrict__ RT, T* __restrict__ R,
-                               double* __restrict__ y, const double* __restrict__ d1b, int64_t o, int64_t v,
-                               int64_t Dp, int64_t o_pad, int64_t ps) {
+__global__ void make_ops_kernel(const double* __restrict__ x, T* __restrict__ A1, T* __restrict__ RT,
+                                T* __restrict__ r1l, double* __restrict__ y, const double* __restrict__ d1b, int64_t o,
+                                int64_t v, int64_t Dp, int64_t o_pad, int64_t kp, int64_t k2) {
   const int64_t oov = o * o * v, ov = o * v;
   const int64_t p = blockIdx.y;
   const double* xp = x + p * Dp + o_pad;
   double* yp = y + p * Dp + o_pad;
-  for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < oov; t += int64_t(gridDim.x) * blockDim.x) {
-    const int64_t e = t % v, m = (t / v) % o, i = t / ov;  // output order [i][m][e]
-    RT[p * ps + t] = cvt<T>(xp[m * ov + i * v + e]);
-    const double xt = xp[t];
-    if (R) R[p * ps + t] = cvt<T>(xt);
-    yp[t] = d1b[t] * xt;
+  const int64_t gid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (r1l && gid < o) r1l[p * o_pad + gid] = cvt<T>(x[p * Dp + gid]);
+  for (int64_t t = gid; t < oov; t += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t e = t % v, m = (t / v) % o, i = t / ov;
+    const int64_t me = m * v + e;
+    const double r = xp[t];
+    const double rt = xp[m * ov + i * v + e];
+    T* a = A1 + (p * o + i) * k2;
+    a[me] = cvt<T>(2.0 * r - rt);
+    a[kp + me] = cvt<T>(-r);
+    RT[(p * o + i) * kp + me] = cvt<T>(rt);
+    yp[t] = d1b[t] * r;
+  }
+  // padding columns of both halves: the products read them (K = kp, 2 kp), and the buffer
+  // is shared with copies in other precisions, so stale bytes must not stay there
+  const int64_t pad = kp - ov;
+  for (int64_t t = gid; t < o * pad; t += int64_t(gridDim.x) * blockDim.x) {
+    T* a = A1 + (p * o + t / pad) * k2 + ov + t % pad;
+    a[0] = cvt<T>(0.0);
+    a[kp] = cvt<T>(0.0);
   }
 }
 
@@ -69,134 +93,123 @@ __global__ void make_ra_kernel(const double* __restrict__ x, T* __restrict__ Ra,
   }
 }
 
+template <typename T>
+__global__ void to_prec_kernel(const double* __restrict__ src, T* __restrict__ dst, int64_t n) {
+  for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < n; t += int64_t(gridDim.x) * blockDim.x)
+    dst[t] = cvt<T>(src[t]);
+}
+
 static unsigned blocks_for(int64_t n) {
   return unsigned(std::min<int64_t>(std::max<int64_t>((n + 255) / 256, 1), 4096));
 }
 
-// A[p][k] of the fused three-body + 2h1p<-1h GEMM: [z_p (v) | 0 | r1_p (o) | 0], row stride ktw
 template <typename T>
-__global__ void make_zr_kernel(const double* __restrict__ z, const double* __restrict__ x, T* __restrict__ A,
-                               int64_t v, int64_t vp, int64_t o, int64_t ktw, int64_t Dp) {
-  const int64_t p = blockIdx.x;
-  for (int64_t k = threadIdx.x; k < ktw; k += blockDim.x) {
-    double val = 0.0;
-    if (k < v)
-      val = z[p * vp + k];
-    else if (k >= vp && k < vp + o)
-      val = x[p * Dp + (k - vp)];
-    A[p * ktw + k] = cvt<T>(val);
-  }
-}
-
-template <typename T>
-static void make_operands(gfcc_ctx* c, int64_t P, const double* x, T* RT, T* R, T* Ra, int64_t ps, double* y,
-                          hipStream_t s) {
+static void make_operands(gfcc_ctx* c, int64_t P, const double* x, bool lowp, double* y, hipStream_t s) {
   const int64_t oov = c->oov;
-  hipLaunchKernelGGL((make_rt_kernel<T>), dim3(std::min<int64_t>((oov + 255) / 256, 1024), unsigned(P)),
-                     dim3(256), 0, s, x, RT, R, y, c->d1b.as<double>(), c->o, c->v, c->Dp, c->o_pad, ps);
+  hipLaunchKernelGGL((make_ops_kernel<T>), dim3(std::min<int64_t>((oov + 255) / 256, 1024), unsigned(P)), dim3(256),
+                     0, s, x, c->ws_A1.as<T>(), c->ws_RT.as<T>(), lowp ? c->ws_r1.as<T>() : nullptr, y,
+                     c->d1b.as<double>(), c->o, c->v, c->Dp, c->o_pad, c->kp, c->k2);
   GFCC_HIP(hipGetLastError());
   dim3 g(unsigned((c->oo + 31) / 32), unsigned((c->v + 31) / 32), unsigned(P));
-  hipLaunchKernelGGL((make_ra_kernel<T>), g, dim3(32, 8), 0, s, x, Ra, c->oo, c->v, c->Dp, c->o_pad, c->op2);
+  hipLaunchKernelGGL((make_ra_kernel<T>), g, dim3(32, 8), 0, s, x, c->ws_Ra.as<T>(), c->oo, c->v, c->Dp, c->o_pad,
+                     c->op2);
   GFCC_HIP(hipGetLastError());
 }
 
-// phases of one sigma: operand copies, the three ring GEMMs, everything else
+// phases of one sigma: operand copies, the two ring GEMMs, everything else
 enum : int { PH_OPS = 1, PH_RING = 2, PH_REST = 4, PH_ALL = 7 };
 
-// With ring_out != nullptr the ring phase returns its three GEMMs (and tile)
+// With ring_out != nullptr the ring phase returns its two GEMMs (and tiles)
 // instead of launching them, for a grouped launch over several systems.
 static void sigma_impl(gfcc_ctx* c, int64_t P, const double* x, double* y, gfcc_precision prec, hipStream_t s,
                        int phases, GemmArgs* ring_out, int* ring_cfg) {
   if (P <= 0) return;
   const int64_t o = c->o, v = c->v, ov = c->ov, oo = c->oo, oov = c->oov;
-  const int64_t Dp = c->Dp, op = c->o_pad, kp = c->kp;
+  const int64_t Dp = c->Dp, op = c->o_pad, kp = c->kp, k2 = c->k2, Qp = c->Qp, Q = c->Q;
   const bool lowp = prec != GFCC_FP64;
   const int li = (prec == GFCC_BF16_IR) ? 1 : 0;
   const Prec rp = !lowp ? Prec::F64 : (li ? Prec::BF16 : Prec::F32);
   const int64_t esz = !lowp ? 8 : (li ? 2 : 4);
   if (lowp) build_lowprec(c, li, s);
-  const int64_t ps = round_up(oov, 8);  // plane stride of operand copies
-  c->ws_RT.ensure(size_t(P * ps * esz), s);
+  c->ws_A1.ensure(size_t(P * o * k2 * esz), s);
+  c->ws_RT.ensure(size_t(P * o * kp * esz), s);
   c->ws_Ra.ensure(size_t(P * v * c->op2 * esz), s);
-  if (lowp) c->ws_R.ensure(size_t(P * ps * esz), s);
-  c->ws_z.ensure(size_t(P * c->vp * 8), s);
+  if (lowp) c->ws_r1.ensure(size_t(P * op * esz), s);
+  c->ws_U.ensure(size_t(P * o * Qp) * 8, s);
+  c->ws_z.ensure(size_t(P * c->vp) * 8, s);
+  if (lowp) c->ws_zl.ensure(size_t(P * c->vp * esz), s);
 
   const bool whole = phases == PH_ALL;
   if (whole) prof_begin(c, "sigma", s);
   if (phases & PH_OPS) {
     switch (rp) {
-      case Prec::F64:
-        make_operands<double>(c, P, x, c->ws_RT.as<double>(), nullptr, c->ws_Ra.as<double>(), ps, y, s);
-        break;
-      case Prec::F32:
-        make_operands<float>(c, P, x, c->ws_RT.as<float>(), c->ws_R.as<float>(), c->ws_Ra.as<float>(), ps, y, s);
-        break;
-      case Prec::BF16:
-        make_operands<__bf16>(c, P, x, c->ws_RT.as<__bf16>(), c->ws_R.as<__bf16>(), c->ws_Ra.as<__bf16>(), ps, y,
-                               s);
-        break;
+      case Prec::F64: make_operands<double>(c, P, x, false, y, s); break;
+      case Prec::F32: make_operands<float>(c, P, x, true, y, s); break;
+      case Prec::BF16: make_operands<__bf16>(c, P, x, true, y, s); break;
     }
   }
   const auto& L = c->lp[li];
-  const void* X1 = lowp ? L.X1.p : c->X1.p;
-  const void* Wvo = lowp ? L.Wvo.p : c->Wvo.p;
-  const void* Wov = lowp ? L.Wov.p : c->Wov.p;
+  const void* WWp = lowp ? L.WW.p : c->WW.p;
   const void* W4T = lowp ? L.W4T.p : c->W4T.p;
-  const void* Zm = lowp ? L.Zm.p : c->Zm.p;
-  const double sX1 = lowp ? 1.0 / L.sX1 : 1.0, sWvo = lowp ? 1.0 / L.sWvo : 1.0;
-  const double sWov = lowp ? 1.0 / L.sWov : 1.0, sW4T = lowp ? 1.0 / L.sW4T : 1.0;
-  const double sZm = lowp ? 1.0 / L.sZm : 1.0;
+  const void* WovooT = lowp ? L.WovooT.p : c->WovooT.p;
+  const void* t2p = lowp ? L.t2.p : static_cast<const void*>(c->t2);
+  const void* LovC = lowp ? L.LovC.p : c->LovC.p;
+  const double sWW = lowp ? 1.0 / L.sWW : 1.0, sW4T = lowp ? 1.0 / L.sW4T : 1.0;
+  const double sWovoo = lowp ? 1.0 / L.sWovooT : 1.0, st2 = lowp ? 1.0 / L.st2 : 1.0;
+  const double sLovC = lowp ? 1.0 / L.sLovC : 1.0;
 
-  const double ring_flops = 2.0 * double(P) * double(o) * double(ov) * double(ov);
+  const double ring1 = 2.0 * double(P) * double(o) * double(ov) * double(ov);  // flops of one (m,e) half
   const char* ring_name = !lowp ? "ring_gemm_fp64" : (li ? "ring_gemm_bf16" : "ring_gemm_fp32");
-  const double ring_bytes = double(ov) * double(kp) * esz + 2.0 * double(P) * double(o) * double(ov) * (esz + 8.0);
+  const double c_rw = 2.0 * double(P) * double(o) * double(ov) * 8.0;  // read + write of the FP64 output
 
   // ---- ring terms
   if (phases & PH_RING) {
     GemmArgs g;
+    // P1: s2[(p,i)][(j,a)] += [2R - RT | -R] . WW^T
+    g.A = c->ws_A1.p;
+    g.am = lin(k2);
+    g.B = WWp;
+    g.bm = lin(k2);
     g.M = P * o;
     g.N = ov;
-    g.K = ov;
+    g.K = k2;
     g.C = y + op;
     g.cm = two(o, Dp, ov);
     g.cn = lin(1);
-    const int cfg = tuned_cfg(c, rp, g.M, g.N, g.K);
-    // P1a
-    if (lowp) {
-      g.A = c->ws_R.p;
-      g.am = two(o, ps, ov);
-    } else {
-      g.A = x + op;
-      g.am = two(o, Dp, ov);
-    }
-    g.B = X1;
-    g.bm = lin(kp);
-    g.alpha = sX1;
+    g.alpha = sWW;
     g.beta = 1.0;  // y2 holds the diagonal one-body part
-    auto run = [&](int k) {
-      if (ring_out) {
-        ring_out[k] = g;
-        *ring_cfg = cfg;
-        return;
-      }
+    const int cfg1 = tuned_cfg(c, rp, g.M, g.N, g.K);
+    if (ring_out) {
+      ring_out[0] = g;
+      ring_cfg[0] = cfg1;
+    } else {
       prof_begin(c, ring_name, s);
-      gemm(rp, g, cfg, s);
-      prof_end(c, ring_name, s, ring_flops, ring_bytes);
-    };
-    run(0);
-    // P1b
-    g.A = c->ws_RT.p;
-    g.am = two(o, ps, ov);
-    g.B = Wvo;
-    g.alpha = -sWvo;
-    g.beta = 1.0;
-    run(1);
+      gemm(rp, g, cfg1, s);
+      prof_end(c, ring_name, s, 2.0 * ring1, double(ov) * 2.0 * ov * esz + double(P) * o * 2.0 * ov * esz + c_rw);
+    }
     // P2: rows (p, j), cols (i, a) -> s2[p][i][j][a]
-    g.B = Wov;
-    g.alpha = -sWov;
-    g.cm = two(o, Dp, v);
-    g.cn = two(v, ov, 1);
-    run(2);
+    GemmArgs h;
+    h.A = c->ws_RT.p;
+    h.am = lin(kp);
+    h.B = static_cast<const char*>(WWp) + kp * esz;
+    h.bm = lin(k2);
+    h.M = P * o;
+    h.N = ov;
+    h.K = ov;
+    h.C = y + op;
+    h.cm = two(o, Dp, v);
+    h.cn = two(v, ov, 1);
+    h.alpha = -sWW;
+    h.beta = 1.0;
+    const int cfg2 = tuned_cfg(c, rp, h.M, h.N, h.K);
+    if (ring_out) {
+      ring_out[1] = h;
+      ring_cfg[1] = cfg2;
+    } else {
+      prof_begin(c, ring_name, s);
+      gemm(rp, h, cfg2, s);
+      prof_end(c, ring_name, s, ring1, double(ov) * ov * esz + double(P) * o * ov * esz + c_rw);
+    }
   }
   if (!(phases & PH_REST)) return;
   // ---- hole-hole ladder: s2[p][(i,j)][a] += sum_(mn) W4T[(i,j)][(m,n)] Ra[(p,a)][(m,n)]
@@ -216,62 +229,90 @@ static void sigma_impl(gfcc_ctx* c, int64_t P, const double* x, double* y, gfcc_
     g.beta = 1.0;
     gemm(rp, g, tuned_cfg(c, rp, g.M, g.N, g.K), s);
   }
-  // ---- three-body: z[p][e] = sum_(mnf) Zm[e][(m,n,f)] r2[p][(m,n,f)];  s2 -= z . t2
+  // ---- three-body: U = (2R - RT) . LovC^T (inner precision), z = U . LovT^T (FP64)
+  {
+    GemmArgs g;
+    g.A = c->ws_A1.p;
+    g.am = lin(k2);
+    g.B = LovC;
+    g.bm = lin(kp);
+    g.M = P * o;
+    g.N = Q;
+    g.K = kp;
+    g.C = c->ws_U.as<double>();
+    g.cm = lin(Qp);
+    g.cn = lin(1);
+    g.alpha = sLovC;
+    g.beta = 0.0;
+    gemm(rp, g, tuned_cfg(c, rp, g.M, g.N, g.K), s);
+    GemmArgs h;
+    h.A = c->ws_U.p;
+    h.am = lin(o * Qp);
+    h.B = c->LovT.p;
+    h.bm = lin(o * Qp);
+    h.M = P;
+    h.N = v;
+    h.K = o * Qp;
+    h.C = c->ws_z.as<double>();
+    h.cm = lin(c->vp);
+    h.cn = lin(1);
+    h.alpha = 1.0;
+    h.beta = 0.0;
+    gemm_auto(Prec::F64, h, c->scr, 0, s);
+  }
+  // ---- three-body second half: s2[p][(i,j,a)] -= sum_e z[p][e] t2[j][i][a][e], batched over i
+  {
+    const void* zA = c->ws_z.p;
+    if (lowp) {
+      const int64_t nz = P * c->vp;
+      if (li)
+        hipLaunchKernelGGL((to_prec_kernel<__bf16>), dim3(blocks_for(nz)), dim3(256), 0, s, c->ws_z.as<double>(),
+                           c->ws_zl.as<__bf16>(), nz);
+      else
+        hipLaunchKernelGGL((to_prec_kernel<float>), dim3(blocks_for(nz)), dim3(256), 0, s, c->ws_z.as<double>(),
+                           c->ws_zl.as<float>(), nz);
+      GFCC_HIP(hipGetLastError());
+      zA = c->ws_zl.p;
+    }
+    GemmArgs g;
+    g.A = zA;
+    g.am = lin(c->vp);
+    g.B = t2p;
+    g.bm = two(v, o * v * v, v);
+    g.M = P;
+    g.N = ov;
+    g.K = v;
+    g.C = y + op;
+    g.cm = lin(Dp);
+    g.cn = lin(1);
+    g.batch = int(o);
+    g.bz = lin(v * v);
+    g.cz = lin(ov);
+    g.alpha = -st2;
+    g.beta = 1.0;
+    gemm(rp, g, gemm_default_cfg(g.M, g.N, g.K), s);
+  }
+  // ---- 2h1p <- 1h: s2[p][(i,j,a)] -= sum_m r1[p][m] Wovoo[m,a,i,j]
   {
     GemmArgs g;
     if (lowp) {
-      g.A = c->ws_R.p;
-      g.am = lin(ps);
+      g.A = c->ws_r1.p;
+      g.am = lin(op);
     } else {
-      g.A = x + op;
+      g.A = x;
       g.am = lin(Dp);
     }
-    g.B = Zm;
-    g.bm = lin(c->ldz);
+    g.B = WovooT;
+    g.bm = lin(op);
     g.M = P;
-    g.N = v;
-    g.K = oov;
-    g.C = c->ws_z.as<double>();
-    g.cm = lin(c->vp);
+    g.N = oov;
+    g.K = o;
+    g.C = y + op;
+    g.cm = lin(Dp);
     g.cn = lin(1);
-    g.alpha = sZm;
-    g.beta = 0.0;
-    gemm_auto(rp, g, c->scr, 0, s);
-  }
-  // ---- three-body second half and 2h1p <- 1h in one GEMM:
-  //      s2[p][(i,j,a)] -= sum_e z[p][e] t2[i,j,e,a] + sum_m r1[p][m] Wovoo[m,a,i,j]
-  {
-    const int64_t ktw = c->ktw;
-    c->ws_zr.ensure(size_t(P * ktw * esz), s);
-    switch (rp) {
-      case Prec::F64:
-        hipLaunchKernelGGL((make_zr_kernel<double>), dim3(unsigned(P)), dim3(256), 0, s, c->ws_z.as<double>(), x,
-                           c->ws_zr.as<double>(), v, c->vp, o, ktw, Dp);
-        break;
-      case Prec::F32:
-        hipLaunchKernelGGL((make_zr_kernel<float>), dim3(unsigned(P)), dim3(256), 0, s, c->ws_z.as<double>(), x,
-                           c->ws_zr.as<float>(), v, c->vp, o, ktw, Dp);
-        break;
-      case Prec::BF16:
-        hipLaunchKernelGGL((make_zr_kernel<__bf16>), dim3(unsigned(P)), dim3(256), 0, s, c->ws_z.as<double>(), x,
-                           c->ws_zr.as<__bf16>(), v, c->vp, o, ktw, Dp);
-        break;
-    }
-    GFCC_HIP(hipGetLastError());
-    GemmArgs h;
-    h.A = c->ws_zr.p;
-    h.am = lin(ktw);
-    h.B = lowp ? L.TW.p : c->TW.p;
-    h.bm = lin(ktw);
-    h.M = P;
-    h.N = oov;
-    h.K = ktw;
-    h.C = y + op;
-    h.cm = lin(Dp);
-    h.cn = lin(1);
-    h.alpha = lowp ? -1.0 / L.sTW : -1.0;
-    h.beta = 1.0;
-    gemm(rp, h, tuned_cfg(c, rp, h.M, h.N, h.K), s);
+    g.alpha = -sWovoo;
+    g.beta = 1.0;
+    gemm(rp, g, tuned_cfg(c, rp, g.M, g.N, g.K), s);
   }
   // ---- 1h rows: s1[p][i] = sum_k x[p][k] Uop[i][k]   (FP64)
   {
@@ -290,9 +331,9 @@ static void sigma_impl(gfcc_ctx* c, int64_t P, const double* x, double* y, gfcc_
     g.beta = 0.0;
     gemm_auto(Prec::F64, g, c->scr, 0, s);
   }
-  const double total_flops = 3.0 * ring_flops + 2.0 * double(P) * (double(oo) * oo * v + 2.0 * oov * v +
-                                                                    double(oov) * v + double(oov) * o +
-                                                                    2.0 * double(oov) * o + double(Dp) * o);
+  const double total_flops = 3.0 * ring1 + 2.0 * double(P) * (double(oo) * oo * v + double(o) * Q * ov +
+                                                              double(o) * Q * v + double(oov) * v + double(oov) * o +
+                                                              double(Dp) * o);
   if (whole) prof_end(c, "sigma", s, total_flops, 0.0);
 }
 
@@ -310,25 +351,26 @@ void sigma_group(const SigmaJob* jobs, int nj, gfcc_precision prec, hipStream_t 
     return;
   }
   const Prec rp = prec == GFCC_FP64 ? Prec::F64 : (prec == GFCC_BF16_IR ? Prec::BF16 : Prec::F32);
-  GemmArgs ring[3][MAX_GEMM_GROUPS];
-  int ng = 0, cfg = 0;
+  GemmArgs ring[2][MAX_GEMM_GROUPS];
+  int ng = 0, cfg[2] = {0, 0};
   double best = -1.0;
   for (int j = 0; j < nj; ++j) {
     const SigmaJob& J = jobs[j];
     if (J.P <= 0) continue;
     sigma_impl(J.c, J.P, J.x, J.y, prec, s, PH_OPS, nullptr, nullptr);
-    GemmArgs g3[3];
-    int cj = 0;
-    sigma_impl(J.c, J.P, J.x, J.y, prec, s, PH_RING, g3, &cj);
-    for (int t = 0; t < 3; ++t) ring[t][ng] = g3[t];
-    const double size = double(g3[0].M) * double(g3[0].N);
+    GemmArgs g2[2];
+    int cj[2] = {0, 0};
+    sigma_impl(J.c, J.P, J.x, J.y, prec, s, PH_RING, g2, cj);
+    for (int t = 0; t < 2; ++t) ring[t][ng] = g2[t];
+    const double size = double(g2[0].M) * double(g2[0].N);
     if (size > best) {
       best = size;
-      cfg = cj;
+      cfg[0] = cj[0];
+      cfg[1] = cj[1];
     }
     ++ng;
   }
-  for (int t = 0; t < 3; ++t) gemm_grouped(rp, ring[t], ng, cfg, s);
+  for (int t = 0; t < 2; ++t) gemm_grouped(rp, ring[t], ng, cfg[t], s);
   for (int j = 0; j < nj; ++j)
     if (jobs[j].P > 0) sigma_impl(jobs[j].c, jobs[j].P, jobs[j].x, jobs[j].y, prec, s, PH_REST, nullptr, nullptr);
 }
@@ -374,8 +416,8 @@ void from_planes(gfcc_ctx* c, int64_t nb, const double* planes, double* xi, hipS
 // e_p; virtual p (a = p - o) gives [a_p, T]|Phi>: b(1h)_i = t_i^a and, in the
 // doublet basis, b(2h1p)_ijb = t_ij^ab.
 __global__ void rhs_rows_kernel(const int64_t* __restrict__ orb, const double* __restrict__ t1,
-                                const double* __restrict__ TW, int64_t ktw, double* __restrict__ out, int64_t o,
-                                int64_t v, int64_t o_pad, int64_t Dp) {
+                                const double* __restrict__ t2, double* __restrict__ out, int64_t o, int64_t v,
+                                int64_t o_pad, int64_t Dp) {
   const int64_t r = blockIdx.y;
   const int64_t p = orb[r];
   const int64_t oov = o * o * v;
@@ -386,10 +428,12 @@ __global__ void rhs_rows_kernel(const int64_t* __restrict__ orb, const double* _
       val = (t == p) ? 1.0 : 0.0;
     } else {
       const int64_t a = p - o;
-      if (t < o)
+      if (t < o) {
         val = t1[t * v + a];
-      else if (t >= o_pad && t - o_pad < oov)
-        val = TW[(t - o_pad) * ktw + a];  // t2[i, j, a, b] at row (i, j, b)
+      } else if (t >= o_pad && t - o_pad < oov) {
+        const int64_t idx = t - o_pad, ij = idx / v, b = idx % v;
+        val = t2[(ij * v + a) * v + b];  // t2[i, j, a, b] at row (i, j, b)
+      }
     }
     row[t] = val;
   }
@@ -400,8 +444,7 @@ __global__ void rhs_rows_kernel(const int64_t* __restrict__ orb, const double* _
 // c(1h)_i = l_i^a, c(2h1p)_klc = 2 l_kl^ac - l_kl^ca.
 __global__ void left_rows_kernel(const int64_t* __restrict__ orb, const double* __restrict__ left_occ,
                                  const double* __restrict__ l1, const double* __restrict__ l2,
-                                 const double* __restrict__ TW, int64_t ktw, double* __restrict__ out, int64_t o,
-                                 int64_t v, int64_t o_pad, int64_t Dp) {
+                                 double* __restrict__ out, int64_t o, int64_t v, int64_t o_pad, int64_t Dp) {
   const int64_t r = blockIdx.y;
   const int64_t q = orb[r];
   const int64_t oov = o * o * v;
@@ -416,10 +459,7 @@ __global__ void left_rows_kernel(const int64_t* __restrict__ orb, const double* 
         val = l1[t * v + a];
       } else if (t >= o_pad && t - o_pad < oov) {
         const int64_t idx = t - o_pad, kl = idx / v, cc = idx % v;  // (k, l, c)
-        if (l2)
-          val = 2.0 * l2[(kl * v + a) * v + cc] - l2[(kl * v + cc) * v + a];
-        else  // l2 = t2: l2[k, l, a, c] at TW row (k, l, c), column a
-          val = 2.0 * TW[idx * ktw + a] - TW[(kl * v + a) * ktw + cc];
+        val = 2.0 * l2[(kl * v + a) * v + cc] - l2[(kl * v + cc) * v + a];
       }
     }
     row[t] = val;
@@ -429,15 +469,15 @@ __global__ void left_rows_kernel(const int64_t* __restrict__ orb, const double* 
 void make_rhs_rows(gfcc_ctx* c, int64_t n, const int64_t* orb_dev, double* out, hipStream_t s) {
   if (n <= 0) return;
   hipLaunchKernelGGL(rhs_rows_kernel, dim3(blocks_for(c->Dp), unsigned(n)), dim3(256), 0, s, orb_dev,
-                     c->t1c.as<double>(), c->TW.as<double>(), c->ktw, out, c->o, c->v, c->o_pad, c->Dp);
+                     c->t1c.as<double>(), c->t2, out, c->o, c->v, c->o_pad, c->Dp);
   GFCC_HIP(hipGetLastError());
 }
 
 void make_left_rows(gfcc_ctx* c, int64_t n, const int64_t* orb_dev, double* out, hipStream_t s) {
   if (n <= 0) return;
   hipLaunchKernelGGL(left_rows_kernel, dim3(blocks_for(c->Dp), unsigned(n)), dim3(256), 0, s, orb_dev,
-                     c->left.as<double>(), c->l1c.as<double>(), c->l2c.p ? c->l2c.as<double>() : nullptr,
-                     c->TW.as<double>(), c->ktw, out, c->o, c->v, c->o_pad, c->Dp);
+                     c->left.as<double>(), c->l1c.as<double>(), c->l2 ? c->l2 : c->t2, out, c->o, c->v, c->o_pad,
+                     c->Dp);
   GFCC_HIP(hipGetLastError());
 }
 

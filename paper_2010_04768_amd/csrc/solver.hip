@@ -1400,10 +1400,12 @@ void solve_batch(gfcc_ctx* c, int64_t nrhs, const int64_t* p, const double* omeg
   for (int64_t r = 0; r < nrhs; ++r) info[r] = gfcc_rhs_info{1, 0, 0, 0, 0.0};
   BatchRun R = make_run(p, omega, eta, nq, q, opts, G, Xout, info, s, rec);
   int B = opts->batch > 0 ? opts->batch : 0;
+  // reduced-precision operands first, so that the window is sized against what is left
+  if (R.prec != GFCC_FP64) build_lowprec(c, R.prec == GFCC_BF16_IR ? 1 : 0, s);
   if (B == 0) {
     size_t freeb = 0, totalb = 0;
     GFCC_HIP(hipMemGetInfo(&freeb, &totalb));
-    const int64_t fit = int64_t(0.5 * double(freeb) / slot_bytes(c, R.m, R.flex));
+    const int64_t fit = int64_t(0.8 * double(freeb) / slot_bytes(c, R.m, R.flex));
     B = int(std::max<int64_t>(1, std::min<int64_t>({fit, 512, nrhs})));
   }
   std::vector<Lane> lanes(1);
@@ -1434,6 +1436,8 @@ void solve_multi(int nsys, gfcc_ctx* const* ctxs, int64_t nrhs, const int32_t* s
     return;
   }
   int64_t Btot = opts->batch > 0 ? opts->batch : std::min<int64_t>(nrhs, 128 * int64_t(used.size()));
+  if (R.prec != GFCC_FP64)
+    for (auto& L : used) build_lowprec(L.c, R.prec == GFCC_BF16_IR ? 1 : 0, s);
   size_t freeb = 0, totalb = 0;
   GFCC_HIP(hipMemGetInfo(&freeb, &totalb));
   for (;;) {  // window share of each system ~ its right-hand sides, within half of free memory

@@ -138,9 +138,11 @@ static void tune_shape(gfcc_ctx* c, Prec p, int64_t M, int64_t N, int64_t K, hip
 
 void tune_ring(gfcc_ctx* c, Prec p, int64_t P, hipStream_t s) {
   if (p != Prec::F64) build_lowprec(c, p == Prec::BF16 ? 1 : 0, s);
-  tune_shape(c, p, P * c->o, c->ov, c->ov, s);  // ring
+  tune_shape(c, p, P * c->o, c->ov, c->k2, s);  // ring, first product (K = [Wovvo | Wovov])
+  tune_shape(c, p, P * c->o, c->ov, c->ov, s);  // ring, second product
   tune_shape(c, p, c->oo, P * c->v, c->oo, s);  // hole-hole ladder
-  tune_shape(c, p, P, c->oov, c->ktw, s);       // three-body + 2h1p <- 1h
+  tune_shape(c, p, P * c->o, c->Q, c->kp, s);   // three-body U
+  tune_shape(c, p, P, c->oov, c->o, s);         // 2h1p <- 1h
 }
 
 int tuned_cfg(gfcc_ctx* c, Prec p, int64_t M, int64_t N, int64_t K) {

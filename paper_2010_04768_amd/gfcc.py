@@ -29,7 +29,7 @@ SYMBOLS = ["gfcc_build_intermediates", "gfcc_dims", "gfcc_export", "gfcc_sigma",
            "gfcc_mlp_forward", "gfcc_mlp_loss_grad", "gfcc_mlp_features", "gfcc_mlp_apply",
            "gfcc_mor_reset", "gfcc_mor_extend", "gfcc_mor_model", "gfcc_mor_export", "gfcc_mor_greens",
            "gfcc_solve_shifts", "gfcc_spectral", "gfcc_solve_multi", "gfcc_mlp_adam_step",
-           "gfcc_greens_noalloc"]
+           "gfcc_greens_noalloc", "gfcc_plan_memory"]
 
 
 class GfccSystem(ctypes.Structure):
@@ -81,6 +81,13 @@ class MorReport(ctypes.Structure):
                 ("t_project", ctypes.c_double), ("t_model", ctypes.c_double)]
 
 
+class MemoryPlan(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_size_t)] + [(n, ctypes.c_double) for n in (
+        "input_L", "input_t2", "input_l2", "ring", "ladder", "wovoo", "wooov", "cholesky", "rows_1h", "left",
+        "vectors", "small", "context_fp64", "context_lowp", "build_fixed", "build_chunk_min", "per_slot",
+        "sigma_workspace", "total", "build_peak")]
+
+
 class GfccError(RuntimeError):
     pass
 
@@ -106,6 +113,9 @@ def load():
     L.gfcc_greens.argtypes = [vp, i64, vp, vp, i64, vp, vp, vp]
     L.gfcc_greens_noalloc.argtypes = [vp, i64, vp, vp, i64, vp, vp, vp]
     L.gfcc_greens_noalloc.restype = ctypes.c_int
+    L.gfcc_plan_memory.argtypes = [i64, i64, i64, ctypes.c_int, ctypes.c_int32, ctypes.c_int32, i64, ctypes.c_int32,
+                                   ctypes.POINTER(MemoryPlan)]
+    L.gfcc_plan_memory.restype = ctypes.c_int
     L.gfcc_prof_enable.argtypes = [vp, ctypes.c_int]
     L.gfcc_prof_get.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(i64), ctypes.POINTER(dbl),
                                 ctypes.POINTER(dbl), ctypes.POINTER(dbl)]
@@ -161,6 +171,15 @@ def _stream():
 
 def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def plan_memory(n_occ, n_vir, n_chol, precision="bf16", restart=30, flexible=False, window=0, lambda_given=False):
+    """Device-memory plan (bytes per operand) of one system; host arithmetic only, no GPU needed."""
+    p = MemoryPlan()
+    p.struct_size = ctypes.sizeof(MemoryPlan)
+    _check(load().gfcc_plan_memory(n_occ, n_vir, n_chol, PRECISIONS[precision], restart, int(flexible), window,
+                                   int(lambda_given), ctypes.byref(p)), "gfcc_plan_memory")
+    return {n: getattr(p, n) for n, _ in MemoryPlan._fields_[1:]}
 
 
 def spectral(G, eta):
@@ -231,7 +250,8 @@ class Context:
         _check(self._lib.gfcc_build_intermediates(ctypes.byref(sysd), _stream(), ctypes.byref(h)),
                "gfcc_build_intermediates")
         self._h = h
-        self._keep = None  # the context copies what it keeps
+        # the context borrows t2 (and l2) until it is destroyed; eps, L, t1, l1 were read by the build
+        self._keep = [a2, b2]
         D = ctypes.c_int64()
         _check(self._lib.gfcc_dims(self._h, ctypes.byref(D), None, None), "gfcc_dims")
         self.dim = D.value
@@ -245,6 +265,7 @@ class Context:
         if getattr(self, "_h", None) is not None and self._h.value:
             self._lib.gfcc_destroy(self._h)
             self._h = None
+        self._keep = None
 
     def __del__(self):
         try:
