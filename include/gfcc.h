@@ -432,8 +432,11 @@ gfcc_status gfcc_mor_greens(gfcc_ctx* ctx, int64_t np, const int64_t* p, int64_t
 
 /* Kernel timing of the library's launches with HIP events on the launch
  * stream.  enable != 0 starts recording (clears totals).  For a kernel class
- * name ("ring_gemm_fp64", "ring_gemm_fp32", "ring_gemm_bf16" -- the three ring
- * GEMMs of sigma --, "sigma", "arnoldi", "mlp") gfcc_prof_get
+ * name ("ring_gemm_fp64", "ring_gemm_fp32", "ring_gemm_bf16" -- the two ring
+ * GEMMs of sigma --, the same split by GEMM tile as "ring_gemm_<prec>:<tile>"
+ * (tiles: 128x128 64x64 128x64 64x128 db128x128 db256x128 db128x256 db256x256
+ * db32_256x256 db32_256x128 db32_128x128 db32_256x256w16 db256x256w16), "sigma",
+ * "arnoldi" (bytes: algorithmic HBM bytes of the Arnoldi step), "mlp") gfcc_prof_get
  * returns the number of launches, total milliseconds and algorithmic flops and
  * bytes summed over them (host outputs).  Blocking. */
 gfcc_status gfcc_prof_enable(gfcc_ctx* ctx, int enable);

@@ -88,18 +88,12 @@ MemPlan plan_memory(int64_t o, int64_t v, int64_t Q, int prec, int restart, int 
 
 namespace {
 
-struct Ctxb {
-  gfcc_ctx* c;
-  hipStream_t s;
-  Scratch& scr;
-};
-
 // FP64 product C(i,j) = alpha sum_k A(i,k) B(j,k) + beta C(i,j) (see GemmArgs); large
 // products on the double-buffered tile, small grids split along K.
 void g64(const GemmArgs& g, Scratch& scr, hipStream_t s) {
   if (g.M <= 0 || g.N <= 0) return;
   if (g.batch == 1 && !g.b_ncontig && g.M >= 1024 && g.N >= 1024)
-    gemm(Prec::F64, g, TILE_DB_256x128, s);
+    gemm(Prec::F64, g, TILE_DB_128x256, s);
   else if (g.batch == 1)
     gemm_auto(Prec::F64, g, scr, 3, s);
   else
@@ -123,8 +117,6 @@ GemmArgs mk(const double* A, RowMap am, const double* B, RowMap bm, double* C, R
   g.beta = beta;
   return g;
 }
-
-constexpr RowMap kZero{int64_t(1) << 40, 0, 0};
 
 __global__ void add_diag_kernel(double* p, int64_t n, int64_t stride, const double* src, double alpha,
                                 double beta) {

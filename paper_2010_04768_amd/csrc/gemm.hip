@@ -675,6 +675,15 @@ const char* tile_name(int cfg) {
   return (cfg >= 0 && cfg < N_TILE_CFG) ? n[cfg] : "?";
 }
 
+// Tiles for large K-contiguous products when no tuned entry exists: the double-buffered
+// families that the autotuner picks for the ring shapes (256x128 in FP64 and FP32, the
+// 16-wave 256x256 tile of 32x32x16 blocks in BF16).
+int gemm_big_cfg(Prec p, int64_t M, int64_t N, int64_t K) {
+  if (M >= 2048 && N >= 2048 && K >= 256)
+    return p == Prec::BF16 ? TILE_DB32_256x256_W16 : TILE_DB_256x128;
+  return gemm_default_cfg(M, N, K);
+}
+
 int gemm_default_cfg(int64_t M, int64_t N, int64_t K) {
   (void)K;
   const int64_t big = (M >= 512 && N >= 512) ? 1 : 0;

@@ -139,6 +139,8 @@ void gemm_splitk(Prec p, const GemmArgs& a, int slices, double* part, hipStream_
 int splitk_slices(int64_t M, int64_t N, int64_t K);
 // heuristic choice when no tuned entry exists
 int gemm_default_cfg(int64_t M, int64_t N, int64_t K);
+// precision-aware choice for large K-contiguous products (double-buffered tiles)
+int gemm_big_cfg(Prec p, int64_t M, int64_t N, int64_t K);
 
 // ---------------------------------------------------------------- tensors
 struct TView {

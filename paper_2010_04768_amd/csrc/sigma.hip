@@ -182,10 +182,14 @@ static void sigma_impl(gfcc_ctx* c, int64_t P, const double* x, double* y, gfcc_
     if (ring_out) {
       ring_out[0] = g;
       ring_cfg[0] = cfg1;
-    } else {
+    } else {  // a one-group grouped launch: the ring products get kernels of their own in traces
+      const std::string by_tile = std::string(ring_name) + ":" + tile_name(cfg1);
+      const double fl = 2.0 * ring1, by = double(ov) * 2.0 * ov * esz + double(P) * o * 2.0 * ov * esz + c_rw;
       prof_begin(c, ring_name, s);
-      gemm(rp, g, cfg1, s);
-      prof_end(c, ring_name, s, 2.0 * ring1, double(ov) * 2.0 * ov * esz + double(P) * o * 2.0 * ov * esz + c_rw);
+      prof_begin(c, by_tile.c_str(), s);
+      gemm_grouped(rp, &g, 1, cfg1, s);
+      prof_end(c, by_tile.c_str(), s, fl, by);
+      prof_end(c, ring_name, s, fl, by);
     }
     // P2: rows (p, j), cols (i, a) -> s2[p][i][j][a]
     GemmArgs h;
@@ -206,9 +210,13 @@ static void sigma_impl(gfcc_ctx* c, int64_t P, const double* x, double* y, gfcc_
       ring_out[1] = h;
       ring_cfg[1] = cfg2;
     } else {
+      const std::string by_tile = std::string(ring_name) + ":" + tile_name(cfg2);
+      const double fl = ring1, by = double(ov) * ov * esz + double(P) * o * ov * esz + c_rw;
       prof_begin(c, ring_name, s);
-      gemm(rp, h, cfg2, s);
-      prof_end(c, ring_name, s, ring1, double(ov) * ov * esz + double(P) * o * ov * esz + c_rw);
+      prof_begin(c, by_tile.c_str(), s);
+      gemm_grouped(rp, &h, 1, cfg2, s);
+      prof_end(c, by_tile.c_str(), s, fl, by);
+      prof_end(c, ring_name, s, fl, by);
     }
   }
   if (!(phases & PH_REST)) return;

@@ -1087,7 +1087,17 @@ struct BatchRun {
                        1);
     hipLaunchKernelGGL(scale_kernel, dim3(L.nch, na), dim3(VT), 0, st, d, act);
     GFCC_HIP(hipGetLastError());
-    prof_end(c, "arnoldi", st, 0.0, 0.0);
+    if (c->prof_on) {
+      // algorithmic HBM bytes of the step, per slot at Krylov step k (planes of Dp doubles):
+      // pass 0 reads u, sigma and V_k (6) and the k+1 basis vectors (2(k+1)), writes w (2);
+      // pass 2 reads the basis again (2(k+1)) and w (2), writes w (2); the scaling reads and
+      // writes w (4)
+      double planes = 0.0;
+      for (int sl : L.active) planes += 4.0 * double(L.hs[size_t(sl)].k + 1) + 16.0;
+      prof_end(c, "arnoldi", st, 0.0, planes * double(L.Dp) * 8.0);
+    } else {
+      prof_end(c, "arnoldi", st, 0.0, 0.0);
+    }
   }
 
   // one inner iteration of every lane with active slots

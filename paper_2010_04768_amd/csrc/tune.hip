@@ -151,7 +151,7 @@ int tuned_cfg(gfcc_ctx* c, Prec p, int64_t M, int64_t N, int64_t K) {
   if (it != c->tuned.end()) return it->second;
   // closest tuned shape with the same precision and K (within a factor 4 overall)
   double best = std::log(4.0);
-  int cfg = gemm_default_cfg(M, N, K);
+  int cfg = gemm_big_cfg(p, M, N, K);
   for (const auto& kv : c->tuned) {
     int pp = 0;
     long long m2 = 0, n2 = 0, k2 = 0;

@@ -103,6 +103,54 @@ def make_system(n_occ: int, n_vir: int, n_chol: int, seed: int, *,
     return System(o, v, Q, eps, L, T1, T2, l1, l2, seed)
 
 
+def make_system_device(n_occ: int, n_vir: int, n_chol: int, seed: int, device, *,
+                       sigma_L: float = 0.05, sigma_t1: float = 1e-3,
+                       occ_range=(-1.2, -0.3), vir_range=(0.1, 2.0), chunk_bytes: float = 2e9):
+    """The recipe of ``make_system`` (same draws, same order) with the large arrays formed
+    as torch tensors on ``device``: the random numbers come from the same numpy PCG64 stream,
+    L is assembled from them on the device and T2 is formed there in blocks of occupied i
+    (the 120/600/3000 system's T2 is 41.5 GB).  Lambda = T^dagger.  Returns a dict with
+    float64 tensors eps, L, t1, t2 and the dimensions."""
+    import torch
+    o, v, Q = int(n_occ), int(n_vir), int(n_chol)
+    n = o + v
+    rng = np.random.Generator(np.random.PCG64(seed))
+    e_occ = np.sort(rng.uniform(occ_range[0], occ_range[1], size=o))
+    e_vir = np.sort(rng.uniform(vir_range[0], vir_range[1], size=v))
+    eps = np.concatenate([e_occ, e_vir])
+    iu, ju = np.triu_indices(n)
+    vals = rng.normal(0.0, sigma_L, size=(Q, iu.size))
+    T1 = rng.normal(0.0, sigma_t1, size=(o, v))
+    dev = torch.device(device)
+    L = torch.zeros((Q, n, n), dtype=torch.float64, device=dev)
+    iu_t = torch.as_tensor(iu, device=dev)
+    ju_t = torch.as_tensor(ju, device=dev)
+    q0 = 0
+    qc = max(1, int(chunk_bytes // max(1, iu.size * 8)))
+    while q0 < Q:  # upload the draws in blocks of Q
+        q1 = min(Q, q0 + qc)
+        blk = torch.from_numpy(vals[q0:q1]).to(dev)
+        L[q0:q1, iu_t, ju_t] = blk
+        L[q0:q1, ju_t, iu_t] = blk
+        q0 = q1
+        del blk
+    del vals
+    eo = torch.from_numpy(e_occ).to(dev)
+    ev = torch.from_numpy(e_vir).to(dev)
+    Lov = L[:, :o, o:].reshape(Q, o * v)
+    T2 = torch.empty((o, o, v, v), dtype=torch.float64, device=dev)
+    ci = max(1, int(chunk_bytes // max(1, v * o * v * 8 * 3)))
+    for i0 in range(0, o, ci):  # T2[i, j, a, b] = (ia|jb) / (e_i + e_j - e_a - e_b)
+        i1 = min(o, i0 + ci)
+        iajb = (Lov[:, i0 * v:i1 * v].T @ Lov).reshape(i1 - i0, v, o, v)
+        den = (eo[i0:i1, None, None, None] + eo[None, None, :, None]
+               - ev[None, :, None, None] - ev[None, None, None, :])
+        T2[i0:i1] = (iajb / den).permute(0, 2, 1, 3)
+        del iajb, den
+    return dict(n_occ=o, n_vir=v, n_chol=Q, seed=seed,
+                eps=torch.from_numpy(eps).to(dev), L=L, t1=torch.from_numpy(T1).to(dev), t2=T2)
+
+
 @dataclasses.dataclass
 class Workload:
     """A named workload: one or more systems plus the (p, omega) grid."""

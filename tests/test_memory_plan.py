@@ -36,3 +36,19 @@ def test_plan_scales_with_window_and_precision():
 def test_plan_rejects_bad_arguments():
     with pytest.raises(gfcc.GfccError):
         gfcc.plan_memory(0, 200, 800)
+
+
+def test_device_generator_follows_the_host_recipe():
+    """synth.make_system_device (used for the 120/600/3000 system, whose arrays are formed on the
+    GPU) draws the same numbers as make_system; on the CPU device, in small blocks, every array
+    agrees with the host recipe to rounding."""
+    torch = pytest.importorskip("torch")
+    import numpy as np
+    from synth import make_system, make_system_device
+    s = make_system(5, 11, 17, 321)
+    d = make_system_device(5, 11, 17, 321, "cpu", chunk_bytes=3000)
+    assert np.array_equal(d["eps"].numpy(), s.eps)
+    assert np.array_equal(d["L"].numpy(), s.L)
+    assert np.array_equal(d["t1"].numpy(), s.t1)
+    t2 = d["t2"].numpy()
+    assert np.abs(t2 - s.t2).max() <= 1e-14 * np.abs(s.t2).max()
