@@ -294,3 +294,115 @@ class IPBruteForce:
     def greens_sa(self, omega, eta, p, q):
         A = (omega - 1j * eta) * np.eye(self.Hsa.shape[0]) + self.Hsa
         return self.c_sa[q] @ np.linalg.solve(A, self.b_sa[p])
+
+
+class EABruteForce:
+    """Dense EA-GFCCSD quantities (the advanced, electron-attached term of G) for one tiny
+    system, from the same determinant matrices as the IP part.
+
+    Paper, Theory: the second term of the GFCC Green's function,
+    ``G^EA_pq = <Phi|(1 + Lambda) abar_p (omega - Hbar_N + i eta)^-1 abar_q^+ |Phi>``, solved
+    through ``(omega - Hbar_N + i eta) Y_q |Phi> = abar_q^+ |Phi>`` with Y_q expanded in
+    one-particle ``a_a^+`` and two-particle one-hole ``a_a^+ a_b^+ a_i`` operators.
+    For every basis operator ``R_mu`` of the 1p + 2p1h space (one extra alpha electron):
+
+    * ``Hbar[mu', mu] = <mu'| [Hbar, R_mu] |Phi>`` (connected form),
+    * ``b_q[mu] = <mu| e^-T a_q^+ e^T |Phi>``,
+    * ``c_p[mu] = <Phi| (1 + Lambda) e^-T a_p e^T |mu>``.
+
+    Spin-adapted basis (doublet, reached through ``E``/``X``):
+
+    * ``y_a``      <-> coefficient of ``a^+_{a alpha}``
+    * ``y_jab``    <-> coefficient of ``a^+_{a alpha} a^+_{b beta} a_{j beta}``
+    * the same-spin component is ``y_jab - y_jba`` on ``a^+_{a alpha} a^+_{b alpha} a_{j alpha}`` (a < b).
+    Layout: ``y[0:v] = y_a``, ``y[v + (j*v + a)*v + b] = y_jab``.
+    """
+
+    def __init__(self, sysobj):
+        o, v = sysobj.n_occ, sysobj.n_vir
+        n = o + v
+        self.o, self.v, self.n = o, v, n
+        so = SpinOrbitalSystem(o, v, sysobj.eps, sysobj.L, sysobj.t1, sysobj.t2, sysobj.l1, sysobj.l2)
+        self.so = so
+        detsN, idxN = sector(n, o, o)
+        detsP, idxP = sector(n, o + 1, o)
+        phi_det = sum(1 << p for p in range(o)) | sum(1 << (n + p) for p in range(o))
+        phi = np.zeros(len(detsN))
+        phi[idxN[phi_det]] = 1.0
+        HN = so.hamiltonian(detsN, idxN)
+        HP = so.hamiltonian(detsP, idxP)
+        Tt = so.cluster_terms("T")
+        TN = op_matrix(Tt, detsN, idxN)
+        TP = op_matrix(Tt, detsP, idxP)
+        LamN = op_matrix(so.cluster_terms("L"), detsN, idxN)
+        eTN, emTN = _expm_nilpotent(TN), _expm_nilpotent(-TN)
+        eTP, emTP = _expm_nilpotent(TP), _expm_nilpotent(-TP)
+        HbN = emTN @ HN @ eTN
+        HbP = emTP @ HP @ eTP
+
+        basis = [("1p", a) for a in range(v)]
+        basis += [("aaa", j, a, b) for j in range(o) for a in range(v) for b in range(a + 1, v)]
+        basis += [("abb", j, a, b) for j in range(o) for a in range(v) for b in range(v)]
+        self.basis = basis
+        ops = []
+        for bb in basis:
+            if bb[0] == "1p":
+                ops.append([(True, o + bb[1])])
+            elif bb[0] == "aaa":
+                _, j, a, b = bb
+                ops.append([(False, j), (True, o + b), (True, o + a)])
+            else:
+                _, j, a, b = bb
+                ops.append([(False, n + j), (True, n + o + b), (True, o + a)])
+        Rmats = [op_matrix([(1.0, sq)], detsN, idxP) for sq in ops]
+        evec = np.stack([R @ phi for R in Rmats], axis=1)
+        HbNphi = HbN @ phi
+        Dso = len(basis)
+        Hso = np.zeros((Dso, Dso))
+        for mu, R in enumerate(Rmats):
+            sig = HbP @ evec[:, mu] - R @ HbNphi
+            Hso[:, mu] = evec.T @ sig
+        self.Hso = Hso
+
+        self.b_so = np.zeros((n, Dso))
+        self.c_so = np.zeros((n, Dso))
+        for p in range(n):
+            Cq = op_matrix([(1.0, [(True, p)])], detsN, idxP)
+            self.b_so[p] = evec.T @ (emTP @ Cq @ eTN @ phi)
+            Ap = op_matrix([(1.0, [(False, p)])], detsP, idxN)
+            row = phi @ (np.eye(len(detsN)) + LamN) @ emTN @ Ap @ eTP
+            self.c_so[p] = row @ evec
+
+        D = v + o * v * v
+        E = np.zeros((Dso, D))
+        X = np.zeros((D, Dso))
+        for mu, bb in enumerate(basis):
+            if bb[0] == "1p":
+                E[mu, bb[1]] = 1.0
+                X[bb[1], mu] = 1.0
+            elif bb[0] == "abb":
+                _, j, a, b = bb
+                k = v + (j * v + a) * v + b
+                E[mu, k] = 1.0
+                X[k, mu] = 1.0
+            else:
+                _, j, a, b = bb
+                E[mu, v + (j * v + a) * v + b] += 1.0
+                E[mu, v + (j * v + b) * v + a] -= 1.0
+        self.E, self.X = E, X
+        self.Hsa = X @ Hso @ E
+        self.b_sa = self.b_so @ X.T
+        self.c_sa = self.c_so @ E
+
+    def doublet_leak(self) -> float:
+        P = self.E @ self.X
+        return float(np.max(np.abs(self.Hso @ self.E - P @ self.Hso @ self.E)))
+
+    def greens_so(self, omega, eta, p, q):
+        """G^EA_pq(omega) = c_p^T (omega + i eta - Hbar)^-1 b_q in the spin-orbital space."""
+        A = (omega + 1j * eta) * np.eye(self.Hso.shape[0]) - self.Hso
+        return self.c_so[p] @ np.linalg.solve(A, self.b_so[q])
+
+    def greens_sa(self, omega, eta, p, q):
+        A = (omega + 1j * eta) * np.eye(self.Hsa.shape[0]) - self.Hsa
+        return self.c_sa[p] @ np.linalg.solve(A, self.b_sa[q])
