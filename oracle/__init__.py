@@ -14,4 +14,7 @@ generator in ``synth``.
 * ``oracle.ipgfcc`` -- O2: a matrix-free spin-adapted closed-shell
   implementation (intermediates, sigma product, diagonal, left vectors,
   GMRES, Green's function), pinned against O1 and closed forms.
+* ``oracle.eagfcc`` -- O2 for the advanced (electron-attached) term: the
+  spin-adapted 1p + 2p1h sigma product, its intermediates, diagonal, right-hand
+  sides and left vectors, pinned against the N+1-sector brute force of O1.
 """
