@@ -105,6 +105,38 @@ typedef struct {
  * device memory runs out. */
 gfcc_status gfcc_build_intermediates(const gfcc_system* sys, void* stream, gfcc_ctx** out);
 
+/* Build the context of the advanced, electron-attached (EA) term of the same system
+ * (Theory section: the second term of the Green's function, the Y_q expansion in
+ * one-particle and two-particle-one-hole operators and its linear system):
+ *
+ *     G^EA_pq(omega) = c'_p^T Y_q(omega),   (omega - Hbar_N + i*eta) Y_q = b'_q,
+ *     b'_q = abar_q^+ |Phi>,   c'_p = <Phi|(1 + Lambda) abar_p   (on 1p + 2p1h).
+ *
+ * Closed-shell spin-adapted basis (doublet), dimension D = v + o*v*v:
+ *     y[0 .. v)                  = y_a     (coefficient of a^+_{a alpha})
+ *     y[v + (j*v + a)*v + b]     = y_jab   (coefficient of a^+_{a alpha} a^+_{b beta} a_{j beta})
+ * the same-spin component being y_jab - y_jba.
+ *
+ * The returned context works with these entry points, with these meanings:
+ *   gfcc_dims        D = v + o v^2
+ *   gfcc_sigma       Y = Hbar_N X on 1p + 2p1h (FP64 only; E_ARG otherwise)
+ *   gfcc_solve_batch for right-hand side r: Y_{p[r]} at omega[r] (the system above, solved as
+ *                    (-omega - i eta + Hbar_N) Y = -b' by the same GMRES; Jacobi uses the EA
+ *                    diagonal); G[r][k] = c'_{q[k]} . Y_{p[r]} = G^EA_{q[k] p[r]}; X receives Y.
+ *                    FP64 only; GFCC_PC_MLP is E_STATE.
+ *   gfcc_greens, gfcc_greens_noalloc   G[r][k] = c'_{q[k]} . X[r]
+ *   gfcc_export      FOO, FVV, FOV (the one-body blocks shared with the IP term) and DIAG [D]
+ *   gfcc_prof_*, gfcc_destroy
+ * Every other entry point returns E_STATE on it.  The full retarded function is
+ * G_pq = G^IP_pq + G^EA_pq (the IP context's G[r][k] is G^IP_{p[r] q[k]}).
+ *
+ * Storage (FP64): the particle-particle ladder Wvvvv as a [v^2][v^2] matrix (the sigma
+ * product's dominant operand, 2 o v^4 flops per vector), Wvvvo [o v^2][v], the 1p rows
+ * [v][D], the ring matrices (3 (ov)^2), the three-body operator [o][o v^2]; t2 (and l2)
+ * are borrowed as for gfcc_build_intermediates.  Build temporaries hold the integral
+ * blocks (ov|vv) and the v^4 product.  Blocking.  Errors as gfcc_build_intermediates. */
+gfcc_status gfcc_build_ea_intermediates(const gfcc_system* sys, void* stream, gfcc_ctx** out);
+
 /* Device-memory plan of one system in bytes (host arithmetic only, no GPU
  * needed): the caller's inputs, each operand the context keeps in FP64 and in
  * the reduced precision `prec`, the build's fixed temporaries and smallest

@@ -60,6 +60,12 @@ static gfcc_status guarded(F&& f) {
 
 static hipStream_t as_stream(void* s) { return static_cast<hipStream_t>(s); }
 
+// entry points built on the ionisation sector's operands only
+static void ip_sector(const gfcc_ctx* c, const char* what) {
+  GFCC_CHECK(c, GFCC_E_ARG, "null context");
+  GFCC_CHECK(c->sector == 0, GFCC_E_STATE, std::string(what) + " is not available on an electron-attachment context");
+}
+
 extern "C" {
 
 gfcc_status gfcc_build_intermediates(const gfcc_system* sys, void* stream, gfcc_ctx** out) {
@@ -82,6 +88,9 @@ gfcc_status gfcc_build_intermediates(const gfcc_system* sys, void* stream, gfcc_
       c->D = c->o + c->oov;
       c->o_pad = round_up(c->o, 8);
       c->Dp = c->o_pad + round_up(c->oov, 8);
+      c->n1 = c->o;
+      c->p1 = c->o_pad;
+      c->n2 = c->oov;
       c->kp = round_up(c->ov, 8);
       c->k2 = 2 * c->kp;
       c->op2 = round_up(c->oo, 8);
@@ -91,6 +100,48 @@ gfcc_status gfcc_build_intermediates(const gfcc_system* sys, void* stream, gfcc_
       GFCC_HIP(hipGetDevice(&c->device));
       c->fixed_scratch = fixed_scratch_address(c->device);
       build_intermediates(c, sys, s);
+      GFCC_HIP(hipStreamSynchronize(s));
+    } catch (...) {
+      delete c;
+      throw;
+    }
+    *out = c;
+  });
+}
+
+gfcc_status gfcc_build_ea_intermediates(const gfcc_system* sys, void* stream, gfcc_ctx** out) {
+  return guarded([&] {
+    GFCC_CHECK(sys && out, GFCC_E_ARG, "null argument");
+    GFCC_CHECK(sys->n_occ >= 1 && sys->n_vir >= 1 && sys->n_chol >= 1, GFCC_E_ARG,
+               "n_occ, n_vir and n_chol must be >= 1");
+    GFCC_CHECK(sys->n_occ <= 4096 && sys->n_vir <= 4096, GFCC_E_ARG, "dimensions out of range");
+    GFCC_CHECK(sys->eps && sys->L && sys->t1 && sys->t2, GFCC_E_ARG, "eps, L, t1 and t2 are required");
+    *out = nullptr;
+    gfcc_ctx* c = new gfcc_ctx();
+    try {
+      c->sector = 1;
+      c->o = sys->n_occ;
+      c->v = sys->n_vir;
+      c->Q = sys->n_chol;
+      c->n = c->o + c->v;
+      c->ov = c->o * c->v;
+      c->oo = c->o * c->o;
+      c->oov = c->oo * c->v;
+      c->n1 = c->v;
+      c->p1 = round_up(c->v, 8);
+      c->n2 = c->o * c->v * c->v;
+      c->D = c->n1 + c->n2;
+      c->Dp = c->p1 + round_up(c->n2, 8);
+      c->o_pad = round_up(c->o, 8);
+      c->kp = round_up(c->ov, 8);
+      c->k2 = 2 * c->kp;
+      c->op2 = round_up(c->oo, 8);
+      c->vp = round_up(c->v, 8);
+      c->Qp = round_up(c->Q, 8);
+      hipStream_t s = as_stream(stream);
+      GFCC_HIP(hipGetDevice(&c->device));
+      c->fixed_scratch = fixed_scratch_address(c->device);
+      build_ea(c, sys, s);
       GFCC_HIP(hipStreamSynchronize(s));
     } catch (...) {
       delete c;
@@ -145,6 +196,8 @@ gfcc_status gfcc_dims(const gfcc_ctx* c, int64_t* D, int64_t* n_occ, int64_t* n_
 gfcc_status gfcc_export(gfcc_ctx* c, gfcc_block which, double* dst, void* stream) {
   return guarded([&] {
     GFCC_CHECK(c && dst, GFCC_E_ARG, "null argument");
+    GFCC_CHECK(c->sector == 0 || which == GFCC_FOO || which == GFCC_FVV || which == GFCC_FOV || which == GFCC_DIAG,
+               GFCC_E_STATE, "an electron-attachment context exports FOO, FVV, FOV and DIAG only");
     hipStream_t s = as_stream(stream);
     const int64_t o = c->o, v = c->v, kp = c->kp, k2 = c->k2;
     const int id4[4] = {0, 1, 2, 3};
@@ -195,8 +248,8 @@ gfcc_status gfcc_export(gfcc_ctx* c, gfcc_block which, double* dst, void* stream
         break;
       }
       case GFCC_DIAG:
-        GFCC_HIP(hipMemcpyAsync(dst, c->diag.p, size_t(o) * 8, hipMemcpyDeviceToDevice, s));
-        GFCC_HIP(hipMemcpyAsync(dst + o, c->diag.as<double>() + c->o_pad, size_t(c->oov) * 8,
+        GFCC_HIP(hipMemcpyAsync(dst, c->diag.p, size_t(c->n1) * 8, hipMemcpyDeviceToDevice, s));
+        GFCC_HIP(hipMemcpyAsync(dst + c->n1, c->diag.as<double>() + c->p1, size_t(c->n2) * 8,
                                 hipMemcpyDeviceToDevice, s));
         break;
       case GFCC_LEFT:
@@ -215,6 +268,7 @@ gfcc_status gfcc_sigma(gfcc_ctx* c, int64_t nrhs, const double* X, double* Y, gf
     GFCC_CHECK(c, GFCC_E_ARG, "null context");
     GFCC_CHECK(nrhs >= 0, GFCC_E_ARG, "nrhs < 0");
     GFCC_CHECK(prec == GFCC_FP64 || prec == GFCC_FP32_IR || prec == GFCC_BF16_IR, GFCC_E_ARG, "bad precision");
+    GFCC_CHECK(c->sector == 0 || prec == GFCC_FP64, GFCC_E_ARG, "the electron-attachment sigma runs in FP64 only");
     if (nrhs == 0) return;
     GFCC_CHECK(X && Y && X != Y, GFCC_E_ARG, "X and Y must be distinct device buffers");
     hipStream_t s = as_stream(stream);
@@ -356,6 +410,16 @@ gfcc_status gfcc_solve_batch(gfcc_ctx* c, int64_t nrhs, const int64_t* p, const 
     GFCC_CHECK(opts->tol > 0.0 && opts->restart >= 1 && opts->max_iter >= 1, GFCC_E_ARG, "bad tolerance/restart/max_iter");
     GFCC_CHECK(opts->precond >= GFCC_PC_NONE && opts->precond <= GFCC_PC_MLP, GFCC_E_ARG, "bad preconditioner");
     GFCC_CHECK(opts->precision >= GFCC_FP64 && opts->precision <= GFCC_BF16_IR, GFCC_E_ARG, "bad precision");
+    if (c->sector != 0) {
+      // (omega - Hbar_N + i eta) Y = abar^+|Phi>  is solved as  (-omega - i eta + Hbar_N) Y = -abar^+|Phi>
+      GFCC_CHECK(opts->precision == GFCC_FP64, GFCC_E_ARG, "the electron-attachment solve runs in FP64 only");
+      GFCC_CHECK(opts->precond != GFCC_PC_MLP, GFCC_E_STATE,
+                 "the learned preconditioner is trained on the ionisation sector only");
+      std::vector<double> wneg(static_cast<size_t>(nrhs));
+      for (int64_t r = 0; r < nrhs; ++r) wneg[size_t(r)] = -omega[r];
+      solve_batch(c, nrhs, p, wneg.data(), eta, nq, q, opts, G, X, info, as_stream(stream), &all_conv, nullptr);
+      return;
+    }
     solve_batch(c, nrhs, p, omega, eta, nq, q, opts, G, X, info, as_stream(stream), &all_conv, nullptr);
   });
   if (st == GFCC_OK && !all_conv) return GFCC_W_NOCONV;
@@ -390,6 +454,7 @@ __global__ void rms_kernel(const double* __restrict__ planes, int64_t Dp, int64_
 
 gfcc_status gfcc_mlp_set_weights(gfcc_ctx* c, int32_t width, const double* params, void* stream) {
   return guarded([&] {
+    ip_sector(c, "gfcc_mlp_set_weights");
     GFCC_CHECK(c && params, GFCC_E_ARG, "null argument");
     hipStream_t s = as_stream(stream);
     mlp_init(c, width, 0, s);
@@ -402,6 +467,7 @@ gfcc_status gfcc_mlp_set_weights(gfcc_ctx* c, int32_t width, const double* param
 
 gfcc_status gfcc_mlp_get_weights(gfcc_ctx* c, int32_t* width, double* params, void* stream) {
   return guarded([&] {
+    ip_sector(c, "gfcc_mlp_get_weights");
     GFCC_CHECK(c && width, GFCC_E_ARG, "null argument");
     GFCC_CHECK(c->mlp != nullptr, GFCC_E_STATE, "no network in this context");
     *width = c->mlp->width;
@@ -413,6 +479,7 @@ gfcc_status gfcc_mlp_get_weights(gfcc_ctx* c, int32_t* width, double* params, vo
 
 gfcc_status gfcc_mlp_adam_step(gfcc_ctx* c, const double* grad, double lr, void* stream) {
   return guarded([&] {
+    ip_sector(c, "gfcc_mlp_adam_step");
     GFCC_CHECK(c && grad, GFCC_E_ARG, "null argument");
     GFCC_CHECK(std::isfinite(lr) && lr > 0.0, GFCC_E_ARG, "lr must be finite and positive");
     GFCC_CHECK(c->mlp != nullptr, GFCC_E_STATE, "no network in this context");
@@ -425,6 +492,7 @@ gfcc_status gfcc_mlp_adam_step(gfcc_ctx* c, const double* grad, double lr, void*
 
 gfcc_status gfcc_mlp_forward(gfcc_ctx* c, int64_t n, const double* X, double* Y, void* stream) {
   return guarded([&] {
+    ip_sector(c, "gfcc_mlp_forward");
     GFCC_CHECK(c && X && Y && n >= 0, GFCC_E_ARG, "bad argument");
     GFCC_CHECK(c->mlp != nullptr, GFCC_E_STATE, "no network in this context");
     if (n == 0) return;
@@ -440,6 +508,7 @@ gfcc_status gfcc_mlp_forward(gfcc_ctx* c, int64_t n, const double* X, double* Y,
 gfcc_status gfcc_mlp_loss_grad(gfcc_ctx* c, int64_t n, const double* X, const double* T, double* loss, double* grad,
                                void* stream) {
   return guarded([&] {
+    ip_sector(c, "gfcc_mlp_loss_grad");
     GFCC_CHECK(c && X && T && loss && grad && n > 0, GFCC_E_ARG, "bad argument");
     GFCC_CHECK(c->mlp != nullptr, GFCC_E_STATE, "no network in this context");
     hipStream_t s = as_stream(stream);
@@ -451,6 +520,7 @@ gfcc_status gfcc_mlp_loss_grad(gfcc_ctx* c, int64_t n, const double* X, const do
 gfcc_status gfcc_mlp_features(gfcc_ctx* c, int64_t nvec, const double* R, const double* omega, double eta, double* X,
                               void* stream) {
   return guarded([&] {
+    ip_sector(c, "gfcc_mlp_features");
     GFCC_CHECK(c && R && omega && X && nvec >= 0, GFCC_E_ARG, "bad argument");
     if (nvec == 0) return;
     hipStream_t s = as_stream(stream);
@@ -471,6 +541,7 @@ gfcc_status gfcc_mlp_features(gfcc_ctx* c, int64_t nvec, const double* R, const 
 gfcc_status gfcc_mlp_apply(gfcc_ctx* c, int64_t nvec, const double* R, const double* omega, double eta, double* U,
                            void* stream) {
   return guarded([&] {
+    ip_sector(c, "gfcc_mlp_apply");
     GFCC_CHECK(c && R && omega && U && nvec >= 0, GFCC_E_ARG, "bad argument");
     GFCC_CHECK(c->mlp && c->mlp->trained, GFCC_E_STATE, "no trained network in this context");
     if (nvec == 0) return;
@@ -502,7 +573,7 @@ gfcc_status gfcc_solve_multi(int32_t nsys, gfcc_ctx* const* ctxs, int64_t nrhs, 
   gfcc_status st = guarded([&] {
     GFCC_CHECK(nsys >= 1 && nsys <= 16 && ctxs, GFCC_E_ARG, "nsys must be in [1, 16]");
     for (int k = 0; k < nsys; ++k) {
-      GFCC_CHECK(ctxs[k], GFCC_E_ARG, "null context");
+      ip_sector(ctxs[k], "gfcc_solve_multi");
       for (int j = 0; j < k; ++j) GFCC_CHECK(ctxs[j] != ctxs[k], GFCC_E_ARG, "a context appears twice");
     }
     GFCC_CHECK(opts && opts->struct_size >= sizeof(gfcc_solve_opts), GFCC_E_ARG, "bad options struct");
@@ -540,6 +611,7 @@ gfcc_status gfcc_solve_shifts(gfcc_ctx* c, int64_t np, const int64_t* p, int64_t
                               double* X, gfcc_rhs_info* info, void* stream) {
   bool all_conv = true;
   gfcc_status st = guarded([&] {
+    ip_sector(c, "gfcc_solve_shifts");
     GFCC_CHECK(c, GFCC_E_ARG, "null context");
     GFCC_CHECK(opts && opts->struct_size >= sizeof(gfcc_shift_opts), GFCC_E_ARG, "bad options struct");
     GFCC_CHECK(np >= 0 && n_omega >= 0, GFCC_E_ARG, "negative size");
@@ -570,6 +642,7 @@ gfcc_status gfcc_solve_shifts(gfcc_ctx* c, int64_t np, const int64_t* p, int64_t
 gfcc_status gfcc_mlp_train(gfcc_ctx* c, int64_t nrhs, const int64_t* p, const double* omega, double eta,
                            const gfcc_mlp_opts* mo, gfcc_mlp_report* rep, void* stream) {
   return guarded([&] {
+    ip_sector(c, "gfcc_mlp_train");
     GFCC_CHECK(c && p && omega && mo && nrhs > 0, GFCC_E_ARG, "bad argument");
     GFCC_CHECK(mo->struct_size >= sizeof(gfcc_mlp_opts), GFCC_E_ARG, "bad options struct");
     GFCC_CHECK(mo->steps >= 0 && mo->batch >= 1 && mo->pair_restart >= 1 && mo->max_pairs >= 1 && mo->lr > 0.0,
@@ -656,6 +729,7 @@ gfcc_status gfcc_mlp_train(gfcc_ctx* c, int64_t nrhs, const int64_t* p, const do
 
 gfcc_status gfcc_mor_reset(gfcc_ctx* c) {
   return guarded([&] {
+    ip_sector(c, "gfcc_mor_reset");
     GFCC_CHECK(c, GFCC_E_ARG, "null context");
     mor_reset(c);
   });
@@ -664,6 +738,7 @@ gfcc_status gfcc_mor_reset(gfcc_ctx* c) {
 gfcc_status gfcc_mor_extend(gfcc_ctx* c, int64_t n, const double* X, double drop_tol, int64_t* m_out,
                             void* stream) {
   return guarded([&] {
+    ip_sector(c, "gfcc_mor_extend");
     GFCC_CHECK(c, GFCC_E_ARG, "null context");
     GFCC_CHECK(n >= 0, GFCC_E_ARG, "n < 0");
     GFCC_CHECK(drop_tol >= 0.0 && drop_tol < 1.0, GFCC_E_ARG, "drop_tol must be in [0, 1)");
@@ -685,6 +760,7 @@ static void check_pq(int64_t limit, int64_t n, const int64_t* v, const char* wha
 gfcc_status gfcc_mor_model(gfcc_ctx* c, int64_t np, const int64_t* p, int64_t nq, const int64_t* q,
                            int64_t n_omega, const double* omega, double eta, double* G, void* stream) {
   return guarded([&] {
+    ip_sector(c, "gfcc_mor_model");
     GFCC_CHECK(c, GFCC_E_ARG, "null context");
     GFCC_CHECK(np >= 1 && n_omega >= 0 && (q == nullptr || nq >= 1), GFCC_E_ARG, "bad sizes");
     if (n_omega == 0) return;
@@ -698,6 +774,7 @@ gfcc_status gfcc_mor_model(gfcc_ctx* c, int64_t np, const int64_t* p, int64_t nq
 
 gfcc_status gfcc_mor_export(gfcc_ctx* c, int32_t which, double* dst, int64_t* m_out, void* stream) {
   return guarded([&] {
+    ip_sector(c, "gfcc_mor_export");
     GFCC_CHECK(c, GFCC_E_ARG, "null context");
     GFCC_CHECK(which == 0 || which == 1, GFCC_E_ARG, "which must be 0 (Hhat) or 1 (basis)");
     if (m_out) *m_out = mor_size(c);
@@ -714,6 +791,7 @@ gfcc_status gfcc_mor_greens(gfcc_ctx* c, int64_t np, const int64_t* p, int64_t n
                             gfcc_mor_report* report, void* stream) {
   bool all_conv = true;
   gfcc_status st = guarded([&] {
+    ip_sector(c, "gfcc_mor_greens");
     GFCC_CHECK(c, GFCC_E_ARG, "null context");
     GFCC_CHECK(opts && opts->struct_size >= sizeof(gfcc_mor_opts), GFCC_E_ARG, "bad options struct");
     GFCC_CHECK(opts->solve.struct_size >= sizeof(gfcc_solve_opts), GFCC_E_ARG, "bad solve options struct");

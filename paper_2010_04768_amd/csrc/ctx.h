@@ -24,6 +24,14 @@ struct gfcc_ctx {
   int64_t vp = 0;     // padded row length for K = v operands
   int64_t Qp = 0;     // padded Cholesky rank (rows of Q-innermost operands)
 
+  // Sector of the expansion: 0 = ionisation (1h + 2h1p), 1 = electron attachment (1p + 2p1h).
+  // A plane holds the first block at [0, n1) and the second at [p1, p1 + n2); D = n1 + n2.
+  int sector = 0;
+  int64_t n1 = 0, p1 = 0, n2 = 0;
+  // right-hand side (and left vector) of orbital `orb` is a materialised row rather than the
+  // implicit unit vector of an occupied orbital of the IP sector
+  bool materialised(int64_t orb) const { return sector != 0 || orb >= o; }
+
   // borrowed inputs (caller memory, valid until gfcc_destroy): t2, and l2 when
   // Lambda is not T^dagger (else nullptr)
   const double* t2 = nullptr;
@@ -44,6 +52,19 @@ struct gfcc_ctx {
   gfcc::DBuf left;    // [o][Dp]          c_q rows
   gfcc::DBuf t1c;     // [o][v]           amplitudes for virtual-orbital right-hand sides
   gfcc::DBuf l1c;     // [o][v]
+
+  // electron-attachment blocks (sector 1), FP64
+  struct EA {
+    int64_t lv = 0;     // row stride of the ladder matrix: round8(v^2)
+    int64_t n2p = 0;    // row stride of zop: round8(o v^2)
+    gfcc::DBuf ladder;  // [(a,b)][lv]    Wvvvv[a,b,c,d] at column (c,d)
+    gfcc::DBuf vvvoT;   // [(j,a,b)][vp]  Wvvvo[a,b,c,j] at column c
+    gfcc::DBuf ring;    // [(j,b)][2kp]   [2 Wovvo[l,b,d,j] - Wovov[l,b,j,d] (+ one-body) | -Wovvo[l,b,c,j]]
+    gfcc::DBuf ring2;   // [(j,a)][kp]    -Wovov[l,a,j,c] (+ one-body)
+    gfcc::DBuf zop;     // [k][n2p]       2 (kc|ld) - (kd|lc) at column (l,c,d)
+    gfcc::DBuf Sl;      // [a][b]         sum_ijc t2[i,j,a,c] (2 l2[i,j,b,c] - l2[i,j,c,b])
+    gfcc::DBuf ws_R, ws_z;  // sigma operand copies
+  } ea;
 
   // reduced-precision copies of the two-body operands with power-of-two scales: [0] FP32, [1] BF16
   struct LowPrec {
@@ -148,6 +169,13 @@ void greens_planes(gfcc_ctx* c, int64_t nb, const double* planes, int64_t nq, co
 int64_t greens_part_doubles(gfcc_ctx* c, int64_t nb, int64_t nq);
 void greens_rows(gfcc_ctx* c, int64_t nb, const double* planes, int64_t nq, const double* rows, double* G,
                  double* part, hipStream_t s);
+
+// electron-attachment sector (ea.hip): blocks of Hbar_N on 1p + 2p1h, sigma on planes, and the
+// rows of the linear system (-omega - i eta + Hbar_N) Y = -abar_q^+|Phi> and of G = c'_p . Y
+void build_ea(gfcc_ctx* c, const gfcc_system* sys, hipStream_t s);
+void ea_sigma_planes(gfcc_ctx* c, int64_t nplanes, const double* x, double* y, hipStream_t s);
+void ea_rhs_rows(gfcc_ctx* c, int64_t n, const int64_t* orb_dev, double* out, hipStream_t s);
+void ea_left_rows(gfcc_ctx* c, int64_t n, const int64_t* orb_dev, double* out, hipStream_t s);
 
 // model-order reduction (mor.hip)
 void mor_reset(gfcc_ctx* c);

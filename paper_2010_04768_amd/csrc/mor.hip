@@ -404,7 +404,7 @@ void mor_export(gfcc_ctx* c, int which, double* dst, hipStream_t s) {
                               hipMemcpyDeviceToDevice, s));
   } else {  // S [m][D]
     hipLaunchKernelGGL(export_basis_kernel, dim3(nblocks(c->D), unsigned(M.m)), dim3(256), 0, s, M.S.as<double>(),
-                       dst, c->D, c->Dp, c->o, c->o_pad);
+                       dst, c->D, c->Dp, c->n1, c->p1);
     GFCC_HIP(hipGetLastError());
   }
 }

@@ -346,6 +346,11 @@ static void sigma_impl(gfcc_ctx* c, int64_t P, const double* x, double* y, gfcc_
 }
 
 void sigma_planes(gfcc_ctx* c, int64_t P, const double* x, double* y, gfcc_precision prec, hipStream_t s) {
+  if (c->sector != 0) {
+    GFCC_CHECK(prec == GFCC_FP64, GFCC_E_ARG, "the electron-attachment sigma runs in FP64 only");
+    ea_sigma_planes(c, P, x, y, s);
+    return;
+  }
   sigma_impl(c, P, x, y, prec, s, PH_ALL, nullptr, nullptr);
 }
 
@@ -408,14 +413,14 @@ __global__ void from_planes_kernel(const double* __restrict__ pl, double* __rest
 void to_planes(gfcc_ctx* c, int64_t nb, const double* xi, double* planes, hipStream_t s) {
   if (nb <= 0) return;
   hipLaunchKernelGGL(to_planes_kernel, dim3(blocks_for(c->D), unsigned(nb)), dim3(256), 0, s, xi, planes, nb,
-                     c->D, c->Dp, c->o, c->o_pad);
+                     c->D, c->Dp, c->n1, c->p1);
   GFCC_HIP(hipGetLastError());
 }
 
 void from_planes(gfcc_ctx* c, int64_t nb, const double* planes, double* xi, hipStream_t s) {
   if (nb <= 0) return;
   hipLaunchKernelGGL(from_planes_kernel, dim3(blocks_for(c->D), unsigned(nb)), dim3(256), 0, s, planes, xi, nb,
-                     c->D, c->Dp, c->o, c->o_pad);
+                     c->D, c->Dp, c->n1, c->p1);
   GFCC_HIP(hipGetLastError());
 }
 
@@ -476,6 +481,10 @@ __global__ void left_rows_kernel(const int64_t* __restrict__ orb, const double* 
 
 void make_rhs_rows(gfcc_ctx* c, int64_t n, const int64_t* orb_dev, double* out, hipStream_t s) {
   if (n <= 0) return;
+  if (c->sector != 0) {
+    ea_rhs_rows(c, n, orb_dev, out, s);
+    return;
+  }
   hipLaunchKernelGGL(rhs_rows_kernel, dim3(blocks_for(c->Dp), unsigned(n)), dim3(256), 0, s, orb_dev,
                      c->t1c.as<double>(), c->t2, out, c->o, c->v, c->o_pad, c->Dp);
   GFCC_HIP(hipGetLastError());
@@ -483,6 +492,10 @@ void make_rhs_rows(gfcc_ctx* c, int64_t n, const int64_t* orb_dev, double* out, 
 
 void make_left_rows(gfcc_ctx* c, int64_t n, const int64_t* orb_dev, double* out, hipStream_t s) {
   if (n <= 0) return;
+  if (c->sector != 0) {
+    ea_left_rows(c, n, orb_dev, out, s);
+    return;
+  }
   hipLaunchKernelGGL(left_rows_kernel, dim3(blocks_for(c->Dp), unsigned(n)), dim3(256), 0, s, orb_dev,
                      c->left.as<double>(), c->l1c.as<double>(), c->l2 ? c->l2 : c->t2, out, c->o, c->v, c->o_pad,
                      c->Dp);

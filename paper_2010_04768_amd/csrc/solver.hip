@@ -725,6 +725,7 @@ struct BatchRun {
       const gfcc_ctx* c = L.c;
       mix(uint64_t(c->o));
       mix(uint64_t(c->v));
+      mix(uint64_t(c->sector));
       mix(uint64_t(c->Q));
       const int64_t n = std::min<int64_t>(c->Dp, 2048);
       std::vector<double> dg(size_t(2 * n));
@@ -915,7 +916,7 @@ struct BatchRun {
     // orbital with its norm; occupied p keep the implicit unit vector e_p.
     std::vector<int64_t> borb;
     for (int64_t r : L.rows)
-      if (p[r] >= c->o && !L.brow_of.count(p[r])) {
+      if (c->materialised(p[r]) && !L.brow_of.count(p[r])) {
         L.brow_of[p[r]] = int(borb.size());
         borb.push_back(p[r]);
       }
@@ -937,7 +938,7 @@ struct BatchRun {
     L.lrows = c->left.as<double>();
     bool virt = false;
     if (q) {
-      for (int64_t k = 0; k < nq; ++k) virt = virt || q[k] >= c->o;
+      for (int64_t k = 0; k < nq; ++k) virt = virt || c->materialised(q[k]);
     } else {
       virt = !borb.empty();
     }
@@ -983,7 +984,7 @@ struct BatchRun {
         ++L.next;
         continue;
       }
-      const int br = p[r] >= c->o ? L.brow_of.at(p[r]) : -1;
+      const int br = c->materialised(p[r]) ? L.brow_of.at(p[r]) : -1;
       const double bn = br < 0 ? 1.0 : L.bnorm_h[size_t(br)];
       if (!(bn > 0.0)) {  // b_p = 0 (no amplitude reaches this orbital): X = 0, G = 0
         info[r] = gfcc_rhs_info{0, 0, 0, 0, 0.0};
@@ -1235,7 +1236,7 @@ struct BatchRun {
                          L.lrows, G);
       if (Xout)
         hipLaunchKernelGGL(xout_kernel, dim3(std::min<int64_t>((c->D + 255) / 256, 1024), nd), dim3(256), 0, s, d,
-                           L.d_list.as<int>(), L.d_rows.as<int64_t>(), Xout, c->D, c->o, c->o_pad);
+                           L.d_list.as<int>(), L.d_rows.as<int64_t>(), Xout, c->D, c->n1, c->p1);
       GFCC_HIP(hipGetLastError());
       GFCC_HIP(hipStreamSynchronize(s));
       ckpt_write(done_rows);
@@ -1258,6 +1259,7 @@ struct BatchRun {
     if (opts->tune_cache) {  // ring-GEMM tiles for each full window (inner precision and FP64)
       const Prec ip = prec == GFCC_FP64 ? Prec::F64 : (prec == GFCC_FP32_IR ? Prec::F32 : Prec::BF16);
       for (auto& L : lanes) {
+        if (L.c->sector != 0) continue;  // the tuned shapes are the ionisation sector's
         tune_load(L.c, opts->tune_cache);
         tune_ring(L.c, ip, 2 * int64_t(L.B), s);
         if (ip != Prec::F64) tune_ring(L.c, Prec::F64, 2 * int64_t(L.B), s);

@@ -29,7 +29,7 @@ SYMBOLS = ["gfcc_build_intermediates", "gfcc_dims", "gfcc_export", "gfcc_sigma",
            "gfcc_mlp_forward", "gfcc_mlp_loss_grad", "gfcc_mlp_features", "gfcc_mlp_apply",
            "gfcc_mor_reset", "gfcc_mor_extend", "gfcc_mor_model", "gfcc_mor_export", "gfcc_mor_greens",
            "gfcc_solve_shifts", "gfcc_spectral", "gfcc_solve_multi", "gfcc_mlp_adam_step",
-           "gfcc_greens_noalloc", "gfcc_plan_memory"]
+           "gfcc_greens_noalloc", "gfcc_plan_memory", "gfcc_build_ea_intermediates"]
 
 
 class GfccSystem(ctypes.Structure):
@@ -105,6 +105,8 @@ def load():
     L = ctypes.CDLL(LIB_PATH)
     vp, i64, dbl = ctypes.c_void_p, ctypes.c_int64, ctypes.c_double
     L.gfcc_build_intermediates.argtypes = [ctypes.POINTER(GfccSystem), vp, ctypes.POINTER(vp)]
+    L.gfcc_build_ea_intermediates.argtypes = [ctypes.POINTER(GfccSystem), vp, ctypes.POINTER(vp)]
+    L.gfcc_build_ea_intermediates.restype = ctypes.c_int
     L.gfcc_dims.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64)]
     L.gfcc_export.argtypes = [vp, ctypes.c_int, vp, vp]
     L.gfcc_sigma.argtypes = [vp, i64, vp, vp, ctypes.c_int, vp]
@@ -227,9 +229,13 @@ def solve_multi(ctxs, sys, p, omega, eta, q=None, tol=1e-8, restart=30, max_iter
 
 
 class Context:
-    """Owns one gfcc_ctx (per-system intermediates on the current device)."""
+    """Owns one gfcc_ctx (per-system intermediates on the current device).
 
-    def __init__(self, eps, L, t1, t2, l1=None, l2=None):
+    ``sector="ip"`` builds the ionisation (retarded) term on 1h + 2h1p; ``sector="ea"`` the
+    electron-attached (advanced) term on 1p + 2p1h, whose ``solve`` returns
+    G[r][k] = G^EA_{q[k] p[r]} (see gfcc_build_ea_intermediates)."""
+
+    def __init__(self, eps, L, t1, t2, l1=None, l2=None, sector="ip"):
         import torch
         self._lib = load()
         dev = torch.device("cuda", torch.cuda.current_device())
@@ -247,8 +253,11 @@ class Context:
                           a2.data_ptr(), b1.data_ptr() if b1 is not None else None,
                           b2.data_ptr() if b2 is not None else None)
         h = ctypes.c_void_p()
-        _check(self._lib.gfcc_build_intermediates(ctypes.byref(sysd), _stream(), ctypes.byref(h)),
-               "gfcc_build_intermediates")
+        if sector not in ("ip", "ea"):
+            raise ValueError("sector must be 'ip' or 'ea'")
+        self.sector = sector
+        build = "gfcc_build_intermediates" if sector == "ip" else "gfcc_build_ea_intermediates"
+        _check(getattr(self._lib, build)(ctypes.byref(sysd), _stream(), ctypes.byref(h)), build)
         self._h = h
         # the context borrows t2 (and l2) until it is destroyed; eps, L, t1, l1 were read by the build
         self._keep = [a2, b2]
@@ -258,8 +267,8 @@ class Context:
         self.device = dev
 
     @classmethod
-    def from_system(cls, s):
-        return cls(s.eps, s.L, s.t1, s.t2, s.l1, s.l2)
+    def from_system(cls, s, sector="ip"):
+        return cls(s.eps, s.L, s.t1, s.t2, s.l1, s.l2, sector=sector)
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

@@ -1,0 +1,179 @@
+"""GPU parity of the electron-attached (advanced) term against its oracle (oracle.eagfcc,
+pinned block by block to the N+1-sector brute force).
+
+* sigma (the 1p + 2p1h product of Hbar_N) elementwise at 1e-12 of its scale, on shapes with
+  odd and even v, several GEMM tiles and ragged tails, Lambda = T^dagger and independent;
+* the exact diagonal and the one-body blocks at 1e-12;
+* G^EA through GMRES (Jacobi and plain) at 1e-10 against the oracle's dense solve, occupied and
+  virtual q and p; the bilinear product on the returned Y;
+* free particles: G = G^IP + G^EA = diag 1/(omega - eps_p -/+ i eta) over every orbital, and
+  A = A^IP + A^EA (the EA term with the opposite sign of eta);
+* entry points that need the IP sector's operands refuse an EA context.
+"""
+import numpy as np
+import pytest
+
+from oracle import eagfcc as E
+from oracle import ipgfcc as O
+from synth import make_system, random_vectors
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2010_04768_amd import gfcc  # noqa: E402
+
+ETA = 0.01
+
+
+def _independent_lambda(s, seed):
+    rng = np.random.default_rng(seed)
+    s.l1 = rng.normal(0, 0.05, s.t1.shape)
+    l2 = rng.normal(0, 0.05, s.t2.shape)
+    s.l2 = l2 + l2.transpose(1, 0, 3, 2)
+    return s
+
+
+SHAPES = [(3, 5, 8, "t"), (4, 7, 12, "indep"), (8, 24, 40, "t"), (10, 33, 50, "indep")]
+
+
+@pytest.fixture(scope="module", params=SHAPES, ids=lambda p: f"o{p[0]}v{p[1]}Q{p[2]}-{p[3]}")
+def sysea(request):
+    o, v, Q, lam = request.param
+    print(f"\n[ea] building o={o} v={v} Q={Q} lambda={lam}", flush=True)
+    s = make_system(o, v, Q, 2010_04768 + 40 + o, sigma_L=0.1, sigma_t1=0.03)
+    if lam == "indep":
+        s = _independent_lambda(s, 9)
+    eim = E.intermediates(s)
+    ctx = gfcc.Context.from_system(s, sector="ea")
+    yield s, eim, ctx
+    ctx.close()
+
+
+def test_dims(sysea):
+    s, eim, ctx = sysea
+    assert ctx.dim == s.n_vir + s.n_occ * s.n_vir ** 2
+
+
+def test_sigma_matches_oracle(sysea):
+    s, eim, ctx = sysea
+    D = ctx.dim
+    Y = random_vectors(5, D, seed=3)
+    got = ctx.sigma(torch.from_numpy(Y)).cpu().numpy()
+    want = E.sigma(eim, Y)
+    scale = np.abs(want).max()
+    err = np.abs(got - want).max()
+    print(f"[ea] sigma max err {err:.3e} (scale {scale:.3e})")
+    assert err <= 1e-12 * scale
+    # real-linear: one real vector alone
+    g1 = ctx.sigma(torch.from_numpy(Y[0].real.astype(complex))).cpu().numpy()
+    assert np.abs(g1 - E.sigma(eim, Y[0].real)).max() <= 1e-12 * scale
+
+
+def test_diagonal_and_one_body_blocks(sysea):
+    s, eim, ctx = sysea
+    d = ctx.export("DIAG").cpu().numpy()
+    dref = E.diagonal(eim)
+    assert np.abs(d - dref).max() <= 1e-12 * np.abs(dref).max()
+    for name, key in [("FOO", "Foo"), ("FVV", "Fvv"), ("FOV", "Fov")]:
+        got = ctx.export(name).cpu().numpy()
+        want = eim[key]
+        assert np.abs(got - want).max() <= 1e-12 * max(1.0, np.abs(want).max()), name
+
+
+def test_greens_matches_oracle(sysea):
+    s, eim, ctx = sysea
+    o, v = s.n_occ, s.n_vir
+    n = o + v
+    if ctx.dim > 6000:
+        pytest.skip("the dense oracle solve is kept to the smaller shapes")
+    H = E.explicit_matrix(eim)
+    D = H.shape[0]
+    qs = [o, n - 1, 0, o - 1, o + v // 2]
+    ws = [0.6, 1.1, 0.35, 0.9, 1.6]
+    ps = list(range(n))
+    C = np.stack([E.left_vector(s, p) for p in ps])
+    for precond in ("jacobi", "none"):
+        G, info, X = ctx.solve(qs, ws, ETA, q=ps, tol=1e-12, restart=40, max_iter=4000, precond=precond,
+                               want_x=True)
+        G = G.cpu().numpy()
+        X = X.cpu().numpy()
+        for r, (q, w) in enumerate(zip(qs, ws)):
+            b = E.rhs(s, q)
+            if not np.any(b):
+                assert info[r]["status"] == 0 and np.abs(G[r]).max() == 0.0
+                continue
+            assert info[r]["status"] == 0 and info[r]["true_rel_resid"] <= 1e-12, info[r]
+            y = np.linalg.solve((w + 1j * ETA) * np.eye(D) - H, b)
+            assert np.abs(X[r] - y).max() <= 1e-10 * np.abs(y).max()
+            gref = C @ y
+            assert np.abs(G[r] - gref).max() <= 1e-10 * max(1.0, np.abs(gref).max()), (precond, q, w)
+        # the bilinear product on the returned vectors
+        Gb = ctx.greens(torch.from_numpy(X), ps).cpu().numpy()
+        assert np.abs(Gb - G).max() <= 1e-12 * max(1.0, np.abs(G).max())
+
+
+def test_greens_larger_shape_against_oracle_gmres(sysea):
+    """Shapes too large for a dense solve: the oracle's own GMRES (tol 1e-13) on a few (q, omega)."""
+    s, eim, ctx = sysea
+    o, v = s.n_occ, s.n_vir
+    if ctx.dim <= 6000:
+        pytest.skip("covered by the dense comparison")
+    qs, ws = [o + 1, 0], [0.8, 1.2]
+    ps = [o + 1, 0, o + v - 1]
+    G, info, _ = ctx.solve(qs, ws, ETA, q=ps, tol=1e-12, restart=60, max_iter=6000)
+    G = G.cpu().numpy()
+    for r, (q, w) in enumerate(zip(qs, ws)):
+        assert info[r]["status"] == 0, info[r]
+        gref = E.greens(s, eim, q, [w], ETA, ps=ps, tol=1e-13, restart=60)[0]
+        assert np.abs(G[r] - gref).max() <= 1e-10 * max(1.0, np.abs(gref).max())
+
+
+def test_full_greens_free_particles():
+    """T = Lambda = L = 0: G^IP + G^EA is diag 1/(omega - eps_p - i eta) for occupied p and
+    1/(omega - eps_p + i eta) for virtual p; the spectral function of the sum is the sum of the
+    Lorentzians."""
+    o, v = 3, 6
+    s = make_system(o, v, 4, 77, t1=False, t2=False, lam=False, L_zero=True)
+    ip = gfcc.Context.from_system(s)
+    ea = gfcc.Context.from_system(s, sector="ea")
+    n = o + v
+    ws = [-0.9, 0.4, 1.3]
+    P = [p for p in range(n) for _ in ws]
+    W = [w for _ in range(n) for w in ws]
+    Gi, ii, _ = ip.solve(P, W, ETA, q=list(range(n)), tol=1e-13)
+    Ge, ie, _ = ea.solve(P, W, ETA, q=list(range(n)), tol=1e-13)
+    G = (Gi + Ge).cpu().numpy()
+    for r, (p, w) in enumerate(zip(P, W)):
+        e = s.eps[p]
+        want = np.zeros(n, complex)
+        want[p] = 1.0 / (w - e - 1j * ETA) if p < o else 1.0 / (w - e + 1j * ETA)
+        assert np.abs(G[r] - want).max() <= 1e-12 * np.abs(want).max(), (p, w)
+    # A(omega) = A^IP + A^EA: the EA poles sit on the other side of the real axis (+i eta), so its
+    # term enters with the opposite sign of eta; sum_p eta/pi / ((omega - eps_p)^2 + eta^2)
+    def diag(Gt):
+        Gt = Gt.cpu().numpy()
+        return torch.from_numpy(np.array([[Gt[p * len(ws) + k, p] for k in range(len(ws))] for p in range(n)]))
+    A = (gfcc.spectral(diag(Gi).to(ip.device), ETA) + gfcc.spectral(diag(Ge).to(ip.device), -ETA)).cpu().numpy()
+    for k, w in enumerate(ws):
+        ref = sum(ETA / np.pi / ((w - s.eps[p]) ** 2 + ETA ** 2) for p in range(n))
+        assert abs(A[k] - ref) <= 1e-10 * ref
+    ip.close()
+    ea.close()
+
+
+def test_ip_only_entry_points_refuse_ea_context(sysea):
+    s, eim, ctx = sysea
+    o = s.n_occ
+    with pytest.raises(RuntimeError, match="electron-attachment"):
+        ctx.sigma(torch.zeros(1, ctx.dim, dtype=torch.complex128), precision="bf16")
+    with pytest.raises(RuntimeError):
+        ctx.solve([o], [0.5], ETA, precond="mlp")
+    with pytest.raises(RuntimeError):
+        ctx.solve([o], [0.5], ETA, precision="bf16")
+    with pytest.raises(RuntimeError, match="electron-attachment"):
+        ctx.solve_shifts([o], [0.5], ETA)
+    with pytest.raises(RuntimeError, match="electron-attachment"):
+        ctx.export("WOVVO")
