@@ -64,6 +64,8 @@ def parse():
     ap.add_argument("--c60-restart", type=int, default=12)
     ap.add_argument("--c60-ref-dim", type=int, default=64, help="basis cap of the multi-shift reference")
     ap.add_argument("--no-secondary", action="store_true", help="skip the 40/200/800 block after the headline")
+    ap.add_argument("--no-ea", action="store_true", help="skip the electron-attachment block")
+    ap.add_argument("--only-ea", action="store_true", help="run the electron-attachment block alone")
     ap.add_argument("--form", default="bf16", choices=["bf16", "fp32", "fp64"])
     ap.add_argument("--precond", default="jacobi", choices=["jacobi", "none", "mlp"])
     ap.add_argument("--batch", type=int, default=0)
@@ -127,12 +129,17 @@ def main():
     if args.shifts_study:
         shifts_study(args)
         return
+    if args.only_ea:
+        print(json.dumps({"ea_o40v200": ea_block(args)}), flush=True)
+        return
     if args.workload == "o40":
         out = o40_main(args)
     else:
         out = c60_main(args)
         if not args.no_secondary:
             out["secondary_o40v200"] = o40_main(args, secondary=True)
+    if out is not None and not args.no_ea:
+        out["ea_o40v200"] = ea_block(args)
     if out is not None:
         print(json.dumps(out), flush=True)
 
@@ -390,6 +397,81 @@ def cpu_baseline_c60(sigmas_per_rhs, n_p, eta, shape):
                       f"step; scaled to 120/600/3000 by {r_sigma:.0f}x (sigma, o^3 v^2) and {r_build:.0f}x "
                       f"(intermediates, o^3 v^3, amortised over 400 frequencies) at {sigmas_per_rhs:.1f} sigma "
                       f"applications per right-hand side (GPU-measured) x {n_p} right-hand sides per frequency"}
+
+
+def ea_block(args):
+    """The electron-attached term on the 40/200/800 system (D = v + o v^2 = 1,600,200).
+
+    Build of the EA context (timed), the sigma product's particle-particle ladder GEMM against
+    the FP64 MFMA peak (HIP events on the library's stream; 2 (P o) v^4 flops per launch for P
+    planes), and G^EA for the 8 lowest virtual orbitals q at 8 frequencies on [0.15, 0.55]
+    (FP64 GMRES, Jacobi, tol 1e-8), with four of them re-solved at tol 1e-12 as the check."""
+    import torch
+
+    from paper_2010_04768_amd import gfcc
+    from synth import make_workload, random_vectors
+
+    torch.cuda.set_device(0)
+    wl = make_workload("plain-o40v200", n_omega=2)
+    s = wl.systems[0]
+    o, v = s.n_occ, s.n_vir
+    dev = torch.device("cuda", 0)
+    keep = [torch.from_numpy(a).to(dev) for a in (s.eps, s.L, s.t1, s.t2)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx = gfcc.Context(*keep, sector="ea")
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    D = ctx.dim
+    log(f"EA context o={o} v={v} Q={s.n_chol} D={D} built in {build_s:.1f}s")
+    nvec = 32  # 64 planes
+    X = torch.from_numpy(random_vectors(nvec, D, seed=7)).to(dev)
+    ctx.sigma(X)  # warm-up (workspaces)
+    torch.cuda.synchronize()
+    ctx.prof_enable(True)
+    reps = 3
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ctx.sigma(X)
+    torch.cuda.synchronize()
+    sig_s = (time.perf_counter() - t0) / reps
+    lad = ctx.prof_get("ea_ladder")
+    ring = ctx.prof_get("ea_ring")
+    ctx.prof_enable(False)
+    lad_ms = lad["ms"] / max(lad["count"], 1)
+    lad_flops = lad["flops"] / max(lad["count"], 1)
+    achieved = lad_flops / (lad_ms * 1e-3)
+    roof = {"kernel": "ea_ladder (FP64 GEMM M = 64 planes x o, N = K = v^2)", "bound": "mfma",
+            "achieved": achieved / 1e12, "peak": PEAK["fp64"] / 1e12, "unit": "TFLOP/s",
+            "frac": achieved / PEAK["fp64"], "avg_ms": lad_ms, "launches": lad["count"]}
+    log(f"EA sigma {nvec} vectors: {sig_s * 1e3:.1f} ms; ladder {lad_ms:.1f} ms = {achieved / 1e12:.1f} TFLOP/s "
+        f"({100 * achieved / PEAK['fp64']:.1f}% of FP64 peak); ring {ring['ms'] / max(ring['count'], 1):.2f} ms")
+    qs = list(range(o, o + 8))
+    ws = list(np.linspace(0.15, 0.55, 8))
+    Q = np.repeat(qs, len(ws))
+    W = np.tile(ws, len(qs))
+    t0 = time.perf_counter()
+    G, info, _ = ctx.solve(Q, W, wl.eta, tol=1e-8, restart=30, max_iter=3000, precond="jacobi", precision="fp64")
+    torch.cuda.synchronize()
+    solve_s = time.perf_counter() - t0
+    G = G.cpu().numpy()[:, 0]
+    its = [i["iters"] for i in info]
+    conv = sum(1 for i in info if i["status"] == 0)
+    pick = [0, 9, 27, 63]
+    Gr, infor, _ = ctx.solve(Q[pick], W[pick], wl.eta, tol=1e-12, restart=60, max_iter=6000, precond="jacobi",
+                             precision="fp64")
+    Gr = Gr.cpu().numpy()[:, 0]
+    rel = float(np.max(np.abs(G[pick] - Gr) / np.abs(Gr)))
+    ctx.close()
+    out = {"system": "40/200/800 (the o40v200 workload's system)", "D": D, "build_s": build_s,
+           "sigma_ms_32vec": sig_s * 1e3, "roofline_ladder": roof,
+           "solve": {"rhs": int(Q.size), "q": "8 lowest virtual orbitals", "omega": "8 points on [0.15, 0.55]",
+                     "eta": wl.eta, "tol": 1e-8, "seconds": solve_s, "omega_pts_per_s": len(ws) / solve_s,
+                     "converged": conv, "iters_min_med_max": [int(min(its)), int(np.median(its)), int(max(its))],
+                     "max_true_rel_resid": float(max(i["true_rel_resid"] for i in info)),
+                     "check_rel_err_vs_tol1e-12": rel}}
+    log(f"EA solve {Q.size} RHS in {solve_s:.1f}s ({conv} converged), G rel err vs tol 1e-12: {rel:.1e}")
+    return out
 
 
 def shift_reference(ctx, plist, omegas, eta, max_dim):
