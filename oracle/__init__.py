@@ -17,4 +17,7 @@ generator in ``synth``.
 * ``oracle.eagfcc`` -- O2 for the advanced (electron-attached) term: the
   spin-adapted 1p + 2p1h sigma product, its intermediates, diagonal, right-hand
   sides and left vectors, pinned against the N+1-sector brute force of O1.
+* ``oracle.openshell`` -- the open-shell (spin-unrestricted) IP term: a brute
+  force over both ionised sectors and the spin-orbital working equations,
+  pinned against it and, for identical spins, against ``oracle.ipgfcc``.
 """

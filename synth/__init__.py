@@ -207,3 +207,133 @@ def random_vectors(n_vec: int, dim: int, seed: int) -> np.ndarray:
     """Complex128 test vectors [n_vec, dim] with N(0,1) real and imaginary parts."""
     rng = np.random.Generator(np.random.PCG64(seed))
     return rng.normal(size=(n_vec, dim)) + 1j * rng.normal(size=(n_vec, dim))
+
+
+# ------------------------------------------------------------------ open-shell (spin-unrestricted) systems
+
+@dataclasses.dataclass
+class OpenShellSystem:
+    """One synthetic spin-unrestricted system in spin blocks (float64, C-contiguous).
+
+    n spatial orbitals per spin; n_occ_a alpha and n_occ_b beta electrons (n_occ_a >= n_occ_b).
+    Chemist integrals between orbitals of spins s and s' are (pq|rs) = sum_Q L_s[Q,p,q] L_s'[Q,r,s].
+    Amplitudes: t1a [oa][va], t1b [ob][vb], t2aa [oa][oa][va][va] and t2bb (antisymmetric in the
+    occupied and in the virtual pair), t2ab [oa][ob][va][vb] (t_{i alpha j beta}^{a alpha b beta});
+    the l's in the same layouts."""
+
+    n: int
+    n_occ_a: int
+    n_occ_b: int
+    n_chol: int
+    eps_a: np.ndarray
+    eps_b: np.ndarray
+    La: np.ndarray
+    Lb: np.ndarray
+    t1a: np.ndarray
+    t1b: np.ndarray
+    t2aa: np.ndarray
+    t2ab: np.ndarray
+    t2bb: np.ndarray
+    l1a: np.ndarray
+    l1b: np.ndarray
+    l2aa: np.ndarray
+    l2ab: np.ndarray
+    l2bb: np.ndarray
+    seed: int
+
+    @property
+    def n_vir_a(self) -> int:
+        return self.n - self.n_occ_a
+
+    @property
+    def n_vir_b(self) -> int:
+        return self.n - self.n_occ_b
+
+    @property
+    def n_occ(self) -> int:
+        """Occupied spin orbitals."""
+        return self.n_occ_a + self.n_occ_b
+
+    @property
+    def n_vir(self) -> int:
+        """Virtual spin orbitals."""
+        return self.n_vir_a + self.n_vir_b
+
+    @property
+    def dim(self) -> int:
+        """Spin-orbital 1h + 2h1p space with both (i, j) orders stored: o + o*o*v."""
+        return self.n_occ + self.n_occ * self.n_occ * self.n_vir
+
+
+def make_open_shell_system(n: int, n_occ_a: int, n_occ_b: int, n_chol: int, seed: int, *,
+                           sigma_L: float = 0.05, sigma_dL: float = 0.02, sigma_t1: float = 1e-3,
+                           occ_range=(-1.2, -0.3), vir_range=(0.1, 2.0),
+                           t1: bool = True, t2: bool = True, lam: bool = True,
+                           L_zero: bool = False) -> OpenShellSystem:
+    """Draw one open-shell system.  Recipe (one PCG64(seed) stream, in this order):
+
+    1. eps_a: n_occ_a occupied ~ U(occ_range), n - n_occ_a virtual ~ U(vir_range), each sorted;
+       eps_b likewise with n_occ_b.
+    2. La symmetric in (p, q), upper triangle i.i.d. N(0, sigma_L^2); Lb = La + a symmetric
+       N(0, sigma_dL^2) perturbation (the beta orbitals differ from the alpha ones).
+    3. t1a ~ N(0, sigma_t1^2), then t1b.
+    4. T2 = MP2 amplitudes <ij||ab> / (e_i + e_j - e_a - e_b) per spin block:
+       aa: (ia|jb) - (ib|ja) from La; bb from Lb; ab: (ia|jb) with (ia) from La, (jb) from Lb.
+    5. Lambda = T^dagger (the l's are copies)."""
+    if not (1 <= n_occ_b <= n_occ_a < n):
+        raise ValueError("need 1 <= n_occ_b <= n_occ_a < n")
+    oa, ob, Q = int(n_occ_a), int(n_occ_b), int(n_chol)
+    va, vb = n - oa, n - ob
+    rng = np.random.Generator(np.random.PCG64(seed))
+
+    def energies(o):
+        eo = np.sort(rng.uniform(occ_range[0], occ_range[1], size=o))
+        ev = np.sort(rng.uniform(vir_range[0], vir_range[1], size=n - o))
+        return np.concatenate([eo, ev])
+
+    eps_a = energies(oa)
+    eps_b = energies(ob)
+    iu, ju = np.triu_indices(n)
+
+    def sym(sig):
+        M = np.zeros((Q, n, n))
+        vals = rng.normal(0.0, sig, size=(Q, iu.size))
+        M[:, iu, ju] = vals
+        M[:, ju, iu] = vals
+        return M
+
+    La = sym(sigma_L)
+    Lb = La + sym(sigma_dL)
+    if L_zero:
+        La[:] = 0.0
+        Lb[:] = 0.0
+    T1a = rng.normal(0.0, sigma_t1, size=(oa, va))
+    T1b = rng.normal(0.0, sigma_t1, size=(ob, vb))
+    if not t1:
+        T1a[:] = 0.0
+        T1b[:] = 0.0
+
+    def ovov(L1, o1, L2, o2):
+        A = L1[:, :o1, o1:].reshape(Q, -1)
+        B = L2[:, :o2, o2:].reshape(Q, -1)
+        return (A.T @ B).reshape(o1, n - o1, o2, n - o2)  # (ia|jb)
+
+    def denom(e1, o1, e2, o2):
+        return (e1[:o1, None, None, None] + e2[None, None, :o2, None]
+                - e1[None, o1:, None, None] - e2[None, None, None, o2:])  # [i, a, j, b]
+
+    if t2:
+        g = ovov(La, oa, La, oa)
+        T2aa = ((g - g.transpose(0, 3, 2, 1)) / denom(eps_a, oa, eps_a, oa)).transpose(0, 2, 1, 3)
+        g = ovov(Lb, ob, Lb, ob)
+        T2bb = ((g - g.transpose(0, 3, 2, 1)) / denom(eps_b, ob, eps_b, ob)).transpose(0, 2, 1, 3)
+        g = ovov(La, oa, Lb, ob)
+        T2ab = (g / denom(eps_a, oa, eps_b, ob)).transpose(0, 2, 1, 3)
+    else:
+        T2aa = np.zeros((oa, oa, va, va))
+        T2bb = np.zeros((ob, ob, vb, vb))
+        T2ab = np.zeros((oa, ob, va, vb))
+    T2aa, T2ab, T2bb = (np.ascontiguousarray(x) for x in (T2aa, T2ab, T2bb))
+    amps = [T1a, T1b, T2aa, T2ab, T2bb]
+    lams = [x.copy() for x in amps] if lam else [np.zeros_like(x) for x in amps]
+    return OpenShellSystem(n, oa, ob, Q, eps_a, eps_b, La, Lb, *amps, *lams, seed)
