@@ -137,6 +137,58 @@ gfcc_status gfcc_build_intermediates(const gfcc_system* sys, void* stream, gfcc_
  * blocks (ov|vv) and the v^4 product.  Blocking.  Errors as gfcc_build_intermediates. */
 gfcc_status gfcc_build_ea_intermediates(const gfcc_system* sys, void* stream, gfcc_ctx** out);
 
+/* One open-shell (spin-unrestricted) system in spin blocks.  Device pointers, FP64.
+ *   n                   spatial orbitals per spin; n_occ_a alpha and n_occ_b beta electrons
+ *                       (1 <= n_occ_b <= n_occ_a < n); va = n - n_occ_a, vb = n - n_occ_b
+ *   eps_a, eps_b [n]    orbital energies of each spin (Fock matrices diagonal), occupied first
+ *   La, Lb [Q][n][n]    Cholesky vectors of each spin's orbitals, symmetric in (p,q):
+ *                       (pq|rs) = sum_Q L_s[Q][p][q] L_s'[Q][r][s] for p,q of spin s and r,s of s'
+ *   t1a [oa][va], t1b [ob][vb]
+ *   t2aa [oa][oa][va][va], t2bb [ob][ob][vb][vb]   antisymmetric in (i,j) and in (a,b)
+ *   t2ab [oa][ob][va][vb]                          t_{i alpha, j beta}^{a alpha, b beta}
+ *   l1a ... l2bb        Lambda in the same layouts; all NULL means Lambda = T^dagger.
+ * Everything is read during gfcc_build_uhf_intermediates only (the context keeps its own
+ * spin-orbital copies). */
+typedef struct {
+  int64_t n, n_occ_a, n_occ_b, n_chol;
+  const double* eps_a;
+  const double* eps_b;
+  const double* La;
+  const double* Lb;
+  const double* t1a;
+  const double* t1b;
+  const double* t2aa;
+  const double* t2ab;
+  const double* t2bb;
+  const double* l1a;
+  const double* l1b;
+  const double* l2aa;
+  const double* l2ab;
+  const double* l2bb;
+} gfcc_uhf_system;
+
+/* Build the context of the retarded IP term for an open-shell reference (Theory section: the
+ * first term of the Green's function and the linear system for X_p; the open-shell
+ * GFCCSD-IP of the Evaluation section, Table 2, treats alpha and beta electrons separately).
+ * Everything is over spin orbitals: o = n_occ_a + n_occ_b occupied ones ordered
+ * [alpha 0..oa-1, beta 0..ob-1], v = va + vb virtual ones ordered [alpha, beta]; orbital
+ * indices p, q of the other entry points run over [0, o + v) in that order (occupied first).
+ * Both ionised sectors (an alpha or a beta electron removed) live in one space of dimension
+ * D = o + o*o*v:
+ *     x[0 .. o)                = r_i
+ *     x[o + (i*o + j)*v + a]   = r_ij^a,  stored for both orders: r_ji^a = -r_ij^a, r_ii^a = 0
+ * with R = sum_i r_i a_i + 1/2 sum_ija r_ij^a a_a^+ a_j a_i.  gfcc_sigma returns Hbar_N X
+ * (antisymmetric inputs give antisymmetric outputs; FP64 only); gfcc_solve_batch solves
+ * (omega + Hbar_N - i eta) X_p = abar_p|Phi> (occupied p: e_p; virtual p = o + a:
+ * r_i = t_i^a, r_ij^b = t_ij^ab) and G[r][k] = G_{q[k] p[r]} = c_q . X_p with the left rows
+ * carrying 1/2 on their 2h1p block (each pair counted once); G vanishes between orbitals of
+ * different spin.  FP64 only; GFCC_PC_MLP is E_STATE.  gfcc_greens(_noalloc), gfcc_export
+ * (FOO, FVV, FOV over spin orbitals, DIAG [D]), gfcc_prof_*, gfcc_destroy work on it; every
+ * other entry point returns E_STATE.  Storage: spin-orbital <oo||vv>, W_oooo, W_ooov, W_ovvo,
+ * W_ovoo and the amplitudes (o^2 v^2 each); the build's temporaries hold the <ov||vv> blocks
+ * and the spin-orbital Cholesky vectors.  Blocking.  E_ARG for bad sizes or missing blocks. */
+gfcc_status gfcc_build_uhf_intermediates(const gfcc_uhf_system* sys, void* stream, gfcc_ctx** out);
+
 /* Device-memory plan of one system in bytes (host arithmetic only, no GPU
  * needed): the caller's inputs, each operand the context keeps in FP64 and in
  * the reduced precision `prec`, the build's fixed temporaries and smallest

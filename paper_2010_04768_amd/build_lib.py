@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libgfcc.so")
-SOURCES = ["gemm.hip", "tensor.hip", "build.hip", "sigma.hip", "solver.hip", "mlp.hip", "tune.hip", "mor.hip", "shifts.hip", "ea.hip", "api.hip"]
+SOURCES = ["gemm.hip", "tensor.hip", "build.hip", "sigma.hip", "solver.hip", "mlp.hip", "tune.hip", "mor.hip", "shifts.hip", "ea.hip", "uhf.hip", "api.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 CFLAGS = ["-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}",

@@ -63,7 +63,8 @@ static hipStream_t as_stream(void* s) { return static_cast<hipStream_t>(s); }
 // entry points built on the ionisation sector's operands only
 static void ip_sector(const gfcc_ctx* c, const char* what) {
   GFCC_CHECK(c, GFCC_E_ARG, "null context");
-  GFCC_CHECK(c->sector == 0, GFCC_E_STATE, std::string(what) + " is not available on an electron-attachment context");
+  GFCC_CHECK(c->sector == 0, GFCC_E_STATE,
+             std::string(what) + " is not available on an electron-attachment or open-shell context");
 }
 
 extern "C" {
@@ -151,6 +152,52 @@ gfcc_status gfcc_build_ea_intermediates(const gfcc_system* sys, void* stream, gf
   });
 }
 
+gfcc_status gfcc_build_uhf_intermediates(const gfcc_uhf_system* sys, void* stream, gfcc_ctx** out) {
+  return guarded([&] {
+    GFCC_CHECK(sys && out, GFCC_E_ARG, "null argument");
+    GFCC_CHECK(sys->n >= 2 && sys->n <= 2048 && sys->n_chol >= 1, GFCC_E_ARG, "bad n or n_chol");
+    GFCC_CHECK(sys->n_occ_b >= 1 && sys->n_occ_b <= sys->n_occ_a && sys->n_occ_a < sys->n, GFCC_E_ARG,
+               "need 1 <= n_occ_b <= n_occ_a < n");
+    GFCC_CHECK(sys->eps_a && sys->eps_b && sys->La && sys->Lb && sys->t1a && sys->t1b && sys->t2aa && sys->t2ab &&
+                   sys->t2bb, GFCC_E_ARG, "eps, L, t1 and t2 blocks are required");
+    const bool lam = sys->l1a || sys->l1b || sys->l2aa || sys->l2ab || sys->l2bb;
+    GFCC_CHECK(!lam || (sys->l1a && sys->l1b && sys->l2aa && sys->l2ab && sys->l2bb), GFCC_E_ARG,
+               "give every Lambda block or none");
+    *out = nullptr;
+    gfcc_ctx* c = new gfcc_ctx();
+    try {
+      c->sector = 2;
+      c->o = sys->n_occ_a + sys->n_occ_b;
+      c->v = 2 * sys->n - c->o;
+      c->Q = sys->n_chol;
+      c->n = c->o + c->v;
+      c->ov = c->o * c->v;
+      c->oo = c->o * c->o;
+      c->oov = c->oo * c->v;
+      c->o_pad = round_up(c->o, 8);
+      c->n1 = c->o;
+      c->p1 = c->o_pad;
+      c->n2 = c->oov;
+      c->D = c->n1 + c->n2;
+      c->Dp = c->p1 + round_up(c->n2, 8);
+      c->kp = round_up(c->ov, 8);
+      c->k2 = 2 * c->kp;
+      c->op2 = round_up(c->oo, 8);
+      c->vp = round_up(c->v, 8);
+      c->Qp = round_up(c->Q, 8);
+      hipStream_t s = as_stream(stream);
+      GFCC_HIP(hipGetDevice(&c->device));
+      c->fixed_scratch = fixed_scratch_address(c->device);
+      build_uhf(c, sys, s);
+      GFCC_HIP(hipStreamSynchronize(s));
+    } catch (...) {
+      delete c;
+      throw;
+    }
+    *out = c;
+  });
+}
+
 gfcc_status gfcc_plan_memory(int64_t n_occ, int64_t n_vir, int64_t n_chol, gfcc_precision prec, int32_t restart,
                              int32_t flexible, int64_t window, int32_t lambda_given, gfcc_memory_plan* out) {
   return guarded([&] {
@@ -197,7 +244,7 @@ gfcc_status gfcc_export(gfcc_ctx* c, gfcc_block which, double* dst, void* stream
   return guarded([&] {
     GFCC_CHECK(c && dst, GFCC_E_ARG, "null argument");
     GFCC_CHECK(c->sector == 0 || which == GFCC_FOO || which == GFCC_FVV || which == GFCC_FOV || which == GFCC_DIAG,
-               GFCC_E_STATE, "an electron-attachment context exports FOO, FVV, FOV and DIAG only");
+               GFCC_E_STATE, "an electron-attachment or open-shell context exports FOO, FVV, FOV and DIAG only");
     hipStream_t s = as_stream(stream);
     const int64_t o = c->o, v = c->v, kp = c->kp, k2 = c->k2;
     const int id4[4] = {0, 1, 2, 3};
@@ -268,7 +315,8 @@ gfcc_status gfcc_sigma(gfcc_ctx* c, int64_t nrhs, const double* X, double* Y, gf
     GFCC_CHECK(c, GFCC_E_ARG, "null context");
     GFCC_CHECK(nrhs >= 0, GFCC_E_ARG, "nrhs < 0");
     GFCC_CHECK(prec == GFCC_FP64 || prec == GFCC_FP32_IR || prec == GFCC_BF16_IR, GFCC_E_ARG, "bad precision");
-    GFCC_CHECK(c->sector == 0 || prec == GFCC_FP64, GFCC_E_ARG, "the electron-attachment sigma runs in FP64 only");
+    GFCC_CHECK(c->sector == 0 || prec == GFCC_FP64, GFCC_E_ARG,
+               "the electron-attachment and open-shell sigma run in FP64 only");
     if (nrhs == 0) return;
     GFCC_CHECK(X && Y && X != Y, GFCC_E_ARG, "X and Y must be distinct device buffers");
     hipStream_t s = as_stream(stream);
@@ -411,10 +459,13 @@ gfcc_status gfcc_solve_batch(gfcc_ctx* c, int64_t nrhs, const int64_t* p, const 
     GFCC_CHECK(opts->precond >= GFCC_PC_NONE && opts->precond <= GFCC_PC_MLP, GFCC_E_ARG, "bad preconditioner");
     GFCC_CHECK(opts->precision >= GFCC_FP64 && opts->precision <= GFCC_BF16_IR, GFCC_E_ARG, "bad precision");
     if (c->sector != 0) {
-      // (omega - Hbar_N + i eta) Y = abar^+|Phi>  is solved as  (-omega - i eta + Hbar_N) Y = -abar^+|Phi>
-      GFCC_CHECK(opts->precision == GFCC_FP64, GFCC_E_ARG, "the electron-attachment solve runs in FP64 only");
+      GFCC_CHECK(opts->precision == GFCC_FP64, GFCC_E_ARG,
+                 "the electron-attachment and open-shell solves run in FP64 only");
       GFCC_CHECK(opts->precond != GFCC_PC_MLP, GFCC_E_STATE,
-                 "the learned preconditioner is trained on the ionisation sector only");
+                 "the learned preconditioner is trained on the closed-shell ionisation sector only");
+    }
+    if (c->sector == 1) {
+      // (omega - Hbar_N + i eta) Y = abar^+|Phi>  is solved as  (-omega - i eta + Hbar_N) Y = -abar^+|Phi>
       std::vector<double> wneg(static_cast<size_t>(nrhs));
       for (int64_t r = 0; r < nrhs; ++r) wneg[size_t(r)] = -omega[r];
       solve_batch(c, nrhs, p, wneg.data(), eta, nq, q, opts, G, X, info, as_stream(stream), &all_conv, nullptr);

@@ -24,7 +24,8 @@ struct gfcc_ctx {
   int64_t vp = 0;     // padded row length for K = v operands
   int64_t Qp = 0;     // padded Cholesky rank (rows of Q-innermost operands)
 
-  // Sector of the expansion: 0 = ionisation (1h + 2h1p), 1 = electron attachment (1p + 2p1h).
+  // Sector of the expansion: 0 = ionisation (1h + 2h1p), 1 = electron attachment (1p + 2p1h),
+  // 2 = ionisation of an open-shell reference over spin orbitals (1h + 2h1p, both pair orders).
   // A plane holds the first block at [0, n1) and the second at [p1, p1 + n2); D = n1 + n2.
   int sector = 0;
   int64_t n1 = 0, p1 = 0, n2 = 0;
@@ -65,6 +66,14 @@ struct gfcc_ctx {
     gfcc::DBuf Sl;      // [a][b]         sum_ijc t2[i,j,a,c] (2 l2[i,j,b,c] - l2[i,j,c,b])
     gfcc::DBuf ws_R, ws_z;  // sigma operand copies
   } ea;
+
+  // open-shell (spin-unrestricted) IP blocks (sector 2), FP64, over spin orbitals
+  struct UHF {
+    gfcc::DBuf t1, t2, l1, l2;              // spin-orbital amplitudes [o][v], [o][o][v][v]
+    gfcc::DBuf oovv, Woooo, Wooov, Wovvo, Wovoo;
+    gfcc::DBuf S;                           // [i][q] left-vector helper
+    gfcc::DBuf ws_z;                        // sigma three-body intermediate
+  } uhf;
 
   // reduced-precision copies of the two-body operands with power-of-two scales: [0] FP32, [1] BF16
   struct LowPrec {
@@ -176,6 +185,12 @@ void build_ea(gfcc_ctx* c, const gfcc_system* sys, hipStream_t s);
 void ea_sigma_planes(gfcc_ctx* c, int64_t nplanes, const double* x, double* y, hipStream_t s);
 void ea_rhs_rows(gfcc_ctx* c, int64_t n, const int64_t* orb_dev, double* out, hipStream_t s);
 void ea_left_rows(gfcc_ctx* c, int64_t n, const int64_t* orb_dev, double* out, hipStream_t s);
+
+// open-shell IP over spin orbitals (uhf.hip)
+void build_uhf(gfcc_ctx* c, const gfcc_uhf_system* sys, hipStream_t s);
+void uhf_sigma_planes(gfcc_ctx* c, int64_t nplanes, const double* x, double* y, hipStream_t s);
+void uhf_rhs_rows(gfcc_ctx* c, int64_t n, const int64_t* orb_dev, double* out, hipStream_t s);
+void uhf_left_rows(gfcc_ctx* c, int64_t n, const int64_t* orb_dev, double* out, hipStream_t s);
 
 // model-order reduction (mor.hip)
 void mor_reset(gfcc_ctx* c);

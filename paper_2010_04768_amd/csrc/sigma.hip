@@ -347,8 +347,11 @@ static void sigma_impl(gfcc_ctx* c, int64_t P, const double* x, double* y, gfcc_
 
 void sigma_planes(gfcc_ctx* c, int64_t P, const double* x, double* y, gfcc_precision prec, hipStream_t s) {
   if (c->sector != 0) {
-    GFCC_CHECK(prec == GFCC_FP64, GFCC_E_ARG, "the electron-attachment sigma runs in FP64 only");
-    ea_sigma_planes(c, P, x, y, s);
+    GFCC_CHECK(prec == GFCC_FP64, GFCC_E_ARG, "the electron-attachment and open-shell sigma run in FP64 only");
+    if (c->sector == 1)
+      ea_sigma_planes(c, P, x, y, s);
+    else
+      uhf_sigma_planes(c, P, x, y, s);
     return;
   }
   sigma_impl(c, P, x, y, prec, s, PH_ALL, nullptr, nullptr);
@@ -482,7 +485,10 @@ __global__ void left_rows_kernel(const int64_t* __restrict__ orb, const double* 
 void make_rhs_rows(gfcc_ctx* c, int64_t n, const int64_t* orb_dev, double* out, hipStream_t s) {
   if (n <= 0) return;
   if (c->sector != 0) {
-    ea_rhs_rows(c, n, orb_dev, out, s);
+    if (c->sector == 1)
+      ea_rhs_rows(c, n, orb_dev, out, s);
+    else
+      uhf_rhs_rows(c, n, orb_dev, out, s);
     return;
   }
   hipLaunchKernelGGL(rhs_rows_kernel, dim3(blocks_for(c->Dp), unsigned(n)), dim3(256), 0, s, orb_dev,
@@ -493,7 +499,10 @@ void make_rhs_rows(gfcc_ctx* c, int64_t n, const int64_t* orb_dev, double* out, 
 void make_left_rows(gfcc_ctx* c, int64_t n, const int64_t* orb_dev, double* out, hipStream_t s) {
   if (n <= 0) return;
   if (c->sector != 0) {
-    ea_left_rows(c, n, orb_dev, out, s);
+    if (c->sector == 1)
+      ea_left_rows(c, n, orb_dev, out, s);
+    else
+      uhf_left_rows(c, n, orb_dev, out, s);
     return;
   }
   hipLaunchKernelGGL(left_rows_kernel, dim3(blocks_for(c->Dp), unsigned(n)), dim3(256), 0, s, orb_dev,

@@ -29,13 +29,21 @@ SYMBOLS = ["gfcc_build_intermediates", "gfcc_dims", "gfcc_export", "gfcc_sigma",
            "gfcc_mlp_forward", "gfcc_mlp_loss_grad", "gfcc_mlp_features", "gfcc_mlp_apply",
            "gfcc_mor_reset", "gfcc_mor_extend", "gfcc_mor_model", "gfcc_mor_export", "gfcc_mor_greens",
            "gfcc_solve_shifts", "gfcc_spectral", "gfcc_solve_multi", "gfcc_mlp_adam_step",
-           "gfcc_greens_noalloc", "gfcc_plan_memory", "gfcc_build_ea_intermediates"]
+           "gfcc_greens_noalloc", "gfcc_plan_memory", "gfcc_build_ea_intermediates",
+           "gfcc_build_uhf_intermediates"]
 
 
 class GfccSystem(ctypes.Structure):
     _fields_ = [("n_occ", ctypes.c_int64), ("n_vir", ctypes.c_int64), ("n_chol", ctypes.c_int64),
                 ("eps", ctypes.c_void_p), ("L", ctypes.c_void_p), ("t1", ctypes.c_void_p),
                 ("t2", ctypes.c_void_p), ("l1", ctypes.c_void_p), ("l2", ctypes.c_void_p)]
+
+
+class UhfSystem(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("n_occ_a", ctypes.c_int64), ("n_occ_b", ctypes.c_int64),
+                ("n_chol", ctypes.c_int64)] + [(nm, ctypes.c_void_p) for nm in
+                                               ("eps_a", "eps_b", "La", "Lb", "t1a", "t1b", "t2aa", "t2ab", "t2bb",
+                                                "l1a", "l1b", "l2aa", "l2ab", "l2bb")]
 
 
 class SolveOpts(ctypes.Structure):
@@ -107,6 +115,8 @@ def load():
     L.gfcc_build_intermediates.argtypes = [ctypes.POINTER(GfccSystem), vp, ctypes.POINTER(vp)]
     L.gfcc_build_ea_intermediates.argtypes = [ctypes.POINTER(GfccSystem), vp, ctypes.POINTER(vp)]
     L.gfcc_build_ea_intermediates.restype = ctypes.c_int
+    L.gfcc_build_uhf_intermediates.argtypes = [ctypes.POINTER(UhfSystem), vp, ctypes.POINTER(vp)]
+    L.gfcc_build_uhf_intermediates.restype = ctypes.c_int
     L.gfcc_dims.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64)]
     L.gfcc_export.argtypes = [vp, ctypes.c_int, vp, vp]
     L.gfcc_sigma.argtypes = [vp, i64, vp, vp, ctypes.c_int, vp]
@@ -269,6 +279,40 @@ class Context:
     @classmethod
     def from_system(cls, s, sector="ip"):
         return cls(s.eps, s.L, s.t1, s.t2, s.l1, s.l2, sector=sector)
+
+    @classmethod
+    def open_shell(cls, s, lam=True):
+        """IP context of an open-shell system (synth.OpenShellSystem layout, spin blocks); lam=False
+        takes Lambda = T^dagger.  Orbital indices run over spin orbitals, occupied [alpha, beta]
+        then virtual [alpha, beta]."""
+        import torch
+        self = cls.__new__(cls)
+        self._lib = load()
+        dev = torch.device("cuda", torch.cuda.current_device())
+
+        def d(a):
+            t = a if isinstance(a, torch.Tensor) else torch.from_numpy(np.ascontiguousarray(a))
+            return t.to(device=dev, dtype=torch.float64).contiguous()
+
+        names = ["eps_a", "eps_b", "La", "Lb", "t1a", "t1b", "t2aa", "t2ab", "t2bb"]
+        if lam:
+            names += ["l1a", "l1b", "l2aa", "l2ab", "l2bb"]
+        keep = {nm: d(getattr(s, nm)) for nm in names}
+        sysd = UhfSystem(s.n, s.n_occ_a, s.n_occ_b, s.n_chol,
+                         *[keep[nm].data_ptr() if nm in keep else None for nm in
+                           ("eps_a", "eps_b", "La", "Lb", "t1a", "t1b", "t2aa", "t2ab", "t2bb",
+                            "l1a", "l1b", "l2aa", "l2ab", "l2bb")])
+        h = ctypes.c_void_p()
+        _check(self._lib.gfcc_build_uhf_intermediates(ctypes.byref(sysd), _stream(), ctypes.byref(h)),
+               "gfcc_build_uhf_intermediates")
+        self._h = h
+        self._keep = None  # the build read every input
+        self.sector = "uhf"
+        D, no, nv = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        _check(self._lib.gfcc_dims(self._h, ctypes.byref(D), ctypes.byref(no), ctypes.byref(nv)), "gfcc_dims")
+        self.dim, self.n_occ, self.n_vir = D.value, no.value, nv.value
+        self.device = dev
+        return self
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
