@@ -66,6 +66,8 @@ def parse():
     ap.add_argument("--no-secondary", action="store_true", help="skip the 40/200/800 block after the headline")
     ap.add_argument("--no-ea", action="store_true", help="skip the electron-attachment block")
     ap.add_argument("--only-ea", action="store_true", help="run the electron-attachment block alone")
+    ap.add_argument("--no-uhf", action="store_true", help="skip the open-shell block")
+    ap.add_argument("--only-uhf", action="store_true", help="run the open-shell block alone")
     ap.add_argument("--form", default="bf16", choices=["bf16", "fp32", "fp64"])
     ap.add_argument("--precond", default="jacobi", choices=["jacobi", "none", "mlp"])
     ap.add_argument("--batch", type=int, default=0)
@@ -132,6 +134,9 @@ def main():
     if args.only_ea:
         print(json.dumps({"ea_o40v200": ea_block(args)}), flush=True)
         return
+    if args.only_uhf:
+        print(json.dumps({"open_shell": uhf_block(args)}), flush=True)
+        return
     if args.workload == "o40":
         out = o40_main(args)
     else:
@@ -140,6 +145,8 @@ def main():
             out["secondary_o40v200"] = o40_main(args, secondary=True)
     if out is not None and not args.no_ea:
         out["ea_o40v200"] = ea_block(args)
+    if out is not None and not args.no_uhf:
+        out["open_shell"] = uhf_block(args)
     if out is not None:
         print(json.dumps(out), flush=True)
 
@@ -471,6 +478,67 @@ def ea_block(args):
                      "max_true_rel_resid": float(max(i["true_rel_resid"] for i in info)),
                      "check_rel_err_vs_tol1e-12": rel}}
     log(f"EA solve {Q.size} RHS in {solve_s:.1f}s ({conv} converged), G rel err vs tol 1e-12: {rel:.1e}")
+    return out
+
+
+def uhf_block(args):
+    """The open-shell IP term: n = 100 spatial orbitals per spin, 21 alpha and 19 beta
+    electrons, Q = 400 (40 occupied and 160 virtual spin orbitals, D = 256,040).  Build (timed),
+    sigma of 32 vectors, and G_pp for all 40 occupied spin orbitals at 8 frequencies on
+    [-1.2, -0.3] (FP64 GMRES, Jacobi, tol 1e-8, eta 0.01); four are re-solved at tol 1e-12 as the
+    check, and every alpha-beta element of G must vanish."""
+    import torch
+
+    from paper_2010_04768_amd import gfcc
+    from synth import BASE_SEED, make_open_shell_system
+
+    torch.cuda.set_device(0)
+    s = make_open_shell_system(100, 21, 19, 400, BASE_SEED + 7)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx = gfcc.Context.open_shell(s, lam=False)
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    o, D = ctx.n_occ, ctx.dim
+    log(f"open-shell context n=100 oa=21 ob=19 Q=400: o={o} v={ctx.n_vir} D={D} built in {build_s:.1f}s")
+    rng = np.random.default_rng(5)
+    r2 = rng.normal(size=(32, o, o, ctx.n_vir))
+    r2 = r2 - r2.transpose(0, 2, 1, 3)
+    X = np.concatenate([rng.normal(size=(32, o)), r2.reshape(32, -1)], axis=1).astype(complex)
+    Xd = torch.from_numpy(X).to("cuda")
+    ctx.sigma(Xd)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(3):
+        ctx.sigma(Xd)
+    torch.cuda.synchronize()
+    sig_ms = (time.perf_counter() - t0) / 3 * 1e3
+    ws = list(np.linspace(-1.2, -0.3, 8))
+    P = np.repeat(np.arange(o), len(ws))
+    W = np.tile(ws, o)
+    t0 = time.perf_counter()
+    G, info, _ = ctx.solve(P, W, 0.01, q=list(range(o)), tol=1e-8, restart=30, max_iter=3000)
+    torch.cuda.synchronize()
+    solve_s = time.perf_counter() - t0
+    G = G.cpu().numpy()
+    spin = (np.arange(o) >= 21).astype(int)
+    cross = max(float(np.abs(G[r, spin != spin[P[r]]]).max()) for r in range(P.size))
+    its = [i["iters"] for i in info]
+    pick = [0, 100, 200, 319]
+    Gr, _, _ = ctx.solve(P[pick], W[pick], 0.01, q=list(range(o)), tol=1e-12, restart=60, max_iter=6000)
+    Gr = Gr.cpu().numpy()
+    rel = float(max(abs(G[k, P[k]] - Gr[j, P[k]]) / abs(Gr[j, P[k]]) for j, k in enumerate(pick)))
+    ctx.close()
+    out = {"system": "open shell, n = 100 per spin, 21 alpha + 19 beta electrons, Q = 400 (synthetic)",
+           "spin_orbitals": {"occ": o, "vir": int(2 * 100 - o)}, "D": D, "build_s": build_s,
+           "sigma_ms_32vec": sig_ms,
+           "solve": {"rhs": int(P.size), "p": "all 40 occupied spin orbitals", "omega": "8 on [-1.2, -0.3]",
+                     "eta": 0.01, "tol": 1e-8, "seconds": solve_s, "omega_pts_per_s": len(ws) / solve_s,
+                     "converged": sum(1 for i in info if i["status"] == 0),
+                     "iters_min_med_max": [int(min(its)), int(np.median(its)), int(max(its))],
+                     "max_alpha_beta_element": cross, "check_rel_err_vs_tol1e-12": rel}}
+    log(f"open-shell sigma 32 vectors {sig_ms:.1f} ms; solve {P.size} RHS in {solve_s:.1f}s, "
+        f"G rel err vs tol 1e-12 {rel:.1e}, max alpha-beta element {cross:.1e}")
     return out
 
 
