@@ -67,6 +67,12 @@ def parse():
     ap.add_argument("--no-ea", action="store_true", help="skip the electron-attachment block")
     ap.add_argument("--only-ea", action="store_true", help="run the electron-attachment block alone")
     ap.add_argument("--no-uhf", action="store_true", help="skip the open-shell block")
+    ap.add_argument("--mixed-full", action="store_true",
+                    help="all 15,360 right-hand sides of the three-system workload in one persistent solve, "
+                         "BF16-IR and FP32-IR, per-system G error against FP64 multi-shift references")
+    ap.add_argument("--mixed-forms", default="bf16,fp32")
+    ap.add_argument("--mixed-resume", default="", help="resume file of an interrupted --mixed-full form "
+                                                         "(rows it holds are restored, not re-solved)")
     ap.add_argument("--only-uhf", action="store_true", help="run the open-shell block alone")
     ap.add_argument("--form", default="bf16", choices=["bf16", "fp32", "fp64"])
     ap.add_argument("--precond", default="jacobi", choices=["jacobi", "none", "mlp"])
@@ -96,9 +102,14 @@ def parse():
     ap.add_argument("--multi-small", action="store_true",
                     help="multi-system study on three different 20/100/400 systems (each too small to fill the GPU)")
     ap.add_argument("--multi-omega", type=int, default=16, help="frequencies per system in the multi-system study")
-    ap.add_argument("--mlp-workload", default="learned-o90v420", choices=["learned-o90v420", "plain-o40v200"],
+    ap.add_argument("--mlp-xstar-ratio", type=float, default=100.0,
+                    help="training pairs of solves stopped at the iteration cap whose residual is this many "
+                         "times their last iterate's (0: converged solves only)")
+    ap.add_argument("--mlp-workload", default="learned-o90v420",
+                    choices=["learned-o90v420", "learned-o90v420-scaled", "plain-o40v200"],
                     help="system of the learned-preconditioner study")
     ap.add_argument("--mlp-steps", type=int, default=400)
+    ap.add_argument("--mlp-lr", type=float, default=1e-3)
     ap.add_argument("--mlp-data-tol", type=float, default=1e-4, help="tolerance of the training solves")
     ap.add_argument("--mlp-data-precision", default="", choices=["", "fp64", "fp32", "bf16"],
                     help="precision of the training solves (default: --form)")
@@ -130,6 +141,9 @@ def main():
         return
     if args.shifts_study:
         shifts_study(args)
+        return
+    if args.mixed_full:
+        mixed_full_study(args)
         return
     if args.only_ea:
         print(json.dumps({"ea_o40v200": ea_block(args)}), flush=True)
@@ -882,6 +896,80 @@ def multi_study(args):
         c.close()
 
 
+def mixed_full_study(args):
+    """The three-system workload in full: every occupied p of the 20/100/400, 40/180/720 and
+    60/300/1200 systems at all 128 frequencies on [-1.2, -0.3] (eta 0.01) -- 15,360 right-hand
+    sides -- in one gfcc_solve_multi per precision form (BF16-IR, FP32-IR; Jacobi, restart 30,
+    tol 1e-8).  Reference per system: FP64 multi-shift GMRES with every (p, omega) accepted on its
+    FP64 true residual <= 1e-11 (restarted FP64 for any left over).  Reported per system and form:
+    max relative G error, mean iterations, converged count; and the time of each solve.  Finished
+    rows stream to a resume file under gpurun_out/ as the solve runs."""
+    import torch
+
+    from paper_2010_04768_amd import gfcc
+    from synth import make_workload
+
+    torch.cuda.set_device(0)
+    wl = make_workload("mixed-3sys", n_omega=128)
+    ctxs = [gfcc.Context.from_system(s) for s in wl.systems]
+    torch.cuda.synchronize()
+    S, P, W = [], [], []
+    for k, s in enumerate(wl.systems):
+        for p in range(s.n_occ):
+            for w in wl.omegas[k]:
+                S.append(k)
+                P.append(p)
+                W.append(w)
+    S, P, W = np.array(S), np.array(P), np.array(W)
+    log(f"mixed full: {len(S)} right-hand sides, per system {[int((S == k).sum()) for k in range(3)]}, "
+        f"dims {[s.dim for s in wl.systems]}")
+    refs = []
+    for k, c in enumerate(ctxs):
+        t0 = time.perf_counter()
+        Gr, _ = shift_reference(c, np.arange(wl.systems[k].n_occ), wl.omegas[k], wl.eta, 160)
+        refs.append(Gr.reshape(-1))  # [p][omega], the order of the rows of system k
+        log(f"reference system {k} in {time.perf_counter() - t0:.1f}s")
+    out = {"metric": "three-system workload in full, one persistent multi-system solve per form",
+           "workload": "mixed-3sys (20/100/400, 40/180/720, 60/300/1200), all occupied p x 128 omega, eta 0.01",
+           "n_rhs": int(len(S)), "forms": {}}
+    os.makedirs(os.path.join(ROOT, "gpurun_out"), exist_ok=True)
+    for form in args.mixed_forms.split(","):
+        ck = os.path.join(ROOT, "gpurun_out", f"mixed_full_{form}.ckpt")
+        if os.path.exists(ck):
+            os.remove(ck)
+        restored = 0
+        if args.mixed_resume:
+            import shutil
+            shutil.copyfile(args.mixed_resume, ck)
+            restored = (os.path.getsize(ck) - 24) // 88  # header 24 bytes, 88 bytes per row with nq = 1
+            log(f"{form}: resuming from {args.mixed_resume} ({restored} finished rows)")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        G, info = gfcc.solve_multi(ctxs, S, P, W, wl.eta, tol=wl.tol, restart=wl.restart, max_iter=3000,
+                                   precision=form, use_graph=True, checkpoint=ck)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        G = G.cpu().numpy()[:, 0]
+        res = {"seconds": dt, "rhs_per_s": (len(S) - restored) / dt, "rows_restored": int(restored), "systems": []}
+        for k in range(3):
+            idx = np.nonzero(S == k)[0]
+            e = np.abs(G[idx] - refs[k]) / np.abs(refs[k])
+            its = [info[r]["iters"] for r in idx]
+            res["systems"].append({"o": wl.systems[k].n_occ, "v": wl.systems[k].n_vir, "n_rhs": int(idx.size),
+                                   "g_max_rel_err": float(e.max()), "g_median_rel_err": float(np.median(e)),
+                                   "iters_mean": float(np.mean(its)), "iters_max": int(max(its)),
+                                   "converged": int(sum(info[r]["status"] == 0 for r in idx)),
+                                   "max_true_rel_resid": float(max(info[r]["true_rel_resid"] for r in idx))})
+        out["forms"][form] = res
+        log(f"{form}: {dt:.1f}s, " + "; ".join(f"sys{k} err {x['g_max_rel_err']:.1e} it {x['iters_mean']:.1f} "
+                                              f"conv {x['converged']}/{x['n_rhs']}"
+                                              for k, x in enumerate(res["systems"])))
+        os.remove(ck)
+    print(json.dumps(out), flush=True)
+    for c in ctxs:
+        c.close()
+
+
 def shifts_study(args):
     """Multi-shift GMRES (FP64, one basis per orbital) on the 20/100/400, 40/180/720 and
     60/300/1200 systems: every occupied p at all 128 frequencies, build + solve timed after an
@@ -971,9 +1059,10 @@ def mlp_study(args):
     t = time.perf_counter()
     try:
         out["training"] = ctx.mlp_train(tp, tw, wl.eta, width=256, steps=args.mlp_steps, batch=8192,
-                                        pair_restart=args.mlp_pair_restart, lr=1e-3, seed=0, max_pairs=128,
+                                        pair_restart=args.mlp_pair_restart, lr=args.mlp_lr, seed=0, max_pairs=128,
                                         data_tol=args.mlp_data_tol,
-                                        data_max_iter=1200, data_precision=args.mlp_data_precision or args.form)
+                                        data_max_iter=1200, data_precision=args.mlp_data_precision or args.form,
+                                        xstar_ratio=args.mlp_xstar_ratio)
         trained = True
     except gfcc.GfccError as e:  # no training solve converged: report it, evaluate Jacobi only
         out["training"] = {"error": str(e)}

@@ -398,6 +398,11 @@ typedef struct {
   int32_t data_precision; /* gfcc_precision of the data-generating solves (their restart
                              residuals are FP64 true residuals in every precision) */
   int32_t reserved;
+  double xstar_ratio;   /* 0: only right-hand sides that reach data_tol give pairs.  > 0: a
+                           right-hand side stopped at data_max_iter also gives its pairs whose
+                           residual is >= xstar_ratio times its last iterate's, with that iterate
+                           as X* (the target's relative error is then about 1/xstar_ratio).
+                           Absent when struct_size predates the field. */
 } gfcc_mlp_opts;
 
 typedef struct {

@@ -1,6 +1,7 @@
 // C ABI of libgfcc (see include/gfcc.h).  Argument checking, error capture
 // and dispatch to the build / sigma / solver / Green's-function code.
 #include <chrono>
+#include <cstddef>
 #include <cmath>
 #include <cstring>
 #include <exception>
@@ -728,11 +729,21 @@ gfcc_status gfcc_mlp_train(gfcc_ctx* c, int64_t nrhs, const int64_t* p, const do
     bool conv = true;
     solve_batch(c, nrhs, p, omega, eta, 1, nullptr, &so, bG.as<double>(), nullptr, inf.data(), s, &conv, &rec);
     GFCC_CHECK(rec.n > 0, GFCC_E_STATE, "training solves produced no restart pairs (lower pair_restart)");
-    // drop pairs whose right-hand side did not converge (no X*)
+    // keep pairs whose right-hand side converged (X* = its solution) and, with xstar_ratio > 0,
+    // pairs of a right-hand side stopped at data_max_iter whose residual is at least
+    // xstar_ratio times that of its last iterate (X* = the last iterate)
+    const double ratio = mo->struct_size >= offsetof(gfcc_mlp_opts, xstar_ratio) + sizeof(double)
+                             ? mo->xstar_ratio : 0.0;
+    GFCC_CHECK(ratio >= 0.0 && std::isfinite(ratio), GFCC_E_ARG, "bad xstar_ratio");
     std::vector<int> keep;
-    for (int64_t k = 0; k < rec.n; ++k)
-      if (inf[size_t(rec.rhs[size_t(k)])].status == 0) keep.push_back(int(k));
-    GFCC_CHECK(!keep.empty(), GFCC_E_STATE, "no converged training right-hand side");
+    for (int64_t k = 0; k < rec.n; ++k) {
+      const size_t r = size_t(rec.rhs[size_t(k)]);
+      const double fin = r < rec.final_nrm.size() ? rec.final_nrm[r] : 0.0;
+      if (inf[r].status == 0 || (ratio > 0.0 && inf[r].status == 1 && fin > 0.0 && rec.nrm[size_t(k)] >= ratio * fin))
+        keep.push_back(int(k));
+    }
+    GFCC_CHECK(!keep.empty(), GFCC_E_STATE,
+               "no training pair: no right-hand side converged and none qualified under xstar_ratio");
     const int64_t npairs = rec.n;
     bE.ensure(size_t(npairs) * 2 * Dp * 8, s);
     DBuf drhs, dom, dnr;

@@ -122,6 +122,9 @@ struct PairRec {
   int64_t cap = 0, n = 0;
   std::vector<int> rhs;
   std::vector<double> omega, nrm;
+  // per right-hand side: |r| / sqrt(D) of the final iterate of a solve that stopped at max_iter
+  // (its iterate is then kept in xstar too); 0 otherwise
+  std::vector<double> final_nrm;
 };
 void solve_batch(gfcc_ctx* c, int64_t nrhs, const int64_t* p, const double* omega, double eta, int64_t nq,
                  const int64_t* q, const gfcc_solve_opts* opts, double* G, double* X, gfcc_rhs_info* info,

@@ -1185,6 +1185,12 @@ struct BatchRun {
         inf.status = 3;
       } else if (h.iters >= opts->max_iter) {
         inf.status = 1;
+        if (rec) {  // the last iterate, for pairs whose residual it undercuts by a wide margin
+          GFCC_HIP(hipMemcpyAsync(rec->xstar + h.rhs * 2 * Dp, d.X + int64_t(sl) * 2 * Dp, size_t(2 * Dp) * 8,
+                                  hipMemcpyDeviceToDevice, s));
+          if (rec->final_nrm.size() <= size_t(h.rhs)) rec->final_nrm.resize(size_t(h.rhs) + 1, 0.0);
+          rec->final_nrm[size_t(h.rhs)] = beta / std::sqrt(double(c->D));
+        }
       } else {
         if (rec && rec->n < rec->cap) {  // (r_k, x_k) pair: V[s][0] holds the unnormalised residual
           GFCC_HIP(hipMemcpyAsync(rec->R + rec->n * 2 * Dp, d.V + int64_t(sl) * (m + 1) * 2 * Dp,

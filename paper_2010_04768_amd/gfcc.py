@@ -68,7 +68,8 @@ class MlpOpts(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_size_t), ("width", ctypes.c_int32), ("steps", ctypes.c_int32),
                 ("batch", ctypes.c_int32), ("pair_restart", ctypes.c_int32), ("lr", ctypes.c_double),
                 ("seed", ctypes.c_uint64), ("max_pairs", ctypes.c_int32), ("data_max_iter", ctypes.c_int32),
-                ("data_tol", ctypes.c_double), ("data_precision", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("data_tol", ctypes.c_double), ("data_precision", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("xstar_ratio", ctypes.c_double)]
 
 
 class MlpReport(ctypes.Structure):
@@ -456,11 +457,11 @@ class Context:
 
     # ---------------------------------------------------------------- learned preconditioner
     def mlp_train(self, p, omega, eta, width=256, steps=1000, batch=8192, pair_restart=4, lr=1e-3, seed=0,
-                  max_pairs=512, data_tol=0.0, data_max_iter=0, data_precision="fp64"):
+                  max_pairs=512, data_tol=0.0, data_max_iter=0, data_precision="fp64", xstar_ratio=0.0):
         p_h = np.ascontiguousarray(np.asarray(p, dtype=np.int64))
         w_h = np.ascontiguousarray(np.asarray(omega, dtype=np.float64))
         o = MlpOpts(ctypes.sizeof(MlpOpts), width, steps, batch, pair_restart, lr, seed, max_pairs, data_max_iter,
-                    data_tol, PRECISIONS[data_precision], 0)
+                    data_tol, PRECISIONS[data_precision], 0, xstar_ratio)
         rep = MlpReport()
         _check(self._lib.gfcc_mlp_train(self._h, p_h.size, p_h.ctypes.data_as(ctypes.c_void_p),
                                         w_h.ctypes.data_as(ctypes.c_void_p), eta, ctypes.byref(o),

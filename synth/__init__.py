@@ -183,6 +183,12 @@ WORKLOADS = {
                        seed_off=[31, 32, 33]),
     "learned-o90v420": dict(shapes=[(90, 420, 1800)], n_omega=256, w=(-1.2, -0.3), eta=0.005,
                             p=30, tol=1e-8, restart=30, seed_off=[4]),
+    # supplementary variant of the 90/420/1800 system (not a substitute for it): sigma_L scaled by
+    # (o v^2 Q / 49152)^(-1/4), which keeps the dressing of the occupied Fock block at the level of
+    # the 4/16/48 system, so that restarted GMRES converges and preconditioners can be compared
+    "learned-o90v420-scaled": dict(shapes=[(90, 420, 1800)], n_omega=256, w=(-1.2, -0.3), eta=0.005,
+                                   p=30, tol=1e-8, restart=30, seed_off=[4],
+                                   sigma_L=0.05 * (90 * 420 ** 2 * 1800 / 49152) ** -0.25),
     "c60-o120v600": dict(shapes=[(120, 600, 3000)], n_omega=400, w=(-1.2, -0.3), eta=0.005,
                          p=30, tol=1e-8, restart=30, seed_off=[5]),
 }
@@ -196,7 +202,7 @@ def make_workload(name: str, n_omega: Optional[int] = None,
     nw = spec["n_omega"] if n_omega is None else int(n_omega)
     systems, omegas, plists = [], [], []
     for (o, v, Q), off in zip(shp, spec["seed_off"]):
-        systems.append(make_system(o, v, Q, BASE_SEED + off))
+        systems.append(make_system(o, v, Q, BASE_SEED + off, sigma_L=spec.get("sigma_L", 0.05)))
         omegas.append(np.linspace(spec["w"][0], spec["w"][1], nw))
         plists.append(np.arange(o, dtype=np.int64) if spec["p"] == "all"
                       else _highest(o, spec["p"]))

@@ -63,3 +63,31 @@ def test_mixed_precision_per_system_error(workload, k):
                 assert abs(Gr[r] - g) <= 1e-10 * abs(g)
     finally:
         ctx.close()
+
+
+def test_oracle_true_residual_of_fp64_solutions(workload):
+    """The 40/180/720 system: the oracle's own true residual ||b - (omega - i eta + Hbar) x|| / ||b||
+    of GPU FP64 solutions (tol 1e-11) at two (p, omega), evaluated with the oracle's sigma."""
+    wl = workload
+    s = wl.systems[1]
+    ctx = gfcc.Context.from_system(s)
+    try:
+        P = np.array([0, s.n_occ - 1], dtype=np.int64)
+        W = np.array([wl.omegas[1][5], wl.omegas[1][100]])
+        G, info, X = ctx.solve(P, W, wl.eta, tol=1e-11, restart=wl.restart, precision="fp64", max_iter=3000,
+                               want_x=True)
+        X = X.cpu().numpy()
+        print("[mixed] oracle intermediates of the 40/180/720 system", flush=True)
+        im = O.intermediates(s)
+        Y = O.sigma(im, X)
+        for r in range(2):
+            b = O.rhs(s, int(P[r]))
+            res = b - ((W[r] - 1j * wl.eta) * X[r] + Y[r])
+            rel = np.linalg.norm(res) / np.linalg.norm(b)
+            print(f"[mixed] p={P[r]} omega={W[r]:.4f}: oracle true residual {rel:.2e}, "
+                  f"library {info[r]['true_rel_resid']:.2e}")
+            assert rel <= 2e-11
+            g = O.left_vector(s, int(P[r])) @ X[r]
+            assert abs(G.cpu().numpy()[r, 0] - g) <= 1e-12 * abs(g)
+    finally:
+        ctx.close()

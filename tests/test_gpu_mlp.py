@@ -151,3 +151,22 @@ def test_nonfinite_network_falls_back_to_jacobi(sysctx):
         x, _, _ = O.solve(s, im, pl[r], wl[r], 0.01, tol=1e-13)
         gref = O.left_vector(s, pl[r]) @ x
         assert abs(G[r] - gref) <= 1e-8 * abs(gref)
+
+
+def test_training_pairs_from_solves_stopped_at_the_cap(sysctx):
+    """With data_max_iter too small for any training solve to converge there are no pairs unless
+    xstar_ratio admits those whose residual the last iterate undercuts by that factor."""
+    s, im, ctx, d, sD = sysctx
+    pt = np.array([1, 3, 5])
+    wt = np.array([-0.9, -0.6, -0.4])
+    with pytest.raises(gfcc.GfccError, match="no training pair"):
+        ctx.mlp_train(pt, wt, 0.01, width=64, steps=10, batch=1024, pair_restart=2, data_tol=1e-12,
+                      data_max_iter=6)
+    rep = ctx.mlp_train(pt, wt, 0.01, width=64, steps=50, batch=1024, pair_restart=2, data_tol=1e-12,
+                        data_max_iter=6, xstar_ratio=10.0)
+    assert rep["n_pairs"] > 0 and np.isfinite(rep["loss_final"])
+    # the trained network still solves to the oracle's G (Jacobi fallback guards it)
+    G, info, _ = ctx.solve([2], [-0.5], 0.01, tol=1e-10, precond="mlp")
+    x, _, _ = O.solve(s, im, 2, -0.5, 0.01, tol=1e-13)
+    assert info[0]["status"] in (0, 4)
+    assert abs(G.cpu().numpy()[0, 0] - O.left_vector(s, 2) @ x) <= 1e-8 * abs(O.left_vector(s, 2) @ x)
