@@ -30,7 +30,7 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK = {"fp64": 78.6e12, "fp32": 157.3e12, "bf16": 2.5e15}
+PEAK = {"fp64": 78.6e12, "fp32": 157.3e12, "bf16": 2.5e15, "fp16": 2.5e15}
 # HBM bytes per 512-slot ring-GEMM launch from rocprofv3 FETCH_SIZE / WRITE_SIZE passes
 # (profiles/ring_gemm_o40v200_bf16ir.md; copy-kernel scale 2.0 for FETCH_SIZE, 1.0 for
 # WRITE_SIZE).  Valid only for the GEMM source they were taken on.
@@ -39,7 +39,7 @@ TRAFFIC = {"gemm_src_sha256_16": "0a24a5c2e6a5af6f",
                     "launch": "512 slots, M=40960 N=K=8000"},
            "fp64": {"fetch_GB": 47.05, "write_GB": 2.956, "tile": "db256x128", "key": "0:40960:8000:8000",
                     "launch": "512 slots, M=40960 N=K=8000"}}
-DTYPE = {"fp64": "f64", "fp32": "f32+f64", "bf16": "bf16+f64"}
+DTYPE = {"fp64": "f64", "fp32": "f32+f64", "bf16": "bf16+f64", "fp16": "f16+f64"}
 # The same for the dominant ring GEMM of the 120/600/3000 headline (filled from its profile).
 TRAFFIC_C60 = {"gemm_src_sha256_16": "b9c1cdede9d41d81",
                "fp64:db256x128": {"fetch_GB": 1057.2, "write_GB": 4.635,
@@ -64,6 +64,8 @@ def parse():
     ap.add_argument("--c60-restart", type=int, default=12)
     ap.add_argument("--c60-ref-dim", type=int, default=64, help="basis cap of the multi-shift reference")
     ap.add_argument("--no-secondary", action="store_true", help="skip the 40/200/800 block after the headline")
+    ap.add_argument("--c60-forms", default="fp16:2,fp64:1",
+                    help="other forms timed after the headline on the same system, form:frequencies")
     ap.add_argument("--no-ea", action="store_true", help="skip the electron-attachment block")
     ap.add_argument("--only-ea", action="store_true", help="run the electron-attachment block alone")
     ap.add_argument("--no-uhf", action="store_true", help="skip the open-shell block")
@@ -74,7 +76,7 @@ def parse():
     ap.add_argument("--mixed-resume", default="", help="resume file of an interrupted --mixed-full form "
                                                          "(rows it holds are restored, not re-solved)")
     ap.add_argument("--only-uhf", action="store_true", help="run the open-shell block alone")
-    ap.add_argument("--form", default="bf16", choices=["bf16", "fp32", "fp64"])
+    ap.add_argument("--form", default="bf16", choices=["bf16", "fp16", "fp32", "fp64"])
     ap.add_argument("--precond", default="jacobi", choices=["jacobi", "none", "mlp"])
     ap.add_argument("--batch", type=int, default=0)
     ap.add_argument("--restart", type=int, default=30)
@@ -261,9 +263,9 @@ def c60_main(args):
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         if last:
-            pr = {n: ctx.prof_get(n) for n in ("ring_gemm_fp64", "ring_gemm_fp32", "ring_gemm_bf16", "sigma",
+            pr = {n: ctx.prof_get(n) for n in ("ring_gemm_fp64", "ring_gemm_fp32", "ring_gemm_bf16", "ring_gemm_fp16", "sigma",
                                                "arnoldi", "mlp")}
-            pr_tile = {f"{pp}:{t}": ctx.prof_get(f"ring_gemm_{pp}:{t}") for pp in ("fp64", "fp32", "bf16")
+            pr_tile = {f"{pp}:{t}": ctx.prof_get(f"ring_gemm_{pp}:{t}") for pp in ("fp64", "fp32", "bf16", "fp16")
                        for t in TILES}
             pr_tile = {kk: vv for kk, vv in pr_tile.items() if vv["count"]}
             ctx.prof_enable(False)
@@ -344,6 +346,39 @@ def c60_main(args):
         "fallback_to_jacobi": int(sum(x["status"] == 4 for x in infos)),
         "hbar_diag_range": {"1h": diag_range[:2], "2h1p": diag_range[2:]},
     }
+    # other forms on the same system and reference: FP16 sigma + FP64 refinement (three more
+    # mantissa bits than BF16, so two refinement cycles suffice) and the plain FP64 batched solver
+    if not args.profile_run and args.c60_forms:
+        out["forms"] = {}
+        for spec in args.c60_forms.split(","):
+            f2, n2 = spec.split(":")
+            t2s, ok2, err2, inf2 = [], [], [], []
+            for k in range(min(int(n2), len(sub))):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                G, info, _ = ctx.solve(plist, np.full(len(plist), sub[k]), eta, tol=tol, restart=args.c60_restart,
+                                       max_iter=600, batch=batch, precond=args.precond, precision=f2,
+                                       use_graph=bool(args.graph))
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+                g = G.cpu().numpy()[:, 0]
+                rel = np.abs(g - Gref[:, k]) / np.abs(Gref[:, k])
+                ok = bool(all(x["status"] in (0, 4) for x in info) and rel.max() <= 1e-8)
+                log(f"{f2} step: omega={sub[k]:.5f} {dt:.2f}s ok={ok} max rel err {rel.max():.2e} "
+                    f"iters {np.mean([x['iters'] for x in info]):.1f} "
+                    f"restarts {np.mean([x['restarts'] for x in info]):.1f}")
+                t2s.append(dt)
+                ok2.append(ok)
+                err2.append(float(rel.max()))
+                inf2 += info
+            out["forms"][f2] = {
+                "omega_points_per_s": int(np.sum(ok2)) / float(np.sum(t2s)), "ms_per_step": 1e3 * float(np.mean(t2s)),
+                "omega_points_ok": int(np.sum(ok2)), "omega_points_timed": len(t2s), "dtype": DTYPE[f2],
+                "g_max_rel_err_vs_fp64_ref": max(err2),
+                "iters_mean": float(np.mean([x["iters"] for x in inf2])),
+                "restarts_mean": float(np.mean([x["restarts"] for x in inf2]))}
+        if "fp64" in out["forms"] and out["forms"]["fp64"]["omega_points_per_s"] > 0:
+            out["speedup_vs_fp64_batched"] = value / out["forms"]["fp64"]["omega_points_per_s"]
     if args.copy_calib:
         a = torch.empty(32 * 1024 * 1024, dtype=torch.float64, device="cuda").fill_(1.0)
         b = torch.empty_like(a)
@@ -605,7 +640,7 @@ def o40_main(args, secondary=False):
                                tune_cache=args.tune_cache or None)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
-        pr = ({k: ctx.prof_get(k) for k in ("ring_gemm_fp64", "ring_gemm_fp32", "ring_gemm_bf16", "sigma",
+        pr = ({k: ctx.prof_get(k) for k in ("ring_gemm_fp64", "ring_gemm_fp32", "ring_gemm_bf16", "ring_gemm_fp16", "sigma",
                                              "arnoldi")} if prof else None)
         ctx.close()
         return G.cpu().numpy()[:, 0], info, t1 - t0, t2 - t1, pr

@@ -56,11 +56,13 @@ typedef enum {
   GFCC_W_NOCONV = 1   /* solve finished; some right-hand sides did not converge (see info) */
 } gfcc_status;
 
-/* Arithmetic of the sigma product.  The FP32/BF16 forms run the two-body
+/* Arithmetic of the sigma product.  The FP32/BF16/FP16 forms run the two-body
  * (W-tensor) contractions on MFMA in that precision with FP32 accumulation;
  * one-body terms, Arnoldi, Givens and the true residual stay FP64 and the
- * solver refines iteratively in FP64 (GMRES-IR). */
-typedef enum { GFCC_FP64 = 0, GFCC_FP32_IR = 1, GFCC_BF16_IR = 2 } gfcc_precision;
+ * solver refines iteratively in FP64 (GMRES-IR).  Operands get power-of-two scales
+ * (amax -> [1, 2)): per tensor for the intermediates, and for FP16, whose exponent
+ * range is narrow, per sigma call for the vectors, computed on the GPU. */
+typedef enum { GFCC_FP64 = 0, GFCC_FP32_IR = 1, GFCC_BF16_IR = 2, GFCC_FP16_IR = 3 } gfcc_precision;
 
 typedef enum {
   GFCC_PC_NONE = 0,   /* plain GMRES */

@@ -204,7 +204,7 @@ gfcc_status gfcc_plan_memory(int64_t n_occ, int64_t n_vir, int64_t n_chol, gfcc_
   return guarded([&] {
     GFCC_CHECK(out && out->struct_size >= sizeof(gfcc_memory_plan), GFCC_E_ARG, "bad plan struct");
     GFCC_CHECK(n_occ >= 1 && n_vir >= 1 && n_chol >= 1 && window >= 0 && restart >= 1, GFCC_E_ARG, "bad sizes");
-    GFCC_CHECK(prec >= GFCC_FP64 && prec <= GFCC_BF16_IR, GFCC_E_ARG, "bad precision");
+    GFCC_CHECK(prec >= GFCC_FP64 && prec <= GFCC_FP16_IR, GFCC_E_ARG, "bad precision");
     const MemPlan p = plan_memory(n_occ, n_vir, n_chol, prec, restart, flexible, window, lambda_given != 0);
     const size_t ss = out->struct_size;
     *out = gfcc_memory_plan{};
@@ -315,7 +315,7 @@ gfcc_status gfcc_sigma(gfcc_ctx* c, int64_t nrhs, const double* X, double* Y, gf
   return guarded([&] {
     GFCC_CHECK(c, GFCC_E_ARG, "null context");
     GFCC_CHECK(nrhs >= 0, GFCC_E_ARG, "nrhs < 0");
-    GFCC_CHECK(prec == GFCC_FP64 || prec == GFCC_FP32_IR || prec == GFCC_BF16_IR, GFCC_E_ARG, "bad precision");
+    GFCC_CHECK(prec >= GFCC_FP64 && prec <= GFCC_FP16_IR, GFCC_E_ARG, "bad precision");
     GFCC_CHECK(c->sector == 0 || prec == GFCC_FP64, GFCC_E_ARG,
                "the electron-attachment and open-shell sigma run in FP64 only");
     if (nrhs == 0) return;
@@ -458,7 +458,7 @@ gfcc_status gfcc_solve_batch(gfcc_ctx* c, int64_t nrhs, const int64_t* p, const 
       for (int64_t k = 0; k < nq; ++k) GFCC_CHECK(q[k] >= 0 && q[k] < c->o + c->v, GFCC_E_ARG, "q out of range");
     GFCC_CHECK(opts->tol > 0.0 && opts->restart >= 1 && opts->max_iter >= 1, GFCC_E_ARG, "bad tolerance/restart/max_iter");
     GFCC_CHECK(opts->precond >= GFCC_PC_NONE && opts->precond <= GFCC_PC_MLP, GFCC_E_ARG, "bad preconditioner");
-    GFCC_CHECK(opts->precision >= GFCC_FP64 && opts->precision <= GFCC_BF16_IR, GFCC_E_ARG, "bad precision");
+    GFCC_CHECK(opts->precision >= GFCC_FP64 && opts->precision <= GFCC_FP16_IR, GFCC_E_ARG, "bad precision");
     if (c->sector != 0) {
       GFCC_CHECK(opts->precision == GFCC_FP64, GFCC_E_ARG,
                  "the electron-attachment and open-shell solves run in FP64 only");
@@ -647,7 +647,7 @@ gfcc_status gfcc_solve_multi(int32_t nsys, gfcc_ctx* const* ctxs, int64_t nrhs, 
           GFCC_CHECK(q[j] >= 0 && q[j] < ctxs[k]->o + ctxs[k]->v, GFCC_E_ARG, "q out of range for a system");
     GFCC_CHECK(opts->tol > 0.0 && opts->restart >= 1 && opts->max_iter >= 1, GFCC_E_ARG, "bad tolerance/restart/max_iter");
     GFCC_CHECK(opts->precond >= GFCC_PC_NONE && opts->precond <= GFCC_PC_MLP, GFCC_E_ARG, "bad preconditioner");
-    GFCC_CHECK(opts->precision >= GFCC_FP64 && opts->precision <= GFCC_BF16_IR, GFCC_E_ARG, "bad precision");
+    GFCC_CHECK(opts->precision >= GFCC_FP64 && opts->precision <= GFCC_FP16_IR, GFCC_E_ARG, "bad precision");
     if (opts->precond == GFCC_PC_MLP)
       for (int k = 0; k < nsys; ++k)
         GFCC_CHECK(ctxs[k]->mlp && ctxs[k]->mlp->trained, GFCC_E_STATE,
@@ -683,7 +683,7 @@ gfcc_status gfcc_solve_shifts(gfcc_ctx* c, int64_t np, const int64_t* p, int64_t
       GFCC_CHECK(f.struct_size >= sizeof(gfcc_solve_opts), GFCC_E_ARG, "bad fallback options struct");
       GFCC_CHECK(f.tol > 0.0 && f.restart >= 1 && f.max_iter >= 1, GFCC_E_ARG, "bad fallback tolerance/restart/max_iter");
       GFCC_CHECK(f.precond >= GFCC_PC_NONE && f.precond <= GFCC_PC_MLP, GFCC_E_ARG, "bad fallback preconditioner");
-      GFCC_CHECK(f.precision >= GFCC_FP64 && f.precision <= GFCC_BF16_IR, GFCC_E_ARG, "bad fallback precision");
+      GFCC_CHECK(f.precision >= GFCC_FP64 && f.precision <= GFCC_FP16_IR, GFCC_E_ARG, "bad fallback precision");
     }
     solve_shifts(c, np, p, n_omega, omega, eta, nq, q, opts, G, X, info, as_stream(stream), &all_conv);
   });
@@ -722,7 +722,7 @@ gfcc_status gfcc_mlp_train(gfcc_ctx* c, int64_t nrhs, const int64_t* p, const do
     so.restart = mo->pair_restart;
     so.max_iter = mo->data_max_iter > 0 ? mo->data_max_iter : 4000;
     so.precond = GFCC_PC_JACOBI;
-    GFCC_CHECK(mo->data_precision >= GFCC_FP64 && mo->data_precision <= GFCC_BF16_IR, GFCC_E_ARG,
+    GFCC_CHECK(mo->data_precision >= GFCC_FP64 && mo->data_precision <= GFCC_FP16_IR, GFCC_E_ARG,
                "bad data_precision");
     so.precision = static_cast<gfcc_precision>(mo->data_precision);
     std::vector<gfcc_rhs_info> inf(static_cast<size_t>(nrhs));
@@ -865,7 +865,7 @@ gfcc_status gfcc_mor_greens(gfcc_ctx* c, int64_t np, const int64_t* p, int64_t n
     const gfcc_solve_opts& so = opts->solve;
     GFCC_CHECK(so.tol > 0.0 && so.restart >= 1 && so.max_iter >= 1, GFCC_E_ARG, "bad solve tolerance/restart/max_iter");
     GFCC_CHECK(so.precond >= GFCC_PC_NONE && so.precond <= GFCC_PC_MLP, GFCC_E_ARG, "bad preconditioner");
-    GFCC_CHECK(so.precision >= GFCC_FP64 && so.precision <= GFCC_BF16_IR, GFCC_E_ARG, "bad precision");
+    GFCC_CHECK(so.precision >= GFCC_FP64 && so.precision <= GFCC_FP16_IR, GFCC_E_ARG, "bad precision");
     for (int64_t k = 0; k < n_omega; ++k) GFCC_CHECK(std::isfinite(omega[k]), GFCC_E_ARG, "non-finite omega");
     if (n_omega >= 3) {
       const double dw = (omega[n_omega - 1] - omega[0]) / double(n_omega - 1);

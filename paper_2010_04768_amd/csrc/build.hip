@@ -68,7 +68,7 @@ MemPlan plan_memory(int64_t o, int64_t v, int64_t Q, int prec, int restart, int 
   p.vectors = (2.0 * Dp + oov) * d;  // diagonal, d1b and the rest of O(D)
   p.small = (oo + v * v + 3.0 * ov) * d;
   p.context_fp64 = p.ring + p.ladder + p.wovoo + p.wooov + p.chol + p.rows_1h + p.left + p.vectors + p.small;
-  const double esz = prec == GFCC_BF16_IR ? 2.0 : (prec == GFCC_FP32_IR ? 4.0 : 0.0);
+  const double esz = (prec == GFCC_BF16_IR || prec == GFCC_FP16_IR) ? 2.0 : (prec == GFCC_FP32_IR ? 4.0 : 0.0);
   p.context_lowp = esz * (ov * 2.0 * kp + oo * op2 + oov * op + oov * v + Q * kp);
   // build temporaries: seven Q-innermost (o v) x Q or o^2 x Q factors and two o^3 v blocks;
   // chunk buffers come on top and shrink to fit
@@ -666,7 +666,15 @@ void build_intermediates(gfcc_ctx* c, const gfcc_system* sys, hipStream_t s) {
 void build_lowprec(gfcc_ctx* c, int which, hipStream_t s) {
   auto& L = c->lp[which];
   if (L.built) return;
-  const Prec p = which == 0 ? Prec::F32 : Prec::BF16;
+  // one reduced-precision set at a time: the others are released (and rebuilt when asked for)
+  for (int w = 0; w < 3; ++w) {
+    if (w == which || !c->lp[w].built) continue;
+    GFCC_HIP(hipStreamSynchronize(s));
+    auto& O = c->lp[w];
+    for (DBuf* b : {&O.WW, &O.W4T, &O.WovooT, &O.t2, &O.LovC}) b->release();
+    O.built = false;
+  }
+  const Prec p = which == 0 ? Prec::F32 : (which == 1 ? Prec::BF16 : Prec::F16);
   const int64_t esz = which == 0 ? 4 : 2;
   auto mk_copy = [&](DBuf& dst, const double* src, int64_t n, double& scale) {
     const double am = amax_host(src, n, s, c->scr);

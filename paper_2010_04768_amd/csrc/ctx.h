@@ -75,17 +75,20 @@ struct gfcc_ctx {
     gfcc::DBuf ws_z;                        // sigma three-body intermediate
   } uhf;
 
-  // reduced-precision copies of the two-body operands with power-of-two scales: [0] FP32, [1] BF16
+  // reduced-precision copies of the two-body operands with power-of-two scales: [0] FP32, [1] BF16, [2] FP16
   struct LowPrec {
     bool built = false;
     gfcc::DBuf WW, W4T, WovooT, t2, LovC;
     double sWW = 1, sW4T = 1, sWovooT = 1, st2 = 1, sLovC = 1;  // stored = value * s
-  } lp[2];
+  } lp[3];
 
   // workspaces
   gfcc::Scratch scr;
   gfcc::DBuf ws_A1, ws_RT, ws_Ra, ws_r1, ws_U, ws_z, ws_zl;  // sigma operand copies
   gfcc::DBuf ws_in, ws_out;                 // planes for gfcc_sigma / gfcc_greens
+  // FP16 sigma: device scales of the vector operands ([0] s, [1] 1/s, [2] s_z, [3] 1/(s s_z)) and
+  // the per-block maxima they are reduced from
+  gfcc::DBuf ws_vsc, ws_vpart;
 
   // kernel timing
   bool prof_on = false;

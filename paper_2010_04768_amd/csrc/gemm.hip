@@ -6,8 +6,8 @@
 // operand fetch and in the epilogue instead of extra passes over HBM.
 //
 // Element types: FP64 (v_mfma_f64_16x16x4f64, FP64 accumulation), FP32
-// (v_mfma_f32_16x16x4f32) and BF16 (v_mfma_f32_16x16x32_bf16, gfx950), the
-// last two accumulating in FP32.  C is always FP64.
+// (v_mfma_f32_16x16x4f32), BF16 and FP16 (v_mfma_f32_16x16x32_{bf16,f16} and the
+// 32x32x16 forms, gfx950), the last three accumulating in FP32.  C is always FP64.
 //
 // Tiling: a workgroup of 4 waves (2 x 2) computes a BM x BN tile; each wave a
 // (BM/2) x (BN/2) sub-tile as (BM/32) x (BN/32) MFMA 16x16 blocks.  K advances
@@ -27,6 +27,7 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef float v16f __attribute__((ext_vector_type(16)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef _Float16 v8h __attribute__((ext_vector_type(8)));
 typedef unsigned int u4 __attribute__((ext_vector_type(4)));
 
 template <typename T> struct Mfma;
@@ -76,6 +77,20 @@ template <> struct Mfma<__bf16> {
   __device__ static inline int orow(int l, int r) { return 4 * (l >> 4) + r; }
   __device__ static inline int ocol(int l) { return l & 15; }
 };
+template <> struct Mfma<_Float16> {
+  using acc_t = v4f;
+  using frag_t = v8h;
+  static constexpr int KS = 32;
+  static constexpr int BLK = 16, NACC = 4;
+  static constexpr bool ROW_INTERLEAVED = false;
+  __device__ static inline acc_t mma(frag_t a, frag_t b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+  }
+  __device__ static inline int frow(int l) { return l & 15; }
+  __device__ static inline int fk(int l) { return (l >> 4) * 8; }
+  __device__ static inline int orow(int l, int r) { return 4 * (l >> 4) + r; }
+  __device__ static inline int ocol(int l) { return l & 15; }
+};
 // 32x32x16 BF16: half the instructions and fragment loads per flop of the 16x16x32 form
 struct Mfma32Bf16 {
   using acc_t = v16f;
@@ -90,6 +105,24 @@ struct Mfma32Bf16 {
   __device__ static inline int orow(int l, int r) { return 8 * (r >> 2) + 4 * (l >> 5) + (r & 3); }
   __device__ static inline int ocol(int l) { return l & 31; }
 };
+// the same shape in FP16 (same lane layout)
+struct Mfma32F16 {
+  using acc_t = v16f;
+  using frag_t = v8h;
+  static constexpr int KS = 16;
+  static constexpr int BLK = 32, NACC = 16;
+  __device__ static inline acc_t mma(frag_t a, frag_t b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
+  }
+  __device__ static inline int frow(int l) { return l & 31; }
+  __device__ static inline int fk(int l) { return (l >> 5) * 8; }
+  __device__ static inline int orow(int l, int r) { return 8 * (r >> 2) + 4 * (l >> 5) + (r & 3); }
+  __device__ static inline int ocol(int l) { return l & 31; }
+};
+// 16-bit element types take the 32x32x16 shape in the DB32 tiles
+template <typename T> struct Wide { using type = Mfma<T>; static constexpr bool on = false; };
+template <> struct Wide<__bf16> { using type = Mfma32Bf16; static constexpr bool on = true; };
+template <> struct Wide<_Float16> { using type = Mfma32F16; static constexpr bool on = true; };
 
 // Workgroups are dealt round-robin over the 8 XCDs (workgroup b runs on XCD
 // b % 8).  Give XCD x a contiguous range of tiles: with ntiles = 8q + r, XCDs
@@ -264,6 +297,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t braw) {
 
   // ---- epilogue
   double* C = g.C + rmap(g.cz, z);
+  const double al = g.alpha_dev ? g.alpha * (*g.alpha_dev) : g.alpha;
   const int jl = lane & 15;
   const int ih = lane >> 4;
 #pragma unroll
@@ -279,7 +313,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t braw) {
         const int64_t i = i0 + wm0 + a * 16 + ii;
         if (i >= g.M) continue;
         double* p = C + rmap(g.cm, i) + cj;
-        const double v = g.alpha * double(acc[a][b][r]);
+        const double v = al * double(acc[a][b][r]);
         *p = (g.beta == 0.0) ? v : v + g.beta * (*p);
       }
     }
@@ -415,6 +449,7 @@ __device__ __forceinline__ void gemm_db_tile(const GemmArgs& g, int64_t braw) {
   }
 
   double* C = g.C + rmap(g.cz, z);
+  const double al = g.alpha_dev ? g.alpha * (*g.alpha_dev) : g.alpha;
   const int jl = MF::ocol(lane);
 #pragma unroll
   for (int b = 0; b < FN; ++b) {
@@ -428,7 +463,7 @@ __device__ __forceinline__ void gemm_db_tile(const GemmArgs& g, int64_t braw) {
         const int64_t i = i0 + wm0 + a * MF::BLK + MF::orow(lane, r);
         if (i >= g.M) continue;
         double* p = C + rmap(g.cm, i) + cj;
-        const double v = g.alpha * double(acc[a][b][r]);
+        const double v = al * double(acc[a][b][r]);
         *p = (g.beta == 0.0) ? v : v + g.beta * (*p);
       }
     }
@@ -512,26 +547,26 @@ static void dispatch(const GemmArgs& a, int cfg, bool vec, hipStream_t s) {
     case TILE_DB_256x128: launch_db<T, 256, 128, 4, 2>(a, vec, s); break;
     case TILE_DB_128x256: launch_db<T, 128, 256, 2, 4>(a, vec, s); break;
     case TILE_DB_256x256: launch_db<T, 256, 256, 4, 2>(a, vec, s); break;
-    // 32x32 MFMA blocks (BF16; other types run the 16x16 kernel of the same tile)
+    // 32x32 MFMA blocks (BF16 and FP16; other types run the 16x16 kernel of the same tile)
     case TILE_DB32_256x256:
-      if constexpr (std::is_same<T, __bf16>::value) launch_db<T, 256, 256, 4, 2, 1, Mfma32Bf16>(a, vec, s);
+      if constexpr (Wide<T>::on) launch_db<T, 256, 256, 4, 2, 1, typename Wide<T>::type>(a, vec, s);
       else launch_db<T, 256, 256, 4, 2>(a, vec, s);
       break;
     case TILE_DB32_256x128:
-      if constexpr (std::is_same<T, __bf16>::value) launch_db<T, 256, 128, 4, 2, 1, Mfma32Bf16>(a, vec, s);
+      if constexpr (Wide<T>::on) launch_db<T, 256, 128, 4, 2, 1, typename Wide<T>::type>(a, vec, s);
       else launch_db<T, 256, 128, 4, 2>(a, vec, s);
       break;
     case TILE_DB32_128x128:
-      if constexpr (std::is_same<T, __bf16>::value) launch_db<T, 128, 128, 2, 2, 1, Mfma32Bf16>(a, vec, s);
+      if constexpr (Wide<T>::on) launch_db<T, 128, 128, 2, 2, 1, typename Wide<T>::type>(a, vec, s);
       else launch_db<T, 128, 128, 2, 2>(a, vec, s);
       break;
-    // 16 waves of 64x64 (BF16): four waves per SIMD hide the global-load latency of the next K stage
+    // 16 waves of 64x64 (BF16, FP16): four waves per SIMD hide the global-load latency of the next K stage
     case TILE_DB32_256x256_W16:
-      if constexpr (std::is_same<T, __bf16>::value) launch_db<T, 256, 256, 4, 4, 1, Mfma32Bf16>(a, vec, s);
+      if constexpr (Wide<T>::on) launch_db<T, 256, 256, 4, 4, 1, typename Wide<T>::type>(a, vec, s);
       else launch_db<T, 256, 256, 4, 2>(a, vec, s);
       break;
     case TILE_DB_256x256_W16:
-      if constexpr (std::is_same<T, __bf16>::value) launch_db<T, 256, 256, 4, 4>(a, vec, s);
+      if constexpr (Wide<T>::on) launch_db<T, 256, 256, 4, 4>(a, vec, s);
       else launch_db<T, 256, 256, 4, 2>(a, vec, s);
       break;
     default: throw Error{GFCC_E_ARG, "bad tile config"};
@@ -587,23 +622,23 @@ static void dispatch_grouped(const GemmGroup& gg, int cfg, bool vec, hipStream_t
     case TILE_DB_128x256: launch_db_grouped<T, 128, 256, 2, 4>(gg, vec, s); break;
     case TILE_DB_256x256: launch_db_grouped<T, 256, 256, 4, 2>(gg, vec, s); break;
     case TILE_DB32_256x256:
-      if constexpr (std::is_same<T, __bf16>::value) launch_db_grouped<T, 256, 256, 4, 2, 1, Mfma32Bf16>(gg, vec, s);
+      if constexpr (Wide<T>::on) launch_db_grouped<T, 256, 256, 4, 2, 1, typename Wide<T>::type>(gg, vec, s);
       else launch_db_grouped<T, 256, 256, 4, 2>(gg, vec, s);
       break;
     case TILE_DB32_256x128:
-      if constexpr (std::is_same<T, __bf16>::value) launch_db_grouped<T, 256, 128, 4, 2, 1, Mfma32Bf16>(gg, vec, s);
+      if constexpr (Wide<T>::on) launch_db_grouped<T, 256, 128, 4, 2, 1, typename Wide<T>::type>(gg, vec, s);
       else launch_db_grouped<T, 256, 128, 4, 2>(gg, vec, s);
       break;
     case TILE_DB32_128x128:
-      if constexpr (std::is_same<T, __bf16>::value) launch_db_grouped<T, 128, 128, 2, 2, 1, Mfma32Bf16>(gg, vec, s);
+      if constexpr (Wide<T>::on) launch_db_grouped<T, 128, 128, 2, 2, 1, typename Wide<T>::type>(gg, vec, s);
       else launch_db_grouped<T, 128, 128, 2, 2>(gg, vec, s);
       break;
     case TILE_DB32_256x256_W16:
-      if constexpr (std::is_same<T, __bf16>::value) launch_db_grouped<T, 256, 256, 4, 4, 1, Mfma32Bf16>(gg, vec, s);
+      if constexpr (Wide<T>::on) launch_db_grouped<T, 256, 256, 4, 4, 1, typename Wide<T>::type>(gg, vec, s);
       else launch_db_grouped<T, 256, 256, 4, 2>(gg, vec, s);
       break;
     case TILE_DB_256x256_W16:
-      if constexpr (std::is_same<T, __bf16>::value) launch_db_grouped<T, 256, 256, 4, 4>(gg, vec, s);
+      if constexpr (Wide<T>::on) launch_db_grouped<T, 256, 256, 4, 4>(gg, vec, s);
       else launch_db_grouped<T, 256, 256, 4, 2>(gg, vec, s);
       break;
     default: throw Error{GFCC_E_ARG, "bad tile config"};
@@ -616,8 +651,9 @@ static bool aligned_map(const RowMap& m, int64_t epc) {
 
 // C(i,j) = alpha * sum_z part[z][i][j] + beta * C(i,j)
 __global__ void splitk_reduce_kernel(const double* __restrict__ part, int slices, int64_t M, int64_t N, double* C,
-                                     RowMap cm, RowMap cn, double alpha, double beta) {
+                                     RowMap cm, RowMap cn, double alpha, double beta, const double* alpha_dev) {
   const int64_t MN = M * N;
+  if (alpha_dev) alpha *= *alpha_dev;
   for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < MN; t += int64_t(gridDim.x) * blockDim.x) {
     double acc = 0.0;
     for (int z = 0; z < slices; ++z) acc += part[z * MN + t];
@@ -651,11 +687,12 @@ void gemm_splitk(Prec p, const GemmArgs& a, int slices, double* part, hipStream_
   g.cz = lin(a.M * a.N);
   g.alpha = 1.0;
   g.beta = 0.0;
+  g.alpha_dev = nullptr;
   gemm(p, g, gemm_default_cfg(a.M, a.N, a.K), s);
   const int64_t MN = a.M * a.N;
   const unsigned nb = unsigned(std::min<int64_t>((MN + 255) / 256, 4096));
   hipLaunchKernelGGL(splitk_reduce_kernel, dim3(nb), dim3(256), 0, s, part, nsl, a.M, a.N, a.C, a.cm, a.cn,
-                     a.alpha, a.beta);
+                     a.alpha, a.beta, a.alpha_dev);
   GFCC_HIP(hipGetLastError());
 }
 
@@ -680,7 +717,7 @@ const char* tile_name(int cfg) {
 // 16-wave 256x256 tile of 32x32x16 blocks in BF16).
 int gemm_big_cfg(Prec p, int64_t M, int64_t N, int64_t K) {
   if (M >= 2048 && N >= 2048 && K >= 256)
-    return p == Prec::BF16 ? TILE_DB32_256x256_W16 : TILE_DB_256x128;
+    return (p == Prec::BF16 || p == Prec::F16) ? TILE_DB32_256x256_W16 : TILE_DB_256x128;
   return gemm_default_cfg(M, N, K);
 }
 
@@ -706,6 +743,7 @@ void gemm(Prec p, const GemmArgs& a, int cfg, hipStream_t s) {
     case Prec::F64: dispatch<double>(a, cfg, vec, s); break;
     case Prec::F32: dispatch<float>(a, cfg, vec, s); break;
     case Prec::BF16: dispatch<__bf16>(a, cfg, vec, s); break;
+    case Prec::F16: dispatch<_Float16>(a, cfg, vec, s); break;
   }
 }
 
@@ -738,6 +776,7 @@ void gemm_grouped(Prec p, const GemmArgs* a, int ng, int cfg, hipStream_t s) {
     case Prec::F64: dispatch_grouped<double>(gg, cfg, vec, s); break;
     case Prec::F32: dispatch_grouped<float>(gg, cfg, vec, s); break;
     case Prec::BF16: dispatch_grouped<__bf16>(gg, cfg, vec, s); break;
+    case Prec::F16: dispatch_grouped<_Float16>(gg, cfg, vec, s); break;
   }
 }
 

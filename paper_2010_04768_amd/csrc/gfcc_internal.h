@@ -88,7 +88,7 @@ struct RowMap {
 inline RowMap lin(int64_t ld) { return RowMap{int64_t(1) << 40, 0, ld}; }
 inline RowMap two(int64_t div, int64_t hi, int64_t lo) { return RowMap{div, hi, lo}; }
 
-enum class Prec : int { F64 = 0, F32 = 1, BF16 = 2 };
+enum class Prec : int { F64 = 0, F32 = 1, BF16 = 2, F16 = 3 };
 
 struct GemmArgs {
   const void* A = nullptr;  // element type given by Prec
@@ -103,6 +103,9 @@ struct GemmArgs {
   int64_t M = 0, N = 0, K = 0;
   int batch = 1;
   double alpha = 1.0, beta = 0.0;
+  // when set, the epilogue multiplies alpha by *alpha_dev (a device scalar: the inverse of an
+  // operand scale computed on the GPU, so that no host round trip sits between the two)
+  const double* alpha_dev = nullptr;
   // split-K: when > 0, grid.z indexes K slices of this length; slice z reads
   // columns [z*k_split, min(K, (z+1)*k_split)) and writes its partial sum to
   // C + cz(z) with alpha = 1, beta = 0 (batch must then equal the slice count)
@@ -141,6 +144,12 @@ int splitk_slices(int64_t M, int64_t N, int64_t K);
 int gemm_default_cfg(int64_t M, int64_t N, int64_t K);
 // precision-aware choice for large K-contiguous products (double-buffered tiles)
 int gemm_big_cfg(Prec p, int64_t M, int64_t N, int64_t K);
+
+// reduced-precision form of a solver precision: index of the context's copy set and element type
+inline int lowp_index(gfcc_precision p) { return p == GFCC_BF16_IR ? 1 : (p == GFCC_FP16_IR ? 2 : 0); }
+inline Prec inner_prec(gfcc_precision p) {
+  return p == GFCC_FP64 ? Prec::F64 : (p == GFCC_FP32_IR ? Prec::F32 : (p == GFCC_BF16_IR ? Prec::BF16 : Prec::F16));
+}
 
 // ---------------------------------------------------------------- tensors
 struct TView {

@@ -37,6 +37,48 @@ template <typename T> __device__ __forceinline__ T cvt(double x);
 template <> __device__ __forceinline__ double cvt<double>(double x) { return x; }
 template <> __device__ __forceinline__ float cvt<float>(double x) { return float(x); }
 template <> __device__ __forceinline__ __bf16 cvt<__bf16>(double x) { return __bf16(float(x)); }
+template <> __device__ __forceinline__ _Float16 cvt<_Float16>(double x) { return _Float16(float(x)); }
+
+// Scale of the vector operands of the FP16 products (FP16 has five exponent bits): the
+// power of two that maps the largest magnitude of the P input planes into [1, 2).  Partial
+// maxima per block, then one block turns them into sc[0] = s and sc[1] = 1/s.  A zero or
+// non-finite maximum gives s = 1 (a non-finite vector then stays non-finite for the solver).
+__global__ void amax_part_kernel(const double* __restrict__ x, int64_t n, double* __restrict__ part) {
+  __shared__ double red[256];
+  double m = 0.0;
+  for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < n; t += int64_t(gridDim.x) * blockDim.x)
+    m = fmax(m, fabs(x[t]));
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (int(threadIdx.x) < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+// which = 0: sc[0] = s, sc[1] = 1/s from the planes;  which = 1: sc[2] = s_z, sc[3] = 1/(s s_z) from z
+__global__ void scale_final_kernel(const double* __restrict__ part, int n, double* __restrict__ sc, int which) {
+  __shared__ double red[256];
+  double m = 0.0;
+  for (int t = threadIdx.x; t < n; t += blockDim.x) m = fmax(m, part[t]);
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (int(threadIdx.x) < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double am = red[0];
+    const double sv = (am > 0.0 && am <= 1.0e300) ? ldexp(1.0, -ilogb(am)) : 1.0;
+    if (which == 0) {
+      sc[0] = sv;
+      sc[1] = 1.0 / sv;
+    } else {
+      sc[2] = sv;
+      sc[3] = 1.0 / (sc[0] * sv);
+    }
+  }
+}
 
 // Per plane p and element t = (i, m, e) of the 2h1p block:
 //   A1[(p,i)][(m,e)] = 2 r[i][m][e] - r[m][i][e],  A1[(p,i)][kp + (m,e)] = -r[i][m][e]  (row stride k2)
@@ -46,22 +88,24 @@ template <> __device__ __forceinline__ __bf16 cvt<__bf16>(double x) { return __b
 template <typename T>
 __global__ void make_ops_kernel(const double* __restrict__ x, T* __restrict__ A1, T* __restrict__ RT,
                                 T* __restrict__ r1l, double* __restrict__ y, const double* __restrict__ d1b, int64_t o,
-                                int64_t v, int64_t Dp, int64_t o_pad, int64_t kp, int64_t k2) {
+                                int64_t v, int64_t Dp, int64_t o_pad, int64_t kp, int64_t k2,
+                                const double* __restrict__ vsc) {
   const int64_t oov = o * o * v, ov = o * v;
   const int64_t p = blockIdx.y;
   const double* xp = x + p * Dp + o_pad;
   double* yp = y + p * Dp + o_pad;
+  const double sv = vsc ? vsc[0] : 1.0;  // operand scale of the FP16 form (1 otherwise)
   const int64_t gid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (r1l && gid < o) r1l[p * o_pad + gid] = cvt<T>(x[p * Dp + gid]);
+  if (r1l && gid < o) r1l[p * o_pad + gid] = cvt<T>(sv * x[p * Dp + gid]);
   for (int64_t t = gid; t < oov; t += int64_t(gridDim.x) * blockDim.x) {
     const int64_t e = t % v, m = (t / v) % o, i = t / ov;
     const int64_t me = m * v + e;
     const double r = xp[t];
     const double rt = xp[m * ov + i * v + e];
     T* a = A1 + (p * o + i) * k2;
-    a[me] = cvt<T>(2.0 * r - rt);
-    a[kp + me] = cvt<T>(-r);
-    RT[(p * o + i) * kp + me] = cvt<T>(rt);
+    a[me] = cvt<T>(sv * (2.0 * r - rt));
+    a[kp + me] = cvt<T>(-sv * r);
+    RT[(p * o + i) * kp + me] = cvt<T>(sv * rt);
     yp[t] = d1b[t] * r;
   }
   // padding columns of both halves: the products read them (K = kp, 2 kp), and the buffer
@@ -77,7 +121,7 @@ __global__ void make_ops_kernel(const double* __restrict__ x, T* __restrict__ A1
 // Ra[p][a][(m,n)] = x[p*Dp + o_pad + (m,n)*v + a]  (row stride op2), LDS-tiled transpose
 template <typename T>
 __global__ void make_ra_kernel(const double* __restrict__ x, T* __restrict__ Ra, int64_t oo, int64_t v,
-                               int64_t Dp, int64_t o_pad, int64_t op2) {
+                               int64_t Dp, int64_t o_pad, int64_t op2, const double* __restrict__ vsc) {
   __shared__ double tile[32][33];
   const int64_t p = blockIdx.z;
   const int64_t r0 = int64_t(blockIdx.x) * 32, c0 = int64_t(blockIdx.y) * 32;  // rows (m,n), cols a
@@ -89,14 +133,16 @@ __global__ void make_ra_kernel(const double* __restrict__ x, T* __restrict__ Ra,
   __syncthreads();
   for (int k = threadIdx.y; k < 32; k += 8) {
     const int64_t a = c0 + k, r = r0 + threadIdx.x;
-    if (a < v && r < oo) Ra[(p * v + a) * op2 + r] = cvt<T>(tile[threadIdx.x][k]);
+    if (a < v && r < oo) Ra[(p * v + a) * op2 + r] = cvt<T>((vsc ? vsc[0] : 1.0) * tile[threadIdx.x][k]);
   }
 }
 
 template <typename T>
-__global__ void to_prec_kernel(const double* __restrict__ src, T* __restrict__ dst, int64_t n) {
+__global__ void to_prec_kernel(const double* __restrict__ src, T* __restrict__ dst, int64_t n,
+                               const double* __restrict__ sc) {
+  const double sv = sc ? *sc : 1.0;
   for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < n; t += int64_t(gridDim.x) * blockDim.x)
-    dst[t] = cvt<T>(src[t]);
+    dst[t] = cvt<T>(sv * src[t]);
 }
 
 static unsigned blocks_for(int64_t n) {
@@ -104,15 +150,25 @@ static unsigned blocks_for(int64_t n) {
 }
 
 template <typename T>
-static void make_operands(gfcc_ctx* c, int64_t P, const double* x, bool lowp, double* y, hipStream_t s) {
+static void make_operands(gfcc_ctx* c, int64_t P, const double* x, bool lowp, double* y, const double* vsc,
+                          hipStream_t s) {
   const int64_t oov = c->oov;
   hipLaunchKernelGGL((make_ops_kernel<T>), dim3(std::min<int64_t>((oov + 255) / 256, 1024), unsigned(P)), dim3(256),
                      0, s, x, c->ws_A1.as<T>(), c->ws_RT.as<T>(), lowp ? c->ws_r1.as<T>() : nullptr, y,
-                     c->d1b.as<double>(), c->o, c->v, c->Dp, c->o_pad, c->kp, c->k2);
+                     c->d1b.as<double>(), c->o, c->v, c->Dp, c->o_pad, c->kp, c->k2, vsc);
   GFCC_HIP(hipGetLastError());
   dim3 g(unsigned((c->oo + 31) / 32), unsigned((c->v + 31) / 32), unsigned(P));
   hipLaunchKernelGGL((make_ra_kernel<T>), g, dim3(32, 8), 0, s, x, c->ws_Ra.as<T>(), c->oo, c->v, c->Dp, c->o_pad,
-                     c->op2);
+                     c->op2, vsc);
+  GFCC_HIP(hipGetLastError());
+}
+
+// the FP16 form's operand scale of n doubles at x into sc[2 which], sc[2 which + 1]
+static void vector_scale(gfcc_ctx* c, const double* x, int64_t n, int which, hipStream_t s) {
+  const unsigned nb = unsigned(std::min<int64_t>(std::max<int64_t>((n + 255) / 256, 1), 1024));
+  hipLaunchKernelGGL(amax_part_kernel, dim3(nb), dim3(256), 0, s, x, n, c->ws_vpart.as<double>());
+  hipLaunchKernelGGL(scale_final_kernel, dim3(1), dim3(256), 0, s, c->ws_vpart.as<double>(), int(nb),
+                     c->ws_vsc.as<double>(), which);
   GFCC_HIP(hipGetLastError());
 }
 
@@ -127,10 +183,18 @@ static void sigma_impl(gfcc_ctx* c, int64_t P, const double* x, double* y, gfcc_
   const int64_t o = c->o, v = c->v, ov = c->ov, oo = c->oo, oov = c->oov;
   const int64_t Dp = c->Dp, op = c->o_pad, kp = c->kp, k2 = c->k2, Qp = c->Qp, Q = c->Q;
   const bool lowp = prec != GFCC_FP64;
-  const int li = (prec == GFCC_BF16_IR) ? 1 : 0;
-  const Prec rp = !lowp ? Prec::F64 : (li ? Prec::BF16 : Prec::F32);
+  const int li = (prec == GFCC_BF16_IR) ? 1 : (prec == GFCC_FP16_IR ? 2 : 0);
+  const bool f16 = li == 2;
+  const Prec rp = !lowp ? Prec::F64 : (li == 1 ? Prec::BF16 : (f16 ? Prec::F16 : Prec::F32));
   const int64_t esz = !lowp ? 8 : (li ? 2 : 4);
   if (lowp) build_lowprec(c, li, s);
+  if (f16) {
+    c->ws_vsc.ensure(8 * 8, s);
+    c->ws_vpart.ensure(1024 * 8, s);
+  }
+  // FP16: the vector operands are scaled by sc[0] on conversion; products unscale on the GPU
+  const double* sc = f16 ? c->ws_vsc.as<double>() : nullptr;
+  const double* inv_s = f16 ? sc + 1 : nullptr;
   c->ws_A1.ensure(size_t(P * o * k2 * esz), s);
   c->ws_RT.ensure(size_t(P * o * kp * esz), s);
   c->ws_Ra.ensure(size_t(P * v * c->op2 * esz), s);
@@ -143,9 +207,13 @@ static void sigma_impl(gfcc_ctx* c, int64_t P, const double* x, double* y, gfcc_
   if (whole) prof_begin(c, "sigma", s);
   if (phases & PH_OPS) {
     switch (rp) {
-      case Prec::F64: make_operands<double>(c, P, x, false, y, s); break;
-      case Prec::F32: make_operands<float>(c, P, x, true, y, s); break;
-      case Prec::BF16: make_operands<__bf16>(c, P, x, true, y, s); break;
+      case Prec::F64: make_operands<double>(c, P, x, false, y, nullptr, s); break;
+      case Prec::F32: make_operands<float>(c, P, x, true, y, nullptr, s); break;
+      case Prec::BF16: make_operands<__bf16>(c, P, x, true, y, nullptr, s); break;
+      case Prec::F16:
+        vector_scale(c, x, P * Dp, 0, s);
+        make_operands<_Float16>(c, P, x, true, y, sc, s);
+        break;
     }
   }
   const auto& L = c->lp[li];
@@ -159,7 +227,7 @@ static void sigma_impl(gfcc_ctx* c, int64_t P, const double* x, double* y, gfcc_
   const double sLovC = lowp ? 1.0 / L.sLovC : 1.0;
 
   const double ring1 = 2.0 * double(P) * double(o) * double(ov) * double(ov);  // flops of one (m,e) half
-  const char* ring_name = !lowp ? "ring_gemm_fp64" : (li ? "ring_gemm_bf16" : "ring_gemm_fp32");
+  const char* ring_name = !lowp ? "ring_gemm_fp64" : (li == 1 ? "ring_gemm_bf16" : (f16 ? "ring_gemm_fp16" : "ring_gemm_fp32"));
   const double c_rw = 2.0 * double(P) * double(o) * double(ov) * 8.0;  // read + write of the FP64 output
 
   // ---- ring terms
@@ -177,6 +245,7 @@ static void sigma_impl(gfcc_ctx* c, int64_t P, const double* x, double* y, gfcc_
     g.cm = two(o, Dp, ov);
     g.cn = lin(1);
     g.alpha = sWW;
+    g.alpha_dev = inv_s;
     g.beta = 1.0;  // y2 holds the diagonal one-body part
     const int cfg1 = tuned_cfg(c, rp, g.M, g.N, g.K);
     if (ring_out) {
@@ -204,6 +273,7 @@ static void sigma_impl(gfcc_ctx* c, int64_t P, const double* x, double* y, gfcc_
     h.cm = two(o, Dp, v);
     h.cn = two(v, ov, 1);
     h.alpha = -sWW;
+    h.alpha_dev = inv_s;
     h.beta = 1.0;
     const int cfg2 = tuned_cfg(c, rp, h.M, h.N, h.K);
     if (ring_out) {
@@ -234,6 +304,7 @@ static void sigma_impl(gfcc_ctx* c, int64_t P, const double* x, double* y, gfcc_
     g.cm = lin(v);
     g.cn = two(v, Dp, 1);
     g.alpha = sW4T;
+    g.alpha_dev = inv_s;
     g.beta = 1.0;
     gemm(rp, g, tuned_cfg(c, rp, g.M, g.N, g.K), s);
   }
@@ -273,12 +344,17 @@ static void sigma_impl(gfcc_ctx* c, int64_t P, const double* x, double* y, gfcc_
     const void* zA = c->ws_z.p;
     if (lowp) {
       const int64_t nz = P * c->vp;
-      if (li)
+      if (f16) {  // z (already carrying sc[0] through U) gets a scale of its own: sc[2]
+        vector_scale(c, c->ws_z.as<double>(), nz, 1, s);
+        hipLaunchKernelGGL((to_prec_kernel<_Float16>), dim3(blocks_for(nz)), dim3(256), 0, s, c->ws_z.as<double>(),
+                           c->ws_zl.as<_Float16>(), nz, sc + 2);
+      } else if (li) {
         hipLaunchKernelGGL((to_prec_kernel<__bf16>), dim3(blocks_for(nz)), dim3(256), 0, s, c->ws_z.as<double>(),
-                           c->ws_zl.as<__bf16>(), nz);
-      else
+                           c->ws_zl.as<__bf16>(), nz, nullptr);
+      } else {
         hipLaunchKernelGGL((to_prec_kernel<float>), dim3(blocks_for(nz)), dim3(256), 0, s, c->ws_z.as<double>(),
-                           c->ws_zl.as<float>(), nz);
+                           c->ws_zl.as<float>(), nz, nullptr);
+      }
       GFCC_HIP(hipGetLastError());
       zA = c->ws_zl.p;
     }
@@ -297,6 +373,7 @@ static void sigma_impl(gfcc_ctx* c, int64_t P, const double* x, double* y, gfcc_
     g.bz = lin(v * v);
     g.cz = lin(ov);
     g.alpha = -st2;
+    g.alpha_dev = f16 ? sc + 3 : nullptr;  // 1 / (s s_z)
     g.beta = 1.0;
     gemm(rp, g, gemm_default_cfg(g.M, g.N, g.K), s);
   }
@@ -319,6 +396,7 @@ static void sigma_impl(gfcc_ctx* c, int64_t P, const double* x, double* y, gfcc_
     g.cm = lin(Dp);
     g.cn = lin(1);
     g.alpha = -sWovoo;
+    g.alpha_dev = inv_s;
     g.beta = 1.0;
     gemm(rp, g, tuned_cfg(c, rp, g.M, g.N, g.K), s);
   }
@@ -366,7 +444,8 @@ void sigma_group(const SigmaJob* jobs, int nj, gfcc_precision prec, hipStream_t 
     for (int j = 0; j < nj; ++j) sigma_planes(jobs[j].c, jobs[j].P, jobs[j].x, jobs[j].y, prec, s);
     return;
   }
-  const Prec rp = prec == GFCC_FP64 ? Prec::F64 : (prec == GFCC_BF16_IR ? Prec::BF16 : Prec::F32);
+  const Prec rp = prec == GFCC_FP64 ? Prec::F64
+                  : (prec == GFCC_BF16_IR ? Prec::BF16 : (prec == GFCC_FP16_IR ? Prec::F16 : Prec::F32));
   GemmArgs ring[2][MAX_GEMM_GROUPS];
   int ng = 0, cfg[2] = {0, 0};
   double best = -1.0;

@@ -628,6 +628,7 @@ static double lp_cycle_rtol(gfcc_precision p) {
   switch (p) {
     case GFCC_FP32_IR: return 1e-6;
     case GFCC_BF16_IR: return 1e-4;
+    case GFCC_FP16_IR: return 2e-5;  // three more mantissa bits than BF16
     default: return 0.0;
   }
 }
@@ -1263,7 +1264,7 @@ struct BatchRun {
     ckpt_open(lanes, nrhs);
     for (auto& L : lanes) setup(L);
     if (opts->tune_cache) {  // ring-GEMM tiles for each full window (inner precision and FP64)
-      const Prec ip = prec == GFCC_FP64 ? Prec::F64 : (prec == GFCC_FP32_IR ? Prec::F32 : Prec::BF16);
+      const Prec ip = inner_prec(prec);
       for (auto& L : lanes) {
         if (L.c->sector != 0) continue;  // the tuned shapes are the ionisation sector's
         tune_load(L.c, opts->tune_cache);
@@ -1419,7 +1420,7 @@ void solve_batch(gfcc_ctx* c, int64_t nrhs, const int64_t* p, const double* omeg
   BatchRun R = make_run(p, omega, eta, nq, q, opts, G, Xout, info, s, rec);
   int B = opts->batch > 0 ? opts->batch : 0;
   // reduced-precision operands first, so that the window is sized against what is left
-  if (R.prec != GFCC_FP64) build_lowprec(c, R.prec == GFCC_BF16_IR ? 1 : 0, s);
+  if (R.prec != GFCC_FP64) build_lowprec(c, lowp_index(R.prec), s);
   if (B == 0) {
     size_t freeb = 0, totalb = 0;
     GFCC_HIP(hipMemGetInfo(&freeb, &totalb));
@@ -1455,7 +1456,7 @@ void solve_multi(int nsys, gfcc_ctx* const* ctxs, int64_t nrhs, const int32_t* s
   }
   int64_t Btot = opts->batch > 0 ? opts->batch : std::min<int64_t>(nrhs, 128 * int64_t(used.size()));
   if (R.prec != GFCC_FP64)
-    for (auto& L : used) build_lowprec(L.c, R.prec == GFCC_BF16_IR ? 1 : 0, s);
+    for (auto& L : used) build_lowprec(L.c, lowp_index(R.prec), s);
   size_t freeb = 0, totalb = 0;
   GFCC_HIP(hipMemGetInfo(&freeb, &totalb));
   for (;;) {  // window share of each system ~ its right-hand sides, within half of free memory

@@ -278,6 +278,8 @@ __global__ void convert_kernel(const double* __restrict__ src, void* __restrict_
       static_cast<float*>(dst)[t] = float(v);
     else if (prec == int(Prec::BF16))
       static_cast<__bf16*>(dst)[t] = __bf16(float(v));
+    else if (prec == int(Prec::F16))
+      static_cast<_Float16*>(dst)[t] = _Float16(float(v));
     else
       static_cast<double*>(dst)[t] = v;
   }

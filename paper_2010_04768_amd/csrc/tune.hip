@@ -82,6 +82,7 @@ static void fill(Prec p, void* dst, int64_t n, double val, hipStream_t s) {
     case Prec::F64: hipLaunchKernelGGL(fill_kernel<double>, g, dim3(256), 0, s, static_cast<double*>(dst), n, val); break;
     case Prec::F32: hipLaunchKernelGGL(fill_kernel<float>, g, dim3(256), 0, s, static_cast<float*>(dst), n, val); break;
     case Prec::BF16: hipLaunchKernelGGL(fill_kernel<__bf16>, g, dim3(256), 0, s, static_cast<__bf16*>(dst), n, val); break;
+    case Prec::F16: hipLaunchKernelGGL(fill_kernel<_Float16>, g, dim3(256), 0, s, static_cast<_Float16*>(dst), n, val); break;
   }
   GFCC_HIP(hipGetLastError());
 }
@@ -137,7 +138,7 @@ static void tune_shape(gfcc_ctx* c, Prec p, int64_t M, int64_t N, int64_t K, hip
 }
 
 void tune_ring(gfcc_ctx* c, Prec p, int64_t P, hipStream_t s) {
-  if (p != Prec::F64) build_lowprec(c, p == Prec::BF16 ? 1 : 0, s);
+  if (p != Prec::F64) build_lowprec(c, p == Prec::BF16 ? 1 : (p == Prec::F16 ? 2 : 0), s);
   tune_shape(c, p, P * c->o, c->ov, c->k2, s);  // ring, first product (K = [Wovvo | Wovov])
   tune_shape(c, p, P * c->o, c->ov, c->ov, s);  // ring, second product
   tune_shape(c, p, c->oo, P * c->v, c->oo, s);  // hole-hole ladder

@@ -16,9 +16,9 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libgfcc.so")
 
-FP64, FP32_IR, BF16_IR = 0, 1, 2
+FP64, FP32_IR, BF16_IR, FP16_IR = 0, 1, 2, 3
 PC_NONE, PC_JACOBI, PC_MLP = 0, 1, 2
-PRECISIONS = {"fp64": FP64, "fp32": FP32_IR, "bf16": BF16_IR}
+PRECISIONS = {"fp64": FP64, "fp32": FP32_IR, "bf16": BF16_IR, "fp16": FP16_IR}
 PRECONDS = {"none": PC_NONE, "jacobi": PC_JACOBI, "mlp": PC_MLP}
 BLOCKS = ["FOO", "FVV", "FOV", "WOOOO", "WOOOV", "WOVOO", "WOVVO", "WOVOV", "DIAG", "LEFT"]
 

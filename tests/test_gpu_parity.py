@@ -70,7 +70,7 @@ def test_sigma_fp64_matches_oracle(cache, shape):
 
 
 @pytest.mark.parametrize("shape", [(5, 7, 9), (8, 40, 60), (12, 45, 50)])
-@pytest.mark.parametrize("prec,bound", [("fp32", 1e-5), ("bf16", 2e-2)])
+@pytest.mark.parametrize("prec,bound", [("fp32", 1e-5), ("bf16", 2e-2), ("fp16", 4e-3)])
 def test_sigma_reduced_precision_bound(cache, shape, prec, bound):
     """Reduced-precision two-body terms: error stated relative to the FP64 result."""
     s, im, ctx = _get(cache, shape)
@@ -79,6 +79,24 @@ def test_sigma_reduced_precision_bound(cache, shape, prec, bound):
     Yref = O.sigma(im, X)
     err = np.linalg.norm(Y - Yref) / np.linalg.norm(Yref)
     assert err < bound, err
+
+
+@pytest.mark.parametrize("mag", [1e-12, 1e9])
+def test_sigma_fp16_vector_scaling(cache, mag):
+    """FP16 has five exponent bits: vectors far from unit size (tiny Jacobi-preconditioned
+    directions, large iterates) keep the FP16 bound because their scale is taken on the GPU
+    per sigma call; without it 1e-12-sized entries would flush to zero."""
+    s, im, ctx = _get(cache, (8, 40, 60))
+    X = random_vectors(3, s.dim, seed=6) * mag
+    Y = ctx.sigma(torch.from_numpy(X), precision="fp16").cpu().numpy()
+    Yref = O.sigma(im, X)
+    err = np.linalg.norm(Y - Yref) / np.linalg.norm(Yref)
+    assert err < 4e-3, err
+    # and BF16 against FP16 on the same vectors: the three extra mantissa bits show
+    Yb = ctx.sigma(torch.from_numpy(X), precision="bf16").cpu().numpy()
+    eb = np.linalg.norm(Yb - Yref) / np.linalg.norm(Yref)
+    print(f"[fp16] mag {mag:g}: fp16 rel err {err:.2e}, bf16 {eb:.2e}")
+    assert err < eb
 
 
 def test_sigma_batch_chunking_and_linearity(cache):
@@ -155,7 +173,7 @@ def test_solve_batch_independence_and_refill():
     assert abs(G3.cpu().numpy()[0, 0] - G1.cpu().numpy()[5, 0]) <= 1e-10 * abs(G3.cpu().numpy()[0, 0])
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp16"])
 def test_solve_mixed_precision_ir(prec):
     """GMRES-IR with reduced-precision sigma reaches the FP64 tolerance."""
     s = _sys(8, 40, 60)
