@@ -5,6 +5,7 @@
 // GEMM shapes (ring: M = vector rows, N = K = o*v; hole-hole ladder; three-body
 // + 2h1p<-1h) and the fastest is kept per (precision, M, N, K).  Results
 // persist in a small JSON file.
+#include <cstdlib>
 #include <cmath>
 #include <cstdio>
 #include <fstream>
@@ -126,6 +127,10 @@ static void tune_shape(gfcc_ctx* c, Prec p, int64_t M, int64_t N, int64_t K, hip
     float ms = 0.f;
     GFCC_HIP(hipEventElapsedTime(&ms, e0, e1));
     ms /= float(reps);
+    if (std::getenv("GFCC_VERBOSE"))
+      std::fprintf(stderr, "[gfcc] tune prec %d M %lld N %lld K %lld %-18s %9.3f ms %8.1f TFLOP/s\n", int(p),
+                   (long long)M, (long long)N, (long long)K, tile_name(cfg), double(ms),
+                   2.0 * double(M) * double(N) * double(K) / (double(ms) * 1e9));
     if (ms < 0.99f * best_ms) {  // a later configuration must win by more than 1% (stable choice)
       best_ms = ms;
       best = cfg;
