@@ -41,8 +41,8 @@ TRAFFIC = {"gemm_src_sha256_16": "0a24a5c2e6a5af6f",
                     "launch": "512 slots, M=40960 N=K=8000"}}
 DTYPE = {"fp64": "f64", "fp32": "f32+f64", "bf16": "bf16+f64", "fp16": "f16+f64"}
 # The same for the dominant ring GEMM of the 120/600/3000 headline (filled from its profile).
-TRAFFIC_C60 = {"gemm_src_sha256_16": "b9c1cdede9d41d81",
-               "fp64:db256x128": {"fetch_GB": 1057.2, "write_GB": 4.635,
+TRAFFIC_C60 = {"gemm_src_sha256_16": "d25da48ca63a4d5a",
+               "fp64:db256x128": {"fetch_GB": 1061.3, "write_GB": 4.617,
                                   "launch": "60 planes: P1 M=7200 N=72000 K=144000 and P2 K=72000, average of 6 "
                                             "(profiles/ring_gemm_c60_o120v600_bf16ir.md)"}}
 TILES = ["128x128", "64x64", "128x64", "64x128", "db128x128", "db256x128", "db128x256", "db256x256",

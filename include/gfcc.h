@@ -522,14 +522,18 @@ gfcc_status gfcc_mor_greens(gfcc_ctx* ctx, int64_t np, const int64_t* p, int64_t
                             gfcc_mor_report* report, void* stream);
 
 /* Kernel timing of the library's launches with HIP events on the launch
- * stream.  enable != 0 starts recording (clears totals).  For a kernel class
- * name ("ring_gemm_fp64", "ring_gemm_fp32", "ring_gemm_bf16" -- the two ring
- * GEMMs of sigma --, the same split by GEMM tile as "ring_gemm_<prec>:<tile>"
- * (tiles: 128x128 64x64 128x64 64x128 db128x128 db256x128 db128x256 db256x256
- * db32_256x256 db32_256x128 db32_128x128 db32_256x256w16 db256x256w16), "sigma",
- * "arnoldi" (bytes: algorithmic HBM bytes of the Arnoldi step), "mlp") gfcc_prof_get
- * returns the number of launches, total milliseconds and algorithmic flops and
- * bytes summed over them (host outputs).  Blocking. */
+ * stream.  enable != 0 starts recording (clears totals); enable = 0 stops it and
+ * also clears them.  For a kernel class name ("ring_gemm_fp64", "ring_gemm_fp32",
+ * "ring_gemm_bf16", "ring_gemm_fp16" -- the two ring GEMMs of sigma --, the same
+ * split by GEMM tile as "ring_gemm_<prec>:<tile>" (tiles: 128x128 64x64 128x64
+ * 64x128 db128x128 db256x128 db128x256 db256x256 db32_256x256 db32_256x128
+ * db32_128x128 db32_256x256w16 db256x256w16), "sigma", "arnoldi" (bytes:
+ * algorithmic HBM bytes of the Arnoldi step), "mlp", "ea_sigma", "ea_ring",
+ * "ea_ladder", "uhf_sigma") gfcc_prof_get returns the number of launches, total
+ * milliseconds and algorithmic flops and bytes summed over them (host outputs).
+ * Counted whether or not recording is on (count only): "graph_capture" and
+ * "graph_replay", the inner iterations the solver captured as a hipGraph and
+ * replayed from one (graph replay is off while recording).  Blocking. */
 gfcc_status gfcc_prof_enable(gfcc_ctx* ctx, int enable);
 gfcc_status gfcc_prof_get(gfcc_ctx* ctx, const char* name, int64_t* count, double* ms,
                           double* flops, double* bytes);

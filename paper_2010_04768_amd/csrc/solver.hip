@@ -1323,6 +1323,7 @@ struct BatchRun {
           auto it = graphs.find(key);
           if (it != graphs.end()) {
             GFCC_HIP(hipGraphLaunch(it->second, s));
+            lanes[0].c->prof["graph_replay"].count += 1;
           } else if (seen.count(key)) {
             // Record on a library stream: the caller's stream may be the legacy
             // default stream, which cannot be captured.  Recording executes
@@ -1348,6 +1349,7 @@ struct BatchRun {
             (void)hipGraphDestroy(gr);
             GFCC_HIP(ie);
             graphs[key] = ex;
+            lanes[0].c->prof["graph_capture"].count += 1;
             GFCC_HIP(hipGraphLaunch(ex, s));
           } else {
             seen.insert(key);

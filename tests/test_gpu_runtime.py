@@ -34,10 +34,16 @@ def test_graph_replay_matches_eager(ctx, prec):
     p = rng.integers(0, s.n_occ, size=24)
     w = rng.uniform(-1.2, -0.3, size=24)
     Ge, ie, _ = c.solve(p, w, 0.01, tol=1e-10, batch=8, precision=prec, use_graph=False)
+    c.prof_enable(False)  # clears the counters
     Gg, ig, _ = c.solve(p, w, 0.01, tol=1e-10, batch=8, precision=prec, use_graph=True)
     assert all(i["status"] == 0 for i in ie + ig)
     assert [i["iters"] for i in ie] == [i["iters"] for i in ig]
     assert torch.equal(Ge, Gg)
+    # the capture is kept across cycle finishing (no buffer is reallocated there): a few window
+    # shapes are captured once each and the rest of the iterations are replays
+    cap, rep = c.prof_get("graph_capture")["count"], c.prof_get("graph_replay")["count"]
+    print(f"[graph] {prec}: {cap} captures, {rep} replays")
+    assert 1 <= cap <= 8 and rep >= 4 * cap
 
 
 def test_autotuner_cache_and_results(ctx, tmp_path):
