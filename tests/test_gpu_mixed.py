@@ -46,7 +46,7 @@ def test_mixed_precision_per_system_error(workload, k):
         assert all(i["status"] == 0 for i in ir)
         Gr = Gr.cpu().numpy()[:, 0]
         errs = {}
-        for form in ("fp32", "bf16"):
+        for form in ("fp32", "bf16", "fp16"):
             G, info, _ = ctx.solve(P, W, wl.eta, tol=wl.tol, restart=wl.restart, precision=form, max_iter=3000)
             assert all(i["status"] == 0 and i["true_rel_resid"] <= wl.tol for i in info), form
             G = G.cpu().numpy()[:, 0]

@@ -61,7 +61,8 @@ def _direct(s, A, p, w):
     return O.left_vector(s, p) @ x
 
 
-@pytest.mark.parametrize("prec,tol,graph", [("fp64", 1e-11, False), ("bf16", 1e-10, False), ("fp64", 1e-11, True)])
+@pytest.mark.parametrize("prec,tol,graph", [("fp64", 1e-11, False), ("bf16", 1e-10, False), ("fp64", 1e-11, True),
+                                           ("fp16", 1e-10, True)])
 def test_multi_matches_single_and_direct(three, prec, tol, graph):
     S, P, W = _queue(three, [9, 7, 8])
     ctxs = [c for _, _, c in three]
