@@ -126,6 +126,8 @@ gfcc_status gfcc_build_intermediates(const gfcc_system* sys, void* stream, gfcc_
  *                    (-omega - i eta + Hbar_N) Y = -b' by the same GMRES; Jacobi uses the EA
  *                    diagonal); G[r][k] = c'_{q[k]} . Y_{p[r]} = G^EA_{q[k] p[r]}; X receives Y.
  *                    FP64 only; GFCC_PC_MLP is E_STATE.
+ *   gfcc_solve_shifts multi-shift GMRES over all frequencies of each right-hand side orbital, the same
+ *                    G^EA_{q p}(omega) layout (FP64; a fallback must be FP64 without the network)
  *   gfcc_greens, gfcc_greens_noalloc   G[r][k] = c'_{q[k]} . X[r]
  *   gfcc_export      FOO, FVV, FOV (the one-body blocks shared with the IP term) and DIAG [D]
  *   gfcc_prof_*, gfcc_destroy
@@ -184,7 +186,8 @@ typedef struct {
  * (omega + Hbar_N - i eta) X_p = abar_p|Phi> (occupied p: e_p; virtual p = o + a:
  * r_i = t_i^a, r_ij^b = t_ij^ab) and G[r][k] = G_{q[k] p[r]} = c_q . X_p with the left rows
  * carrying 1/2 on their 2h1p block (each pair counted once); G vanishes between orbitals of
- * different spin.  FP64 only; GFCC_PC_MLP is E_STATE.  gfcc_greens(_noalloc), gfcc_export
+ * different spin.  FP64 only; GFCC_PC_MLP is E_STATE.  gfcc_solve_shifts (FP64 fallback only),
+ * gfcc_greens(_noalloc), gfcc_export
  * (FOO, FVV, FOV over spin orbitals, DIAG [D]), gfcc_prof_*, gfcc_destroy work on it; every
  * other entry point returns E_STATE.  Storage: spin-orbital <oo||vv>, W_oooo, W_ooov, W_ovvo,
  * W_ovoo and the amplitudes (o^2 v^2 each); the build's temporaries hold the <ov||vv> blocks

@@ -663,7 +663,6 @@ gfcc_status gfcc_solve_shifts(gfcc_ctx* c, int64_t np, const int64_t* p, int64_t
                               double* X, gfcc_rhs_info* info, void* stream) {
   bool all_conv = true;
   gfcc_status st = guarded([&] {
-    ip_sector(c, "gfcc_solve_shifts");
     GFCC_CHECK(c, GFCC_E_ARG, "null context");
     GFCC_CHECK(opts && opts->struct_size >= sizeof(gfcc_shift_opts), GFCC_E_ARG, "bad options struct");
     GFCC_CHECK(np >= 0 && n_omega >= 0, GFCC_E_ARG, "negative size");
@@ -684,6 +683,14 @@ gfcc_status gfcc_solve_shifts(gfcc_ctx* c, int64_t np, const int64_t* p, int64_t
       GFCC_CHECK(f.tol > 0.0 && f.restart >= 1 && f.max_iter >= 1, GFCC_E_ARG, "bad fallback tolerance/restart/max_iter");
       GFCC_CHECK(f.precond >= GFCC_PC_NONE && f.precond <= GFCC_PC_MLP, GFCC_E_ARG, "bad fallback preconditioner");
       GFCC_CHECK(f.precision >= GFCC_FP64 && f.precision <= GFCC_FP16_IR, GFCC_E_ARG, "bad fallback precision");
+      GFCC_CHECK(c->sector == 0 || (f.precision == GFCC_FP64 && f.precond != GFCC_PC_MLP), GFCC_E_ARG,
+                 "the fallback of an electron-attachment or open-shell context is FP64 without the network");
+    }
+    if (c->sector == 1) {  // the EA system (omega - Hbar_N + i eta) Y = b' as (-omega - i eta + Hbar_N) Y = -b'
+      std::vector<double> wneg(static_cast<size_t>(n_omega));
+      for (int64_t k = 0; k < n_omega; ++k) wneg[size_t(k)] = -omega[k];
+      solve_shifts(c, np, p, n_omega, wneg.data(), eta, nq, q, opts, G, X, info, as_stream(stream), &all_conv);
+      return;
     }
     solve_shifts(c, np, p, n_omega, omega, eta, nq, q, opts, G, X, info, as_stream(stream), &all_conv);
   });

@@ -397,7 +397,7 @@ void solve_shifts(gfcc_ctx* c, int64_t np, const int64_t* p, int64_t nw, const d
   std::map<int64_t, int> brow_of;
   std::vector<int64_t> borb;
   for (int64_t r = 0; r < np; ++r)
-    if (p[r] >= c->o && !brow_of.count(p[r])) {
+    if (c->materialised(p[r]) && !brow_of.count(p[r])) {
       brow_of[p[r]] = int(borb.size());
       borb.push_back(p[r]);
     }
@@ -467,7 +467,7 @@ void solve_shifts(gfcc_ctx* c, int64_t np, const int64_t* p, int64_t nw, const d
   auto refill = [&]() {
     std::vector<int> sl, pl, bl;
     while (!free_slots.empty() && next < np) {
-      const int br = p[next] >= c->o ? brow_of.at(p[next]) : -1;
+      const int br = c->materialised(p[next]) ? brow_of.at(p[next]) : -1;
       const double bn = br < 0 ? 1.0 : bnorm_h[size_t(br)];
       if (!(bn > 0.0)) {  // b_p = 0: X = 0 and G = 0 at every shift
         GFCC_HIP(hipMemsetAsync(G + next * nw * nql * 2, 0, size_t(nw * nql) * 16, s));
@@ -668,7 +668,7 @@ void solve_shifts(gfcc_ctx* c, int64_t np, const int64_t* p, int64_t nw, const d
     return true;
   };
 
-  if (o->tune_cache) {  // FP64 sigma tiles for a full orbital window
+  if (o->tune_cache && c->sector == 0) {  // FP64 sigma tiles for a full orbital window
     tune_load(c, o->tune_cache);
     tune_ring(c, Prec::F64, int64_t(B), s);
     tune_save(c, o->tune_cache);

@@ -142,13 +142,33 @@ def test_identical_spins_match_closed_shell_context():
     uhf.close()
 
 
+def test_multishift_matches_oracle(sysos):
+    """Multi-shift GMRES on the open-shell context against the oracle's GMRES at 1e-10."""
+    s, im, ctx = sysos
+    so = im["so"]
+    o = so["o"]
+    ps = [0, o - 1, o]
+    ws = [-1.0, -0.6, -0.35]
+    qs = [0, o - 1, o]
+    G, info, _ = ctx.solve_shifts(ps, ws, ETA, q=qs, tol=1e-11, max_dim=400,
+                                  fallback=dict(precond="jacobi", precision="fp64", tol=1e-11, restart=60,
+                                                max_iter=6000))
+    G = G.cpu().numpy()
+    for i, p in enumerate(ps):
+        if not np.any(OS.rhs(so, p)):
+            assert np.abs(G[i]).max() == 0.0
+            continue
+        ref = OS.greens(im, so, p, ws, ETA, qs=qs, tol=1e-13, restart=60)
+        for k in range(len(ws)):
+            assert info[i][k]["status"] in (0, 4), info[i][k]
+            assert np.abs(G[i, k] - ref[k]).max() <= 1e-10 * max(1.0, np.abs(ref[k]).max()), (p, ws[k])
+
+
 def test_closed_shell_only_entry_points_refuse(sysos):
     s, im, ctx = sysos
     with pytest.raises(RuntimeError, match="open-shell"):
         ctx.sigma(torch.zeros(1, ctx.dim, dtype=torch.complex128), precision="bf16")
     with pytest.raises(RuntimeError):
         ctx.solve([0], [-0.5], ETA, precond="mlp")
-    with pytest.raises(RuntimeError, match="open-shell"):
-        ctx.solve_shifts([0], [-0.5], ETA)
     with pytest.raises(RuntimeError, match="open-shell"):
         ctx.export("WOVVO")
