@@ -529,7 +529,8 @@ def ea_block(args):
     Build of the EA context (timed), the sigma product's particle-particle ladder GEMM against
     the FP64 MFMA peak (HIP events on the library's stream; 2 (P o) v^4 flops per launch for P
     planes), and G^EA for the 8 lowest virtual orbitals q at 8 frequencies on [0.15, 0.55]
-    (FP64 GMRES, Jacobi, tol 1e-8), with four of them re-solved at tol 1e-12 as the check."""
+    (FP64 GMRES, Jacobi, tol 1e-8), with four of them re-solved at tol 1e-12 as the check; then the
+    same sigma with FP16 products and the same 64 solves as FP16 GMRES-IR (FP64 residuals)."""
     import torch
 
     from paper_2010_04768_amd import gfcc
@@ -586,6 +587,29 @@ def ea_block(args):
                              precision="fp64")
     Gr = Gr.cpu().numpy()[:, 0]
     rel = float(np.max(np.abs(G[pick] - Gr) / np.abs(Gr)))
+    # FP16 products: sigma timing, the ladder against the FP16 MFMA peak, and GMRES-IR
+    ctx.sigma(X, precision="fp16")
+    torch.cuda.synchronize()
+    ctx.prof_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ctx.sigma(X, precision="fp16")
+    torch.cuda.synchronize()
+    sig16_s = (time.perf_counter() - t0) / reps
+    lad16 = ctx.prof_get("ea_ladder")
+    ctx.prof_enable(False)
+    lad16_ms = lad16["ms"] / max(lad16["count"], 1)
+    ach16 = (lad16["flops"] / max(lad16["count"], 1)) / (lad16_ms * 1e-3)
+    t0 = time.perf_counter()
+    G16, info16, _ = ctx.solve(Q, W, wl.eta, tol=1e-8, restart=30, max_iter=3000, precond="jacobi",
+                               precision="fp16")
+    torch.cuda.synchronize()
+    solve16_s = time.perf_counter() - t0
+    G16 = G16.cpu().numpy()[:, 0]
+    rel16 = float(np.max(np.abs(G16[pick] - Gr) / np.abs(Gr)))
+    conv16 = sum(1 for i in info16 if i["status"] == 0)
+    log(f"EA FP16 sigma {sig16_s * 1e3:.1f} ms (ladder {lad16_ms:.2f} ms = {ach16 / 1e12:.0f} TFLOP/s); "
+        f"FP16-IR solve {solve16_s:.1f}s ({conv16} converged), rel err vs tol 1e-12: {rel16:.1e}")
     # multi-shift GMRES over a 64-point grid that contains the 8 frequencies above
     wgrid = np.linspace(0.15, 0.55, 64)
     wgrid[np.round(np.linspace(0, 63, 8)).astype(int)] = ws
@@ -607,6 +631,13 @@ def ea_block(args):
                      "converged": conv, "iters_min_med_max": [int(min(its)), int(np.median(its)), int(max(its))],
                      "max_true_rel_resid": float(max(i["true_rel_resid"] for i in info)),
                      "check_rel_err_vs_tol1e-12": rel},
+           "fp16": {"sigma_ms_32vec": sig16_s * 1e3,
+                    "ladder": {"avg_ms": lad16_ms, "achieved_tflops": ach16 / 1e12,
+                               "frac_of_fp16_peak": ach16 / PEAK["fp16"]},
+                    "solve_ir": {"seconds": solve16_s, "omega_pts_per_s": len(ws) / solve16_s,
+                                 "converged": conv16, "speedup_vs_fp64": solve_s / solve16_s,
+                                 "max_true_rel_resid": float(max(i["true_rel_resid"] for i in info16)),
+                                 "check_rel_err_vs_tol1e-12": rel16}},
            "multishift": {"omega": "64 on [0.15, 0.55] (containing the 8 above)", "rhs": int(len(qs) * 64),
                           "seconds": ms_s, "omega_points_per_s": 64 / ms_s, "converged": ms_conv,
                           "max_rel_diff_vs_restarted_on_the_8": ms_rel}}

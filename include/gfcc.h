@@ -121,11 +121,14 @@ gfcc_status gfcc_build_intermediates(const gfcc_system* sys, void* stream, gfcc_
  *
  * The returned context works with these entry points, with these meanings:
  *   gfcc_dims        D = v + o v^2
- *   gfcc_sigma       Y = Hbar_N X on 1p + 2p1h (FP64 only; E_ARG otherwise)
+ *   gfcc_sigma       Y = Hbar_N X on 1p + 2p1h, GFCC_FP64 or GFCC_FP16_IR (FP16 copies of the
+ *                    five two-body blocks and t2 with power-of-two scales, FP32 accumulation, the
+ *                    vector scale taken on the GPU per call); E_ARG for FP32 and BF16
  *   gfcc_solve_batch for right-hand side r: Y_{p[r]} at omega[r] (the system above, solved as
  *                    (-omega - i eta + Hbar_N) Y = -b' by the same GMRES; Jacobi uses the EA
  *                    diagonal); G[r][k] = c'_{q[k]} . Y_{p[r]} = G^EA_{q[k] p[r]}; X receives Y.
- *                    FP64 only; GFCC_PC_MLP is E_STATE.
+ *                    GFCC_FP64 or GFCC_FP16_IR (FP16 sigma in the restart cycles, FP64 true
+ *                    residuals between them); GFCC_PC_MLP is E_STATE.
  *   gfcc_solve_shifts multi-shift GMRES over all frequencies of each right-hand side orbital, the same
  *                    G^EA_{q p}(omega) layout (FP64; a fallback must be FP64 without the network)
  *   gfcc_greens, gfcc_greens_noalloc   G[r][k] = c'_{q[k]} . X[r]

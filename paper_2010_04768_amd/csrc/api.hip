@@ -316,8 +316,8 @@ gfcc_status gfcc_sigma(gfcc_ctx* c, int64_t nrhs, const double* X, double* Y, gf
     GFCC_CHECK(c, GFCC_E_ARG, "null context");
     GFCC_CHECK(nrhs >= 0, GFCC_E_ARG, "nrhs < 0");
     GFCC_CHECK(prec >= GFCC_FP64 && prec <= GFCC_FP16_IR, GFCC_E_ARG, "bad precision");
-    GFCC_CHECK(c->sector == 0 || prec == GFCC_FP64, GFCC_E_ARG,
-               "the electron-attachment and open-shell sigma run in FP64 only");
+    GFCC_CHECK(c->sector == 0 || prec == GFCC_FP64 || (c->sector == 1 && prec == GFCC_FP16_IR), GFCC_E_ARG,
+               "the electron-attachment sigma runs in FP64 or FP16, the open-shell sigma in FP64");
     if (nrhs == 0) return;
     GFCC_CHECK(X && Y && X != Y, GFCC_E_ARG, "X and Y must be distinct device buffers");
     hipStream_t s = as_stream(stream);
@@ -460,8 +460,8 @@ gfcc_status gfcc_solve_batch(gfcc_ctx* c, int64_t nrhs, const int64_t* p, const 
     GFCC_CHECK(opts->precond >= GFCC_PC_NONE && opts->precond <= GFCC_PC_MLP, GFCC_E_ARG, "bad preconditioner");
     GFCC_CHECK(opts->precision >= GFCC_FP64 && opts->precision <= GFCC_FP16_IR, GFCC_E_ARG, "bad precision");
     if (c->sector != 0) {
-      GFCC_CHECK(opts->precision == GFCC_FP64, GFCC_E_ARG,
-                 "the electron-attachment and open-shell solves run in FP64 only");
+      GFCC_CHECK(opts->precision == GFCC_FP64 || (c->sector == 1 && opts->precision == GFCC_FP16_IR), GFCC_E_ARG,
+                 "the electron-attachment solve runs in FP64 or FP16-IR, the open-shell solve in FP64");
       GFCC_CHECK(opts->precond != GFCC_PC_MLP, GFCC_E_STATE,
                  "the learned preconditioner is trained on the closed-shell ionisation sector only");
     }

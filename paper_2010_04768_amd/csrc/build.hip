@@ -664,6 +664,12 @@ void build_intermediates(gfcc_ctx* c, const gfcc_system* sys, hipStream_t s) {
 
 // Reduced-precision copies of the two-body operands with power-of-two scales.
 void build_lowprec(gfcc_ctx* c, int which, hipStream_t s) {
+  if (c->sector == 1) {
+    GFCC_CHECK(which == 2, GFCC_E_ARG, "the electron-attachment context has FP16 copies only");
+    build_ea_lowprec(c, s);
+    return;
+  }
+  GFCC_CHECK(c->sector == 0, GFCC_E_ARG, "the open-shell context has no reduced-precision copies");
   auto& L = c->lp[which];
   if (L.built) return;
   // one reduced-precision set at a time: the others are released (and rebuilt when asked for)

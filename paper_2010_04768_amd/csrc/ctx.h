@@ -65,6 +65,13 @@ struct gfcc_ctx {
     gfcc::DBuf zop;     // [k][n2p]       2 (kc|ld) - (kd|lc) at column (l,c,d)
     gfcc::DBuf Sl;      // [a][b]         sum_ijc t2[i,j,a,c] (2 l2[i,j,b,c] - l2[i,j,c,b])
     gfcc::DBuf ws_R, ws_z;  // sigma operand copies
+    // FP16 copies for the FP16-IR form (per-tensor power-of-two scales, stored = value * s)
+    struct Half {
+      bool built = false;
+      gfcc::DBuf ladder, vvvoT, Uop, ring, ring2, zop, t2;
+      double sL = 1, sV = 1, sU = 1, sR = 1, sR2 = 1, sZ = 1, sT = 1;
+    } h;
+    gfcc::DBuf ws_xh, ws_Rh, ws_zh;  // FP16 operand copies of a sigma call
   } ea;
 
   // open-shell (spin-unrestricted) IP blocks (sector 2), FP64, over spin orbitals
@@ -188,7 +195,11 @@ void greens_rows(gfcc_ctx* c, int64_t nb, const double* planes, int64_t nq, cons
 // electron-attachment sector (ea.hip): blocks of Hbar_N on 1p + 2p1h, sigma on planes, and the
 // rows of the linear system (-omega - i eta + Hbar_N) Y = -abar_q^+|Phi> and of G = c'_p . Y
 void build_ea(gfcc_ctx* c, const gfcc_system* sys, hipStream_t s);
-void ea_sigma_planes(gfcc_ctx* c, int64_t nplanes, const double* x, double* y, hipStream_t s);
+void ea_sigma_planes(gfcc_ctx* c, int64_t nplanes, const double* x, double* y, gfcc_precision prec, hipStream_t s);
+void build_ea_lowprec(gfcc_ctx* c, hipStream_t s);
+// FP16 operand scale of n doubles at x: which = 0 writes ws_vsc[0] = s, [1] = 1/s; which = 1 writes
+// [2] = s_z and [3] = 1/([0] s_z) (sigma.hip)
+void vector_scale(gfcc_ctx* c, const double* x, int64_t n, int which, hipStream_t s);
 void ea_rhs_rows(gfcc_ctx* c, int64_t n, const int64_t* orb_dev, double* out, hipStream_t s);
 void ea_left_rows(gfcc_ctx* c, int64_t n, const int64_t* orb_dev, double* out, hipStream_t s);
 

@@ -114,14 +114,17 @@ __global__ void ea_diag_kernel(double* __restrict__ dg, const double* __restrict
 
 // ------------------------------------------------------------------ sigma kernels
 
-// R[(x,a)][(l,d)] = y[x][p1 + (l,a,d)],  R[(x,a)][kp + (l,c)] = y[x][p1 + (l,c,a)]; padding zero
-__global__ void ea_ring_operand_kernel(const double* __restrict__ x, double* __restrict__ R, int64_t o, int64_t v,
-                                       int64_t p1, int64_t Dp, int64_t kp) {
+// R[(x,a)][(l,d)] = y[x][p1 + (l,a,d)],  R[(x,a)][kp + (l,c)] = y[x][p1 + (l,c,a)]; padding zero.
+// T = _Float16: values multiplied by the device scale sc[0] on conversion.
+template <typename T>
+__global__ void ea_ring_operand_kernel(const double* __restrict__ x, T* __restrict__ R, int64_t o, int64_t v,
+                                       int64_t p1, int64_t Dp, int64_t kp, const double* __restrict__ sc) {
   const int64_t row = blockIdx.x;  // (plane, a)
   const int64_t pl = row / v, a = row % v;
   const double* y = x + pl * Dp + p1;
-  double* r = R + row * 2 * kp;
+  T* r = R + row * 2 * kp;
   const int64_t ov = o * v;
+  const double sv = sc ? sc[0] : 1.0;
   for (int64_t t = threadIdx.x; t < kp; t += blockDim.x) {
     double u = 0.0, w = 0.0;
     if (t < ov) {
@@ -129,9 +132,22 @@ __global__ void ea_ring_operand_kernel(const double* __restrict__ x, double* __r
       u = y[(l * v + a) * v + e];
       w = y[(l * v + e) * v + a];
     }
-    r[t] = u;
-    r[kp + t] = w;
+    r[t] = T(sv * u);
+    r[kp + t] = T(sv * w);
   }
+}
+
+__global__ void fill_zero_kernel(double* __restrict__ p, int64_t n) {
+  for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < n; t += int64_t(gridDim.x) * blockDim.x)
+    p[t] = 0.0;
+}
+
+// dst = f16(sc * src) over n elements (sc a device scalar)
+__global__ void to_f16_scaled_kernel(const double* __restrict__ src, _Float16* __restrict__ dst, int64_t n,
+                                     const double* __restrict__ sc) {
+  const double sv = *sc;
+  for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < n; t += int64_t(gridDim.x) * blockDim.x)
+    dst[t] = _Float16(float(sv * src[t]));
 }
 
 // padding of output planes: [n1, p1) and [p1 + n2, Dp)
@@ -398,8 +414,14 @@ void build_ea(gfcc_ctx* c, const gfcc_system* sys, hipStream_t s) {
 
 // ------------------------------------------------------------------ sigma
 
-void ea_sigma_planes(gfcc_ctx* c, int64_t P, const double* x, double* y, hipStream_t s) {
+static void ea_sigma_f16(gfcc_ctx* c, int64_t P, const double* x, double* y, hipStream_t s);
+
+void ea_sigma_planes(gfcc_ctx* c, int64_t P, const double* x, double* y, gfcc_precision prec, hipStream_t s) {
   if (P <= 0) return;
+  if (prec == GFCC_FP16_IR) {
+    ea_sigma_f16(c, P, x, y, s);
+    return;
+  }
   const int64_t o = c->o, v = c->v, ov = c->ov, kp = c->kp, p1 = c->p1, Dp = c->Dp, vv = v * v;
   const int64_t n2 = c->n2, lv = c->ea.lv, n2p = c->ea.n2p, op = round_up(o, 8);
   c->ea.ws_R.ensure(size_t(P * v * 2 * kp) * 8, s);
@@ -427,7 +449,8 @@ void ea_sigma_planes(gfcc_ctx* c, int64_t P, const double* x, double* y, hipStre
     run64(c, g, s);
   }
   // ring products
-  hipLaunchKernelGGL(ea_ring_operand_kernel, dim3(unsigned(P * v)), dim3(256), 0, s, x, R, o, v, p1, Dp, kp);
+  hipLaunchKernelGGL((ea_ring_operand_kernel<double>), dim3(unsigned(P * v)), dim3(256), 0, s, x, R, o, v, p1, Dp, kp,
+                     nullptr);
   GFCC_HIP(hipGetLastError());
   {
     GemmArgs g;  // rows (x,a), cols (j,b): s2[x,j,a,b]
@@ -473,6 +496,133 @@ void ea_sigma_planes(gfcc_ctx* c, int64_t P, const double* x, double* y, hipStre
     h.C = y + p1; h.cm = lin(Dp); h.cn = lin(1);
     h.M = P; h.N = n2; h.K = o; h.alpha = -1.0; h.beta = 1.0;
     run64(c, h, s);
+  }
+  hipLaunchKernelGGL(zero_pads_kernel, dim3(1, unsigned(P)), dim3(256), 0, s, y, c->n1, p1, n2, Dp);
+  GFCC_HIP(hipGetLastError());
+  prof_end(c, "ea_sigma", s, 0.0, 0.0);
+}
+
+// ------------------------------------------------------------------ FP16 form
+
+void build_ea_lowprec(gfcc_ctx* c, hipStream_t s) {
+  auto& H = c->ea.h;
+  if (H.built) return;
+  const int64_t o = c->o, v = c->v, ov = c->ov, kp = c->kp, Dp = c->Dp, vv = v * v;
+  auto mk = [&](DBuf& dst, const double* src, int64_t n, double& scale) {
+    const double am = amax_host(src, n, s, c->scr);
+    scale = (am > 0.0) ? std::ldexp(1.0, -std::ilogb(am)) : 1.0;  // amax -> [1, 2)
+    dst.ensure(size_t(n) * 2, s);
+    convert_f64(src, dst.p, Prec::F16, n, scale, s);
+  };
+  mk(H.ladder, c->ea.ladder.as<double>(), vv * c->ea.lv, H.sL);
+  mk(H.vvvoT, c->ea.vvvoT.as<double>(), o * vv * c->vp, H.sV);
+  mk(H.Uop, c->Uop.as<double>(), v * Dp, H.sU);
+  mk(H.ring, c->ea.ring.as<double>(), ov * 2 * kp, H.sR);
+  mk(H.ring2, c->ea.ring2.as<double>(), ov * kp, H.sR2);
+  mk(H.zop, c->ea.zop.as<double>(), o * c->ea.n2p, H.sZ);
+  mk(H.t2, c->t2, o * o * vv, H.sT);
+  GFCC_HIP(hipStreamSynchronize(s));
+  H.built = true;
+}
+
+// FP16 products with FP32 accumulation: the plane operands are scaled on the GPU (sc[0]) and every
+// product undoes that scale from device memory; the three-body vector z gets a scale of its own.
+static void ea_sigma_f16(gfcc_ctx* c, int64_t P, const double* x, double* y, hipStream_t s) {
+  const int64_t o = c->o, v = c->v, ov = c->ov, kp = c->kp, p1 = c->p1, Dp = c->Dp, vv = v * v;
+  const int64_t n2 = c->n2, lv = c->ea.lv, n2p = c->ea.n2p, op = round_up(o, 8);
+  build_ea_lowprec(c, s);
+  const auto& H = c->ea.h;
+  c->ea.ws_xh.ensure(size_t(P * Dp) * 2, s);
+  c->ea.ws_Rh.ensure(size_t(P * v * 2 * kp) * 2, s);
+  c->ea.ws_z.ensure(size_t(P * op) * 8, s);
+  c->ea.ws_zh.ensure(size_t(P * op) * 2, s);
+  _Float16* xh = c->ea.ws_xh.as<_Float16>();
+  _Float16* Rh = c->ea.ws_Rh.as<_Float16>();
+  double* z = c->ea.ws_z.as<double>();
+  _Float16* zh = c->ea.ws_zh.as<_Float16>();
+  prof_begin(c, "ea_sigma", s);
+  vector_scale(c, x, P * Dp, 0, s);
+  const double* sc = c->ws_vsc.as<double>();
+  hipLaunchKernelGGL(to_f16_scaled_kernel, dim3(nblk(P * Dp)), dim3(256), 0, s, x, xh, P * Dp, sc);
+  hipLaunchKernelGGL((ea_ring_operand_kernel<_Float16>), dim3(unsigned(P * v)), dim3(256), 0, s, x, Rh, o, v, p1, Dp,
+                     kp, sc);
+  GFCC_HIP(hipGetLastError());
+  auto run16 = [&](const GemmArgs& g) {
+    if (!g.b_ncontig && g.batch == 1 && g.M >= 2048 && g.N >= 2048 && g.K >= 256)
+      gemm(Prec::F16, g, gemm_big_cfg(Prec::F16, g.M, g.N, g.K), s);
+    else
+      gemm_auto(Prec::F16, g, c->scr, 3, s);
+  };
+  {  // 1p <- plane
+    GemmArgs g;
+    g.A = xh; g.am = lin(Dp);
+    g.B = H.Uop.p; g.bm = lin(Dp);
+    g.C = y; g.cm = lin(Dp); g.cn = lin(1);
+    g.M = P; g.N = v; g.K = Dp;
+    g.alpha = 1.0 / H.sU; g.alpha_dev = sc + 1;
+    run16(g);
+  }
+  {  // 2p1h <- 1p
+    GemmArgs g;
+    g.A = xh; g.am = lin(Dp);
+    g.B = H.vvvoT.p; g.bm = lin(c->vp);
+    g.C = y + p1; g.cm = lin(Dp); g.cn = lin(1);
+    g.M = P; g.N = n2; g.K = v;
+    g.alpha = 1.0 / H.sV; g.alpha_dev = sc + 1;
+    run16(g);
+  }
+  {
+    GemmArgs g;  // ring 1: rows (x,a), cols (j,b)
+    g.A = Rh; g.am = lin(2 * kp);
+    g.B = H.ring.p; g.bm = lin(2 * kp);
+    g.C = y + p1; g.cm = two(v, Dp, v); g.cn = two(v, vv, 1);
+    g.M = P * v; g.N = ov; g.K = 2 * kp; g.beta = 1.0;
+    g.alpha = 1.0 / H.sR; g.alpha_dev = sc + 1;
+    prof_begin(c, "ea_ring", s);
+    run16(g);
+    prof_end(c, "ea_ring", s, 2.0 * double(g.M) * double(g.N) * double(g.K), 0.0);
+  }
+  {
+    GemmArgs g;  // ring 2: rows (x,b), cols (j,a)
+    g.A = Rh + kp; g.am = lin(2 * kp);
+    g.B = H.ring2.p; g.bm = lin(kp);
+    g.C = y + p1; g.cm = two(v, Dp, 1); g.cn = two(v, vv, v);
+    g.M = P * v; g.N = ov; g.K = kp; g.beta = 1.0;
+    g.alpha = 1.0 / H.sR2; g.alpha_dev = sc + 1;
+    run16(g);
+  }
+  {
+    GemmArgs g;  // ladder
+    g.A = xh + p1; g.am = two(o, Dp, vv);
+    g.B = H.ladder.p; g.bm = lin(lv);
+    g.C = y + p1; g.cm = two(o, Dp, vv); g.cn = lin(1);
+    g.M = P * o; g.N = vv; g.K = vv; g.beta = 1.0;
+    g.alpha = 1.0 / H.sL; g.alpha_dev = sc + 1;
+    prof_begin(c, "ea_ladder", s);
+    run16(g);
+    prof_end(c, "ea_ladder", s, 2.0 * double(g.M) * double(g.N) * double(g.K),
+             2.0 * (double(vv) * double(vv) + 2.0 * double(g.M) * double(vv)));
+  }
+  {  // three-body: z (carrying sc[0]) = y2 . zop, then y2 -= z . t2 with z scaled by sc[2]
+    // (the pad columns of z enter its scale, so they are cleared first)
+    hipLaunchKernelGGL(fill_zero_kernel, dim3(nblk(P * op)), dim3(256), 0, s, z, P * op);
+    GemmArgs g;
+    g.A = xh + p1; g.am = lin(Dp);
+    g.B = H.zop.p; g.bm = lin(n2p);
+    g.C = z; g.cm = lin(op); g.cn = lin(1);
+    g.M = P; g.N = o; g.K = n2;
+    g.alpha = 1.0 / H.sZ;
+    run16(g);
+    vector_scale(c, z, P * op, 1, s);
+    hipLaunchKernelGGL(to_f16_scaled_kernel, dim3(nblk(P * op)), dim3(256), 0, s, z, zh, P * op, sc + 2);
+    GFCC_HIP(hipGetLastError());
+    GemmArgs h;
+    h.A = zh; h.am = lin(op);
+    h.B = H.t2.p; h.bm = lin(n2); h.b_ncontig = 1;
+    h.C = y + p1; h.cm = lin(Dp); h.cn = lin(1);
+    h.M = P; h.N = n2; h.K = o; h.beta = 1.0;
+    h.alpha = -1.0 / H.sT; h.alpha_dev = sc + 3;
+    run16(h);
   }
   hipLaunchKernelGGL(zero_pads_kernel, dim3(1, unsigned(P)), dim3(256), 0, s, y, c->n1, p1, n2, Dp);
   GFCC_HIP(hipGetLastError());

@@ -164,7 +164,9 @@ static void make_operands(gfcc_ctx* c, int64_t P, const double* x, bool lowp, do
 }
 
 // the FP16 form's operand scale of n doubles at x into sc[2 which], sc[2 which + 1]
-static void vector_scale(gfcc_ctx* c, const double* x, int64_t n, int which, hipStream_t s) {
+void vector_scale(gfcc_ctx* c, const double* x, int64_t n, int which, hipStream_t s) {
+  c->ws_vsc.ensure(8 * 8, s);
+  c->ws_vpart.ensure(1024 * 8, s);
   const unsigned nb = unsigned(std::min<int64_t>(std::max<int64_t>((n + 255) / 256, 1), 1024));
   hipLaunchKernelGGL(amax_part_kernel, dim3(nb), dim3(256), 0, s, x, n, c->ws_vpart.as<double>());
   hipLaunchKernelGGL(scale_final_kernel, dim3(1), dim3(256), 0, s, c->ws_vpart.as<double>(), int(nb),
@@ -424,12 +426,15 @@ static void sigma_impl(gfcc_ctx* c, int64_t P, const double* x, double* y, gfcc_
 }
 
 void sigma_planes(gfcc_ctx* c, int64_t P, const double* x, double* y, gfcc_precision prec, hipStream_t s) {
-  if (c->sector != 0) {
-    GFCC_CHECK(prec == GFCC_FP64, GFCC_E_ARG, "the electron-attachment and open-shell sigma run in FP64 only");
-    if (c->sector == 1)
-      ea_sigma_planes(c, P, x, y, s);
-    else
-      uhf_sigma_planes(c, P, x, y, s);
+  if (c->sector == 1) {
+    GFCC_CHECK(prec == GFCC_FP64 || prec == GFCC_FP16_IR, GFCC_E_ARG,
+               "the electron-attachment sigma runs in FP64 or FP16");
+    ea_sigma_planes(c, P, x, y, prec, s);
+    return;
+  }
+  if (c->sector == 2) {
+    GFCC_CHECK(prec == GFCC_FP64, GFCC_E_ARG, "the open-shell sigma runs in FP64 only");
+    uhf_sigma_planes(c, P, x, y, s);
     return;
   }
   sigma_impl(c, P, x, y, prec, s, PH_ALL, nullptr, nullptr);

@@ -8,6 +8,8 @@ pinned block by block to the N+1-sector brute force).
   virtual q and p; the bilinear product on the returned Y;
 * free particles: G = G^IP + G^EA = diag 1/(omega - eps_p -/+ i eta) over every orbital, and
   A = A^IP + A^EA (the EA term with the opposite sign of eta);
+* FP16 products: sigma within the FP16 bound of the oracle, also on vectors far from unit
+  size; GMRES-IR (FP16 inner cycles, FP64 residuals) reaching G at 1e-8 of the oracle's;
 * entry points that need the IP sector's operands refuse an EA context.
 """
 import numpy as np
@@ -70,6 +72,36 @@ def test_sigma_matches_oracle(sysea):
     # real-linear: one real vector alone
     g1 = ctx.sigma(torch.from_numpy(Y[0].real.astype(complex))).cpu().numpy()
     assert np.abs(g1 - E.sigma(eim, Y[0].real)).max() <= 1e-12 * scale
+
+
+@pytest.mark.parametrize("mag", [1.0, 1e-12, 1e9])
+def test_sigma_fp16_bound(sysea, mag):
+    """FP16 copies of the EA operands with power-of-two scales, FP32 accumulation: the relative
+    error stays within the FP16 bound (11-bit significand, a few times 2^-11 over the products),
+    and the per-call vector scale keeps it for tiny and huge vectors."""
+    s, eim, ctx = sysea
+    Y = random_vectors(3, ctx.dim, seed=8) * mag
+    got = ctx.sigma(torch.from_numpy(Y), precision="fp16").cpu().numpy()
+    want = E.sigma(eim, Y)
+    err = np.linalg.norm(got - want) / np.linalg.norm(want)
+    print(f"[ea] fp16 sigma rel err {err:.2e} (mag {mag:g})")
+    assert err < 4e-3, err
+    assert err > 1e-9  # the reduced-precision products did run
+
+
+def test_greens_fp16_ir(sysea):
+    """GMRES-IR: FP16 sigma inside restart cycles, FP64 true residuals between them; G reaches the
+    oracle's at 1e-8 and the reported residual is the FP64 one."""
+    s, eim, ctx = sysea
+    o, v = s.n_occ, s.n_vir
+    qs, ws = [o, o + v - 1, 0], [0.6, 1.2, 0.9]
+    ps = [o, 0, o + v - 1]
+    G, info, _ = ctx.solve(qs, ws, ETA, q=ps, tol=1e-10, restart=40, max_iter=6000, precision="fp16")
+    G = G.cpu().numpy()
+    for r, (q, w) in enumerate(zip(qs, ws)):
+        assert info[r]["status"] == 0 and info[r]["true_rel_resid"] <= 1e-10, info[r]
+        gref = E.greens(s, eim, q, [w], ETA, ps=ps, tol=1e-13, restart=60)[0]
+        assert np.abs(G[r] - gref).max() <= 1e-8 * max(1.0, np.abs(gref).max()), (q, w)
 
 
 def test_diagonal_and_one_body_blocks(sysea):
@@ -196,5 +228,7 @@ def test_ip_only_entry_points_refuse_ea_context(sysea):
         ctx.solve([o], [0.5], ETA, precond="mlp")
     with pytest.raises(RuntimeError):
         ctx.solve([o], [0.5], ETA, precision="bf16")
+    with pytest.raises(RuntimeError):
+        ctx.solve([o], [0.5], ETA, precision="fp32")
     with pytest.raises(RuntimeError, match="electron-attachment"):
         ctx.export("WOVVO")

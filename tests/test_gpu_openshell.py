@@ -171,4 +171,6 @@ def test_closed_shell_only_entry_points_refuse(sysos):
     with pytest.raises(RuntimeError):
         ctx.solve([0], [-0.5], ETA, precond="mlp")
     with pytest.raises(RuntimeError, match="open-shell"):
+        ctx.sigma(torch.zeros(1, ctx.dim, dtype=torch.complex128), precision="fp16")
+    with pytest.raises(RuntimeError, match="open-shell"):
         ctx.export("WOVVO")
