@@ -989,8 +989,9 @@ def multi_study(args):
     [-1.2, -0.3]): --multi-p highest occupied p x --multi-omega frequencies per system, BF16 sigma +
     FP64 refinement to tol 1e-8, Jacobi, restart 30, graph replay.  Timed: one gfcc_solve_multi over all
     right-hand sides (window 128 in all) against one gfcc_solve_batch per system in turn (window 42 each);
-    both after one untimed warm-up that fills the tile cache.  G of every system is checked against its
-    FP64 solve (tol 1e-11, untimed)."""
+    both after one untimed warm-up that fills the tile cache, each with the automatic number of inner
+    iterations between host synchronisations and with one synchronisation per iteration.  G of every
+    system is checked against its FP64 solve (tol 1e-11, untimed)."""
     import torch
 
     from paper_2010_04768_amd import gfcc
@@ -1015,37 +1016,54 @@ def multi_study(args):
         f"dims {[s.dim for s in wl.systems]}")
     kw = dict(tol=wl.tol, precision="bf16", batch=128, use_graph=True, tune_cache=args.tune_cache or None)
 
-    def one_launch():
+    def counters():
+        return {k: sum(c.prof_get(k)["count"] for c in ctxs) for k in ("host_sync", "loop_sync", "inner_iter",
+                                                                         "slot_iter")}
+
+    def reset():
+        for c in ctxs:
+            c.prof_enable(False)  # clears the counters
+
+    def one_launch(se=0):
+        reset()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        G, info = gfcc.solve_multi(ctxs, S, P, W, wl.eta, **kw)
+        G, info = gfcc.solve_multi(ctxs, S, P, W, wl.eta, sync_every=se, **kw)
         torch.cuda.synchronize()
-        return G.cpu().numpy()[:, 0], info, time.perf_counter() - t0
+        return G.cpu().numpy()[:, 0], info, time.perf_counter() - t0, counters()
 
-    def per_system():
+    def per_system(se=0):
+        reset()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         G = np.zeros(len(S), dtype=complex)
         info = [None] * len(S)
         for k, c in enumerate(ctxs):
             idx = np.nonzero(S == k)[0]
-            Gk, ik, _ = c.solve(P[idx], W[idx], wl.eta, **dict(kw, batch=128 // len(ctxs)))
+            Gk, ik, _ = c.solve(P[idx], W[idx], wl.eta, sync_every=se, **dict(kw, batch=128 // len(ctxs)))
             G[idx] = Gk.cpu().numpy()[:, 0]
             for j, r in enumerate(idx):
                 info[r] = ik[j]
         torch.cuda.synchronize()
-        return G, info, time.perf_counter() - t0
+        return G, info, time.perf_counter() - t0, counters()
 
     one_launch()
     per_system()
-    Gm, im_, tm = one_launch()
-    Gs, is_, ts = per_system()
-    log(f"one launch {tm:.2f}s, per system {ts:.2f}s")
+    Gm, im_, tm, km = one_launch()
+    Gs, is_, ts, ks = per_system()
+    _, _, tm1, km1 = one_launch(1)
+    _, _, ts1, ks1 = per_system(1)
+    log(f"one launch {tm:.2f}s {km}, per system {ts:.2f}s {ks}; one synchronisation per iteration: "
+        f"one launch {tm1:.2f}s {km1}, per system {ts1:.2f}s {ks1}")
     out = {"metric": "multi-system solve (BF16-IR), one persistent launch vs one solve per system",
            "workload": ("three different 20/100/400 systems" if args.multi_small else
                         "mixed-3sys (20/100/400, 40/180/720, 60/300/1200)") + ", eta 0.01, sampled "
                        f"{args.multi_p} p x {args.multi_omega} omega per system", "n_rhs": int(len(S)),
-           "one_launch_s": tm, "per_system_s": ts, "speedup": ts / tm, "systems": []}
+           "one_launch_s": tm, "per_system_s": ts, "speedup": ts / tm,
+           "counters": {"one_launch": km, "per_system": ks},
+           "sync_every_iteration": {"one_launch_s": tm1, "per_system_s": ts1,
+                                    "counters": {"one_launch": km1, "per_system": ks1}},
+           "systems": []}
     for k, c in enumerate(ctxs):
         idx = np.nonzero(S == k)[0]
         Gr, ir, _ = c.solve(P[idx], W[idx], wl.eta, tol=1e-11, precision="fp64", max_iter=3000)

@@ -269,6 +269,15 @@ typedef struct {
                                gfcc_solve_batch and gfcc_solve_multi; ignored by the solves that
                                model-order reduction and the multi-shift fallback run.  Restored
                                rows get X = 0 when X is requested. */
+  int32_t sync_every;       /* inner iterations between host synchronisations of the solver loop
+                               (flags, Krylov steps and residual estimates copied back in one
+                               transfer).  0 = automatic: the next run of iterations ends at 85% of
+                               the iterations the first active right-hand side is predicted to need
+                               to reach its cycle target (from the observed decrease of its
+                               residual estimate), at most 16; 1 = after every iteration.  A slot
+                               whose cycle stops inside a run is frozen on the device, so G, X and
+                               info do not depend on this value; it is 1 whenever the learned
+                               preconditioner or profiling is on. */
 } gfcc_solve_opts;
 
 /* Per right-hand side result (host memory). status: 0 converged, 1 max_iter,

@@ -459,6 +459,7 @@ gfcc_status gfcc_solve_batch(gfcc_ctx* c, int64_t nrhs, const int64_t* p, const 
     GFCC_CHECK(opts->tol > 0.0 && opts->restart >= 1 && opts->max_iter >= 1, GFCC_E_ARG, "bad tolerance/restart/max_iter");
     GFCC_CHECK(opts->precond >= GFCC_PC_NONE && opts->precond <= GFCC_PC_MLP, GFCC_E_ARG, "bad preconditioner");
     GFCC_CHECK(opts->precision >= GFCC_FP64 && opts->precision <= GFCC_FP16_IR, GFCC_E_ARG, "bad precision");
+    GFCC_CHECK(opts->sync_every >= 0, GFCC_E_ARG, "sync_every < 0");
     if (c->sector != 0) {
       GFCC_CHECK(opts->precision == GFCC_FP64 || (c->sector == 1 && opts->precision == GFCC_FP16_IR), GFCC_E_ARG,
                  "the electron-attachment solve runs in FP64 or FP16-IR, the open-shell solve in FP64");
@@ -648,6 +649,7 @@ gfcc_status gfcc_solve_multi(int32_t nsys, gfcc_ctx* const* ctxs, int64_t nrhs, 
     GFCC_CHECK(opts->tol > 0.0 && opts->restart >= 1 && opts->max_iter >= 1, GFCC_E_ARG, "bad tolerance/restart/max_iter");
     GFCC_CHECK(opts->precond >= GFCC_PC_NONE && opts->precond <= GFCC_PC_MLP, GFCC_E_ARG, "bad preconditioner");
     GFCC_CHECK(opts->precision >= GFCC_FP64 && opts->precision <= GFCC_FP16_IR, GFCC_E_ARG, "bad precision");
+    GFCC_CHECK(opts->sync_every >= 0, GFCC_E_ARG, "sync_every < 0");
     if (opts->precond == GFCC_PC_MLP)
       for (int k = 0; k < nsys; ++k)
         GFCC_CHECK(ctxs[k]->mlp && ctxs[k]->mlp->trained, GFCC_E_STATE,

@@ -70,7 +70,8 @@ struct SolverDev {
   int* kk;         // [B]  current Krylov step
   double* ctol;    // [B]  cycle tolerance (absolute)
   double* res;     // [B]  residual estimate |g_{k+1}|
-  int* flag;       // [B]  1: cycle done
+  int* flag;       // [B]  0 while the cycle runs; 1 done, 3 non-finite: the slot's kernels skip it
+  int* fresh;      // [B]  1 in the iteration whose Givens step stopped the cycle (its scaling still runs)
   cplx* part;      // [na][nch][PS] partial dots: <V_j, w> at j, <V_j, V_k> at MAXM+1+j
   cplx* Gm;        // [B][m][m+1]   Gm[s][k][j] = <V_j, V_k>, j <= k
   cplx* h;         // [na][MAXM+1]
@@ -116,6 +117,7 @@ __global__ void init_slots_kernel(SolverDev d, const int* slots, const int* ps, 
     d.ctol[s] = ctol[q];
     d.res[s] = bn;
     d.flag[s] = 0;
+    d.fresh[s] = 0;
     for (int j = 0; j <= d.m; ++j) d.g[int64_t(s) * (d.m + 1) + j] = cplx{j == 0 ? bn : 0.0, 0.0};
   }
 }
@@ -124,6 +126,7 @@ __global__ void init_slots_kernel(SolverDev d, const int* slots, const int* ps, 
 __global__ void precond_kernel(SolverDev d, const int* act, double* win, const double* diag, int mode, int flex) {
   const int q = blockIdx.y;
   const int s = act[q];
+  if (d.flag[s] != 0) return;  // cycle stopped earlier in this run of iterations
   const int k = d.kk[s];
   const cplx z = d.z[s];
   const double* vr = vec(d, s, k, 0);
@@ -158,6 +161,7 @@ __global__ __launch_bounds__(VT) void arnoldi_kernel(SolverDev d, const int* act
                                                      const double* wout, int pass) {
   const int q = blockIdx.y;
   const int s = act[q];
+  if (d.flag[s] != 0) return;
   const int k = d.kk[s];
   const int64_t i0 = int64_t(blockIdx.x) * CH;
   double* wr = vec(d, s, k + 1, 0);
@@ -283,6 +287,7 @@ __global__ __launch_bounds__(VT) void arnoldi_kernel(SolverDev d, const int* act
 __global__ void reduce_hg_kernel(SolverDev d, const int* act) {
   const int q = blockIdx.x;
   const int s = act[q];
+  if (d.flag[s] != 0) return;
   const int k = d.kk[s];
   const int m = d.m;
   const int j = threadIdx.x;
@@ -321,9 +326,24 @@ __global__ void reduce_hg_kernel(SolverDev d, const int* act) {
 }
 
 // ||w||, H(k+1, k), Givens rotation, residual estimate, cycle flag
-__global__ void givens_kernel(SolverDev d, const int* act, int* flags_out, double* res_out, int iters_left_any) {
+// stat (window size B): flags at [0, B), Krylov steps at [B, 2B), residual estimates as doubles from
+// int offset 2B, each indexed by the position in the active list.  A slot whose cycle stopped in an
+// earlier iteration only reports its state.
+__global__ void givens_kernel(SolverDev d, const int* act, int* stat, int B, int iters_left_any) {
   const int q = blockIdx.x;
   const int s = act[q];
+  int* flags_out = stat;
+  int* k_out = stat + B;
+  double* res_out = reinterpret_cast<double*>(stat + 2 * B);
+  if (d.flag[s] != 0) {
+    if (threadIdx.x == 0) {
+      d.fresh[s] = 0;
+      flags_out[q] = d.flag[s];
+      k_out[q] = d.kk[s];
+      res_out[q] = d.res[s];
+    }
+    return;
+  }
   __shared__ double red[64];
   double acc = 0.0;
   for (int c = threadIdx.x; c < d.nch; c += 64) acc += d.npart[int64_t(q) * d.nch + c];
@@ -376,13 +396,19 @@ __global__ void givens_kernel(SolverDev d, const int* act, int* flags_out, doubl
   if (!(r == r) || !(nrm == nrm) || std::isinf(r)) f = 3;              // non-finite
   else if (r <= d.ctol[s] || knew >= m || nrm == 0.0 || iters_left_any == 0) f = 1;
   flags_out[q] = f;
+  k_out[q] = knew;
   res_out[q] = r;
+  if (f != 0) {
+    d.flag[s] = f;
+    d.fresh[s] = 1;
+  }
 }
 
 // V[k] (new) *= 1/||w||  (k already advanced)
 __global__ void scale_kernel(SolverDev d, const int* act) {
   const int q = blockIdx.y;
   const int s = act[q];
+  if (d.flag[s] != 0 && d.fresh[s] == 0) return;
   const int k = d.kk[s];
   const double nrm = d.norm[q];
   const double f = nrm > 0.0 ? 1.0 / nrm : 0.0;
@@ -537,6 +563,8 @@ __global__ void restart_kernel(SolverDev d, const int* slots, const double* beta
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     d.kk[s] = 0;
+    d.flag[s] = 0;
+    d.fresh[s] = 0;
     d.ctol[s] = ctol[q];
     d.res[s] = b;
     for (int j = 0; j <= d.m; ++j) d.g[int64_t(s) * (d.m + 1) + j] = cplx{j == 0 ? b : 0.0, 0.0};
@@ -622,6 +650,39 @@ struct HostSlot {
   double beta = 1.0;       // residual at the start of the current cycle
   double bn = 1.0;         // |b_p|
   int brow = -1;           // row of b_p in the materialised right-hand sides (-1: e_p)
+  double ctol = 0.0;       // the current cycle's target for the residual estimate
+  double res = 1.0;        // residual estimate at the last synchronisation
+  double lrate = 0.0;      // log of its reduction per iteration (0: not observed yet)
+};
+
+// Page-locked host memory: device-to-host copies into it stay asynchronous.
+struct HBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  HBuf() = default;
+  HBuf(const HBuf&) = delete;
+  HBuf& operator=(const HBuf&) = delete;
+  HBuf(HBuf&& o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+  HBuf& operator=(HBuf&& o) noexcept {
+    if (this != &o) { release(); p = o.p; bytes = o.bytes; o.p = nullptr; o.bytes = 0; }
+    return *this;
+  }
+  ~HBuf() { release(); }
+  void release() {
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  void ensure(size_t n) {
+    if (n <= bytes && p) return;
+    release();
+    if (hipHostMalloc(&p, n, hipHostMallocDefault) != hipSuccess) {
+      p = nullptr;
+      throw Error{GFCC_E_OOM, "hipHostMalloc of " + std::to_string(n) + " bytes failed"};
+    }
+    bytes = n;
+  }
+  template <typename T> T* as() const { return static_cast<T*>(p); }
 };
 
 static double lp_cycle_rtol(gfcc_precision p) {
@@ -633,12 +694,6 @@ static double lp_cycle_rtol(gfcc_precision p) {
   }
 }
 
-template <typename T>
-static void upload(DBuf& b, const std::vector<T>& v, hipStream_t s) {
-  b.ensure(std::max<size_t>(v.size(), 1) * sizeof(T), s);
-  if (!v.empty()) GFCC_HIP(hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
-}
-
 // One system's share of the solve: a window of B slots on its context, the
 // queue of its right-hand sides (global indices) and the device state.
 struct Lane {
@@ -647,9 +702,9 @@ struct Lane {
   size_t next = 0;
   int B = 0, nch = 0;
   int64_t Dp = 0;
-  DBuf bV, bZ, bX, bH, bcs, bsn, bg, by, bz, bkk, bctol, bres, bflag, bpart, bGm, bh, bnpart, bnorm;
+  DBuf bV, bZ, bX, bH, bcs, bsn, bg, by, bz, bkk, bctol, bres, bflag, bfresh, bpart, bGm, bh, bnpart, bnorm;
   SolverDev d{};
-  DBuf d_act, d_flags, d_res, d_list, d_plist, d_brow, d_zlist, d_ctl, d_beta, d_rows, d_q;
+  DBuf d_act, d_stat, d_list, d_plist, d_brow, d_zlist, d_ctl, d_beta, d_rows, d_q;
   DBuf d_msrc, d_mzoff, d_mom, d_pmode;
   DBuf d_ag, d_agb, d_agt, d_drop;  // restart and dropped-cycle lists of cycle finishing
   std::map<int64_t, int> brow_of;  // virtual p -> row of bB
@@ -660,8 +715,9 @@ struct Lane {
   DBuf d_lorb, bL;
   std::vector<HostSlot> hs;
   std::vector<int> free_slots, active, pending;
-  std::vector<int> hflags;
-  std::vector<double> hres, hbeta;
+  std::vector<int> act_dev;  // the active list as last uploaded to d_act
+  HBuf hstat;                // page-locked copy of d_stat
+  std::vector<double> hbeta;
   int64_t lrow(int64_t orb) const { return lrow_of.empty() ? orb : lrow_of.at(orb); }
 };
 
@@ -684,6 +740,37 @@ struct BatchRun {
   gfcc_precision prec = GFCC_FP64;
   double tol = 0.0, rtol_lp = 0.0;
   bool ok_all = true;
+  int64_t n_sync = 0;        // host synchronisations of the run
+  int64_t n_loop_sync = 0;   // of which after inner iterations
+  int64_t n_iter = 0;        // inner iterations launched (one per window step)
+  int64_t n_plane_iter = 0;  // right-hand-side iterations launched (frozen slots included)
+
+  void sync(hipStream_t st) {
+    ++n_sync;
+    GFCC_HIP(hipStreamSynchronize(st));
+    stage_off = 0;  // every staged copy has completed
+  }
+
+  // Host-to-device copies of small lists go through page-locked staging memory,
+  // so they are asynchronous and need no synchronisation before the host list
+  // goes away; the staging area is reused after the next synchronisation.
+  HBuf stage;
+  size_t stage_off = 0;
+  template <typename T>
+  void upload(DBuf& b, const std::vector<T>& v, hipStream_t st) {
+    b.ensure(std::max<size_t>(v.size(), 1) * sizeof(T), st);
+    if (v.empty()) return;
+    const size_t n = v.size() * sizeof(T);
+    size_t off = (stage_off + 15) & ~size_t(15);
+    if (off + n > stage.bytes) {
+      if (stage_off > 0) sync(st);
+      stage.ensure(std::max(n, size_t(1) << 20));
+      off = 0;
+    }
+    std::memcpy(stage.as<char>() + off, v.data(), n);
+    GFCC_HIP(hipMemcpyAsync(b.p, stage.as<char>() + off, n, hipMemcpyHostToDevice, st));
+    stage_off = off + n;
+  }
 
   // Resume file: a header (magic, version, record size, fingerprint of the
   // request), then one record per finished right-hand side, appended as it finishes.
@@ -733,7 +820,7 @@ struct BatchRun {
       GFCC_HIP(hipMemcpyAsync(dg.data(), c->diag.p, size_t(n) * 8, hipMemcpyDeviceToHost, s));
       GFCC_HIP(hipMemcpyAsync(dg.data() + n, c->diag.as<double>() + (c->Dp - n), size_t(n) * 8,
                               hipMemcpyDeviceToHost, s));
-      GFCC_HIP(hipStreamSynchronize(s));
+      sync(s);
       for (double x : dg) mixd(x);
     }
     if (sysv)
@@ -824,7 +911,7 @@ struct BatchRun {
         GFCC_HIP(hipMemsetAsync(Xout + rows[k] * D * 2, 0, size_t(D) * 16, s));
       }
     }
-    GFCC_HIP(hipStreamSynchronize(s));  // gbuf goes out of scope
+    sync(s);  // gbuf goes out of scope
     ck = std::fopen(opts->checkpoint, fresh ? "wb" : "ab");
     GFCC_CHECK(ck, GFCC_E_ARG, std::string("cannot open resume file ") + opts->checkpoint);
     if (fresh) {
@@ -840,7 +927,7 @@ struct BatchRun {
     for (size_t k = 0; k < rows.size(); ++k)
       GFCC_HIP(hipMemcpyAsync(g.data() + k * 2 * nq, G + rows[k] * nq * 2, size_t(nq) * 16,
                               hipMemcpyDeviceToHost, s));
-    GFCC_HIP(hipStreamSynchronize(s));
+    sync(s);
     for (size_t k = 0; k < rows.size(); ++k) {
       const int64_t r = rows[k];
       CkptRec rec{r, p[r], nq, qhash, omega[r], eta, info[r]};
@@ -876,6 +963,7 @@ struct BatchRun {
     L.bctol.ensure(size_t(B) * 8, s);
     L.bres.ensure(size_t(B) * 8, s);
     L.bflag.ensure(size_t(B) * sizeof(int), s);
+    L.bfresh.ensure(size_t(B) * sizeof(int), s);
     L.bpart.ensure(size_t(B) * nch * PS * sizeof(cplx), s);
     L.bGm.ensure(size_t(B) * m * (m + 1) * sizeof(cplx), s);
     L.bh.ensure(size_t(B) * (MAXM + 1) * sizeof(cplx), s);
@@ -897,6 +985,7 @@ struct BatchRun {
     d.ctol = L.bctol.as<double>();
     d.res = L.bres.as<double>();
     d.flag = L.bflag.as<int>();
+    d.fresh = L.bfresh.as<int>();
     d.part = L.bpart.as<cplx>();
     d.Gm = L.bGm.as<cplx>();
     d.h = L.bh.as<cplx>();
@@ -905,8 +994,8 @@ struct BatchRun {
     d.m = m;
     d.Dp = Dp;
     d.nch = nch;
-    L.d_flags.ensure(size_t(B) * sizeof(int), s);
-    L.d_res.ensure(size_t(B) * 8, s);
+    L.d_stat.ensure(size_t(B) * 16, s);  // flags, Krylov steps, residual estimates
+    L.hstat.ensure(size_t(B) * 16);
     L.d_beta.ensure(size_t(B) * 8, s);
     // lists of at most B entries, sized once so that cycle finishing allocates nothing
     for (DBuf* b : {&L.d_act, &L.d_list, &L.d_plist, &L.d_brow, &L.d_ag, &L.d_agt, &L.d_drop})
@@ -932,7 +1021,7 @@ struct BatchRun {
                          L.bBn.as<double>());
       GFCC_HIP(hipGetLastError());
       GFCC_HIP(hipMemcpyAsync(L.bnorm_h.data(), L.bBn.p, size_t(nb) * 8, hipMemcpyDeviceToHost, s));
-      GFCC_HIP(hipStreamSynchronize(s));
+      sync(s);
     }
     // Left vectors: the occupied rows built with the intermediates, or, when a
     // virtual orbital is asked for, one materialised row per distinct orbital.
@@ -967,10 +1056,8 @@ struct BatchRun {
     }
     L.hs.assign(size_t(B), HostSlot{});
     for (int i = B - 1; i >= 0; --i) L.free_slots.push_back(i);
-    L.hflags.assign(size_t(B), 0);
-    L.hres.assign(size_t(B), 0.0);
     L.hbeta.assign(size_t(B), 0.0);
-    GFCC_HIP(hipStreamSynchronize(s));
+    sync(s);
   }
 
   void refill(Lane& L) {
@@ -1004,11 +1091,13 @@ struct BatchRun {
       h.bn = bn;
       h.beta = bn;
       h.brow = br;
+      h.res = bn;
+      h.ctol = bn * std::max(0.5 * tol, rtol_lp);
       sl.push_back(sidx);
       pl.push_back(int(p[r]));
       bl.push_back(br);
       zl.push_back(cplx{omega[r], -eta});
-      tl.push_back(bn * std::max(0.5 * tol, rtol_lp));
+      tl.push_back(h.ctol);
       L.active.push_back(sidx);
       ++L.next;
     }
@@ -1023,7 +1112,6 @@ struct BatchRun {
                        L.d_plist.as<int>(), L.d_brow.as<int>(), L.bB.as<double>(), L.bBn.as<double>(),
                        L.d_zlist.as<cplx>(), L.d_ctl.as<double>(), int(sl.size()));
     GFCC_HIP(hipGetLastError());
-    GFCC_HIP(hipStreamSynchronize(s));  // host vectors above go out of scope
   }
 
   // preconditioner step of one inner iteration: u = M^-1 V[k] into ws_in
@@ -1069,7 +1157,6 @@ struct BatchRun {
     prof_end(c, "mlp", st, 2.0 * double(na) * double(c->D) *
                                (double(MLP_F) * c->mlp->width + double(c->mlp->width) * c->mlp->width +
                                 2.0 * c->mlp->width), 0.0);
-    GFCC_HIP(hipStreamSynchronize(st));  // host vectors above go out of scope
   }
 
   // CGS2 Arnoldi step and Givens update after the sigma
@@ -1085,8 +1172,7 @@ struct BatchRun {
     hipLaunchKernelGGL(arnoldi_kernel, dim3(L.nch, na), dim3(VT), 0, st, d, act, c->ws_in.as<double>(),
                        c->ws_out.as<double>(), 2);
     GFCC_HIP(hipGetLastError());
-    hipLaunchKernelGGL(givens_kernel, dim3(na), dim3(64), 0, st, d, act, L.d_flags.as<int>(), L.d_res.as<double>(),
-                       1);
+    hipLaunchKernelGGL(givens_kernel, dim3(na), dim3(64), 0, st, d, act, L.d_stat.as<int>(), L.B, 1);
     hipLaunchKernelGGL(scale_kernel, dim3(L.nch, na), dim3(VT), 0, st, d, act);
     GFCC_HIP(hipGetLastError());
     if (c->prof_on) {
@@ -1159,7 +1245,7 @@ struct BatchRun {
     hipLaunchKernelGGL(rnorm_kernel, dim3(nf), dim3(64), 0, s, d, nf, L.d_beta.as<double>());
     GFCC_HIP(hipGetLastError());
     GFCC_HIP(hipMemcpyAsync(L.hbeta.data(), L.d_beta.p, nf * 8, hipMemcpyDeviceToHost, s));
-    GFCC_HIP(hipStreamSynchronize(s));
+    sync(s);
 
     std::vector<int> done, again, done_p;
     std::vector<int64_t> done_rows;
@@ -1213,9 +1299,11 @@ struct BatchRun {
         h.beta = beta;
         h.k = 0;
         h.restarts += 1;
+        h.res = beta;
+        h.ctol = std::max(0.5 * tol * h.bn, rtol_lp * beta);
         again.push_back(sl);
         again_beta.push_back(beta);
-        again_tol.push_back(std::max(0.5 * tol * h.bn, rtol_lp * beta));
+        again_tol.push_back(h.ctol);
         continue;
       }
       if (inf.status != 0 && inf.status != 4) ok_all = false;
@@ -1231,7 +1319,6 @@ struct BatchRun {
       hipLaunchKernelGGL(restart_kernel, dim3(L.nch, nr), dim3(VT), 0, s, d, L.d_ag.as<int>(), L.d_agb.as<double>(),
                          L.d_agt.as<double>(), nr);
       GFCC_HIP(hipGetLastError());
-      GFCC_HIP(hipStreamSynchronize(s));
     }
     if (!done.empty()) {
       const int nd = int(done.size());
@@ -1245,8 +1332,7 @@ struct BatchRun {
         hipLaunchKernelGGL(xout_kernel, dim3(std::min<int64_t>((c->D + 255) / 256, 1024), nd), dim3(256), 0, s, d,
                            L.d_list.as<int>(), L.d_rows.as<int64_t>(), Xout, c->D, c->n1, c->p1);
       GFCC_HIP(hipGetLastError());
-      GFCC_HIP(hipStreamSynchronize(s));
-      ckpt_write(done_rows);
+      ckpt_write(done_rows);  // copies the rows back and synchronises only with a resume file
       for (int sl : done) {
         L.hs[size_t(sl)].rhs = -1;
         L.free_slots.push_back(sl);
@@ -1302,10 +1388,14 @@ struct BatchRun {
       if (!live.empty()) {
         std::string key;
         for (Lane* L : live) {
-          upload(L->d_act, L->active, s);
+          if (L->act_dev != L->active) {  // the list on the device changes only with the active set
+            upload(L->d_act, L->active, s);
+            L->act_dev = L->active;
+          }
           key += std::to_string(L->active.size()) + "@" + std::to_string(reinterpret_cast<uintptr_t>(L->d_act.p)) +
                  ";";
         }
+        const int nb = burst(live);
         // One inner iteration of every live lane: precondition, sigma (the ring
         // GEMMs of all lanes in grouped launches), CGS2, Givens.  With use_graph
         // (and a plain preconditioner) it is captured once per window shape --
@@ -1317,6 +1407,9 @@ struct BatchRun {
           seen.clear();
           graph_gen = alloc_generation();
         }
+        for (int b = 0; b < nb; ++b) {
+        ++n_iter;
+        for (Lane* L : live) n_plane_iter += int64_t(L->active.size());
         if (!graphable) {
           iteration(live, s);
         } else {
@@ -1356,21 +1449,28 @@ struct BatchRun {
             iteration(live, s);
           }
         }
-        for (Lane* L : live) {
-          const size_t na = L->active.size();
-          GFCC_HIP(hipMemcpyAsync(L->hflags.data(), L->d_flags.p, na * sizeof(int), hipMemcpyDeviceToHost, s));
-          GFCC_HIP(hipMemcpyAsync(L->hres.data(), L->d_res.p, na * 8, hipMemcpyDeviceToHost, s));
         }
-        GFCC_HIP(hipStreamSynchronize(s));
+        // one copy of every lane's flags, Krylov steps and residual estimates, one synchronisation
+        for (Lane* L : live)
+          GFCC_HIP(hipMemcpyAsync(L->hstat.p, L->d_stat.p, size_t(L->B) * 16, hipMemcpyDeviceToHost, s));
+        sync(s);
+        ++n_loop_sync;
         for (Lane* L : live) {
+          const int* hf = L->hstat.as<int>();
+          const int* hk = hf + L->B;
+          const double* hr = reinterpret_cast<const double*>(hf + 2 * L->B);
           std::vector<int> still;
           for (size_t i = 0; i < L->active.size(); ++i) {
             const int sl = L->active[i];
             HostSlot& h = L->hs[size_t(sl)];
-            h.iters += 1;
-            h.k += 1;
-            if (L->hflags[i] == 3) h.nonfinite = true;
-            if (L->hflags[i] != 0 || h.iters >= opts->max_iter)
+            const int dk = hk[i] - h.k;  // iterations the slot ran in this burst
+            if (dk > 0 && hr[i] > 0.0 && hr[i] < h.res && h.res > 0.0)
+              h.lrate = std::log(hr[i] / h.res) / double(dk);
+            h.res = hr[i];
+            h.iters += dk;
+            h.k = hk[i];
+            if (hf[i] == 3) h.nonfinite = true;
+            if (hf[i] != 0 || h.iters >= opts->max_iter)
               L->pending.push_back(sl);
             else
               still.push_back(sl);
@@ -1387,7 +1487,63 @@ struct BatchRun {
         finish(L);
       }
     }
-    GFCC_HIP(hipStreamSynchronize(s));
+    sync(s);
+    gfcc_ctx* c0 = lanes[0].c;
+    c0->prof["host_sync"].count += n_sync;
+    c0->prof["loop_sync"].count += n_loop_sync;
+    c0->prof["inner_iter"].count += n_iter;
+    c0->prof["slot_iter"].count += n_plane_iter;
+  }
+
+  // Inner iterations to run before the next host synchronisation.  A slot whose
+  // cycle stops inside the run is frozen on the device (its kernels return at
+  // once; its planes of the batched sigma are computed and ignored), so the
+  // length trades idle sigma work against synchronisations; it never passes a
+  // slot's iteration budget.  Automatic lengths use each slot's predicted
+  // iterations to its cycle target (from the observed decrease of its residual
+  // estimate, capped by the restart length).  Where an iteration is short (the
+  // estimated sigma time of the window under 2 ms, so that a synchronisation
+  // is a visible share of it) the run goes on until half of a lane's slots are
+  // predicted to stop -- the point where cycle finishing starts anyway; where
+  // it is long, it ends at 85% of the first slot's prediction.
+  int burst(const std::vector<Lane*>& live) const {
+    const int se = opts->sync_every;
+    if (se == 1 || use_mlp) return 1;
+    for (Lane* L : live)
+      if (L->c->prof_on) return 1;  // per-iteration traffic accounting needs every step's k
+    int hard = 1 << 20;  // iteration budgets
+    for (Lane* L : live)
+      for (int sl : L->active) hard = std::min(hard, opts->max_iter - L->hs[size_t(sl)].iters);
+    if (se > 1) return std::max(1, std::min(se, hard));
+    const double rate = prec == GFCC_FP64 ? 50e12 : (prec == GFCC_FP32_IR ? 100e12 : 400e12);
+    double t_est = 0.0;
+    for (Lane* L : live) {
+      const gfcc_ctx* c = L->c;
+      const double per_plane = double(c->Dp) * (6.0 * double(c->ov) + (c->sector == 1 ? 2.0 * c->v * c->v : 0.0));
+      t_est += 2.0 * double(L->active.size()) * per_plane / rate;
+    }
+    const bool short_iter = t_est < 2e-3;
+    int S = 16;
+    for (Lane* L : live) {
+      std::vector<int> n;
+      for (int sl : L->active) {
+        const HostSlot& h = L->hs[size_t(sl)];
+        int pred = short_iter ? 6 : 2;  // no rate observed yet
+        if (h.lrate < 0.0)
+          pred = h.res > h.ctol ? int(std::ceil(std::log(h.ctol / h.res) / h.lrate)) : 1;
+        n.push_back(std::max(1, std::min(pred, m - h.k)));
+      }
+      std::sort(n.begin(), n.end());
+      if (short_iter) {
+        // slots still to stop before half of the lane's live slots are pending
+        const size_t tot = L->active.size() + L->pending.size();
+        const size_t need = (tot + 1) / 2 > L->pending.size() ? (tot + 1) / 2 - L->pending.size() : 1;
+        S = std::min(S, n[std::min(need, n.size()) - 1]);
+      } else {
+        S = std::min(S, std::max(1, int(0.85 * n[0])));
+      }
+    }
+    return std::max(1, std::min(S, hard));
   }
 };
 

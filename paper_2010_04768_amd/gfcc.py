@@ -50,7 +50,8 @@ class SolveOpts(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_size_t), ("tol", ctypes.c_double), ("restart", ctypes.c_int32),
                 ("max_iter", ctypes.c_int32), ("batch", ctypes.c_int32), ("precond", ctypes.c_int),
                 ("precision", ctypes.c_int), ("use_graph", ctypes.c_int32), ("tune_cache", ctypes.c_char_p),
-                ("ir_inner_rtol", ctypes.c_double), ("checkpoint", ctypes.c_char_p)]
+                ("ir_inner_rtol", ctypes.c_double), ("checkpoint", ctypes.c_char_p),
+                ("sync_every", ctypes.c_int32)]
 
 
 class RhsInfo(ctypes.Structure):
@@ -208,10 +209,11 @@ def spectral(G, eta):
 
 def solve_multi(ctxs, sys, p, omega, eta, q=None, tol=1e-8, restart=30, max_iter=2000, batch=0,
                 precond="jacobi", precision="fp64", use_graph=False, ir_inner_rtol=0.0, tune_cache=None,
-                checkpoint=None):
+                checkpoint=None, sync_every=0):
     """Right-hand sides of several systems (contexts) in one persistent solve: right-hand side r
     belongs to ctxs[sys[r]].  Returns (G [nrhs, nq] complex128 device tensor, info list).
-    `checkpoint`: resume file (finished rows are appended; rows it already holds are restored)."""
+    `checkpoint`: resume file (finished rows are appended; rows it already holds are restored).
+    `sync_every`: as in Context.solve."""
     import torch
     s_h = np.ascontiguousarray(np.asarray(sys, dtype=np.int32))
     p_h = np.ascontiguousarray(np.asarray(p, dtype=np.int64))
@@ -228,7 +230,7 @@ def solve_multi(ctxs, sys, p, omega, eta, q=None, tol=1e-8, restart=30, max_iter
     handles = (ctypes.c_void_p * len(ctxs))(*[c._h.value for c in ctxs])
     opts = SolveOpts(ctypes.sizeof(SolveOpts), tol, restart, max_iter, batch, PRECONDS[precond],
                      PRECISIONS[precision], int(use_graph), tune_cache.encode() if tune_cache else None,
-                     ir_inner_rtol, checkpoint.encode() if checkpoint else None)
+                     ir_inner_rtol, checkpoint.encode() if checkpoint else None, sync_every)
     st = load().gfcc_solve_multi(len(ctxs), handles, n, s_h.ctypes.data_as(ctypes.c_void_p),
                                  p_h.ctypes.data_as(ctypes.c_void_p), w_h.ctypes.data_as(ctypes.c_void_p), eta, nq,
                                  q_h.ctypes.data_as(ctypes.c_void_p) if q_h is not None else None,
@@ -354,9 +356,12 @@ class Context:
     # ---------------------------------------------------------------- solve
     def solve(self, p: Sequence[int], omega: Sequence[float], eta: float, q: Optional[Sequence[int]] = None,
               tol=1e-8, restart=30, max_iter=2000, batch=0, precond="jacobi", precision="fp64",
-              use_graph=False, want_x=False, ir_inner_rtol=0.0, tune_cache=None, checkpoint=None, x_out=None):
+              use_graph=False, want_x=False, ir_inner_rtol=0.0, tune_cache=None, checkpoint=None, x_out=None,
+              sync_every=0):
         """Returns (G [nrhs, nq] complex128 device tensor, info list of dicts, X or None).
-        `x_out`: caller buffer [nrhs, D] complex128 for X (with want_x; default: a new zero tensor)."""
+        `x_out`: caller buffer [nrhs, D] complex128 for X (with want_x; default: a new zero tensor).
+        `sync_every`: inner iterations between host synchronisations (0: sized from the predicted
+        end of the next cycle; 1: after every iteration)."""
         import torch
         p_h = np.ascontiguousarray(np.asarray(p, dtype=np.int64))
         w_h = np.ascontiguousarray(np.asarray(omega, dtype=np.float64))
@@ -376,7 +381,7 @@ class Context:
         opts = SolveOpts(ctypes.sizeof(SolveOpts), tol, restart, max_iter, batch, PRECONDS[precond],
                          PRECISIONS[precision], int(use_graph),
                          tune_cache.encode() if tune_cache else None, ir_inner_rtol,
-                         checkpoint.encode() if checkpoint else None)
+                         checkpoint.encode() if checkpoint else None, sync_every)
         st = self._lib.gfcc_solve_batch(
             self._h, n, p_h.ctypes.data_as(ctypes.c_void_p), w_h.ctypes.data_as(ctypes.c_void_p), eta, nq,
             q_h.ctypes.data_as(ctypes.c_void_p) if q_h is not None else None, ctypes.byref(opts), _ptr(G),

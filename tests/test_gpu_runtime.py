@@ -46,6 +46,60 @@ def test_graph_replay_matches_eager(ctx, prec):
     assert 1 <= cap <= 8 and rep >= 4 * cap  # measured: 1 capture, 35 (FP64) and 40 (BF16) replays
 
 
+def _counters(c):
+    return {k: c.prof_get(k)["count"] for k in ("host_sync", "loop_sync", "inner_iter", "slot_iter")}
+
+
+@pytest.mark.parametrize("prec,graph", [("fp64", False), ("bf16", True), ("fp16", False)])
+def test_runs_between_synchronisations(ctx, prec, graph):
+    """Runs of several inner iterations between host synchronisations: a slot whose cycle stops
+    inside a run is frozen on the device, so G, the iteration counts and the true residuals are
+    the same bits as with a synchronisation after every iteration; the automatic run length cuts
+    the inner-loop synchronisations at least threefold (measured 3.5-4x) and all host
+    synchronisations of the solve at least twofold.  (FP16: the per-call vector scale is taken
+    over every plane of the batch, frozen ones included, so a scale can differ by a power of two and
+    move which tiny entries are subnormal: G agrees to the solve tolerance instead of bitwise.)"""
+    s, c = ctx
+    rng = np.random.default_rng(11)
+    p = rng.integers(0, s.n_occ, size=40)
+    w = rng.uniform(-1.2, -0.3, size=40)
+    runs = {}
+    for se in (1, 0, 5):
+        c.prof_enable(False)  # clears the counters
+        G, info, _ = c.solve(p, w, 0.01, tol=1e-10, restart=30, batch=16, precision=prec, use_graph=graph,
+                             sync_every=se)
+        runs[se] = (G, info, _counters(c))
+    G1, i1, k1 = runs[1]
+    assert all(i["status"] == 0 for i in i1)
+    assert k1["loop_sync"] == k1["inner_iter"]
+    for se in (0, 5):
+        G, info, k = runs[se]
+        print(f"[sync] {prec} sync_every={se}: {k} (every iteration: {k1})")
+        if prec == "fp16":
+            assert all(i["status"] == 0 and i["true_rel_resid"] <= 1e-10 for i in info)
+            assert ((G - G1).abs() / G1.abs()).max().item() < 1e-8
+            continue
+        assert torch.equal(G, G1), se
+        assert info == i1, se
+        assert k["slot_iter"] >= k1["slot_iter"]
+    k0 = runs[0][2]
+    assert 3 * k0["loop_sync"] <= k1["loop_sync"], (k0, k1)
+    assert 2 * k0["host_sync"] <= k1["host_sync"], (k0, k1)
+    # the price: sigma planes of frozen slots (right-hand-side iterations launched)
+    assert k0["slot_iter"] <= 1.5 * k1["slot_iter"], (k0, k1)
+
+
+def test_runs_respect_the_iteration_budget(ctx):
+    """max_iter is an exact budget also inside runs of iterations (status 1, iters == max_iter)."""
+    s, c = ctx
+    p = [0, 3, 7]
+    w = [-0.5, -0.8, -1.1]
+    for se in (0, 6):
+        G, info, _ = c.solve(p, w, 0.01, tol=1e-15, restart=30, max_iter=13, batch=3, sync_every=se)
+        assert [i["status"] for i in info] == [1, 1, 1]
+        assert [i["iters"] for i in info] == [13, 13, 13]
+
+
 def test_autotuner_cache_and_results(ctx, tmp_path):
     s, c = ctx
     cache = str(tmp_path / "tune.json")
