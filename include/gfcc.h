@@ -542,7 +542,10 @@ gfcc_status gfcc_mor_greens(gfcc_ctx* ctx, int64_t np, const int64_t* p, int64_t
  * "ring_gemm_bf16", "ring_gemm_fp16" -- the two ring GEMMs of sigma --, the same
  * split by GEMM tile as "ring_gemm_<prec>:<tile>" (tiles: 128x128 64x64 128x64
  * 64x128 db128x128 db256x128 db128x256 db256x256 db32_256x256 db32_256x128
- * db32_128x128 db32_256x256w16 db256x256w16), "sigma", "arnoldi" (bytes:
+ * db32_128x128 db32_256x256w16 db256x256w16 dma3_256x256 dma4_256x256 dma3_256x256w8
+ * dma3_256x256w8t dma2k64_256x256; the environment variable GFCC_TILE_<FP64|FP32|BF16|FP16>
+ * set to one of these names forces that tile for every product of that precision that would
+ * take a tuned or default large tile), "sigma", "arnoldi" (bytes:
  * algorithmic HBM bytes of the Arnoldi step), "mlp", "ea_sigma", "ea_ring",
  * "ea_ladder", "uhf_sigma") gfcc_prof_get returns the number of launches, total
  * milliseconds and algorithmic flops and bytes summed over them (host outputs).

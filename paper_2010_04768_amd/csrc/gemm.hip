@@ -475,6 +475,246 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_db_kernel(GemmArgs g) {
   gemm_db_tile<T, MF, BM, BN, WGM, WGN, KM, VEC>(g, blockIdx.x);
 }
 
+// ---------------------------------------------------------------- direct-to-LDS pipeline
+// 16-bit operands, 256 x 256 tile, 16 waves of 64 x 64 (32x32x16 MFMA blocks), K in steps of
+// 32 through NS LDS stages.  Each step is one global_load_lds_dwordx4 per wave and operand:
+// lane l of wave w moves one 16-byte chunk straight into LDS at byte (64 w + l) * 16 of the
+// stage, i.e. row r = (64 w + l) / 4, slot l % 4 of a 64-byte row; the chunk it fetches is
+// k-chunk slot ^ ((r / 4) % 4) of that row, so the fragment reads (16 lanes = 16 rows of one
+// k-chunk) meet 16 different bank groups.  Loads run NS - 1 steps ahead with no register
+// staging; a wave waits only for its own loads of the step it is about to read
+// (s_waitcnt vmcnt) and a barrier then publishes every wave's part of the stage.  The loads
+// are issued from inline assembly (they write no register), so the compiler adds no waits of
+// its own for them: every wait on them is the explicit one below.  Operand rows are clamped
+// into range (their products land outside C and are dropped); a K remainder below 32 is
+// staged through registers with zero fill.  K is summed in 16-element MFMA steps in
+// ascending order, as in the double-buffered kernels, so both give the same bits.
+typedef __attribute__((address_space(3))) void* lds_void_ptr;
+
+// M0 holds the wave's LDS destination (the same for every lane); lane l lands at M0 + 16 l.
+// M0 is written here only; no compiler-generated code in these kernels reads it.
+__device__ __forceinline__ void lds_dma16(const void* src, void* lds_dst) {
+  const uint32_t m0v = __builtin_amdgcn_readfirstlane(uint32_t(uintptr_t(lds_void_ptr(lds_dst))));
+  asm volatile("s_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, off" ::"v"(src), "s"(m0v) : "memory", "m0");
+}
+// s_waitcnt with vmcnt(n) and lgkmcnt(0) (expcnt not waited): gfx9 encoding
+template <int N>
+__device__ __forceinline__ void wait_vm_lgkm0() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4));
+}
+__device__ __forceinline__ void wg_barrier() {
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
+
+// Slot permutation of the 16-byte k-chunks of row r (CPR chunks per row), chosen by measurement
+// (no LDS bank conflicts counted for the fragment reads): rows r and r + 16 / CPR .. of one
+// k-chunk spread over the 16-byte bank groups of a 256-byte bank row.
+template <int CPR>
+__device__ __forceinline__ int dma_swz(int r) {
+  return (r / (16 / CPR)) % CPR;
+}
+
+template <typename T, typename MF, int NS, int WGM, int WGN, int BK>
+__device__ __forceinline__ void gemm_dma_tile(const GemmArgs& g, int64_t braw) {
+  constexpr int BM = 256, BN = 256, NT = 64 * WGM * WGN;
+  constexpr int WM = BM / WGM, WN = BN / WGN, FM = WM / MF::BLK, FN = WN / MF::BLK;
+  constexpr int STAGE = 256 * BK;    // elements per operand and stage
+  constexpr int CPR = BK / 8;        // 16-byte chunks per row
+  constexpr int CPT = 256 * CPR / NT;  // chunks per thread, operand and stage
+  static_assert((BK == 32 || BK == 64) && CPT >= 1 && CPT * NT == 256 * CPR, "threads must divide the stage");
+  static_assert(NS * 2 * STAGE * 2 <= 160 * 1024, "LDS");
+  static_assert(sizeof(T) == 2 && MF::KS == 16 && MF::BLK == 32, "16-bit 32x32x16 blocks");
+  static_assert(NS >= 2 && NS <= 4, "stages");
+  __shared__ __attribute__((aligned(1024))) T sA0[STAGE];
+  __shared__ __attribute__((aligned(1024))) T sB0[STAGE];
+  __shared__ __attribute__((aligned(1024))) T sA1[STAGE];
+  __shared__ __attribute__((aligned(1024))) T sB1[STAGE];
+  __shared__ __attribute__((aligned(1024))) T sA2[NS > 2 ? STAGE : 1];
+  __shared__ __attribute__((aligned(1024))) T sB2[NS > 2 ? STAGE : 1];
+  __shared__ __attribute__((aligned(1024))) T sA3[NS > 3 ? STAGE : 1];
+  __shared__ __attribute__((aligned(1024))) T sB3[NS > 3 ? STAGE : 1];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm0 = (wave / WGN) * WM;
+  const int wn0 = (wave % WGN) * WN;
+
+  const int64_t tiles_m = (g.M + BM - 1) / BM;
+  const int64_t tiles_n = (g.N + BN - 1) / BN;
+  const int64_t ntiles = tiles_m * tiles_n;
+  int64_t bid = xcd_remap(braw, ntiles);
+  constexpr int64_t GROUP = 4;
+  const int64_t per_group = GROUP * tiles_n;
+  const int64_t grp = bid / per_group;
+  const int64_t first_m = grp * GROUP;
+  const int64_t gsz = (tiles_m - first_m) < GROUP ? (tiles_m - first_m) : GROUP;
+  const int64_t in_grp = bid - grp * per_group;
+  const int64_t tm = first_m + in_grp % gsz;
+  const int64_t tn = in_grp / gsz;
+  const int64_t i0 = tm * BM, j0 = tn * BN;
+
+  const T* A = static_cast<const T*>(g.A);
+  const T* B = static_cast<const T*>(g.B);
+  const int64_t Kz = g.K;
+  // this thread's chunks of every stage: chunk c = p NT + tid sits at row c / CPR, slot c % CPR
+  // and holds k-chunk kc[p] = slot ^ swz(row) of that row
+  const T* asrc[CPT];
+  const T* bsrc[CPT];
+  auto chunk_src = [&](int p, const T*& a, const T*& b) {  // row clamped into range
+    const int c = p * NT + tid;
+    const int r = c / CPR;
+    const int kc = (c % CPR) ^ dma_swz<CPR>(r);
+    const int64_t ia = (i0 + r < g.M) ? i0 + r : g.M - 1;
+    const int64_t jb = (j0 + r < g.N) ? j0 + r : g.N - 1;
+    a = A + rmap(g.am, ia) + kc * 8;
+    b = B + rmap(g.bm, jb) + kc * 8;
+  };
+#pragma unroll
+  for (int p = 0; p < CPT; ++p) chunk_src(p, asrc[p], bsrc[p]);
+  const int wofs = wave * 512;  // this wave's 1 KB of a stage part, in elements
+
+  auto stage_a = [&](auto S_) -> T* {
+    constexpr int S = decltype(S_)::value;
+    if constexpr (S == 0) return sA0;
+    else if constexpr (S == 1) return sA1;
+    else if constexpr (S == 2) return sA2;
+    else return sA3;
+  };
+  auto stage_b = [&](auto S_) -> T* {
+    constexpr int S = decltype(S_)::value;
+    if constexpr (S == 0) return sB0;
+    else if constexpr (S == 1) return sB1;
+    else if constexpr (S == 2) return sB2;
+    else return sB3;
+  };
+  auto issue = [&](auto S_, int64_t k0) {
+#pragma unroll
+    for (int p = 0; p < CPT; ++p) {
+      lds_dma16(asrc[p] + k0, stage_a(S_) + p * NT * 8 + wofs);
+      lds_dma16(bsrc[p] + k0, stage_b(S_) + p * NT * 8 + wofs);
+    }
+  };
+
+  typename MF::acc_t acc[FM][FN];
+#pragma unroll
+  for (int a = 0; a < FM; ++a)
+#pragma unroll
+    for (int b = 0; b < FN; ++b) acc[a][b] = typename MF::acc_t{};
+
+  // fragment element offset within a stage: row rr, k-chunk c (swizzled slot)
+  auto foff = [](int rr, int c) { return rr * BK + ((c ^ dma_swz<CPR>(rr)) << 3); };
+  const int fr = lane & 31;
+  const int fh = lane >> 5;
+  auto compute = [&](const T* sa, const T* sb) {
+#pragma unroll
+    for (int h = 0; h < BK / MF::KS; ++h) {
+      typename MF::frag_t af[FM], bf[FN];
+#pragma unroll
+      for (int a = 0; a < FM; ++a)
+        af[a] = *reinterpret_cast<const typename MF::frag_t*>(sa + foff(wm0 + a * 32 + fr, 2 * h + fh));
+#pragma unroll
+      for (int b = 0; b < FN; ++b)
+        bf[b] = *reinterpret_cast<const typename MF::frag_t*>(sb + foff(wn0 + b * 32 + fr, 2 * h + fh));
+#pragma unroll
+      for (int a = 0; a < FM; ++a)
+#pragma unroll
+        for (int b = 0; b < FN; ++b) acc[a][b] = MF::mma(af[a], bf[b], acc[a][b]);
+    }
+  };
+
+  const int nk = int(Kz / BK);  // full steps through the pipeline
+  if (nk > 0) {
+    // Every step issues exactly 2 CPT loads, also past the last step (then a harmless re-read
+    // of step 0 into a stage nobody reads again), so the number of loads younger than step
+    // kt's is always 2 CPT (NS - 2) and each wait is one fixed count on every path.
+    auto kstep = [&](int kt) { return kt < nk ? int64_t(kt) * BK : int64_t(0); };
+    issue(std::integral_constant<int, 0>{}, 0);
+    if constexpr (NS > 2) issue(std::integral_constant<int, 1>{}, kstep(1));
+    if constexpr (NS > 3) issue(std::integral_constant<int, 2>{}, kstep(2));
+    // one step: wait for step kt (stage S), publish it, refill the stage read one step ago
+    // with step kt + NS - 1, compute on stage S
+    auto step = [&](auto S_, int kt) {
+      constexpr int S = decltype(S_)::value;
+      wait_vm_lgkm0<2 * CPT * (NS - 2)>();
+      wg_barrier();
+      issue(std::integral_constant<int, (S + NS - 1) % NS>{}, kstep(kt + NS - 1));
+      compute(stage_a(S_), stage_b(S_));
+    };
+    for (int kt = 0; kt < nk; kt += NS) {
+      step(std::integral_constant<int, 0>{}, kt);
+      if (kt + 1 < nk) step(std::integral_constant<int, 1 % NS>{}, kt + 1);
+      if constexpr (NS > 2)
+        if (kt + 2 < nk) step(std::integral_constant<int, 2 % NS>{}, kt + 2);
+      if constexpr (NS > 3)
+        if (kt + 3 < nk) step(std::integral_constant<int, 3 % NS>{}, kt + 3);
+    }
+    wait_vm_lgkm0<0>();  // no load may land in LDS after the workgroup ends
+  }
+  if (Kz > int64_t(nk) * BK) {  // K remainder: registers, zero fill, stage 0
+    u4 va[CPT], vb[CPT];
+#pragma unroll
+    for (int p = 0; p < CPT; ++p) {
+      const T* a = nullptr;
+      const T* b = nullptr;
+      chunk_src(p, a, b);  // element kc * 8 of the row
+      const int c = p * NT + tid;
+      const int kc = (c % CPR) ^ dma_swz<CPR>(c / CPR);
+      const int64_t k = int64_t(nk) * BK + kc * 8;  // absolute K index of the chunk
+      T ta[8], tb[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        ta[e] = (k + e < Kz) ? a[int64_t(nk) * BK + e] : T(0);
+        tb[e] = (k + e < Kz) ? b[int64_t(nk) * BK + e] : T(0);
+      }
+      va[p] = *reinterpret_cast<const u4*>(ta);
+      vb[p] = *reinterpret_cast<const u4*>(tb);
+    }
+    wait_vm_lgkm0<0>();
+    wg_barrier();  // every wave is done with the stages
+#pragma unroll
+    for (int p = 0; p < CPT; ++p) {
+      *reinterpret_cast<u4*>(sA0 + (p * NT + tid) * 8) = va[p];
+      *reinterpret_cast<u4*>(sB0 + (p * NT + tid) * 8) = vb[p];
+    }
+    wait_vm_lgkm0<0>();
+    wg_barrier();
+    compute(sA0, sB0);
+  }
+
+  double* C = g.C;
+  const double al = g.alpha_dev ? g.alpha * (*g.alpha_dev) : g.alpha;
+  const int jl = MF::ocol(lane);
+#pragma unroll
+  for (int b = 0; b < FN; ++b) {
+    const int64_t j = j0 + wn0 + b * MF::BLK + jl;
+    if (j >= g.N) continue;
+    const int64_t cj = rmap(g.cn, j);
+#pragma unroll
+    for (int a = 0; a < FM; ++a) {
+#pragma unroll
+      for (int rr = 0; rr < MF::NACC; ++rr) {
+        const int64_t i = i0 + wm0 + a * MF::BLK + MF::orow(lane, rr);
+        if (i >= g.M) continue;
+        double* p = C + rmap(g.cm, i) + cj;
+        const double v = al * double(acc[a][b][rr]);
+        *p = (g.beta == 0.0) ? v : v + g.beta * (*p);
+      }
+    }
+  }
+}
+
+template <typename T, typename MF, int NS, int WGM, int WGN, int BK>
+__global__ __launch_bounds__(64 * WGM * WGN) void gemm_dma_kernel(GemmArgs g) {
+  gemm_dma_tile<T, MF, NS, WGM, WGN, BK>(g, blockIdx.x);
+}
+
+// the direct-to-LDS tile takes K-contiguous, 16-byte aligned operands without batch or split-K
+static bool dma_ok(const GemmArgs& a, bool vec) { return vec && !a.b_ncontig && a.batch == 1 && a.k_split == 0; }
+
 // Grouped launch: group gi owns blocks [start[gi], start[gi+1]); starts are
 // multiples of 8 so a group's blocks keep the XCD round-robin of a plain launch.
 template <int BM, int BN>
@@ -496,6 +736,14 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_db_grouped_kernel(GemmGro
   gemm_db_tile<T, MF, BM, BN, WGM, WGN, KM, VEC>(gg.g[gi], local);
 }
 
+template <typename T, typename MF, int NS, int WGM, int WGN, int BK>
+__global__ __launch_bounds__(64 * WGM * WGN) void gemm_dma_grouped_kernel(GemmGroup gg) {
+  int64_t local = 0;
+  const int64_t gi = group_of<256, 256>(gg, &local);
+  if (gi < 0) return;
+  gemm_dma_tile<T, MF, NS, WGM, WGN, BK>(gg.g[gi], local);
+}
+
 template <typename T, int BM, int BN, bool VEC>
 __global__ __launch_bounds__(256) void gemm_grouped_kernel(GemmGroup gg) {
   int64_t local = 0;
@@ -514,6 +762,21 @@ static void launch_db(const GemmArgs& a, bool vec, hipStream_t s) {
     hipLaunchKernelGGL((gemm_db_kernel<T, MF, BM, BN, WGM, WGN, KM, true>), grid, dim3(64 * WGM * WGN), 0, s, a);
   else
     hipLaunchKernelGGL((gemm_db_kernel<T, MF, BM, BN, WGM, WGN, KM, false>), grid, dim3(64 * WGM * WGN), 0, s, a);
+  GFCC_HIP(hipGetLastError());
+}
+
+template <typename T, int NS, int WGM, int WGN, int BK = 32>
+static void launch_dma(const GemmArgs& a, hipStream_t s) {
+  const int64_t tiles = ((a.M + 255) / 256) * ((a.N + 255) / 256);
+  GFCC_CHECK(tiles < (int64_t(1) << 31), GFCC_E_ARG, "GEMM grid too large");
+  hipLaunchKernelGGL((gemm_dma_kernel<T, typename Wide<T>::type, NS, WGM, WGN, BK>), dim3(unsigned(tiles)),
+                     dim3(64 * WGM * WGN), 0, s, a);
+  GFCC_HIP(hipGetLastError());
+}
+template <typename T, int NS, int WGM, int WGN, int BK = 32>
+static void launch_dma_grouped(const GemmGroup& gg, hipStream_t s) {
+  hipLaunchKernelGGL((gemm_dma_grouped_kernel<T, typename Wide<T>::type, NS, WGM, WGN, BK>),
+                     dim3(unsigned(gg.start[gg.ng])), dim3(64 * WGM * WGN), 0, s, gg);
   GFCC_HIP(hipGetLastError());
 }
 
@@ -569,6 +832,22 @@ static void dispatch(const GemmArgs& a, int cfg, bool vec, hipStream_t s) {
       if constexpr (Wide<T>::on) launch_db<T, 256, 256, 4, 4>(a, vec, s);
       else launch_db<T, 256, 256, 4, 2>(a, vec, s);
       break;
+    case TILE_DMA3_256x256:
+    case TILE_DMA4_256x256:
+    case TILE_DMA3_256x256_W8:
+    case TILE_DMA3_256x256_W8T:
+    case TILE_DMA2K64_256x256:
+      if constexpr (Wide<T>::on) {
+        if (!dma_ok(a, vec)) launch_db<T, 256, 256, 4, 4, 1, typename Wide<T>::type>(a, vec, s);
+        else if (cfg == TILE_DMA3_256x256) launch_dma<T, 3, 4, 4>(a, s);
+        else if (cfg == TILE_DMA4_256x256) launch_dma<T, 4, 4, 4>(a, s);
+        else if (cfg == TILE_DMA3_256x256_W8) launch_dma<T, 3, 2, 4>(a, s);
+        else if (cfg == TILE_DMA3_256x256_W8T) launch_dma<T, 3, 4, 2>(a, s);
+        else launch_dma<T, 2, 4, 4, 64>(a, s);
+      } else {
+        launch_db<T, 256, 256, 4, 2>(a, vec, s);
+      }
+      break;
     default: throw Error{GFCC_E_ARG, "bad tile config"};
   }
 }
@@ -605,6 +884,8 @@ static void tile_dims(int cfg, int* bm, int* bn) {
     case TILE_DB_256x128: case TILE_DB32_256x128: *bm = 256; *bn = 128; return;
     case TILE_DB_128x256: *bm = 128; *bn = 256; return;
     case TILE_DB_256x256: case TILE_DB32_256x256: case TILE_DB32_256x256_W16: case TILE_DB_256x256_W16:
+    case TILE_DMA3_256x256: case TILE_DMA4_256x256: case TILE_DMA3_256x256_W8: case TILE_DMA3_256x256_W8T:
+    case TILE_DMA2K64_256x256:
       *bm = 256; *bn = 256; return;
     default: throw Error{GFCC_E_ARG, "bad tile config"};
   }
@@ -640,6 +921,22 @@ static void dispatch_grouped(const GemmGroup& gg, int cfg, bool vec, hipStream_t
     case TILE_DB_256x256_W16:
       if constexpr (Wide<T>::on) launch_db_grouped<T, 256, 256, 4, 4>(gg, vec, s);
       else launch_db_grouped<T, 256, 256, 4, 2>(gg, vec, s);
+      break;
+    case TILE_DMA3_256x256:
+    case TILE_DMA4_256x256:
+    case TILE_DMA3_256x256_W8:
+    case TILE_DMA3_256x256_W8T:
+    case TILE_DMA2K64_256x256:
+      if constexpr (Wide<T>::on) {
+        if (!vec) launch_db_grouped<T, 256, 256, 4, 4, 1, typename Wide<T>::type>(gg, vec, s);
+        else if (cfg == TILE_DMA3_256x256) launch_dma_grouped<T, 3, 4, 4>(gg, s);
+        else if (cfg == TILE_DMA4_256x256) launch_dma_grouped<T, 4, 4, 4>(gg, s);
+        else if (cfg == TILE_DMA3_256x256_W8) launch_dma_grouped<T, 3, 2, 4>(gg, s);
+        else if (cfg == TILE_DMA3_256x256_W8T) launch_dma_grouped<T, 3, 4, 2>(gg, s);
+        else launch_dma_grouped<T, 2, 4, 4, 64>(gg, s);
+      } else {
+        launch_db_grouped<T, 256, 256, 4, 2>(gg, vec, s);
+      }
       break;
     default: throw Error{GFCC_E_ARG, "bad tile config"};
   }
@@ -708,16 +1005,17 @@ void gemm_auto(Prec p, const GemmArgs& a, Scratch& scr, int scr_slot, hipStream_
 
 const char* tile_name(int cfg) {
   static const char* n[] = {"128x128", "64x64", "128x64", "64x128", "db128x128", "db256x128", "db128x256",
-                            "db256x256", "db32_256x256", "db32_256x128", "db32_128x128", "db32_256x256w16", "db256x256w16"};
+                            "db256x256", "db32_256x256", "db32_256x128", "db32_128x128", "db32_256x256w16", "db256x256w16",
+                            "dma3_256x256", "dma4_256x256", "dma3_256x256w8", "dma3_256x256w8t", "dma2k64_256x256"};
   return (cfg >= 0 && cfg < N_TILE_CFG) ? n[cfg] : "?";
 }
 
 // Tiles for large K-contiguous products when no tuned entry exists: the double-buffered
-// families that the autotuner picks for the ring shapes (256x128 in FP64 and FP32, the
-// 16-wave 256x256 tile of 32x32x16 blocks in BF16).
+// 256x128 tile in FP64 and FP32, and in BF16 and FP16 the 16-wave 256x256 tile that loads
+// straight into two LDS stages of K = 64 (the fastest on the ring shapes).
 int gemm_big_cfg(Prec p, int64_t M, int64_t N, int64_t K) {
   if (M >= 2048 && N >= 2048 && K >= 256)
-    return (p == Prec::BF16 || p == Prec::F16) ? TILE_DB32_256x256_W16 : TILE_DB_256x128;
+    return (p == Prec::BF16 || p == Prec::F16) ? TILE_DMA2K64_256x256 : TILE_DB_256x128;
   return gemm_default_cfg(M, N, K);
 }
 

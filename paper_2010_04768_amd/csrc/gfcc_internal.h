@@ -129,7 +129,12 @@ enum TileCfg : int {
   TILE_DB32_256x256 = 8, TILE_DB32_256x128 = 9, TILE_DB32_128x128 = 10,
   // 256x256 with 16 waves of 64x64 (BF16; other types: the 8-wave kernel of the same tile)
   TILE_DB32_256x256_W16 = 11, TILE_DB_256x256_W16 = 12,
-  N_TILE_CFG = 13
+  // 16-bit types: 256x256 tiles with loads straight into LDS stages of K = 32: 3 or 4 stages and
+  // 16 waves of 64x64, 3 stages and 8 waves of 128x64 or 64x128; or 2 stages of K = 64 and 16
+  // waves (others: the 16-wave tile above)
+  TILE_DMA3_256x256 = 13, TILE_DMA4_256x256 = 14, TILE_DMA3_256x256_W8 = 15, TILE_DMA3_256x256_W8T = 16,
+  TILE_DMA2K64_256x256 = 17,
+  N_TILE_CFG = 18
 };
 const char* tile_name(int cfg);
 

@@ -151,7 +151,19 @@ void tune_ring(gfcc_ctx* c, Prec p, int64_t P, hipStream_t s) {
   tune_shape(c, p, P, c->oov, c->o, s);         // 2h1p <- 1h
 }
 
+// GFCC_TILE_<PREC> (FP64, FP32, BF16, FP16) = a tile name forces that tile for every product that
+// would otherwise take a tuned or default large tile of that precision (tests and tuning studies)
+static int forced_cfg(Prec p) {
+  static const char* var[4] = {"GFCC_TILE_FP64", "GFCC_TILE_FP32", "GFCC_TILE_BF16", "GFCC_TILE_FP16"};
+  const char* v = std::getenv(var[int(p)]);
+  if (!v || !*v) return -1;
+  for (int cfg = 0; cfg < N_TILE_CFG; ++cfg)
+    if (std::string(v) == tile_name(cfg)) return cfg;
+  return -1;
+}
+
 int tuned_cfg(gfcc_ctx* c, Prec p, int64_t M, int64_t N, int64_t K) {
+  if (forced_cfg(p) >= 0) return forced_cfg(p);
   const std::string key = tune_key(p, M, N, K);
   auto it = c->tuned.find(key);
   if (it != c->tuned.end()) return it->second;
