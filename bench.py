@@ -46,7 +46,8 @@ TRAFFIC_C60 = {"gemm_src_sha256_16": "d25da48ca63a4d5a",
                                   "launch": "60 planes: P1 M=7200 N=72000 K=144000 and P2 K=72000, average of 6 "
                                             "(profiles/ring_gemm_c60_o120v600_bf16ir.md)"}}
 TILES = ["128x128", "64x64", "128x64", "64x128", "db128x128", "db256x128", "db128x256", "db256x256",
-         "db32_256x256", "db32_256x128", "db32_128x128", "db32_256x256w16", "db256x256w16"]
+         "db32_256x256", "db32_256x128", "db32_128x128", "db32_256x256w16", "db256x256w16", "dma3_256x256",
+         "dma4_256x256", "dma3_256x256w8", "dma3_256x256w8t", "dma2k64_256x256", "dma3_256x128", "dma2_256x128"]
 
 
 def log(*a):

@@ -517,25 +517,27 @@ __device__ __forceinline__ int dma_swz(int r) {
   return (r / (16 / CPR)) % CPR;
 }
 
-template <typename T, typename MF, int NS, int WGM, int WGN, int BK>
+template <typename T, typename MF, int NS, int WGM, int WGN, int BK, int BM = 256, int BN = 256>
 __device__ __forceinline__ void gemm_dma_tile(const GemmArgs& g, int64_t braw) {
-  constexpr int BM = 256, BN = 256, NT = 64 * WGM * WGN;
+  constexpr int NT = 64 * WGM * WGN;
   constexpr int WM = BM / WGM, WN = BN / WGN, FM = WM / MF::BLK, FN = WN / MF::BLK;
-  constexpr int STAGE = 256 * BK;    // elements per operand and stage
-  constexpr int CPR = BK / 8;        // 16-byte chunks per row
-  constexpr int CPT = 256 * CPR / NT;  // chunks per thread, operand and stage
-  static_assert((BK == 32 || BK == 64) && CPT >= 1 && CPT * NT == 256 * CPR, "threads must divide the stage");
-  static_assert(NS * 2 * STAGE * 2 <= 160 * 1024, "LDS");
-  static_assert(sizeof(T) == 2 && MF::KS == 16 && MF::BLK == 32, "16-bit 32x32x16 blocks");
+  constexpr int EPC = 16 / int(sizeof(T));   // elements per 16-byte chunk
+  constexpr int SA = BM * BK, SB = BN * BK;  // elements per operand and stage
+  constexpr int CPR = BK / EPC;              // 16-byte chunks per row
+  constexpr int CPTA = BM * CPR / NT, CPTB = BN * CPR / NT;  // chunks per thread and stage
+  static_assert((CPR == 4 || CPR == 8) && CPTA >= 1 && CPTB >= 1 && CPTA * NT == BM * CPR &&
+                    CPTB * NT == BN * CPR, "threads must divide the stage");
+  static_assert(NS * (SA + SB) * int(sizeof(T)) <= 160 * 1024, "LDS");
+  static_assert(BK % MF::KS == 0 && WM % MF::BLK == 0 && WN % MF::BLK == 0, "MFMA blocks");
   static_assert(NS >= 2 && NS <= 4, "stages");
-  __shared__ __attribute__((aligned(1024))) T sA0[STAGE];
-  __shared__ __attribute__((aligned(1024))) T sB0[STAGE];
-  __shared__ __attribute__((aligned(1024))) T sA1[STAGE];
-  __shared__ __attribute__((aligned(1024))) T sB1[STAGE];
-  __shared__ __attribute__((aligned(1024))) T sA2[NS > 2 ? STAGE : 1];
-  __shared__ __attribute__((aligned(1024))) T sB2[NS > 2 ? STAGE : 1];
-  __shared__ __attribute__((aligned(1024))) T sA3[NS > 3 ? STAGE : 1];
-  __shared__ __attribute__((aligned(1024))) T sB3[NS > 3 ? STAGE : 1];
+  __shared__ __attribute__((aligned(1024))) T sA0[SA];
+  __shared__ __attribute__((aligned(1024))) T sB0[SB];
+  __shared__ __attribute__((aligned(1024))) T sA1[SA];
+  __shared__ __attribute__((aligned(1024))) T sB1[SB];
+  __shared__ __attribute__((aligned(1024))) T sA2[NS > 2 ? SA : 1];
+  __shared__ __attribute__((aligned(1024))) T sB2[NS > 2 ? SB : 1];
+  __shared__ __attribute__((aligned(1024))) T sA3[NS > 3 ? SA : 1];
+  __shared__ __attribute__((aligned(1024))) T sB3[NS > 3 ? SB : 1];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -562,20 +564,28 @@ __device__ __forceinline__ void gemm_dma_tile(const GemmArgs& g, int64_t braw) {
   const int64_t Kz = g.K;
   // this thread's chunks of every stage: chunk c = p NT + tid sits at row c / CPR, slot c % CPR
   // and holds k-chunk kc[p] = slot ^ swz(row) of that row
-  const T* asrc[CPT];
-  const T* bsrc[CPT];
-  auto chunk_src = [&](int p, const T*& a, const T*& b) {  // row clamped into range
+  const T* asrc[CPTA];
+  const T* bsrc[CPTB];
+  // chunk p of this thread: element kc * EPC of its row (row clamped into range)
+  auto chunk_kc = [&](int p) {
     const int c = p * NT + tid;
-    const int r = c / CPR;
-    const int kc = (c % CPR) ^ dma_swz<CPR>(r);
+    return (c % CPR) ^ dma_swz<CPR>(c / CPR);
+  };
+  auto src_a = [&](int p) {
+    const int r = (p * NT + tid) / CPR;
     const int64_t ia = (i0 + r < g.M) ? i0 + r : g.M - 1;
+    return A + rmap(g.am, ia) + chunk_kc(p) * EPC;
+  };
+  auto src_b = [&](int p) {
+    const int r = (p * NT + tid) / CPR;
     const int64_t jb = (j0 + r < g.N) ? j0 + r : g.N - 1;
-    a = A + rmap(g.am, ia) + kc * 8;
-    b = B + rmap(g.bm, jb) + kc * 8;
+    return B + rmap(g.bm, jb) + chunk_kc(p) * EPC;
   };
 #pragma unroll
-  for (int p = 0; p < CPT; ++p) chunk_src(p, asrc[p], bsrc[p]);
-  const int wofs = wave * 512;  // this wave's 1 KB of a stage part, in elements
+  for (int p = 0; p < CPTA; ++p) asrc[p] = src_a(p);
+#pragma unroll
+  for (int p = 0; p < CPTB; ++p) bsrc[p] = src_b(p);
+  const int wofs = wave * 64 * EPC;  // this wave's 1 KB of a stage part, in elements
 
   auto stage_a = [&](auto S_) -> T* {
     constexpr int S = decltype(S_)::value;
@@ -593,10 +603,9 @@ __device__ __forceinline__ void gemm_dma_tile(const GemmArgs& g, int64_t braw) {
   };
   auto issue = [&](auto S_, int64_t k0) {
 #pragma unroll
-    for (int p = 0; p < CPT; ++p) {
-      lds_dma16(asrc[p] + k0, stage_a(S_) + p * NT * 8 + wofs);
-      lds_dma16(bsrc[p] + k0, stage_b(S_) + p * NT * 8 + wofs);
-    }
+    for (int p = 0; p < CPTA; ++p) lds_dma16(asrc[p] + k0, stage_a(S_) + p * NT * EPC + wofs);
+#pragma unroll
+    for (int p = 0; p < CPTB; ++p) lds_dma16(bsrc[p] + k0, stage_b(S_) + p * NT * EPC + wofs);
   };
 
   typename MF::acc_t acc[FM][FN];
@@ -605,20 +614,20 @@ __device__ __forceinline__ void gemm_dma_tile(const GemmArgs& g, int64_t braw) {
 #pragma unroll
     for (int b = 0; b < FN; ++b) acc[a][b] = typename MF::acc_t{};
 
-  // fragment element offset within a stage: row rr, k-chunk c (swizzled slot)
-  auto foff = [](int rr, int c) { return rr * BK + ((c ^ dma_swz<CPR>(rr)) << 3); };
-  const int fr = lane & 31;
-  const int fh = lane >> 5;
+  // element offset within a stage of row rr, element k of the step (swizzled chunk)
+  auto foff = [](int rr, int k) { return rr * BK + (((k / EPC) ^ dma_swz<CPR>(rr)) * EPC) + k % EPC; };
+  const int fr = MF::frow(lane);
+  const int fk = MF::fk(lane);
   auto compute = [&](const T* sa, const T* sb) {
 #pragma unroll
-    for (int h = 0; h < BK / MF::KS; ++h) {
+    for (int ks = 0; ks < BK; ks += MF::KS) {
       typename MF::frag_t af[FM], bf[FN];
 #pragma unroll
       for (int a = 0; a < FM; ++a)
-        af[a] = *reinterpret_cast<const typename MF::frag_t*>(sa + foff(wm0 + a * 32 + fr, 2 * h + fh));
+        af[a] = *reinterpret_cast<const typename MF::frag_t*>(sa + foff(wm0 + a * MF::BLK + fr, ks + fk));
 #pragma unroll
       for (int b = 0; b < FN; ++b)
-        bf[b] = *reinterpret_cast<const typename MF::frag_t*>(sb + foff(wn0 + b * 32 + fr, 2 * h + fh));
+        bf[b] = *reinterpret_cast<const typename MF::frag_t*>(sb + foff(wn0 + b * MF::BLK + fr, ks + fk));
 #pragma unroll
       for (int a = 0; a < FM; ++a)
 #pragma unroll
@@ -628,9 +637,9 @@ __device__ __forceinline__ void gemm_dma_tile(const GemmArgs& g, int64_t braw) {
 
   const int nk = int(Kz / BK);  // full steps through the pipeline
   if (nk > 0) {
-    // Every step issues exactly 2 CPT loads, also past the last step (then a harmless re-read
-    // of step 0 into a stage nobody reads again), so the number of loads younger than step
-    // kt's is always 2 CPT (NS - 2) and each wait is one fixed count on every path.
+    // Every step issues exactly CPTA + CPTB loads, also past the last step (then a harmless
+    // re-read of step 0 into a stage nobody reads again), so the number of loads younger than
+    // step kt's is always (CPTA + CPTB) (NS - 2) and each wait is one fixed count on every path.
     auto kstep = [&](int kt) { return kt < nk ? int64_t(kt) * BK : int64_t(0); };
     issue(std::integral_constant<int, 0>{}, 0);
     if constexpr (NS > 2) issue(std::integral_constant<int, 1>{}, kstep(1));
@@ -639,7 +648,7 @@ __device__ __forceinline__ void gemm_dma_tile(const GemmArgs& g, int64_t braw) {
     // with step kt + NS - 1, compute on stage S
     auto step = [&](auto S_, int kt) {
       constexpr int S = decltype(S_)::value;
-      wait_vm_lgkm0<2 * CPT * (NS - 2)>();
+      wait_vm_lgkm0<(CPTA + CPTB) * (NS - 2)>();
       wg_barrier();
       issue(std::integral_constant<int, (S + NS - 1) % NS>{}, kstep(kt + NS - 1));
       compute(stage_a(S_), stage_b(S_));
@@ -655,31 +664,24 @@ __device__ __forceinline__ void gemm_dma_tile(const GemmArgs& g, int64_t braw) {
     wait_vm_lgkm0<0>();  // no load may land in LDS after the workgroup ends
   }
   if (Kz > int64_t(nk) * BK) {  // K remainder: registers, zero fill, stage 0
-    u4 va[CPT], vb[CPT];
+    u4 va[CPTA], vb[CPTB];
+    auto tail_chunk = [&](const T* src, int p) {  // src: element kc * EPC of the row
+      const int64_t k = int64_t(nk) * BK + chunk_kc(p) * EPC;  // absolute K index of the chunk
+      T t[EPC];
 #pragma unroll
-    for (int p = 0; p < CPT; ++p) {
-      const T* a = nullptr;
-      const T* b = nullptr;
-      chunk_src(p, a, b);  // element kc * 8 of the row
-      const int c = p * NT + tid;
-      const int kc = (c % CPR) ^ dma_swz<CPR>(c / CPR);
-      const int64_t k = int64_t(nk) * BK + kc * 8;  // absolute K index of the chunk
-      T ta[8], tb[8];
+      for (int e = 0; e < EPC; ++e) t[e] = (k + e < Kz) ? src[int64_t(nk) * BK + e] : T(0);
+      return *reinterpret_cast<const u4*>(t);
+    };
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        ta[e] = (k + e < Kz) ? a[int64_t(nk) * BK + e] : T(0);
-        tb[e] = (k + e < Kz) ? b[int64_t(nk) * BK + e] : T(0);
-      }
-      va[p] = *reinterpret_cast<const u4*>(ta);
-      vb[p] = *reinterpret_cast<const u4*>(tb);
-    }
+    for (int p = 0; p < CPTA; ++p) va[p] = tail_chunk(src_a(p), p);
+#pragma unroll
+    for (int p = 0; p < CPTB; ++p) vb[p] = tail_chunk(src_b(p), p);
     wait_vm_lgkm0<0>();
     wg_barrier();  // every wave is done with the stages
 #pragma unroll
-    for (int p = 0; p < CPT; ++p) {
-      *reinterpret_cast<u4*>(sA0 + (p * NT + tid) * 8) = va[p];
-      *reinterpret_cast<u4*>(sB0 + (p * NT + tid) * 8) = vb[p];
-    }
+    for (int p = 0; p < CPTA; ++p) *reinterpret_cast<u4*>(sA0 + (p * NT + tid) * EPC) = va[p];
+#pragma unroll
+    for (int p = 0; p < CPTB; ++p) *reinterpret_cast<u4*>(sB0 + (p * NT + tid) * EPC) = vb[p];
     wait_vm_lgkm0<0>();
     wg_barrier();
     compute(sA0, sB0);
@@ -707,9 +709,9 @@ __device__ __forceinline__ void gemm_dma_tile(const GemmArgs& g, int64_t braw) {
   }
 }
 
-template <typename T, typename MF, int NS, int WGM, int WGN, int BK>
+template <typename T, typename MF, int NS, int WGM, int WGN, int BK, int BM, int BN>
 __global__ __launch_bounds__(64 * WGM * WGN) void gemm_dma_kernel(GemmArgs g) {
-  gemm_dma_tile<T, MF, NS, WGM, WGN, BK>(g, blockIdx.x);
+  gemm_dma_tile<T, MF, NS, WGM, WGN, BK, BM, BN>(g, blockIdx.x);
 }
 
 // the direct-to-LDS tile takes K-contiguous, 16-byte aligned operands without batch or split-K
@@ -736,12 +738,12 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_db_grouped_kernel(GemmGro
   gemm_db_tile<T, MF, BM, BN, WGM, WGN, KM, VEC>(gg.g[gi], local);
 }
 
-template <typename T, typename MF, int NS, int WGM, int WGN, int BK>
+template <typename T, typename MF, int NS, int WGM, int WGN, int BK, int BM, int BN>
 __global__ __launch_bounds__(64 * WGM * WGN) void gemm_dma_grouped_kernel(GemmGroup gg) {
   int64_t local = 0;
-  const int64_t gi = group_of<256, 256>(gg, &local);
+  const int64_t gi = group_of<BM, BN>(gg, &local);
   if (gi < 0) return;
-  gemm_dma_tile<T, MF, NS, WGM, WGN, BK>(gg.g[gi], local);
+  gemm_dma_tile<T, MF, NS, WGM, WGN, BK, BM, BN>(gg.g[gi], local);
 }
 
 template <typename T, int BM, int BN, bool VEC>
@@ -765,18 +767,21 @@ static void launch_db(const GemmArgs& a, bool vec, hipStream_t s) {
   GFCC_HIP(hipGetLastError());
 }
 
-template <typename T, int NS, int WGM, int WGN, int BK = 32>
+// 16-bit types take the 32x32x16 blocks, FP64 the 16x16x4 ones; BK in elements
+template <typename T, int NS, int WGM, int WGN, int BK = 32, int BM = 256, int BN = 256>
 static void launch_dma(const GemmArgs& a, hipStream_t s) {
-  const int64_t tiles = ((a.M + 255) / 256) * ((a.N + 255) / 256);
+  using MF = std::conditional_t<sizeof(T) == 2, typename Wide<T>::type, Mfma<T>>;
+  const int64_t tiles = ((a.M + BM - 1) / BM) * ((a.N + BN - 1) / BN);
   GFCC_CHECK(tiles < (int64_t(1) << 31), GFCC_E_ARG, "GEMM grid too large");
-  hipLaunchKernelGGL((gemm_dma_kernel<T, typename Wide<T>::type, NS, WGM, WGN, BK>), dim3(unsigned(tiles)),
-                     dim3(64 * WGM * WGN), 0, s, a);
+  hipLaunchKernelGGL((gemm_dma_kernel<T, MF, NS, WGM, WGN, BK, BM, BN>), dim3(unsigned(tiles)), dim3(64 * WGM * WGN),
+                     0, s, a);
   GFCC_HIP(hipGetLastError());
 }
-template <typename T, int NS, int WGM, int WGN, int BK = 32>
+template <typename T, int NS, int WGM, int WGN, int BK = 32, int BM = 256, int BN = 256>
 static void launch_dma_grouped(const GemmGroup& gg, hipStream_t s) {
-  hipLaunchKernelGGL((gemm_dma_grouped_kernel<T, typename Wide<T>::type, NS, WGM, WGN, BK>),
-                     dim3(unsigned(gg.start[gg.ng])), dim3(64 * WGM * WGN), 0, s, gg);
+  using MF = std::conditional_t<sizeof(T) == 2, typename Wide<T>::type, Mfma<T>>;
+  hipLaunchKernelGGL((gemm_dma_grouped_kernel<T, MF, NS, WGM, WGN, BK, BM, BN>), dim3(unsigned(gg.start[gg.ng])),
+                     dim3(64 * WGM * WGN), 0, s, gg);
   GFCC_HIP(hipGetLastError());
 }
 
@@ -848,6 +853,16 @@ static void dispatch(const GemmArgs& a, int cfg, bool vec, hipStream_t s) {
         launch_db<T, 256, 256, 4, 2>(a, vec, s);
       }
       break;
+    case TILE_DMA3_256x128:
+    case TILE_DMA2_256x128:
+      if constexpr (std::is_same_v<T, double>) {
+        if (!dma_ok(a, vec)) launch_db<T, 256, 128, 4, 2>(a, vec, s);
+        else if (cfg == TILE_DMA3_256x128) launch_dma<T, 3, 4, 2, 16, 256, 128>(a, s);
+        else launch_dma<T, 2, 4, 2, 16, 256, 128>(a, s);
+      } else {
+        launch_db<T, 256, 128, 4, 2>(a, vec, s);
+      }
+      break;
     default: throw Error{GFCC_E_ARG, "bad tile config"};
   }
 }
@@ -881,7 +896,8 @@ static void tile_dims(int cfg, int* bm, int* bn) {
     case TILE_64x64: *bm = 64; *bn = 64; return;
     case TILE_128x64: *bm = 128; *bn = 64; return;
     case TILE_64x128: *bm = 64; *bn = 128; return;
-    case TILE_DB_256x128: case TILE_DB32_256x128: *bm = 256; *bn = 128; return;
+    case TILE_DB_256x128: case TILE_DB32_256x128: case TILE_DMA3_256x128: case TILE_DMA2_256x128:
+      *bm = 256; *bn = 128; return;
     case TILE_DB_128x256: *bm = 128; *bn = 256; return;
     case TILE_DB_256x256: case TILE_DB32_256x256: case TILE_DB32_256x256_W16: case TILE_DB_256x256_W16:
     case TILE_DMA3_256x256: case TILE_DMA4_256x256: case TILE_DMA3_256x256_W8: case TILE_DMA3_256x256_W8T:
@@ -936,6 +952,16 @@ static void dispatch_grouped(const GemmGroup& gg, int cfg, bool vec, hipStream_t
         else launch_dma_grouped<T, 2, 4, 4, 64>(gg, s);
       } else {
         launch_db_grouped<T, 256, 256, 4, 2>(gg, vec, s);
+      }
+      break;
+    case TILE_DMA3_256x128:
+    case TILE_DMA2_256x128:
+      if constexpr (std::is_same_v<T, double>) {
+        if (!vec) launch_db_grouped<T, 256, 128, 4, 2>(gg, vec, s);
+        else if (cfg == TILE_DMA3_256x128) launch_dma_grouped<T, 3, 4, 2, 16, 256, 128>(gg, s);
+        else launch_dma_grouped<T, 2, 4, 2, 16, 256, 128>(gg, s);
+      } else {
+        launch_db_grouped<T, 256, 128, 4, 2>(gg, vec, s);
       }
       break;
     default: throw Error{GFCC_E_ARG, "bad tile config"};
@@ -1006,16 +1032,19 @@ void gemm_auto(Prec p, const GemmArgs& a, Scratch& scr, int scr_slot, hipStream_
 const char* tile_name(int cfg) {
   static const char* n[] = {"128x128", "64x64", "128x64", "64x128", "db128x128", "db256x128", "db128x256",
                             "db256x256", "db32_256x256", "db32_256x128", "db32_128x128", "db32_256x256w16", "db256x256w16",
-                            "dma3_256x256", "dma4_256x256", "dma3_256x256w8", "dma3_256x256w8t", "dma2k64_256x256"};
+                            "dma3_256x256", "dma4_256x256", "dma3_256x256w8", "dma3_256x256w8t", "dma2k64_256x256", "dma3_256x128", "dma2_256x128"};
   return (cfg >= 0 && cfg < N_TILE_CFG) ? n[cfg] : "?";
 }
 
-// Tiles for large K-contiguous products when no tuned entry exists: the double-buffered
-// 256x128 tile in FP64 and FP32, and in BF16 and FP16 the 16-wave 256x256 tile that loads
-// straight into two LDS stages of K = 64 (the fastest on the ring shapes).
+// Tiles for large K-contiguous products when no tuned entry exists (the fastest on the ring
+// shapes): in FP64 the 256x128 tile that loads straight into two LDS stages, in FP32 the
+// double-buffered 256x128 tile, in BF16 and FP16 the 16-wave 256x256 tile with two LDS stages
+// of K = 64 filled by direct loads.
 int gemm_big_cfg(Prec p, int64_t M, int64_t N, int64_t K) {
-  if (M >= 2048 && N >= 2048 && K >= 256)
-    return (p == Prec::BF16 || p == Prec::F16) ? TILE_DMA2K64_256x256 : TILE_DB_256x128;
+  if (M >= 2048 && N >= 2048 && K >= 256) {
+    if (p == Prec::BF16 || p == Prec::F16) return TILE_DMA2K64_256x256;
+    return p == Prec::F64 ? TILE_DMA2_256x128 : TILE_DB_256x128;
+  }
   return gemm_default_cfg(M, N, K);
 }
 
