@@ -89,11 +89,11 @@ MemPlan plan_memory(int64_t o, int64_t v, int64_t Q, int prec, int restart, int 
 namespace {
 
 // FP64 product C(i,j) = alpha sum_k A(i,k) B(j,k) + beta C(i,j) (see GemmArgs); large
-// products on the double-buffered tile, small grids split along K.
+// products on the 128x256 tile with direct-to-LDS loads, small grids split along K.
 void g64(const GemmArgs& g, Scratch& scr, hipStream_t s) {
   if (g.M <= 0 || g.N <= 0) return;
   if (g.batch == 1 && !g.b_ncontig && g.M >= 1024 && g.N >= 1024)
-    gemm(Prec::F64, g, TILE_DB_128x256, s);
+    gemm(Prec::F64, g, TILE_DMA2_128x256, s);
   else if (g.batch == 1)
     gemm_auto(Prec::F64, g, scr, 3, s);
   else

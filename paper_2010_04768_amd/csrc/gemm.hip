@@ -863,6 +863,14 @@ static void dispatch(const GemmArgs& a, int cfg, bool vec, hipStream_t s) {
         launch_db<T, 256, 128, 4, 2>(a, vec, s);
       }
       break;
+    case TILE_DMA2_128x256:
+      if constexpr (std::is_same_v<T, double>) {
+        if (!dma_ok(a, vec)) launch_db<T, 128, 256, 2, 4>(a, vec, s);
+        else launch_dma<T, 2, 2, 4, 16, 128, 256>(a, s);
+      } else {
+        launch_db<T, 128, 256, 2, 4>(a, vec, s);
+      }
+      break;
     default: throw Error{GFCC_E_ARG, "bad tile config"};
   }
 }
@@ -898,7 +906,7 @@ static void tile_dims(int cfg, int* bm, int* bn) {
     case TILE_64x128: *bm = 64; *bn = 128; return;
     case TILE_DB_256x128: case TILE_DB32_256x128: case TILE_DMA3_256x128: case TILE_DMA2_256x128:
       *bm = 256; *bn = 128; return;
-    case TILE_DB_128x256: *bm = 128; *bn = 256; return;
+    case TILE_DB_128x256: case TILE_DMA2_128x256: *bm = 128; *bn = 256; return;
     case TILE_DB_256x256: case TILE_DB32_256x256: case TILE_DB32_256x256_W16: case TILE_DB_256x256_W16:
     case TILE_DMA3_256x256: case TILE_DMA4_256x256: case TILE_DMA3_256x256_W8: case TILE_DMA3_256x256_W8T:
     case TILE_DMA2K64_256x256:
@@ -962,6 +970,14 @@ static void dispatch_grouped(const GemmGroup& gg, int cfg, bool vec, hipStream_t
         else launch_dma_grouped<T, 2, 4, 2, 16, 256, 128>(gg, s);
       } else {
         launch_db_grouped<T, 256, 128, 4, 2>(gg, vec, s);
+      }
+      break;
+    case TILE_DMA2_128x256:
+      if constexpr (std::is_same_v<T, double>) {
+        if (!vec) launch_db_grouped<T, 128, 256, 2, 4>(gg, vec, s);
+        else launch_dma_grouped<T, 2, 2, 4, 16, 128, 256>(gg, s);
+      } else {
+        launch_db_grouped<T, 128, 256, 2, 4>(gg, vec, s);
       }
       break;
     default: throw Error{GFCC_E_ARG, "bad tile config"};
@@ -1032,7 +1048,7 @@ void gemm_auto(Prec p, const GemmArgs& a, Scratch& scr, int scr_slot, hipStream_
 const char* tile_name(int cfg) {
   static const char* n[] = {"128x128", "64x64", "128x64", "64x128", "db128x128", "db256x128", "db128x256",
                             "db256x256", "db32_256x256", "db32_256x128", "db32_128x128", "db32_256x256w16", "db256x256w16",
-                            "dma3_256x256", "dma4_256x256", "dma3_256x256w8", "dma3_256x256w8t", "dma2k64_256x256", "dma3_256x128", "dma2_256x128"};
+                            "dma3_256x256", "dma4_256x256", "dma3_256x256w8", "dma3_256x256w8t", "dma2k64_256x256", "dma3_256x128", "dma2_256x128", "dma2_128x256"};
   return (cfg >= 0 && cfg < N_TILE_CFG) ? n[cfg] : "?";
 }
 

@@ -137,7 +137,9 @@ enum TileCfg : int {
   // FP64: 256x128 tiles, 8 waves of 64x64, loads straight into 3 or 2 LDS stages of K = 16
   // (other types: the double-buffered 256x128 tile)
   TILE_DMA3_256x128 = 18, TILE_DMA2_256x128 = 19,
-  N_TILE_CFG = 20
+  // FP64: 128x256, 8 waves of 64x64, two LDS stages of K = 16 (other types: the double-buffered 128x256)
+  TILE_DMA2_128x256 = 20,
+  N_TILE_CFG = 21
 };
 const char* tile_name(int cfg);
 

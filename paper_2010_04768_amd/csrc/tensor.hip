@@ -157,11 +157,11 @@ static void to_matrix(const TView& src, const std::string& sl, const std::string
   permute(src, perm, 1.0, out, 0.0, s);
 }
 
-// Large products go to the double-buffered 256x128 tile (the one the tuner picks for the
-// FP64 ring GEMMs); the rest to the default tile or split-K.
+// Large products go to the 256x128 tile with direct-to-LDS loads (the FP64 ring GEMMs' tile);
+// the rest to the default tile or split-K.
 static void contract_gemm(const GemmArgs& g, Scratch& scr, hipStream_t s) {
   if (g.M >= 2048 && g.N >= 2048 && g.batch == 1 && !g.b_ncontig)
-    gemm(Prec::F64, g, TILE_DB_256x128, s);
+    gemm(Prec::F64, g, TILE_DMA2_256x128, s);
   else
     gemm_auto(Prec::F64, g, scr, 3, s);
 }

@@ -17,7 +17,7 @@ if not torch.cuda.is_available():  # pragma: no cover
 from paper_2010_04768_amd import gfcc  # noqa: E402
 
 DMA_TILES = {"bf16": ["dma3_256x256", "dma4_256x256", "dma3_256x256w8", "dma3_256x256w8t", "dma2k64_256x256"],
-             "fp64": ["dma3_256x128", "dma2_256x128"]}
+             "fp64": ["dma3_256x128", "dma2_256x128", "dma2_128x256"]}
 DMA_TILES["fp16"] = DMA_TILES["bf16"]
 REF_TILE = {"bf16": "db32_256x256w16", "fp16": "db32_256x256w16", "fp64": "db256x128"}
 

@@ -109,7 +109,7 @@ def test_autotuner_cache_and_results(ctx, tmp_path):
     G1, _, _ = c.solve(p, w, 0.01, tol=1e-11, batch=16, tune_cache=cache)
     assert os.path.exists(cache)
     ent = json.load(open(cache))["entries"]
-    assert ent and all(0 <= e["cfg"] < 20 for e in ent)
+    assert ent and all(0 <= e["cfg"] < 21 for e in ent)
     rel = (torch.abs(G1 - G0) / torch.abs(G0)).max().item()
     assert rel < 1e-10
 
