@@ -332,7 +332,7 @@ def c60_main(args):
                    "step": "one frequency: 30 right-hand sides in one persistent window; intermediates built once"},
         "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK[dom] / 1e12, "unit": "TFLOP/s",
                      "frac": achieved / PEAK[dom], "traffic": traffic, "traffic_detail": traffic_detail,
-                     "kernel": f"ring GEMM {dom}, tile {dom_tile} (gemm_db_grouped_kernel)",
+                     "kernel": f"ring GEMM {dom}, tile {dom_tile} (one-group grouped launch)",
                      "avg_launch_ms": ring["ms"] / max(ring["count"], 1),
                      "launches": ring["count"]},
         "kernels": kernels,
