@@ -468,7 +468,8 @@ def spectral_block(args):
     lie thousands of Eh away): G_pp for the 8 highest occupied and the 8 lowest virtual orbitals at
     128 frequencies on [-1.5, 2.5] (eta 0.02), the IP
     term from an IP context and the EA term from an EA context, both by multi-shift GMRES (FP64,
-    tol 1e-8); A = A^IP + A^EA with the EA term taken at -eta (its poles lie on the other side of the
+    tol 1e-8; shifts that do not converge within the basis fall back to restarted GMRES, FP64 for
+    the IP term and FP16-IR for the EA term); A = A^IP + A^EA with the EA term taken at -eta (its poles lie on the other side of the
     real axis).  Reported: the time of each term, the largest relative difference of a few entries
     against restarted FP64 solves, min/max of A, and its integral over the window, which the sum
     rule puts near the number of orbitals (each G_pp carries unit weight over both terms) less the
@@ -497,8 +498,9 @@ def spectral_block(args):
         torch.cuda.synchronize()
         tb = time.perf_counter() - t0
         t0 = time.perf_counter()
+        fb = "fp16" if sector == "ea" else "fp64"
         Gs, infs, _ = ctx.solve_shifts(orbs, w, eta, tol=1e-8, max_dim=400,
-                                       fallback=dict(precond="jacobi", precision="fp64", tol=1e-8, restart=60))
+                                       fallback=dict(precond="jacobi", precision=fb, tol=1e-8, restart=60))
         torch.cuda.synchronize()
         ts = time.perf_counter() - t0
         G[sector] = Gs[:, :, 0]

@@ -130,7 +130,8 @@ gfcc_status gfcc_build_intermediates(const gfcc_system* sys, void* stream, gfcc_
  *                    GFCC_FP64 or GFCC_FP16_IR (FP16 sigma in the restart cycles, FP64 true
  *                    residuals between them); GFCC_PC_MLP is E_STATE.
  *   gfcc_solve_shifts multi-shift GMRES over all frequencies of each right-hand side orbital, the same
- *                    G^EA_{q p}(omega) layout (FP64; a fallback must be FP64 without the network)
+ *                    G^EA_{q p}(omega) layout (FP64; a fallback runs in FP64 or FP16-IR without the
+ *                    network)
  *   gfcc_greens, gfcc_greens_noalloc   G[r][k] = c'_{q[k]} . X[r]
  *   gfcc_export      FOO, FVV, FOV (the one-body blocks shared with the IP term) and DIAG [D]
  *   gfcc_prof_*, gfcc_destroy

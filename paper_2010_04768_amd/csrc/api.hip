@@ -685,8 +685,12 @@ gfcc_status gfcc_solve_shifts(gfcc_ctx* c, int64_t np, const int64_t* p, int64_t
       GFCC_CHECK(f.tol > 0.0 && f.restart >= 1 && f.max_iter >= 1, GFCC_E_ARG, "bad fallback tolerance/restart/max_iter");
       GFCC_CHECK(f.precond >= GFCC_PC_NONE && f.precond <= GFCC_PC_MLP, GFCC_E_ARG, "bad fallback preconditioner");
       GFCC_CHECK(f.precision >= GFCC_FP64 && f.precision <= GFCC_FP16_IR, GFCC_E_ARG, "bad fallback precision");
-      GFCC_CHECK(c->sector == 0 || (f.precision == GFCC_FP64 && f.precond != GFCC_PC_MLP), GFCC_E_ARG,
-                 "the fallback of an electron-attachment or open-shell context is FP64 without the network");
+      GFCC_CHECK(c->sector == 0 ||
+                     ((f.precision == GFCC_FP64 || (c->sector == 1 && f.precision == GFCC_FP16_IR)) &&
+                      f.precond != GFCC_PC_MLP),
+                 GFCC_E_ARG,
+                 "the fallback of an electron-attachment context is FP64 or FP16-IR, of an open-shell context FP64, "
+                 "both without the network");
     }
     if (c->sector == 1) {  // the EA system (omega - Hbar_N + i eta) Y = b' as (-omega - i eta + Hbar_N) Y = -b'
       std::vector<double> wneg(static_cast<size_t>(n_omega));

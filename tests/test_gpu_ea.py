@@ -219,6 +219,26 @@ def test_multishift_matches_oracle(sysea):
             assert np.abs(G[i, k] - ref[k]).max() <= 1e-10 * max(1.0, np.abs(ref[k]).max()), (p, ws[k])
 
 
+def test_multishift_fp16_ir_fallback(sysea):
+    """Multi-shift GMRES with a 6-vector basis, too small to reach 1e-11, so every shift falls back
+    to restarted GMRES, here FP16-IR (FP16 sigma in the cycles, FP64 true residuals): G still
+    matches the oracle at 1e-10."""
+    s, eim, ctx = sysea
+    o, v = s.n_occ, s.n_vir
+    ps = [o, o + v - 1]
+    ws = [0.35, 0.7, 1.05]
+    qs = [o, 0]
+    G, info, _ = ctx.solve_shifts(ps, ws, ETA, q=qs, tol=1e-11, max_dim=6,
+                                  fallback=dict(precond="jacobi", precision="fp16", tol=1e-11, restart=40,
+                                                max_iter=6000))
+    G = G.cpu().numpy()
+    for i, p in enumerate(ps):
+        ref = E.greens(s, eim, p, ws, ETA, ps=qs, tol=1e-13, restart=60)
+        for k in range(len(ws)):
+            assert info[i][k]["status"] in (0, 4), info[i][k]
+            assert np.abs(G[i, k] - ref[k]).max() <= 1e-10 * max(1.0, np.abs(ref[k]).max()), (p, ws[k])
+
+
 def test_ip_only_entry_points_refuse_ea_context(sysea):
     s, eim, ctx = sysea
     o = s.n_occ
