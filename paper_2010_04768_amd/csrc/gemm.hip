@@ -859,6 +859,10 @@ static void dispatch(const GemmArgs& a, int cfg, bool vec, hipStream_t s) {
         if (!dma_ok(a, vec)) launch_db<T, 256, 128, 4, 2>(a, vec, s);
         else if (cfg == TILE_DMA3_256x128) launch_dma<T, 3, 4, 2, 16, 256, 128>(a, s);
         else launch_dma<T, 2, 4, 2, 16, 256, 128>(a, s);
+      } else if constexpr (std::is_same_v<T, float>) {
+        if (!dma_ok(a, vec)) launch_db<T, 256, 128, 4, 2>(a, vec, s);
+        else if (cfg == TILE_DMA3_256x128) launch_dma<T, 3, 4, 2, 32, 256, 128>(a, s);
+        else launch_dma<T, 2, 4, 2, 32, 256, 128>(a, s);
       } else {
         launch_db<T, 256, 128, 4, 2>(a, vec, s);
       }
@@ -968,6 +972,10 @@ static void dispatch_grouped(const GemmGroup& gg, int cfg, bool vec, hipStream_t
         if (!vec) launch_db_grouped<T, 256, 128, 4, 2>(gg, vec, s);
         else if (cfg == TILE_DMA3_256x128) launch_dma_grouped<T, 3, 4, 2, 16, 256, 128>(gg, s);
         else launch_dma_grouped<T, 2, 4, 2, 16, 256, 128>(gg, s);
+      } else if constexpr (std::is_same_v<T, float>) {
+        if (!vec) launch_db_grouped<T, 256, 128, 4, 2>(gg, vec, s);
+        else if (cfg == TILE_DMA3_256x128) launch_dma_grouped<T, 3, 4, 2, 32, 256, 128>(gg, s);
+        else launch_dma_grouped<T, 2, 4, 2, 32, 256, 128>(gg, s);
       } else {
         launch_db_grouped<T, 256, 128, 4, 2>(gg, vec, s);
       }
@@ -1053,13 +1061,12 @@ const char* tile_name(int cfg) {
 }
 
 // Tiles for large K-contiguous products when no tuned entry exists (the fastest on the ring
-// shapes): in FP64 the 256x128 tile that loads straight into two LDS stages, in FP32 the
-// double-buffered 256x128 tile, in BF16 and FP16 the 16-wave 256x256 tile with two LDS stages
-// of K = 64 filled by direct loads.
+// shapes): the 256x128 tile that loads straight into two (FP64) or three (FP32) LDS stages, and
+// in BF16 and FP16 the 16-wave 256x256 tile with two LDS stages of K = 64 filled the same way.
 int gemm_big_cfg(Prec p, int64_t M, int64_t N, int64_t K) {
   if (M >= 2048 && N >= 2048 && K >= 256) {
     if (p == Prec::BF16 || p == Prec::F16) return TILE_DMA2K64_256x256;
-    return p == Prec::F64 ? TILE_DMA2_256x128 : TILE_DB_256x128;
+    return p == Prec::F64 ? TILE_DMA2_256x128 : TILE_DMA3_256x128;
   }
   return gemm_default_cfg(M, N, K);
 }

@@ -134,8 +134,8 @@ enum TileCfg : int {
   // waves (others: the 16-wave tile above)
   TILE_DMA3_256x256 = 13, TILE_DMA4_256x256 = 14, TILE_DMA3_256x256_W8 = 15, TILE_DMA3_256x256_W8T = 16,
   TILE_DMA2K64_256x256 = 17,
-  // FP64: 256x128 tiles, 8 waves of 64x64, loads straight into 3 or 2 LDS stages of K = 16
-  // (other types: the double-buffered 256x128 tile)
+  // FP64 and FP32: 256x128 tiles, 8 waves of 64x64, loads straight into 3 or 2 LDS stages of
+  // 128-byte rows (K = 16 doubles or 32 floats; other types: the double-buffered 256x128 tile)
   TILE_DMA3_256x128 = 18, TILE_DMA2_256x128 = 19,
   // FP64: 128x256, 8 waves of 64x64, two LDS stages of K = 16 (other types: the double-buffered 128x256)
   TILE_DMA2_128x256 = 20,

@@ -1,6 +1,6 @@
 """The GEMM tiles that load operands straight into LDS stages (global_load_lds) against the
 register-staged tiles of the same precision: the same K order of the MFMA steps, so sigma is the
-same to the bit in BF16, FP16 (against the 16-wave 256x256 tile) and FP64 (against the
+same to the bit in BF16, FP16 (against the 16-wave 256x256 tile), FP64 and FP32 (against the
 double-buffered 256x128 tile), on shapes with ragged M, N and K (a K remainder below one stage, K
 below one stage) and one that fills several tiles.  The tile is forced through GFCC_TILE_<prec>."""
 import numpy as np
@@ -19,11 +19,12 @@ from paper_2010_04768_amd import gfcc  # noqa: E402
 DMA_TILES = {"bf16": ["dma3_256x256", "dma4_256x256", "dma3_256x256w8", "dma3_256x256w8t", "dma2k64_256x256"],
              "fp64": ["dma3_256x128", "dma2_256x128", "dma2_128x256"]}
 DMA_TILES["fp16"] = DMA_TILES["bf16"]
-REF_TILE = {"bf16": "db32_256x256w16", "fp16": "db32_256x256w16", "fp64": "db256x128"}
+DMA_TILES["fp32"] = ["dma3_256x128", "dma2_256x128"]
+REF_TILE = {"bf16": "db32_256x256w16", "fp16": "db32_256x256w16", "fp64": "db256x128", "fp32": "db256x128"}
 
 
 @pytest.mark.parametrize("shape,nvec", [((5, 7, 9), 3), ((12, 45, 50), 5), ((20, 100, 400), 64)])
-@pytest.mark.parametrize("prec", ["bf16", "fp16", "fp64"])
+@pytest.mark.parametrize("prec", ["bf16", "fp16", "fp64", "fp32"])
 def test_dma_tiles_match_register_staged_tile(monkeypatch, shape, nvec, prec):
     o, v, Q = shape
     s = make_system(o, v, Q, 606 + o, sigma_L=0.1, sigma_t1=0.01)
