@@ -34,11 +34,11 @@ PEAK = {"fp64": 78.6e12, "fp32": 157.3e12, "bf16": 2.5e15, "fp16": 2.5e15}
 # HBM bytes per 512-slot ring-GEMM launch from rocprofv3 FETCH_SIZE / WRITE_SIZE passes
 # (profiles/ring_gemm_o40v200_bf16ir.md; copy-kernel scale 2.0 for FETCH_SIZE, 1.0 for
 # WRITE_SIZE).  Valid only for the GEMM source they were taken on.
-TRAFFIC = {"gemm_src_sha256_16": "0a24a5c2e6a5af6f",
-           "bf16": {"fetch_GB": 11.55, "write_GB": 2.623, "tile": "db32_256x256w16", "key": "2:40960:8000:8000",
-                    "launch": "512 slots, M=40960 N=K=8000"},
-           "fp64": {"fetch_GB": 47.05, "write_GB": 2.956, "tile": "db256x128", "key": "0:40960:8000:8000",
-                    "launch": "512 slots, M=40960 N=K=8000"}}
+TRAFFIC = {"gemm_src_sha256_16": "556e5fcfe26d9420",
+           "bf16": {"fetch_GB": 14.96, "write_GB": 2.622, "tile": "dma2k64_256x256", "key": "2:40960:8000:8000",
+                    "launch": "512 slots, M=40960 N=8000 K=16000 and 8000 (average of 54)"},
+           "fp64": {"fetch_GB": 69.83, "write_GB": 2.974, "tile": "dma3_256x128", "key": "0:40960:8000:8000",
+                    "launch": "512 slots, M=40960 N=8000 K=16000 and 8000 (average of 2)"}}
 DTYPE = {"fp64": "f64", "fp32": "f32+f64", "bf16": "bf16+f64", "fp16": "f16+f64"}
 # The same for the dominant ring GEMM of the 120/600/3000 headline (filled from its profile).
 TRAFFIC_C60 = {"gemm_src_sha256_16": "94c78b68f3e849c0",
