@@ -41,8 +41,8 @@ TRAFFIC = {"gemm_src_sha256_16": "556e5fcfe26d9420",
                     "launch": "512 slots, M=40960 N=8000 K=16000 and 8000 (average of 2)"}}
 DTYPE = {"fp64": "f64", "fp32": "f32+f64", "bf16": "bf16+f64", "fp16": "f16+f64"}
 # The same for the dominant ring GEMM of the 120/600/3000 headline (filled from its profile).
-TRAFFIC_C60 = {"gemm_src_sha256_16": "94c78b68f3e849c0",
-               "fp64:dma2_256x128": {"fetch_GB": 1541.1, "write_GB": 4.556,
+TRAFFIC_C60 = {"gemm_src_sha256_16": "556e5fcfe26d9420",
+               "fp64:dma2_256x128": {"fetch_GB": 1575.1, "write_GB": 4.551,
                                   "launch": "60 planes: P1 M=7200 N=72000 K=144000 and P2 K=72000, average of 6 "
                                             "(profiles/ring_gemm_c60_o120v600_bf16ir.md)"}}
 TILES = ["128x128", "64x64", "128x64", "64x128", "db128x128", "db256x128", "db128x256", "db256x256",
