@@ -89,6 +89,28 @@ def test_runs_between_synchronisations(ctx, prec, graph):
     assert k0["slot_iter"] <= 1.5 * k1["slot_iter"], (k0, k1)
 
 
+def test_runs_between_synchronisations_several_systems(ctx):
+    """The same bit identity for several systems in one persistent solve (lanes of different size
+    and convergence), eager and with graph replay."""
+    s, c = ctx
+    s2 = make_system(6, 20, 30, 779, sigma_L=0.1, sigma_t1=0.01)
+    c2 = gfcc.Context.from_system(s2)
+    try:
+        rng = np.random.default_rng(13)
+        sys_ = np.array([0, 1] * 15)
+        p = np.array([int(rng.integers(0, 10)) if k == 0 else int(rng.integers(0, 6)) for k in sys_])
+        w = rng.uniform(-1.2, -0.3, size=30)
+        for graph in (False, True):
+            M1, i1 = gfcc.solve_multi([c, c2], sys_, p, w, 0.01, tol=1e-10, batch=12, precision="bf16",
+                                      use_graph=graph, sync_every=1)
+            M0, i0 = gfcc.solve_multi([c, c2], sys_, p, w, 0.01, tol=1e-10, batch=12, precision="bf16",
+                                      use_graph=graph, sync_every=0)
+            assert all(x["status"] == 0 for x in i1)
+            assert torch.equal(M0, M1) and i0 == i1, graph
+    finally:
+        c2.close()
+
+
 def test_runs_respect_the_iteration_budget(ctx):
     """max_iter is an exact budget also inside runs of iterations (status 1, iters == max_iter)."""
     s, c = ctx
