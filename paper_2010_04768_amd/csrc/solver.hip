@@ -701,6 +701,7 @@ struct Lane {
   std::vector<int64_t> rows;
   size_t next = 0;
   int B = 0, nch = 0;
+  int defer = 0;  // inner iterations cycle finishing has waited for the last active slots
   int64_t Dp = 0;
   DBuf bV, bZ, bX, bH, bcs, bsn, bg, by, bz, bkk, bctol, bres, bflag, bfresh, bpart, bGm, bh, bnpart, bnorm;
   SolverDev d{};
@@ -1480,10 +1481,18 @@ struct BatchRun {
       }
       // finish cycles in groups: wait until half of a lane's live slots are
       // pending (slots advance in near lock-step, so this costs little
-      // latency) so the FP64 true-residual sigma runs on a wide batch
+      // latency) so the FP64 true-residual sigma runs on a wide batch; when
+      // every still active slot is predicted to stop within two iterations,
+      // wait for them too (at most two iterations), so that they do not need
+      // a true-residual sigma of their own on a few planes
       for (auto& L : lanes) {
         if (L.pending.empty()) continue;
         if (!L.active.empty() && L.pending.size() * 2 < L.active.size() + L.pending.size()) continue;
+        if (!L.active.empty() && L.defer < 2 && all_stop_soon(L, 2)) {
+          ++L.defer;
+          continue;
+        }
+        L.defer = 0;
         finish(L);
       }
     }
@@ -1493,6 +1502,18 @@ struct BatchRun {
     c0->prof["loop_sync"].count += n_loop_sync;
     c0->prof["inner_iter"].count += n_iter;
     c0->prof["slot_iter"].count += n_plane_iter;
+  }
+
+  // every active slot of the lane stops its cycle within n more iterations (by its predicted
+  // convergence, its restart length or its iteration budget)
+  bool all_stop_soon(const Lane& L, int n) const {
+    for (int sl : L.active) {
+      const HostSlot& h = L.hs[size_t(sl)];
+      if (m - h.k <= n || opts->max_iter - h.iters <= n) continue;
+      if (!(h.lrate < 0.0)) return false;
+      if (h.res > h.ctol && std::log(h.ctol / h.res) / h.lrate > double(n)) return false;
+    }
+    return true;
   }
 
   // Inner iterations to run before the next host synchronisation.  A slot whose
