@@ -272,13 +272,17 @@ typedef struct {
                                rows get X = 0 when X is requested. */
   int32_t sync_every;       /* inner iterations between host synchronisations of the solver loop
                                (flags, Krylov steps and residual estimates copied back in one
-                               transfer).  0 = automatic: the next run of iterations ends at 85% of
-                               the iterations the first active right-hand side is predicted to need
-                               to reach its cycle target (from the observed decrease of its
-                               residual estimate), at most 16; 1 = after every iteration.  A slot
-                               whose cycle stops inside a run is frozen on the device, so G, X and
-                               info do not depend on this value; it is 1 whenever the learned
-                               preconditioner or profiling is on. */
+                               transfer).  0 = automatic, from each active right-hand side's
+                               predicted iterations to its cycle target (the observed decrease of
+                               its residual estimate, capped by the restart length): where the
+                               window's sigma is estimated under 2 ms per iteration the run lasts
+                               until half of a system's slots are predicted to stop, otherwise it
+                               ends at 85% of the first slot's prediction; at most 16.  1 = after
+                               every iteration; k > 1 = runs of k.  A slot whose cycle stops inside
+                               a run is frozen on the device, so G, X and info do not depend on this
+                               value (FP16-IR: up to rounding, as the per-call vector scale sees the
+                               frozen planes); it is 1 whenever the learned preconditioner or
+                               profiling is on.  Runs never pass a right-hand side's max_iter. */
 } gfcc_solve_opts;
 
 /* Per right-hand side result (host memory). status: 0 converged, 1 max_iter,
